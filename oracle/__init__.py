@@ -1,0 +1,171 @@
+"""Plain FP64 CPU oracle of the ADER-DG step (ctypes binding of adg_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg of
+the benchmark use this package; the product library never imports it, and it
+imports nothing from the product.
+
+Arrays use the layouts documented at the top of adg_oracle.c (they are the
+same documented layouts the product's C ABI uses, so results compare element
+by element).
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "adg_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+NV = 5
+SIDE_CONFORMING, SIDE_FINE, SIDE_COARSE = 0, 1, 2
+
+
+def build():
+    """Compile the oracle with gcc (OpenMP over independent cells)."""
+    cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
+           "-o", _LIB + ".tmp", _SRC, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(_LIB + ".tmp", _LIB)
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        L.orc_gauss_legendre.argtypes = [ctypes.c_int, P, P]
+        L.orc_basis.argtypes = [ctypes.c_int, P, P, P, P, P, P, P]
+        L.orc_transfer.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P]
+        L.orc_mesh_build.restype = P
+        L.orc_mesh_build.argtypes = [ctypes.c_int, P, P, P, ctypes.c_int, ctypes.c_long, P]
+        L.orc_mesh_free.argtypes = [P]
+        L.orc_mesh_ncells.restype = ctypes.c_long
+        L.orc_mesh_ncells.argtypes = [P]
+        L.orc_mesh_cells.argtypes = [P, P]
+        L.orc_mesh_sides.argtypes = [P, P, P]
+        L.orc_node_coords.argtypes = [P, P]
+        L.orc_cfl.restype = ctypes.c_double
+        L.orc_cfl.argtypes = [P, ctypes.c_double, ctypes.c_double, P, P]
+        L.orc_predictor.argtypes = [P, ctypes.c_double, ctypes.c_int, ctypes.c_double, P, P, P]
+        L.orc_riemann.restype = ctypes.c_int
+        L.orc_riemann.argtypes = [P, ctypes.c_double, P, P]
+        L.orc_corrector.argtypes = [P, ctypes.c_double, P, P, P]
+        L.orc_run.restype = ctypes.c_int
+        L.orc_run.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                              ctypes.c_double, P, ctypes.c_int, P]
+        L.orc_num_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a
+
+
+def gauss_legendre(N):
+    xi, w = np.zeros(N), np.zeros(N)
+    assert lib().orc_gauss_legendre(N, _p(xi), _p(w)) == 0
+    return xi, w
+
+
+def basis(N):
+    """dict with xi, w, D, L, R, Kinv, Kw (see adg_oracle.c)."""
+    xi, w, L, R = (np.zeros(N) for _ in range(4))
+    D, Kinv, Kw = (np.zeros((N, N)) for _ in range(3))
+    assert lib().orc_basis(N, _p(xi), _p(w), _p(D), _p(L), _p(R), _p(Kinv), _p(Kw)) == 0
+    return dict(xi=xi, w=w, D=D, L=L, R=R, Kinv=Kinv, Kw=Kw)
+
+
+def transfer(N, r, s):
+    P, Rm = np.zeros((N, N)), np.zeros((N, N))
+    assert lib().orc_transfer(N, r, s, _p(P), _p(Rm)) == 0
+    return P, Rm
+
+
+class Mesh:
+    """Leaf mesh of a periodic box: base grid n, recursive 3x3x3 refinement."""
+
+    def __init__(self, order, n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), max_level=0, refine=None):
+        self.order = int(order)
+        self.N = self.order + 1
+        n = np.asarray(n, dtype=np.int32)
+        lo = _f64(lo)
+        hi = _f64(hi)
+        ref = np.zeros((0, 4), dtype=np.int32) if refine is None else np.ascontiguousarray(refine, dtype=np.int32)
+        h = lib().orc_mesh_build(self.N, _p(n), _p(lo), _p(hi), int(max_level), ref.shape[0], _p(ref))
+        if not h:
+            raise ValueError("oracle: invalid mesh description")
+        self._h = h
+        self.nc = lib().orc_mesh_ncells(h)
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().orc_mesh_free(self._h)
+            self._h = None
+
+    def cells(self):
+        out = np.zeros((self.nc, 4), dtype=np.int32)
+        lib().orc_mesh_cells(self._h, _p(out))
+        return out
+
+    def sides(self):
+        kind = np.zeros((self.nc, 6), dtype=np.int32)
+        nbr = np.zeros((self.nc, 6), dtype=np.int64)
+        lib().orc_mesh_sides(self._h, _p(kind), _p(nbr))
+        return kind, nbr
+
+    def node_coords(self):
+        xyz = np.zeros((3, self.nc, self.N ** 3))
+        lib().orc_node_coords(self._h, _p(xyz))
+        return xyz
+
+    def cfl(self, u, gamma=1.4, cfl=0.4):
+        u = _f64(u)
+        st = np.zeros(1, dtype=np.int32)
+        dt = lib().orc_cfl(self._h, gamma, cfl, _p(u), _p(st))
+        return dt, int(st[0])
+
+    def predictor(self, u, dt, gamma=1.4, npic=None):
+        u = _f64(u)
+        npic = self.N if npic is None else npic
+        us = np.zeros_like(u)
+        tr = np.zeros((6, 2, NV, self.nc, self.N ** 2))
+        lib().orc_predictor(self._h, gamma, int(npic), float(dt), _p(u), _p(us), _p(tr))
+        return us, tr
+
+    def riemann(self, traces, gamma=1.4):
+        traces = _f64(traces)
+        fs = np.zeros((6, NV, self.nc, self.N ** 2))
+        bad = lib().orc_riemann(self._h, gamma, _p(traces), _p(fs))
+        return fs, int(bad)
+
+    def corrector(self, ustar, fside, dt):
+        ustar, fside = _f64(ustar), _f64(fside)
+        un = np.zeros_like(ustar)
+        lib().orc_corrector(self._h, float(dt), _p(ustar), _p(fside), _p(un))
+        return un
+
+    def run(self, u, nsteps, gamma=1.4, cfl=0.4, npic=None, dt_fixed=0.0, t_end=0.0):
+        """Returns (u_final, dt_history, status)."""
+        u = np.array(u, dtype=np.float64, copy=True, order="C")
+        npic = self.N if npic is None else npic
+        hist = np.zeros(max(nsteps, 1))
+        rc = lib().orc_run(self._h, gamma, cfl, int(npic), float(dt_fixed), float(t_end), _p(u),
+                           int(nsteps), _p(hist))
+        return u, hist[:nsteps], int(rc)
+
+
+def num_threads():
+    return lib().orc_num_threads()

@@ -1,0 +1,872 @@
+/*
+ * adg_oracle.c -- plain, slow, FP64 CPU oracle for one ADER-DG time step of the
+ * 3-D compressible Euler equations on (adaptive) Cartesian meshes.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, includes or
+ * calls this file; only the test-suite, the smoke check and the CPU-baseline leg
+ * of the benchmark use it.  It shares no code, header, table or constant
+ * generator with the HIP path.
+ *
+ * What it follows (Charrier, Hazelwood, Weinzierl, "Enclave tasking for DG
+ * methods on dynamically adaptive meshes", arXiv:1806.07984):
+ *   - the conservation law dQ/dt + div F(Q) = 0 with m = 5 Euler variables
+ *     (Sec. 2, Eq. 1; source and point terms absent);
+ *   - the Lagrange basis on Gauss-Legendre points, same order in time (Sec. 2.1);
+ *   - the space-time predictor C_STP, element-local, jump terms dropped, solved
+ *     by Picard iterations, partial integration in time injecting Q_h(T)
+ *     (Sec. 2.1, Eq. 2 and the STP paragraph; Eq. 3);
+ *   - keep only the time-integrated face projections id|dc and the volume
+ *     data (Sec. 2.2, text after Eq. 3);
+ *   - one Rusanov solve per face over the whole time span (Sec. 2.4, Alg. 1);
+ *   - the corrector C_Corr that merges predictor and Riemann results (Eq. 4);
+ *   - adaptive meshes: virtual cells filled by interpolation from the coarse
+ *     cell (only their face projections are needed), Riemann solves on the
+ *     finest resolution, restriction (transpose of the interpolation) into the
+ *     parent face (Sec. 2.3, Assumption 1), 3-partitioning.
+ * Where the paper leaves a detail open (node family, Picard start and count,
+ * CFL formula, what the Riemann solver sees, the weighting of the
+ * restriction), this file takes the readings stated next to each function.
+ *
+ * Style: loops follow the definitions directly; no blocking, no fusion beyond
+ * what the definitions state.  OpenMP only distributes independent cells.
+ *
+ * Layouts (all arrays FP64 unless noted, cells ordered by (level, k, j, i)):
+ *   volume node  a = a0 + N*a1 + N*N*a2   (a0 along x fastest)
+ *   face node    b = a_t1 + N*a_t2 with (t1 < t2) the two tangential axes
+ *   sides        s = 2*d + (0: minus, 1: plus), d = 0,1,2
+ *   u, ustar     [5][ncell][N^3]
+ *   traces       [6 sides][2: (time-averaged Q, time-averaged normal flux)][5][ncell][N^2]
+ *   fside        [6 sides][5][ncell][N^2]  the face flux each cell side sees
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define NV 5
+#define MAXN 10
+
+/* ------------------------------------------------------------------------- */
+/* 1-D basis on [0,1]                                                        */
+/* ------------------------------------------------------------------------- */
+
+/* Legendre polynomial P_n(x) and its derivative by the three-term recurrence
+ * (k+1) P_{k+1} = (2k+1) x P_k - k P_{k-1}. */
+static void legendre_eval(int n, double x, double *P, double *dP)
+{
+    double p0 = 1.0, p1 = x;
+    if (n == 0) { *P = 1.0; *dP = 0.0; return; }
+    for (int k = 1; k < n; ++k) {
+        double p2 = ((2.0 * k + 1.0) * x * p1 - k * p0) / (k + 1.0);
+        p0 = p1;
+        p1 = p2;
+    }
+    *P = p1;
+    /* (1 - x^2) P_n' = n (P_{n-1} - x P_n) */
+    *dP = n * (p0 - x * p1) / (1.0 - x * x);
+}
+
+/* Gauss-Legendre nodes (ascending) and weights on [0,1], weights summing to 1.
+ * Roots of P_N by Newton's method from the Chebyshev-like initial guess. */
+int orc_gauss_legendre(int N, double *xi, double *w)
+{
+    if (N < 1 || N > MAXN) return 1;
+    for (int k = 0; k < N; ++k) {
+        double x = cos(M_PI * (k + 0.75) / (N + 0.5));
+        double P, dP;
+        for (int it = 0; it < 100; ++it) {
+            legendre_eval(N, x, &P, &dP);
+            double dx = P / dP;
+            x -= dx;
+            if (fabs(dx) < 1e-16) break;
+        }
+        legendre_eval(N, x, &P, &dP);
+        /* x runs from near +1 down to near -1 as k increases */
+        xi[k] = 0.5 * (1.0 - x);
+        w[k] = 1.0 / ((1.0 - x * x) * dP * dP); /* = (2/((1-x^2)P'^2)) / 2 */
+    }
+    return 0;
+}
+
+/* Lagrange basis polynomial phi_e on the nodes xi, evaluated at x. */
+static double lagrange(int N, const double *xi, int e, double x)
+{
+    double v = 1.0;
+    for (int m = 0; m < N; ++m)
+        if (m != e) v *= (x - xi[m]) / (xi[e] - xi[m]);
+    return v;
+}
+
+/* Derivative of phi_e at x (product rule written out). */
+static double lagrange_deriv(int N, const double *xi, int e, double x)
+{
+    double s = 0.0;
+    for (int k = 0; k < N; ++k) {
+        if (k == e) continue;
+        double t = 1.0 / (xi[e] - xi[k]);
+        for (int m = 0; m < N; ++m)
+            if (m != e && m != k) t *= (x - xi[m]) / (xi[e] - xi[m]);
+        s += t;
+    }
+    return s;
+}
+
+/* Inverse of an n x n matrix by Gauss-Jordan elimination with partial
+ * pivoting.  Returns nonzero if singular. */
+static int invert(int n, const double *A, double *Ainv)
+{
+    double M[MAXN][2 * MAXN];
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            M[i][j] = A[i * n + j];
+            M[i][n + j] = (i == j) ? 1.0 : 0.0;
+        }
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int i = c + 1; i < n; ++i)
+            if (fabs(M[i][c]) > fabs(M[piv][c])) piv = i;
+        if (M[piv][c] == 0.0) return 1;
+        if (piv != c)
+            for (int j = 0; j < 2 * n; ++j) {
+                double t = M[c][j]; M[c][j] = M[piv][j]; M[piv][j] = t;
+            }
+        double d = M[c][c];
+        for (int j = 0; j < 2 * n; ++j) M[c][j] /= d;
+        for (int i = 0; i < n; ++i) {
+            if (i == c) continue;
+            double f = M[i][c];
+            for (int j = 0; j < 2 * n; ++j) M[i][j] -= f * M[c][j];
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Ainv[i * n + j] = M[i][n + j];
+    return 0;
+}
+
+/* The 1-D operators of one order (N = p+1 nodes):
+ *   D[a][e]   = phi_e'(xi_a)                     derivative at the nodes
+ *   L[e], R[e]= phi_e(0), phi_e(1)               extrapolation to the faces
+ *   K1[k][l]  = phi_k(1) phi_l(1) - int phi_k' phi_l
+ *             = R_k R_l - w_l D[l][k]            time operator after partial
+ *               integration in time with Q_h(T) injected at tau = 0
+ *   Kinv      = K1^{-1}
+ *   Kw[a][e]  = int phi_a' phi_e = w_e D[e][a]   weak stiffness (exact by GL)
+ */
+int orc_basis(int N, double *xi, double *w, double *D, double *L, double *R,
+              double *Kinv, double *Kw)
+{
+    if (orc_gauss_legendre(N, xi, w)) return 1;
+    for (int a = 0; a < N; ++a)
+        for (int e = 0; e < N; ++e) D[a * N + e] = lagrange_deriv(N, xi, e, xi[a]);
+    for (int e = 0; e < N; ++e) {
+        L[e] = lagrange(N, xi, e, 0.0);
+        R[e] = lagrange(N, xi, e, 1.0);
+    }
+    double K1[MAXN * MAXN];
+    for (int k = 0; k < N; ++k)
+        for (int l = 0; l < N; ++l) K1[k * N + l] = R[k] * R[l] - w[l] * D[l * N + k];
+    if (invert(N, K1, Kinv)) return 2;
+    for (int a = 0; a < N; ++a)
+        for (int e = 0; e < N; ++e) Kw[a * N + e] = w[e] * D[e * N + a];
+    return 0;
+}
+
+/* Inter-grid transfer along one axis for a child interval s of a parent
+ * interval split into r equal parts (r = 3^dl with 3-partitioning):
+ *   P[k][e] = phi_e((s + xi_k)/r)      interpolation coarse -> child nodes
+ *   Rm[k][e] = (1/r)(w_e/w_k) phi_k((s + xi_e)/r)
+ * Rm is the transpose of P taken in the quadrature-weighted inner product
+ * (Rm = r^{-1} W^{-1} P^T W), which makes the restriction conservative and
+ * sum_s Rm^(s) P^(s) = I. */
+int orc_transfer(int N, int r, int s, double *P, double *Rm)
+{
+    double xi[MAXN], w[MAXN];
+    if (orc_gauss_legendre(N, xi, w)) return 1;
+    if (r < 1 || s < 0 || s >= r) return 2;
+    for (int k = 0; k < N; ++k)
+        for (int e = 0; e < N; ++e) {
+            P[k * N + e] = lagrange(N, xi, e, (s + xi[k]) / r);
+            Rm[k * N + e] = (w[e] / w[k]) * lagrange(N, xi, k, (s + xi[e]) / r) / r;
+        }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Euler equations                                                           */
+/* ------------------------------------------------------------------------- */
+
+static double pressure(double g, const double q[NV])
+{
+    return (g - 1.0) * (q[4] - 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0]);
+}
+
+/* Flux along axis d: (m_d, m_d m/rho + p e_d, m_d (E + p)/rho). */
+static void euler_flux(double g, const double q[NV], int d, double f[NV])
+{
+    double p = pressure(g, q);
+    double vd = q[1 + d] / q[0];
+    f[0] = q[1 + d];
+    f[1] = vd * q[1];
+    f[2] = vd * q[2];
+    f[3] = vd * q[3];
+    f[1 + d] += p;
+    f[4] = vd * (q[4] + p);
+}
+
+/* Largest characteristic speed along d: |u_d| + c, c = sqrt(gamma p / rho). */
+static double euler_speed(double g, const double q[NV], int d)
+{
+    double p = pressure(g, q);
+    return fabs(q[1 + d] / q[0]) + sqrt(g * p / q[0]);
+}
+
+static int unphysical(double g, const double q[NV])
+{
+    for (int v = 0; v < NV; ++v)
+        if (!isfinite(q[v])) return 1;
+    if (!(q[0] > 0.0)) return 1;
+    if (!(pressure(g, q) > 0.0)) return 1;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Mesh: conformal base grid, recursive 3x3x3 refinement (Assumption 1)      */
+/* ------------------------------------------------------------------------- */
+
+enum { SIDE_CONFORMING = 0, SIDE_FINE = 1, SIDE_COARSE = 2 };
+
+typedef struct {
+    int N;
+    int n[3];
+    double lo[3], hi[3];
+    int max_level;
+    long nc;
+    int *lev;     /* [nc] */
+    int *ijk;     /* [3*nc] integer cell coordinates at the cell's level */
+    /* per cell side (6 per cell):
+     *   kind[6*c+s]  SIDE_CONFORMING: same-level neighbour nbr
+     *                SIDE_FINE: neighbour nbr is coarser (hanging face, this
+     *                           cell is the fine side)
+     *                SIDE_COARSE: the region beyond is refined further   */
+    int *kind;
+    long *nbr;
+} orc_mesh;
+
+static long ipow3(int e)
+{
+    long r = 1;
+    while (e-- > 0) r *= 3;
+    return r;
+}
+
+/* lexicographic key compare: (level, k, j, i) */
+static int key_cmp(int la, const int *a, int lb, const int *b)
+{
+    if (la != lb) return la < lb ? -1 : 1;
+    for (int d = 2; d >= 0; --d)
+        if (a[d] != b[d]) return a[d] < b[d] ? -1 : 1;
+    return 0;
+}
+
+static long find_cell(const orc_mesh *m, int l, const int *c)
+{
+    long lo = 0, hi = m->nc - 1;
+    while (lo <= hi) {
+        long mid = (lo + hi) / 2;
+        int r = key_cmp(m->lev[mid], &m->ijk[3 * mid], l, c);
+        if (r == 0) return mid;
+        if (r < 0) lo = mid + 1; else hi = mid - 1;
+    }
+    return -1;
+}
+
+typedef struct { int l, i[3]; } cellkey;
+
+static int cellkey_cmp(const void *pa, const void *pb)
+{
+    const cellkey *a = (const cellkey *)pa, *b = (const cellkey *)pb;
+    return key_cmp(a->l, a->i, b->l, b->i);
+}
+
+void orc_mesh_free(orc_mesh *m)
+{
+    if (!m) return;
+    free(m->lev); free(m->ijk); free(m->kind); free(m->nbr);
+    free(m);
+}
+
+/* Build the leaf mesh.  refine holds n_refine entries (level, i, j, k); each
+ * names a leaf that is split into 27 children.  Entries of level l must refer
+ * to leaves that exist once all entries of levels < l are applied.  Only fully
+ * periodic domains are represented.  Returns NULL on invalid input. */
+orc_mesh *orc_mesh_build(int N, const int *n, const double *lo, const double *hi,
+                         int max_level, long n_refine, const int *refine)
+{
+    if (N < 1 || N > MAXN || max_level < 0 || max_level > 4) return NULL;
+    for (int d = 0; d < 3; ++d)
+        if (n[d] < 1 || !(hi[d] > lo[d])) return NULL;
+    /* current leaves, as keys */
+    long cap = (long)n[0] * n[1] * n[2];
+    cellkey *leaves = (cellkey *)malloc(sizeof(cellkey) * cap);
+    long nl = 0;
+    for (int k = 0; k < n[2]; ++k)
+        for (int j = 0; j < n[1]; ++j)
+            for (int i = 0; i < n[0]; ++i) {
+                leaves[nl].l = 0;
+                leaves[nl].i[0] = i; leaves[nl].i[1] = j; leaves[nl].i[2] = k;
+                ++nl;
+            }
+    /* sorted refine list */
+    cellkey *ref = (cellkey *)malloc(sizeof(cellkey) * (n_refine > 0 ? n_refine : 1));
+    for (long r = 0; r < n_refine; ++r) {
+        ref[r].l = refine[4 * r];
+        for (int d = 0; d < 3; ++d) ref[r].i[d] = refine[4 * r + 1 + d];
+        if (ref[r].l < 0 || ref[r].l >= max_level) { free(leaves); free(ref); return NULL; }
+    }
+    qsort(ref, n_refine, sizeof(cellkey), cellkey_cmp);
+    for (long r = 1; r < n_refine; ++r)
+        if (cellkey_cmp(&ref[r - 1], &ref[r]) == 0) { free(leaves); free(ref); return NULL; }
+    /* apply level by level; leaves stay sorted because children are appended
+     * at a strictly greater level and re-sorted */
+    long used = 0;
+    for (int l = 0; l < max_level; ++l) {
+        long first = used;
+        while (used < n_refine && ref[used].l == l) ++used;
+        long nr = used - first;
+        if (nr == 0) continue;
+        cellkey *next = (cellkey *)malloc(sizeof(cellkey) * (nl - nr + 27 * nr));
+        long nn = 0, found = 0;
+        for (long q = 0; q < nl; ++q) {
+            cellkey *c = &leaves[q];
+            int is_ref = 0;
+            if (c->l == l) {
+                cellkey *hit = (cellkey *)bsearch(c, ref + first, nr, sizeof(cellkey), cellkey_cmp);
+                is_ref = hit != NULL;
+            }
+            if (!is_ref) { next[nn++] = *c; continue; }
+            ++found;
+            for (int dz = 0; dz < 3; ++dz)
+                for (int dy = 0; dy < 3; ++dy)
+                    for (int dx = 0; dx < 3; ++dx) {
+                        next[nn].l = l + 1;
+                        next[nn].i[0] = 3 * c->i[0] + dx;
+                        next[nn].i[1] = 3 * c->i[1] + dy;
+                        next[nn].i[2] = 3 * c->i[2] + dz;
+                        ++nn;
+                    }
+        }
+        free(leaves);
+        leaves = next;
+        nl = nn;
+        if (found != nr) { free(leaves); free(ref); return NULL; }
+        qsort(leaves, nl, sizeof(cellkey), cellkey_cmp);
+    }
+    free(ref);
+
+    orc_mesh *m = (orc_mesh *)calloc(1, sizeof(orc_mesh));
+    m->N = N;
+    for (int d = 0; d < 3; ++d) { m->n[d] = n[d]; m->lo[d] = lo[d]; m->hi[d] = hi[d]; }
+    m->max_level = max_level;
+    m->nc = nl;
+    m->lev = (int *)malloc(sizeof(int) * nl);
+    m->ijk = (int *)malloc(sizeof(int) * 3 * nl);
+    m->kind = (int *)malloc(sizeof(int) * 6 * nl);
+    m->nbr = (long *)malloc(sizeof(long) * 6 * nl);
+    for (long c = 0; c < nl; ++c) {
+        m->lev[c] = leaves[c].l;
+        for (int d = 0; d < 3; ++d) m->ijk[3 * c + d] = leaves[c].i[d];
+    }
+    free(leaves);
+
+    /* neighbour search: same level first, then coarser levels; otherwise the
+     * region beyond the face is refined further */
+    for (long c = 0; c < nl; ++c) {
+        int l = m->lev[c];
+        for (int s = 0; s < 6; ++s) {
+            int d = s / 2, dir = (s % 2) ? 1 : -1;
+            int q[3] = { m->ijk[3 * c], m->ijk[3 * c + 1], m->ijk[3 * c + 2] };
+            long extent = n[d] * ipow3(l);
+            q[d] = (int)(((long)q[d] + dir + extent) % extent);
+            long hit = find_cell(m, l, q);
+            if (hit >= 0) { m->kind[6 * c + s] = SIDE_CONFORMING; m->nbr[6 * c + s] = hit; continue; }
+            m->kind[6 * c + s] = SIDE_COARSE;
+            m->nbr[6 * c + s] = -1;
+            for (int lc = l - 1; lc >= 0; --lc) {
+                long f = ipow3(l - lc);
+                int qc[3] = { (int)(q[0] / f), (int)(q[1] / f), (int)(q[2] / f) };
+                hit = find_cell(m, lc, qc);
+                if (hit >= 0) { m->kind[6 * c + s] = SIDE_FINE; m->nbr[6 * c + s] = hit; break; }
+            }
+        }
+    }
+    return m;
+}
+
+long orc_mesh_ncells(const orc_mesh *m) { return m->nc; }
+
+/* level, i, j, k of every cell */
+void orc_mesh_cells(const orc_mesh *m, int *out)
+{
+    for (long c = 0; c < m->nc; ++c) {
+        out[4 * c] = m->lev[c];
+        for (int d = 0; d < 3; ++d) out[4 * c + 1 + d] = m->ijk[3 * c + d];
+    }
+}
+
+/* kind and neighbour of every cell side: kind[6*nc], nbr[6*nc] */
+void orc_mesh_sides(const orc_mesh *m, int *kind, long *nbr)
+{
+    memcpy(kind, m->kind, sizeof(int) * 6 * m->nc);
+    memcpy(nbr, m->nbr, sizeof(long) * 6 * m->nc);
+}
+
+static void cell_dx(const orc_mesh *m, long c, double dx[3])
+{
+    double f = (double)ipow3(m->lev[c]);
+    for (int d = 0; d < 3; ++d) dx[d] = (m->hi[d] - m->lo[d]) / (m->n[d] * f);
+}
+
+/* Physical coordinates of every node: xyz[3][nc][N^3]. */
+void orc_node_coords(const orc_mesh *m, double *xyz)
+{
+    int N = m->N, N3 = N * N * N;
+    double xi[MAXN], w[MAXN];
+    orc_gauss_legendre(N, xi, w);
+    for (long c = 0; c < m->nc; ++c) {
+        double dx[3];
+        cell_dx(m, c, dx);
+        for (int a2 = 0; a2 < N; ++a2)
+            for (int a1 = 0; a1 < N; ++a1)
+                for (int a0 = 0; a0 < N; ++a0) {
+                    int a = a0 + N * a1 + N * N * a2;
+                    int aa[3] = { a0, a1, a2 };
+                    for (int d = 0; d < 3; ++d)
+                        xyz[((long)d * m->nc + c) * N3 + a] =
+                            m->lo[d] + (m->ijk[3 * c + d] + xi[aa[d]]) * dx[d];
+                }
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Index helpers                                                             */
+/* ------------------------------------------------------------------------- */
+
+/* volume node index with the index along axis d replaced by e */
+static int node_with(int N, int a, int d, int e)
+{
+    int aa[3] = { a % N, (a / N) % N, a / (N * N) };
+    aa[d] = e;
+    return aa[0] + N * aa[1] + N * N * aa[2];
+}
+
+/* face node index b of volume node a for a face normal to d */
+static int face_index(int N, int a, int d)
+{
+    int aa[3] = { a % N, (a / N) % N, a / (N * N) };
+    int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+    return aa[t1] + N * aa[t2];
+}
+
+/* volume node with index e along d and face index b on the tangential axes */
+static int node_from_face(int N, int d, int e, int b)
+{
+    int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+    int aa[3];
+    aa[d] = e;
+    aa[t1] = b % N;
+    aa[t2] = b / N;
+    return aa[0] + N * aa[1] + N * N * aa[2];
+}
+
+/* ------------------------------------------------------------------------- */
+/* Time step size (global time stepping, one dt for all cells)               */
+/* ------------------------------------------------------------------------- */
+
+/* dt = cfl / ((2p+1) * max_{cells,nodes} sum_d lambda_d(u)/dx_d), lambda_d =
+ * |u_d| + c.  Sets *status = 1 if any node is unphysical (rho <= 0, p <= 0 or
+ * a non-finite value). */
+double orc_cfl(const orc_mesh *m, double g, double cfl, const double *u, int *status)
+{
+    int N = m->N, N3 = N * N * N;
+    long nc = m->nc;
+    double lam = 0.0;
+    int bad = 0;
+#pragma omp parallel for reduction(max : lam) reduction(| : bad) schedule(static)
+    for (long c = 0; c < nc; ++c) {
+        double dx[3];
+        cell_dx(m, c, dx);
+        for (int a = 0; a < N3; ++a) {
+            double q[NV];
+            for (int v = 0; v < NV; ++v) q[v] = u[((long)v * nc + c) * N3 + a];
+            if (unphysical(g, q)) { bad = 1; continue; }
+            double s = 0.0;
+            for (int d = 0; d < 3; ++d) s += euler_speed(g, q, d) / dx[d];
+            if (s > lam) lam = s;
+        }
+    }
+    *status = bad;
+    if (bad || !(lam > 0.0)) return 0.0;
+    return cfl / ((2.0 * (N - 1) + 1.0) * lam);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Space-time predictor + volume term + face projections                     */
+/* ------------------------------------------------------------------------- */
+
+/* Per cell, with tau in [0,1] mapped to (T, T+dt) and reference coordinates:
+ *   q_l  (l = time node) starts as u at every time node,
+ *   repeat npic times:
+ *     G_j   = sum_d (dt/dx_d) (D along axis d) f_d(q_j)
+ *     q_l  <- u - sum_j Kinv[l][j] w_j G_j
+ *   qbar  = sum_j w_j q_j,  Fbar_d = sum_j w_j f_d(q_j)   (final iterate)
+ *   ustar = u + sum_d (dt/dx_d) (1/w_{a_d}) sum_e Kw[a_d][e] Fbar_d(..e..)
+ *   traces: qbar and Fbar_d extrapolated with L (minus side) or R (plus side)
+ *   along d; only the normal flux component d is kept. */
+void orc_predictor(const orc_mesh *m, double g, int npic, double dt,
+                   const double *u, double *ustar, double *traces)
+{
+    int N = m->N, N2 = N * N, N3 = N2 * N;
+    long nc = m->nc;
+    double xi[MAXN], w[MAXN], D[MAXN * MAXN], L[MAXN], R[MAXN], Kinv[MAXN * MAXN], Kw[MAXN * MAXN];
+    orc_basis(N, xi, w, D, L, R, Kinv, Kw);
+
+#pragma omp parallel
+    {
+        double *q = (double *)malloc(sizeof(double) * N * NV * N3);      /* [l][v][a] */
+        double *qn = (double *)malloc(sizeof(double) * N * NV * N3);
+        double *F = (double *)malloc(sizeof(double) * N * 3 * NV * N3);  /* [j][d][v][a] */
+        double *G = (double *)malloc(sizeof(double) * N * NV * N3);      /* [j][v][a] */
+        double *qbar = (double *)malloc(sizeof(double) * NV * N3);
+        double *Fbar = (double *)malloc(sizeof(double) * 3 * NV * N3);
+#pragma omp for schedule(static)
+        for (long c = 0; c < nc; ++c) {
+            double dx[3];
+            cell_dx(m, c, dx);
+            double uc[NV][MAXN * MAXN * MAXN];
+            for (int v = 0; v < NV; ++v)
+                for (int a = 0; a < N3; ++a) uc[v][a] = u[((long)v * nc + c) * N3 + a];
+
+            for (int l = 0; l < N; ++l)
+                for (int v = 0; v < NV; ++v)
+                    for (int a = 0; a < N3; ++a) q[(l * NV + v) * N3 + a] = uc[v][a];
+
+            for (int it = 0; it <= npic; ++it) {
+                /* fluxes of the current iterate */
+                for (int j = 0; j < N; ++j)
+                    for (int a = 0; a < N3; ++a) {
+                        double qq[NV], f[NV];
+                        for (int v = 0; v < NV; ++v) qq[v] = q[(j * NV + v) * N3 + a];
+                        for (int d = 0; d < 3; ++d) {
+                            euler_flux(g, qq, d, f);
+                            for (int v = 0; v < NV; ++v) F[((j * 3 + d) * NV + v) * N3 + a] = f[v];
+                        }
+                    }
+                if (it == npic) break; /* the final fluxes feed the time averages */
+                /* G_j = sum_d (dt/dx_d) D_d f_d(q_j) */
+                for (int j = 0; j < N; ++j)
+                    for (int v = 0; v < NV; ++v)
+                        for (int a = 0; a < N3; ++a) {
+                            int aa[3] = { a % N, (a / N) % N, a / N2 };
+                            double s = 0.0;
+                            for (int d = 0; d < 3; ++d) {
+                                double sd = 0.0;
+                                for (int e = 0; e < N; ++e)
+                                    sd += D[aa[d] * N + e] * F[((j * 3 + d) * NV + v) * N3 + node_with(N, a, d, e)];
+                                s += (dt / dx[d]) * sd;
+                            }
+                            G[(j * NV + v) * N3 + a] = s;
+                        }
+                /* q_l = u - sum_j Kinv[l][j] w_j G_j */
+                for (int l = 0; l < N; ++l)
+                    for (int v = 0; v < NV; ++v)
+                        for (int a = 0; a < N3; ++a) {
+                            double s = 0.0;
+                            for (int j = 0; j < N; ++j) s += Kinv[l * N + j] * w[j] * G[(j * NV + v) * N3 + a];
+                            qn[(l * NV + v) * N3 + a] = uc[v][a] - s;
+                        }
+                double *t = q; q = qn; qn = t;
+            }
+            /* time averages of the final iterate */
+            for (int v = 0; v < NV; ++v)
+                for (int a = 0; a < N3; ++a) {
+                    double s = 0.0;
+                    for (int j = 0; j < N; ++j) s += w[j] * q[(j * NV + v) * N3 + a];
+                    qbar[v * N3 + a] = s;
+                    for (int d = 0; d < 3; ++d) {
+                        double sf = 0.0;
+                        for (int j = 0; j < N; ++j) sf += w[j] * F[((j * 3 + d) * NV + v) * N3 + a];
+                        Fbar[(d * NV + v) * N3 + a] = sf;
+                    }
+                }
+            /* volume term */
+            for (int v = 0; v < NV; ++v)
+                for (int a = 0; a < N3; ++a) {
+                    int aa[3] = { a % N, (a / N) % N, a / N2 };
+                    double s = 0.0;
+                    for (int d = 0; d < 3; ++d) {
+                        double sd = 0.0;
+                        for (int e = 0; e < N; ++e)
+                            sd += Kw[aa[d] * N + e] * Fbar[(d * NV + v) * N3 + node_with(N, a, d, e)];
+                        s += (dt / dx[d]) * sd / w[aa[d]];
+                    }
+                    ustar[((long)v * nc + c) * N3 + a] = uc[v][a] + s;
+                }
+            /* face projections of the time-averaged data */
+            for (int s = 0; s < 6; ++s) {
+                int d = s / 2;
+                const double *E = (s % 2) ? R : L;
+                for (int v = 0; v < NV; ++v)
+                    for (int b = 0; b < N2; ++b) {
+                        double sq = 0.0, sf = 0.0;
+                        for (int e = 0; e < N; ++e) {
+                            int a = node_from_face(N, d, e, b);
+                            sq += E[e] * qbar[v * N3 + a];
+                            sf += E[e] * Fbar[(d * NV + v) * N3 + a];
+                        }
+                        traces[(((long)(s * 2 + 0) * NV + v) * nc + c) * N2 + b] = sq;
+                        traces[(((long)(s * 2 + 1) * NV + v) * nc + c) * N2 + b] = sf;
+                    }
+            }
+        }
+        free(q); free(qn); free(F); free(G); free(qbar); free(Fbar);
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Riemann solves (Rusanov), with virtual cells and restriction on AMR       */
+/* ------------------------------------------------------------------------- */
+
+/* Rusanov flux on one face with N2 nodes, normal axis d, left state (QL, FL)
+ * on the minus side and right state (QR, FR) on the plus side; one wave
+ * speed s per face, the largest |u_d| + c over the face nodes of both sides.
+ * Arrays are [5][N2]. Returns 1 if a node is unphysical. */
+static int rusanov(double g, int d, int N2, const double *QL, const double *FL,
+                   const double *QR, const double *FR, double *Fs)
+{
+    double smax = 0.0;
+    int bad = 0;
+    for (int b = 0; b < N2; ++b) {
+        double ql[NV], qr[NV];
+        for (int v = 0; v < NV; ++v) { ql[v] = QL[v * N2 + b]; qr[v] = QR[v * N2 + b]; }
+        if (unphysical(g, ql) || unphysical(g, qr)) bad = 1;
+        double sl = euler_speed(g, ql, d), sr = euler_speed(g, qr, d);
+        if (sl > smax) smax = sl;
+        if (sr > smax) smax = sr;
+    }
+    for (int v = 0; v < NV; ++v)
+        for (int b = 0; b < N2; ++b)
+            Fs[v * N2 + b] = 0.5 * (FL[v * N2 + b] + FR[v * N2 + b])
+                             - 0.5 * smax * (QR[v * N2 + b] - QL[v * N2 + b]);
+    return bad;
+}
+
+static void get_trace(const orc_mesh *m, const double *traces, long c, int s, int arr, double *out)
+{
+    int N2 = m->N * m->N;
+    for (int v = 0; v < NV; ++v)
+        for (int b = 0; b < N2; ++b)
+            out[v * N2 + b] = traces[(((long)(s * 2 + arr) * NV + v) * m->nc + c) * N2 + b];
+}
+
+static void put_side(const orc_mesh *m, double *fside, long c, int s, const double *F)
+{
+    int N2 = m->N * m->N;
+    for (int v = 0; v < NV; ++v)
+        for (int b = 0; b < N2; ++b)
+            fside[((long)(s * NV + v) * m->nc + c) * N2 + b] = F[v * N2 + b];
+}
+
+/* tangential axes of a face normal to d, increasing */
+static void tangential(int d, int *t1, int *t2)
+{
+    *t1 = (d == 0) ? 1 : 0;
+    *t2 = (d == 2) ? 1 : 2;
+}
+
+/* Virtual-cell face data: the coarse cell's face projection interpolated to
+ * the child face (s1, s2) with 1-D interpolation P along each tangential
+ * axis (the exact restriction of the coarse polynomial to the child face). */
+static void prolong_face(int N, int r, int s1, int s2, const double *coarse, double *fine)
+{
+    int N2 = N * N;
+    double P1[MAXN * MAXN], P2[MAXN * MAXN], Rm[MAXN * MAXN];
+    orc_transfer(N, r, s1, P1, Rm);
+    orc_transfer(N, r, s2, P2, Rm);
+    for (int v = 0; v < NV; ++v)
+        for (int k2 = 0; k2 < N; ++k2)
+            for (int k1 = 0; k1 < N; ++k1) {
+                double s = 0.0;
+                for (int e2 = 0; e2 < N; ++e2)
+                    for (int e1 = 0; e1 < N; ++e1)
+                        s += P1[k1 * N + e1] * P2[k2 * N + e2] * coarse[v * N2 + e1 + N * e2];
+                fine[v * N2 + k1 + N * k2] = s;
+            }
+}
+
+/* child sub-position of fine cell f inside the coarse cell, along axis t */
+static int sub_position(const orc_mesh *m, long f, long cc, int t)
+{
+    long r = ipow3(m->lev[f] - m->lev[cc]);
+    return (int)(m->ijk[3 * f + t] - r * m->ijk[3 * cc + t]);
+}
+
+/* Fills fside for every cell side.  Conforming faces: one Rusanov solve,
+ * written to both sides.  Hanging faces: the Rusanov solve runs on the child
+ * face between the fine cell and the virtual cell; the fine cell sees the
+ * result; the coarse side receives the sum over its child faces of the
+ * restricted results (accumulated in increasing fine-cell order).
+ * Returns 1 if an unphysical state was met. */
+int orc_riemann(const orc_mesh *m, double g, const double *traces, double *fside)
+{
+    int N = m->N, N2 = N * N;
+    long nc = m->nc;
+    int bad = 0;
+#pragma omp parallel reduction(| : bad)
+    {
+        double *QL = (double *)malloc(sizeof(double) * NV * N2 * 6);
+        double *FL = QL + NV * N2, *QR = FL + NV * N2, *FR = QR + NV * N2;
+        double *Fs = FR + NV * N2, *tmp = Fs + NV * N2;
+#pragma omp for schedule(static)
+        for (long c = 0; c < nc; ++c) {
+            for (int s = 0; s < 6; ++s) {
+                int d = s / 2, plus = s % 2;
+                int kind = m->kind[6 * c + s];
+                long o = m->nbr[6 * c + s];
+                if (kind == SIDE_COARSE) continue;
+                int so = 2 * d + (1 - plus); /* the neighbour's side facing c */
+                double *Qc = plus ? QL : QR, *Fc = plus ? FL : FR;
+                double *Qo = plus ? QR : QL, *Fo = plus ? FR : FL;
+                get_trace(m, traces, c, s, 0, Qc);
+                get_trace(m, traces, c, s, 1, Fc);
+                if (kind == SIDE_CONFORMING) {
+                    get_trace(m, traces, o, so, 0, Qo);
+                    get_trace(m, traces, o, so, 1, Fo);
+                } else {
+                    int t1, t2;
+                    tangential(d, &t1, &t2);
+                    int r = (int)ipow3(m->lev[c] - m->lev[o]);
+                    int s1 = sub_position(m, c, o, t1), s2 = sub_position(m, c, o, t2);
+                    get_trace(m, traces, o, so, 0, tmp);
+                    prolong_face(N, r, s1, s2, tmp, Qo);
+                    get_trace(m, traces, o, so, 1, tmp);
+                    prolong_face(N, r, s1, s2, tmp, Fo);
+                }
+                bad |= rusanov(g, d, N2, QL, FL, QR, FR, Fs);
+                put_side(m, fside, c, s, Fs);
+            }
+        }
+        free(QL);
+    }
+    /* restriction into coarse sides: zero, then accumulate child results */
+    for (long c = 0; c < nc; ++c)
+        for (int s = 0; s < 6; ++s)
+            if (m->kind[6 * c + s] == SIDE_COARSE)
+                for (int v = 0; v < NV; ++v)
+                    for (int b = 0; b < N2; ++b) fside[((long)(s * NV + v) * nc + c) * N2 + b] = 0.0;
+    for (long f = 0; f < nc; ++f) {
+        for (int s = 0; s < 6; ++s) {
+            if (m->kind[6 * f + s] != SIDE_FINE) continue;
+            int d = s / 2, plus = s % 2;
+            long cc = m->nbr[6 * f + s];
+            int sc = 2 * d + (1 - plus);
+            int t1, t2;
+            tangential(d, &t1, &t2);
+            int r = (int)ipow3(m->lev[f] - m->lev[cc]);
+            int s1 = sub_position(m, f, cc, t1), s2 = sub_position(m, f, cc, t2);
+            double P[MAXN * MAXN], R1[MAXN * MAXN], R2[MAXN * MAXN];
+            orc_transfer(N, r, s1, P, R1);
+            orc_transfer(N, r, s2, P, R2);
+            for (int v = 0; v < NV; ++v)
+                for (int k2 = 0; k2 < N; ++k2)
+                    for (int k1 = 0; k1 < N; ++k1) {
+                        double acc = 0.0;
+                        for (int e2 = 0; e2 < N; ++e2)
+                            for (int e1 = 0; e1 < N; ++e1)
+                                acc += R1[k1 * N + e1] * R2[k2 * N + e2] *
+                                       fside[((long)(s * NV + v) * nc + f) * N2 + e1 + N * e2];
+                        fside[((long)(sc * NV + v) * nc + cc) * N2 + k1 + N * k2] += acc;
+                    }
+        }
+    }
+    return bad;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Corrector                                                                 */
+/* ------------------------------------------------------------------------- */
+
+/* u_new = ustar - sum_d (dt/dx_d)(1/w_{a_d}) [R_{a_d} F*_{d+} - L_{a_d} F*_{d-}]
+ * with F*_{d+-} the face flux of the cell side at the node's face index. */
+void orc_corrector(const orc_mesh *m, double dt, const double *ustar, const double *fside, double *unew)
+{
+    int N = m->N, N2 = N * N, N3 = N2 * N;
+    long nc = m->nc;
+    double xi[MAXN], w[MAXN], D[MAXN * MAXN], L[MAXN], R[MAXN], Kinv[MAXN * MAXN], Kw[MAXN * MAXN];
+    orc_basis(N, xi, w, D, L, R, Kinv, Kw);
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < nc; ++c) {
+        double dx[3];
+        cell_dx(m, c, dx);
+        for (int v = 0; v < NV; ++v)
+            for (int a = 0; a < N3; ++a) {
+                int aa[3] = { a % N, (a / N) % N, a / N2 };
+                double s = 0.0;
+                for (int d = 0; d < 3; ++d) {
+                    int b = face_index(N, a, d);
+                    double fm = fside[((long)((2 * d) * NV + v) * nc + c) * N2 + b];
+                    double fp = fside[((long)((2 * d + 1) * NV + v) * nc + c) * N2 + b];
+                    s += (dt / dx[d]) * (R[aa[d]] * fp - L[aa[d]] * fm) / w[aa[d]];
+                }
+                unew[((long)v * nc + c) * N3 + a] = ustar[((long)v * nc + c) * N3 + a] - s;
+            }
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Whole steps                                                               */
+/* ------------------------------------------------------------------------- */
+
+/* Runs nsteps ADER-DG steps in place on u.  dt per step from orc_cfl, or the
+ * fixed value dt_fixed when dt_fixed > 0; t_end > 0 clamps the last step and
+ * ends the run once t_end is reached (later dt_hist entries stay untouched).
+ * Writes the dt of every step to dt_hist (may be NULL).  Returns 0 on success,
+ * 1 if an unphysical state was met (u then holds the last valid state),
+ * 2 on allocation failure. */
+int orc_run(const orc_mesh *m, double g, double cfl, int npic, double dt_fixed, double t_end,
+            double *u, int nsteps, double *dt_hist)
+{
+    int N = m->N, N2 = N * N, N3 = N2 * N;
+    long nc = m->nc;
+    double *us = (double *)malloc(sizeof(double) * NV * nc * N3);
+    double *tr = (double *)malloc(sizeof(double) * 6 * 2 * NV * nc * N2);
+    double *fs = (double *)malloc(sizeof(double) * 6 * NV * nc * N2);
+    if (!us || !tr || !fs) { free(us); free(tr); free(fs); return 2; }
+    double t = 0.0;
+    int rc = 0;
+    for (int n = 0; n < nsteps; ++n) {
+        if (t_end > 0.0 && t >= t_end) break; /* final time reached */
+        int st = 0;
+        double dt = dt_fixed > 0.0 ? dt_fixed : orc_cfl(m, g, cfl, u, &st);
+        if (st) { rc = 1; break; }
+        if (t_end > 0.0 && t + dt > t_end) dt = t_end - t;
+        if (dt_hist) dt_hist[n] = dt;
+        orc_predictor(m, g, npic, dt, u, us, tr);
+        if (orc_riemann(m, g, tr, fs)) { rc = 1; break; }
+        orc_corrector(m, dt, us, fs, u);
+        t += dt;
+    }
+    free(us); free(tr); free(fs);
+    return rc;
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
