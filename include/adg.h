@@ -1,0 +1,175 @@
+/*
+ * adg.h -- C ABI of the MI355X (gfx950) ADER-DG time-step library.
+ *
+ * The library advances the 3-D compressible Euler equations
+ *     dQ/dt + div F(Q) = 0,  Q = (rho, m1, m2, m3, E),  p = (gamma-1)(E - |m|^2/(2 rho))
+ * (Charrier, Hazelwood, Weinzierl, arXiv:1806.07984, Sec. 2, Eq. 1 without
+ * source and point terms) with the ADER-DG scheme of Eq. 4: a cell-local
+ * space-time predictor C_STP (Eq. 3, Picard iterations), projections of its
+ * time average onto the faces (id|dc, Sec. 2.2), one Rusanov solve per face
+ * over the whole time step (F_R, Alg. 1, Sec. 2.4) and the corrector C_Corr.
+ * On adaptive meshes (Sec. 2.3, Assumption 1, 3-partitioning) hanging faces
+ * are solved on the fine side against data interpolated from the coarse cell
+ * (virtual cells) and the results are restricted into the coarse face.
+ *
+ * Conventions for every call
+ *   - Every function returns adg_status and never throws.  On a non-OK return
+ *     adg_last_error() gives a message (thread-local).
+ *   - Pointers named *_dev are HIP device memory OWNED BY THE CALLER.  The
+ *     mesh handle owns only connectivity, basis constants and small scratch.
+ *   - All device work is enqueued asynchronously on the given stream(s); no
+ *     call synchronises the host unless its comment says so.  The time step
+ *     size lives in device memory and is never read back by the step loop.
+ *   - Argument errors are detected on the host before anything is enqueued.
+ *     Non-physical states met on the device (rho <= 0, p <= 0, non-finite) are
+ *     latched in the handle and reported by adg_get_status().
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *
+ * Numbering and layouts (shared with every array argument)
+ *   N = p + 1 Gauss-Legendre nodes per axis on [0,1]; m = 5 variables.
+ *   cells      ordered by (level, k, j, i), i fastest; level 0 = base grid.
+ *   volume     node a = a0 + N a1 + N^2 a2 (a0 along x).
+ *   sides      s = 2 d + (0: minus, 1: plus), d = 0 (x), 1 (y), 2 (z).
+ *   face node  b = a_t1 + N a_t2, t1 < t2 the two axes tangential to d.
+ *   u, u*      double [5][n_cells][N^3]            ("solution layout")
+ *   traces     real   [6][2][5][n_cells][N^2]      [side][0: time-averaged Q,
+ *                                                  1: time-averaged normal flux]
+ *   fside      real   [6][5][n_cells][N^2]         face flux seen by each side
+ *   real = double for ADG_FP64, float for ADG_FP32_MFMA.
+ *   Batched handles (n_instances > 1) concatenate the instances' arrays: the
+ *   offsets of instance i are reported by adg_instance_info().
+ */
+#ifndef ADG_H
+#define ADG_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct adg_mesh adg_mesh;
+
+typedef enum {
+    ADG_OK = 0,
+    ADG_ERR_INVALID_ARG = 1,  /* bad descriptor, null pointer, size mismatch  */
+    ADG_ERR_UNSUPPORTED = 2,  /* order, level count or boundary not supported */
+    ADG_ERR_OOM = 3,          /* device or host allocation failed             */
+    ADG_ERR_HIP = 4,          /* a HIP runtime call failed                    */
+    ADG_ERR_NONPHYSICAL = 5,  /* rho <= 0, p <= 0 or non-finite state met     */
+    ADG_ERR_WORKSPACE = 6     /* workspace smaller than adg_mesh_info reports */
+} adg_status;
+
+typedef enum {
+    ADG_FP64 = 0,       /* every step in FP64                                    */
+    ADG_FP32_MFMA = 1   /* predictor, traces, Riemann in FP32 (contractions on
+                           MFMA); u, u*, dt and the corrector accumulation FP64 */
+} adg_precision;
+
+/* One periodic box with an optional static 3:1 refinement (Assumption 1). */
+typedef struct {
+    int32_t order;           /* p in [0, 7]; N = p+1 nodes per axis                */
+    int32_t n[3];            /* base cells per axis, >= 1                          */
+    double lo[3], hi[3];     /* domain box, hi > lo                                */
+    uint32_t periodic_mask;  /* must be 7 (periodic along x, y and z)              */
+    int32_t max_level;       /* 0 = uniform; at most 3 refinement levels           */
+    int64_t n_refine;        /* number of (level, i, j, k) rows in refine          */
+    const int32_t *refine;   /* host array; each row names a leaf to split 3x3x3.
+                                Rows of level l must name leaves that exist once
+                                all rows of lower levels are applied; l < max_level */
+    double gamma;            /* ratio of specific heats, > 1                       */
+    double cfl;              /* dt = cfl / ((2p+1) max sum_d (|u_d|+c)/dx_d)       */
+    int32_t picard_iters;    /* predictor iterations; 0 selects p+1                */
+} adg_instance_desc;
+
+typedef struct {
+    int32_t n_instances;
+    int64_t n_cells;          /* total over instances                            */
+    int64_t n_dofs;           /* 5 * sum_i n_cells_i * N_i^3                      */
+    int64_t u_elems;          /* doubles in a solution array (= n_dofs)           */
+    int64_t trace_elems;      /* reals in a traces array                          */
+    int64_t fside_elems;      /* reals in an fside array                          */
+    int64_t workspace_bytes;  /* device bytes adg_step needs in ws                */
+    int64_t n_conforming_faces, n_hanging_faces, n_skeleton_cells;
+    int32_t real_bytes;       /* 8 (FP64) or 4 (FP32_MFMA)                        */
+} adg_info;
+
+typedef struct {
+    int32_t order;
+    int64_t n_cells;
+    int64_t cell_offset;      /* first cell of the instance                       */
+    int64_t u_offset;         /* first double of the instance in u / u*           */
+    int64_t trace_offset;     /* first real of the instance in traces             */
+    int64_t fside_offset;     /* first real of the instance in fside              */
+} adg_instance_geom;
+
+/* Builds the leaf meshes, face lists, skeleton/enclave lists and basis
+ * constants of n_instances descriptors (desc[0..n_instances-1]) on the current
+ * HIP device.  All instances of one handle use the same precision.
+ * Returns ADG_ERR_INVALID_ARG for inconsistent descriptors (including refine
+ * rows naming non-leaves), ADG_ERR_UNSUPPORTED for p > 7, max_level > 3 or a
+ * non-periodic box.  *out is set only on success; free with adg_free_mesh. */
+adg_status adg_init_mesh(const adg_instance_desc *desc, int32_t n_instances,
+                         adg_precision prec, adg_mesh **out);
+void adg_free_mesh(adg_mesh *mesh);
+
+adg_status adg_mesh_info(const adg_mesh *mesh, adg_info *info);
+adg_status adg_instance_info(const adg_mesh *mesh, int32_t instance, adg_instance_geom *info);
+
+/* Host copy of the cell table: level, i, j, k per cell (4 * n_cells int32). */
+adg_status adg_mesh_cells(const adg_mesh *mesh, int32_t *cells_host);
+
+/* Physical coordinates of every node, xyz_dev = double [3][u_elems / 5]
+ * (per instance: [3][n_cells][N^3] at offset 3 * u_offset / 5). */
+adg_status adg_node_coords(const adg_mesh *mesh, double *xyz_dev, hipStream_t stream);
+
+/* Global time step size per instance (Sec. 2.2: global time stepping, one dt
+ * for all cells): dt_dev[i] = cfl / ((2p+1) max_{cells,nodes} sum_d
+ * (|u_d| + c)/dx_d), c = sqrt(gamma p / rho).  Non-physical nodes latch
+ * ADG_ERR_NONPHYSICAL and give dt = 0.  dt_dev holds n_instances doubles. */
+adg_status adg_cfl(adg_mesh *mesh, const double *u_dev, double *dt_dev, hipStream_t stream);
+
+/* C_STP plus id|dc and the volume part of C_Corr (Eq. 3-4): for every cell,
+ * Picard iterations of the element-local space-time problem starting from
+ * u at every time node, then u* = u + volume term of the time-averaged flux,
+ * and the face projections of the time-averaged state and normal flux. */
+adg_status adg_predictor(adg_mesh *mesh, const double *u_dev, const double *dt_dev,
+                         double *ustar_dev, void *traces_dev, hipStream_t stream);
+
+/* F_R (Alg. 1, Sec. 2.4): one Rusanov solve per face, F* = (F_L + F_R)/2 -
+ * s (Q_R - Q_L)/2 with s the largest |u_d| + c over the face's nodes on both
+ * sides; hanging faces (Sec. 2.3) are solved on each child face against the
+ * coarse cell's projection interpolated to it, and the coarse side receives
+ * the restriction (quadrature-weighted transpose of the interpolation) of
+ * its child results.  Writes the flux every cell side sees into fside. */
+adg_status adg_riemann(adg_mesh *mesh, const void *traces_dev, void *fside_dev, hipStream_t stream);
+
+/* C_Corr (Eq. 4): u_out = u* - sum_d (dt/dx_d)(1/w_{a_d})
+ * [phi_{a_d}(1) F*_{d+} - phi_{a_d}(0) F*_{d-}], accumulated in FP64.
+ * u_out may alias ustar. */
+adg_status adg_corrector(adg_mesh *mesh, const double *ustar_dev, const void *fside_dev,
+                         const double *dt_dev, double *u_out_dev, hipStream_t stream);
+
+/* n_steps whole steps in place on u_dev (cfl -> predictor -> riemann ->
+ * corrector per step).  ws_dev must hold workspace_bytes.  dt_hist_dev, if not
+ * NULL, receives n_steps * n_instances doubles (step-major).  Skeleton cells
+ * (cells at a resolution transition) run their predictor on stream_skeleton
+ * and the hanging-face work follows them there; enclave cells run on
+ * stream_enclave; both streams are joined before the corrector.  Passing the
+ * same stream twice serialises the phases.  Results do not depend on the
+ * schedule. */
+adg_status adg_step(adg_mesh *mesh, double *u_dev, int32_t n_steps, double *dt_hist_dev,
+                    void *ws_dev, hipStream_t stream_skeleton, hipStream_t stream_enclave);
+
+/* Synchronises the handle's device work and returns ADG_ERR_NONPHYSICAL if a
+ * non-physical state was met since the last call (then clears the latch). */
+adg_status adg_get_status(adg_mesh *mesh);
+
+const char *adg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ADG_H */

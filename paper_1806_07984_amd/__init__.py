@@ -1,0 +1,249 @@
+"""MI355X-native ADER-DG time step for the 3-D compressible Euler equations.
+
+Thin Python binding of the C ABI in include/adg.h (libadg.so, built in-tree by
+``python -m paper_1806_07984_amd.build``).  This module only marshals
+arguments: every phase of the step runs in the library's HIP kernels.  PyTorch
+supplies device memory and streams.  If the library is missing, loading fails
+with an error; there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libadg.so")
+
+NV = 5
+FP64, FP32_MFMA = 0, 1
+
+STATUS = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "OOM", 4: "HIP", 5: "NONPHYSICAL", 6: "WORKSPACE"}
+
+EXPORTS = ["adg_init_mesh", "adg_free_mesh", "adg_mesh_info", "adg_instance_info", "adg_mesh_cells",
+           "adg_node_coords", "adg_cfl", "adg_predictor", "adg_riemann", "adg_corrector", "adg_step",
+           "adg_get_status", "adg_last_error"]
+
+
+class AdgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"adg error {STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class InstanceDesc(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int32), ("n", ctypes.c_int32 * 3), ("lo", ctypes.c_double * 3),
+                ("hi", ctypes.c_double * 3), ("periodic_mask", ctypes.c_uint32), ("max_level", ctypes.c_int32),
+                ("n_refine", ctypes.c_int64), ("refine", ctypes.c_void_p), ("gamma", ctypes.c_double),
+                ("cfl", ctypes.c_double), ("picard_iters", ctypes.c_int32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n_instances", ctypes.c_int32), ("n_cells", ctypes.c_int64), ("n_dofs", ctypes.c_int64),
+                ("u_elems", ctypes.c_int64), ("trace_elems", ctypes.c_int64), ("fside_elems", ctypes.c_int64),
+                ("workspace_bytes", ctypes.c_int64), ("n_conforming_faces", ctypes.c_int64),
+                ("n_hanging_faces", ctypes.c_int64), ("n_skeleton_cells", ctypes.c_int64),
+                ("real_bytes", ctypes.c_int32)]
+
+
+class InstanceGeom(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int32), ("n_cells", ctypes.c_int64), ("cell_offset", ctypes.c_int64),
+                ("u_offset", ctypes.c_int64), ("trace_offset", ctypes.c_int64), ("fside_offset", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load():
+    """Load libadg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} not found: build it with `python -m paper_1806_07984_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    sig = {
+        "adg_init_mesh": [ctypes.POINTER(InstanceDesc), I32, I32, ctypes.POINTER(P)],
+        "adg_free_mesh": [P],
+        "adg_mesh_info": [P, ctypes.POINTER(Info)],
+        "adg_instance_info": [P, I32, ctypes.POINTER(InstanceGeom)],
+        "adg_mesh_cells": [P, P],
+        "adg_node_coords": [P, P, P],
+        "adg_cfl": [P, P, P, P],
+        "adg_predictor": [P, P, P, P, P, P],
+        "adg_riemann": [P, P, P, P],
+        "adg_corrector": [P, P, P, P, P, P],
+        "adg_step": [P, P, I32, P, P, P, P],
+        "adg_get_status": [P],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = None if name == "adg_free_mesh" else ctypes.c_int
+    L.adg_last_error.restype = ctypes.c_char_p
+    L.adg_last_error.argtypes = []
+    _lib = L
+    return L
+
+
+def _check(code):
+    if code != 0:
+        raise AdgError(code, load().adg_last_error().decode())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t, dtype, numel, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def instance(order, n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), max_level=0, refine=None, gamma=1.4, cfl=0.4,
+             picard_iters=0):
+    """Descriptor of one periodic box (see adg_instance_desc)."""
+    return dict(order=order, n=tuple(n), lo=tuple(lo), hi=tuple(hi), max_level=max_level, refine=refine,
+                gamma=gamma, cfl=cfl, picard_iters=picard_iters)
+
+
+class Mesh:
+    """Handle over one or more instances (adg_init_mesh).
+
+    precision: "fp64" (ADG_FP64) or "fp32" (ADG_FP32_MFMA)."""
+
+    def __init__(self, descs, precision="fp64"):
+        L = load()
+        if isinstance(descs, dict):
+            descs = [descs]
+        self.precision = precision
+        prec = {"fp64": FP64, "fp32": FP32_MFMA}[precision]
+        arr = (InstanceDesc * len(descs))()
+        self._keep = []
+        for i, d in enumerate(descs):
+            ref = np.zeros((0, 4), dtype=np.int32) if d.get("refine") is None else \
+                np.ascontiguousarray(d["refine"], dtype=np.int32)
+            self._keep.append(ref)
+            a = arr[i]
+            a.order = d["order"]
+            a.n[:] = list(d["n"])
+            a.lo[:] = list(d.get("lo", (0.0, 0.0, 0.0)))
+            a.hi[:] = list(d.get("hi", (1.0, 1.0, 1.0)))
+            a.periodic_mask = 7
+            a.max_level = d.get("max_level", 0)
+            a.n_refine = ref.shape[0]
+            a.refine = ref.ctypes.data if ref.shape[0] else None
+            a.gamma = d.get("gamma", 1.4)
+            a.cfl = d.get("cfl", 0.4)
+            a.picard_iters = d.get("picard_iters", 0)
+        h = ctypes.c_void_p()
+        _check(L.adg_init_mesh(arr, len(descs), prec, ctypes.byref(h)))
+        self._h = h
+        info = Info()
+        _check(L.adg_mesh_info(self._h, ctypes.byref(info)))
+        self.info = {k: getattr(info, k) for k, _ in Info._fields_}
+        self.instances = []
+        for i in range(len(descs)):
+            g = InstanceGeom()
+            _check(L.adg_instance_info(self._h, i, ctypes.byref(g)))
+            self.instances.append({k: getattr(g, k) for k, _ in InstanceGeom._fields_})
+        self.n_instances = len(descs)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().adg_free_mesh(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- sizes and allocation ------------------------------------------------
+    @property
+    def real_dtype(self):
+        import torch
+        return torch.float64 if self.precision == "fp64" else torch.float32
+
+    def empty_u(self, device="cuda"):
+        import torch
+        return torch.empty(self.info["u_elems"], dtype=torch.float64, device=device)
+
+    def empty_traces(self, device="cuda"):
+        import torch
+        return torch.empty(self.info["trace_elems"], dtype=self.real_dtype, device=device)
+
+    def empty_fside(self, device="cuda"):
+        import torch
+        return torch.empty(self.info["fside_elems"], dtype=self.real_dtype, device=device)
+
+    def empty_workspace(self, device="cuda"):
+        import torch
+        return torch.empty(self.info["workspace_bytes"], dtype=torch.uint8, device=device)
+
+    def cells(self):
+        out = np.zeros((self.info["n_cells"], 4), dtype=np.int32)
+        _check(load().adg_mesh_cells(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    # -- calls ---------------------------------------------------------------
+    def node_coords(self, stream=None):
+        import torch
+        xyz = torch.empty(3 * self.info["u_elems"] // NV, dtype=torch.float64, device="cuda")
+        _check(load().adg_node_coords(self._h, _ptr(xyz, torch.float64, None, "xyz"), _stream(stream)))
+        return xyz
+
+    def cfl(self, u, dt, stream=None):
+        import torch
+        _check(load().adg_cfl(self._h, _ptr(u, torch.float64, self.info["u_elems"], "u"),
+                              _ptr(dt, torch.float64, self.n_instances, "dt"), _stream(stream)))
+
+    def predictor(self, u, dt, ustar, traces, stream=None):
+        import torch
+        n = self.info["u_elems"]
+        _check(load().adg_predictor(self._h, _ptr(u, torch.float64, n, "u"),
+                                    _ptr(dt, torch.float64, self.n_instances, "dt"),
+                                    _ptr(ustar, torch.float64, n, "ustar"),
+                                    _ptr(traces, self.real_dtype, self.info["trace_elems"], "traces"),
+                                    _stream(stream)))
+
+    def riemann(self, traces, fside, stream=None):
+        _check(load().adg_riemann(self._h, _ptr(traces, self.real_dtype, self.info["trace_elems"], "traces"),
+                                  _ptr(fside, self.real_dtype, self.info["fside_elems"], "fside"),
+                                  _stream(stream)))
+
+    def corrector(self, ustar, fside, dt, uout, stream=None):
+        import torch
+        n = self.info["u_elems"]
+        _check(load().adg_corrector(self._h, _ptr(ustar, torch.float64, n, "ustar"),
+                                    _ptr(fside, self.real_dtype, self.info["fside_elems"], "fside"),
+                                    _ptr(dt, torch.float64, self.n_instances, "dt"),
+                                    _ptr(uout, torch.float64, n, "uout"), _stream(stream)))
+
+    def step(self, u, n_steps, ws, dt_hist=None, stream_skeleton=None, stream_enclave=None):
+        """n_steps whole steps in place on u (adg_step)."""
+        import torch
+        hist = ctypes.c_void_p(0) if dt_hist is None else \
+            _ptr(dt_hist, torch.float64, n_steps * self.n_instances, "dt_hist")
+        s1 = _stream(stream_skeleton)
+        s2 = _stream(stream_enclave) if stream_enclave is not None else s1
+        if ws.numel() < self.info["workspace_bytes"]:
+            raise ValueError("workspace too small")
+        _check(load().adg_step(self._h, _ptr(u, torch.float64, self.info["u_elems"], "u"), int(n_steps), hist,
+                               ctypes.c_void_p(ws.data_ptr()), s1, s2))
+
+    def status(self):
+        """Synchronises; raises AdgError(NONPHYSICAL) if a bad state was met."""
+        _check(load().adg_get_status(self._h))

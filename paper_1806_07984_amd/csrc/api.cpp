@@ -1,0 +1,554 @@
+// C ABI of the ADER-DG library: handle management, argument checking and the
+// launch sequences of the phases and of whole steps.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+
+#include "adg_internal.h"
+#include "kernels.h"
+
+namespace adg {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+namespace {
+
+struct Instance {
+    HostMesh hm;
+    int N = 0, order = 0, npic = 0;
+    double gamma = 1.4, cfl = 0.4;
+    int64_t nc = 0, cell_off = 0, u_off = 0, tr_off = 0, fs_off = 0;
+    Geo geo{};
+    int8_t *level = nullptr;   // null on uniform meshes
+    int32_t *ijk = nullptr;
+    int32_t *face_m[3] = {nullptr, nullptr, nullptr}, *face_p[3] = {nullptr, nullptr, nullptr};
+    int64_t nf[3] = {0, 0, 0};
+    HangDev *hang = nullptr;
+    int64_t nh = 0;
+    int32_t *ccell = nullptr, *cptr = nullptr, *cchild = nullptr;
+    int8_t *cside = nullptr;
+    int64_t ncs = 0;
+    int32_t *skel = nullptr, *encl = nullptr;
+    int64_t nskel = 0, nencl = 0;
+    double *ptab = nullptr;
+    double *partial = nullptr;
+};
+
+}  // namespace
+}  // namespace adg
+
+struct adg_mesh {
+    int device = 0;
+    adg_precision prec = ADG_FP64;
+    std::vector<adg::Instance> inst;
+    std::vector<void *> allocs;
+    int *status_dev = nullptr;
+    double *dt_dev = nullptr;  // one per instance
+    hipEvent_t ev_dt = nullptr, ev_skel = nullptr, ev_encl = nullptr;
+    adg_info info{};
+};
+
+namespace adg {
+namespace {
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+template <typename P>
+bool dev_alloc(adg_mesh *m, P *&ptr, size_t count)
+{
+    ptr = nullptr;
+    if (count == 0) return true;
+    void *p = nullptr;
+    if (hipMalloc(&p, count * sizeof(P)) != hipSuccess) return false;
+    m->allocs.push_back(p);
+    ptr = static_cast<P *>(p);
+    return true;
+}
+
+template <typename P>
+bool upload(adg_mesh *m, P *&dst, const P *src, size_t count)
+{
+    if (!dev_alloc(m, dst, count)) return false;
+    if (count == 0) return true;
+    return hipMemcpy(dst, src, count * sizeof(P), hipMemcpyHostToDevice) == hipSuccess;
+}
+
+std::mutex g_basis_mutex;
+bool g_basis_uploaded[64] = {false};
+
+adg_status ensure_basis(int device)
+{
+    std::lock_guard<std::mutex> lk(g_basis_mutex);
+    if (device < 0 || device >= 64) {
+        set_error("device index out of range");
+        return ADG_ERR_UNSUPPORTED;
+    }
+    if (g_basis_uploaded[device]) return ADG_OK;
+    static DevBasis tab[NMAX + 1];
+    std::memset(tab, 0, sizeof(tab));
+    for (int N = 1; N <= NMAX; ++N) {
+        Basis b;
+        if (!make_basis(N, b)) {
+            set_error("basis construction failed");
+            return ADG_ERR_INVALID_ARG;
+        }
+        std::memcpy(tab[N].D, b.D, sizeof(b.D));
+        std::memcpy(tab[N].KW, b.KW, sizeof(b.KW));
+        std::memcpy(tab[N].Kw, b.Kw, sizeof(b.Kw));
+        for (int e = 0; e < NMAX; ++e) {
+            tab[N].w[e] = b.w[e];
+            tab[N].winv[e] = e < N ? 1.0 / b.w[e] : 0.0;
+            tab[N].L[e] = b.L[e];
+            tab[N].R[e] = b.R[e];
+            tab[N].xi[e] = b.xi[e];
+        }
+    }
+    if (upload_basis(tab) != hipSuccess) {
+        set_error("uploading basis constants failed");
+        return ADG_ERR_HIP;
+    }
+    g_basis_uploaded[device] = true;
+    return ADG_OK;
+}
+
+adg_status hip_fail(hipError_t e, const char *what)
+{
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return ADG_ERR_HIP;
+}
+
+#define ADG_HIP(call, what)                       \
+    do {                                          \
+        hipError_t e_ = (call);                   \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+void free_all(adg_mesh *m)
+{
+    for (void *p : m->allocs) (void)hipFree(p);
+    m->allocs.clear();
+    if (m->ev_dt) (void)hipEventDestroy(m->ev_dt);
+    if (m->ev_skel) (void)hipEventDestroy(m->ev_skel);
+    if (m->ev_encl) (void)hipEventDestroy(m->ev_encl);
+}
+
+bool valid_mesh(const adg_mesh *m)
+{
+    if (!m) {
+        set_error("null mesh handle");
+        return false;
+    }
+    return true;
+}
+
+template <typename T>
+adg_status do_predictor(adg_mesh *m, const double *u, const double *dt, double *ustar, T *traces,
+                        hipStream_t st_skel, hipStream_t st_encl, bool split)
+{
+    for (size_t i = 0; i < m->inst.size(); ++i) {
+        Instance &I = m->inst[i];
+        const double *ui = u + I.u_off;
+        double *usi = ustar + I.u_off;
+        T *tri = traces + I.tr_off;
+        if (split && I.nskel > 0) {
+            ADG_HIP(launch_predictor<T>(I.N, ui, usi, tri, I.skel, I.nskel, I.nc, I.level, I.geo, dt + i,
+                                        I.gamma, I.npic, st_skel), "predictor (skeleton)");
+            ADG_HIP(launch_predictor<T>(I.N, ui, usi, tri, I.encl, I.nencl, I.nc, I.level, I.geo, dt + i,
+                                        I.gamma, I.npic, st_encl), "predictor (enclave)");
+        } else {
+            ADG_HIP(launch_predictor<T>(I.N, ui, usi, tri, nullptr, I.nc, I.nc, I.level, I.geo, dt + i, I.gamma,
+                                        I.npic, st_encl), "predictor");
+        }
+    }
+    return ADG_OK;
+}
+
+template <typename T>
+adg_status do_hanging(adg_mesh *m, const T *traces, T *fside, hipStream_t st)
+{
+    for (auto &I : m->inst) {
+        if (I.nh == 0) continue;
+        ADG_HIP(launch_hang<T>(I.N, traces + I.tr_off, fside + I.fs_off, I.hang, I.nh, I.nc, I.ptab, I.gamma,
+                               m->status_dev, st), "hanging faces");
+        ADG_HIP(launch_restrict<T>(I.N, fside + I.fs_off, I.hang, I.ccell, I.cside, I.cptr, I.cchild, I.ncs, I.nc,
+                                   I.ptab, st), "restriction");
+    }
+    return ADG_OK;
+}
+
+template <typename T>
+adg_status do_conforming(adg_mesh *m, const T *traces, T *fside, hipStream_t st)
+{
+    for (auto &I : m->inst)
+        for (int d = 0; d < 3; ++d)
+            ADG_HIP(launch_riemann<T>(I.N, traces + I.tr_off, fside + I.fs_off, I.face_m[d], I.face_p[d], I.nf[d],
+                                      d, I.nc, I.gamma, m->status_dev, st), "riemann");
+    return ADG_OK;
+}
+
+template <typename T>
+adg_status do_corrector(adg_mesh *m, const double *ustar, const T *fside, const double *dt, double *uout,
+                        hipStream_t st)
+{
+    for (size_t i = 0; i < m->inst.size(); ++i) {
+        Instance &I = m->inst[i];
+        ADG_HIP(launch_corrector<T>(I.N, ustar + I.u_off, fside + I.fs_off, dt + i, uout + I.u_off, I.nc, I.level,
+                                    I.geo, st), "corrector");
+    }
+    return ADG_OK;
+}
+
+adg_status do_cfl(adg_mesh *m, const double *u, double *dt, double *hist, hipStream_t st)
+{
+    for (size_t i = 0; i < m->inst.size(); ++i) {
+        Instance &I = m->inst[i];
+        const double factor = I.cfl / (2.0 * I.order + 1.0);
+        ADG_HIP(launch_cfl(I.N, u + I.u_off, I.nc, I.level, I.geo, I.gamma, factor, I.partial, m->status_dev,
+                           dt + i, hist ? hist + i : nullptr, st), "cfl");
+    }
+    return ADG_OK;
+}
+
+template <typename T>
+adg_status step_impl(adg_mesh *m, double *u, int32_t n_steps, double *hist, void *ws, hipStream_t s_skel,
+                     hipStream_t s_encl)
+{
+    char *w = static_cast<char *>(ws);
+    double *ustar = reinterpret_cast<double *>(w);
+    w += align_up(sizeof(double) * m->info.u_elems);
+    T *traces = reinterpret_cast<T *>(w);
+    w += align_up(sizeof(T) * m->info.trace_elems);
+    T *fside = reinterpret_cast<T *>(w);
+    const bool two = s_skel != s_encl;
+    const int ni = int(m->inst.size());
+    for (int n = 0; n < n_steps; ++n) {
+        adg_status st = do_cfl(m, u, m->dt_dev, hist ? hist + int64_t(n) * ni : nullptr, s_skel);
+        if (st != ADG_OK) return st;
+        if (two) {
+            ADG_HIP(hipEventRecord(m->ev_dt, s_skel), "event record");
+            ADG_HIP(hipStreamWaitEvent(s_encl, m->ev_dt, 0), "stream wait");
+        }
+        st = do_predictor<T>(m, u, m->dt_dev, ustar, traces, s_skel, s_encl, true);
+        if (st != ADG_OK) return st;
+        st = do_hanging<T>(m, traces, fside, s_skel);
+        if (st != ADG_OK) return st;
+        if (two) {
+            ADG_HIP(hipEventRecord(m->ev_encl, s_encl), "event record");
+            ADG_HIP(hipStreamWaitEvent(s_skel, m->ev_encl, 0), "stream wait");
+        }
+        st = do_conforming<T>(m, traces, fside, s_skel);
+        if (st != ADG_OK) return st;
+        st = do_corrector<T>(m, ustar, fside, m->dt_dev, u, s_skel);
+        if (st != ADG_OK) return st;
+    }
+    if (two) {
+        // leave both streams ordered after the last corrector
+        ADG_HIP(hipEventRecord(m->ev_skel, s_skel), "event record");
+        ADG_HIP(hipStreamWaitEvent(s_encl, m->ev_skel, 0), "stream wait");
+    }
+    return ADG_OK;
+}
+
+}  // namespace
+}  // namespace adg
+
+using namespace adg;
+
+extern "C" {
+
+const char *adg_last_error(void) { return g_last_error.c_str(); }
+
+adg_status adg_init_mesh(const adg_instance_desc *desc, int32_t n_instances, adg_precision prec, adg_mesh **out)
+{
+    if (!desc || !out || n_instances < 1) {
+        set_error("adg_init_mesh: null argument or n_instances < 1");
+        return ADG_ERR_INVALID_ARG;
+    }
+    if (prec != ADG_FP64 && prec != ADG_FP32_MFMA) {
+        set_error("adg_init_mesh: unknown precision");
+        return ADG_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    adg_mesh *m = new (std::nothrow) adg_mesh();
+    if (!m) {
+        set_error("out of host memory");
+        return ADG_ERR_OOM;
+    }
+    m->prec = prec;
+    const int rb = prec == ADG_FP64 ? 8 : 4;
+    m->inst.resize(n_instances);
+    int64_t cell_off = 0, u_off = 0, tr_off = 0, fs_off = 0;
+    int64_t ncf = 0, nhang = 0, nskel = 0;
+    for (int i = 0; i < n_instances; ++i) {
+        const adg_instance_desc &d = desc[i];
+        Instance &I = m->inst[i];
+        std::string err = build_host_mesh(d, I.hm);
+        if (!err.empty()) {
+            set_error("instance " + std::to_string(i) + ": " + err);
+            delete m;
+            return err.rfind("unsupported", 0) == 0 ? ADG_ERR_UNSUPPORTED : ADG_ERR_INVALID_ARG;
+        }
+        I.N = I.hm.N;
+        I.order = d.order;
+        I.npic = d.picard_iters > 0 ? d.picard_iters : d.order + 1;
+        I.gamma = d.gamma;
+        I.cfl = d.cfl;
+        I.nc = I.hm.nc;
+        I.cell_off = cell_off;
+        I.u_off = u_off;
+        I.tr_off = tr_off;
+        I.fs_off = fs_off;
+        const int64_t N2 = int64_t(I.N) * I.N, N3 = N2 * I.N;
+        cell_off += I.nc;
+        u_off += NV * I.nc * N3;
+        tr_off += 12 * NV * I.nc * N2;
+        fs_off += 6 * NV * I.nc * N2;
+        for (int l = 0; l <= LMAX; ++l)
+            for (int a = 0; a < 3; ++a) {
+                double f = 1.0;
+                for (int k = 0; k < l; ++k) f *= 3.0;
+                I.geo.inv_dx[l][a] = (d.n[a] * f) / (d.hi[a] - d.lo[a]);
+            }
+        for (int a = 0; a < 3; ++a) ncf += int64_t(I.hm.face_m[a].size());
+        nhang += int64_t(I.hm.hang.size());
+        nskel += int64_t(I.hm.skeleton.size());
+    }
+    if (hipGetDevice(&m->device) != hipSuccess) {
+        set_error("no HIP device");
+        delete m;
+        return ADG_ERR_HIP;
+    }
+    adg_status bs = ensure_basis(m->device);
+    if (bs != ADG_OK) {
+        delete m;
+        return bs;
+    }
+    bool ok = true;
+    for (auto &I : m->inst) {
+        HostMesh &h = I.hm;
+        if (h.max_level > 0) ok = ok && upload(m, I.level, h.level.data(), h.level.size());
+        ok = ok && upload(m, I.ijk, h.ijk.data(), h.ijk.size());
+        for (int a = 0; a < 3; ++a) {
+            I.nf[a] = int64_t(h.face_m[a].size());
+            ok = ok && upload(m, I.face_m[a], h.face_m[a].data(), h.face_m[a].size());
+            ok = ok && upload(m, I.face_p[a], h.face_p[a].data(), h.face_p[a].size());
+        }
+        std::vector<HangDev> hd(h.hang.size());
+        for (size_t k = 0; k < h.hang.size(); ++k) {
+            const auto &H = h.hang[k];
+            hd[k] = HangDev{H.fine, H.coarse, H.d, H.fine_minus, H.dl, H.s1, H.s2, {0, 0, 0}};
+        }
+        I.nh = int64_t(hd.size());
+        ok = ok && upload(m, I.hang, hd.data(), hd.size());
+        I.ncs = int64_t(h.coarse_cell.size());
+        ok = ok && upload(m, I.ccell, h.coarse_cell.data(), h.coarse_cell.size());
+        ok = ok && upload(m, I.cside, h.coarse_side.data(), h.coarse_side.size());
+        ok = ok && upload(m, I.cptr, h.coarse_ptr.data(), I.ncs > 0 ? h.coarse_ptr.size() : 0);
+        ok = ok && upload(m, I.cchild, h.coarse_child.data(), h.coarse_child.size());
+        I.nskel = int64_t(h.skeleton.size());
+        I.nencl = int64_t(h.enclave.size());
+        ok = ok && upload(m, I.skel, h.skeleton.data(), h.skeleton.size());
+        ok = ok && upload(m, I.encl, h.enclave.data(), h.enclave.size());
+        // transfer table
+        Basis b;
+        make_basis(I.N, b);
+        const int N2 = I.N * I.N;
+        std::vector<double> pt(size_t(TRANSFER_BLOCKS) * 2 * N2, 0.0);
+        for (int dl = 1; dl <= LMAX; ++dl) {
+            int r = 1;
+            for (int k = 0; k < dl; ++k) r *= 3;
+            for (int s = 0; s < r; ++s) {
+                double *blk = &pt[size_t(transfer_base(dl) + s) * 2 * N2];
+                make_transfer(b, r, s, blk, blk + N2);
+            }
+        }
+        ok = ok && upload(m, I.ptab, pt.data(), pt.size());
+        ok = ok && dev_alloc(m, I.partial, CFL_MAX_BLOCKS);
+        // the host copy of the cell table is kept (adg_mesh_cells); face lists are not needed
+        for (int a = 0; a < 3; ++a) {
+            std::vector<int32_t>().swap(h.face_m[a]);
+            std::vector<int32_t>().swap(h.face_p[a]);
+        }
+    }
+    ok = ok && dev_alloc(m, m->status_dev, 1) && dev_alloc(m, m->dt_dev, size_t(n_instances));
+    if (ok) {
+        int zero = 0;
+        ok = hipMemcpy(m->status_dev, &zero, sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+    }
+    if (ok)
+        ok = hipEventCreateWithFlags(&m->ev_dt, hipEventDisableTiming) == hipSuccess &&
+             hipEventCreateWithFlags(&m->ev_skel, hipEventDisableTiming) == hipSuccess &&
+             hipEventCreateWithFlags(&m->ev_encl, hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        set_error("device allocation or upload failed");
+        free_all(m);
+        delete m;
+        return ADG_ERR_OOM;
+    }
+    adg_info &inf = m->info;
+    inf.n_instances = n_instances;
+    inf.n_cells = cell_off;
+    inf.n_dofs = u_off;
+    inf.u_elems = u_off;
+    inf.trace_elems = tr_off;
+    inf.fside_elems = fs_off;
+    inf.workspace_bytes = int64_t(align_up(sizeof(double) * u_off) + align_up(size_t(rb) * tr_off) +
+                                  align_up(size_t(rb) * fs_off));
+    inf.n_conforming_faces = ncf;
+    inf.n_hanging_faces = nhang;
+    inf.n_skeleton_cells = nskel;
+    inf.real_bytes = rb;
+    *out = m;
+    return ADG_OK;
+}
+
+void adg_free_mesh(adg_mesh *mesh)
+{
+    if (!mesh) return;
+    (void)hipDeviceSynchronize();
+    free_all(mesh);
+    delete mesh;
+}
+
+adg_status adg_mesh_info(const adg_mesh *mesh, adg_info *info)
+{
+    if (!valid_mesh(mesh) || !info) {
+        set_error("adg_mesh_info: null argument");
+        return ADG_ERR_INVALID_ARG;
+    }
+    *info = mesh->info;
+    return ADG_OK;
+}
+
+adg_status adg_instance_info(const adg_mesh *mesh, int32_t instance, adg_instance_geom *info)
+{
+    if (!valid_mesh(mesh) || !info || instance < 0 || instance >= int32_t(mesh->inst.size())) {
+        set_error("adg_instance_info: bad argument");
+        return ADG_ERR_INVALID_ARG;
+    }
+    const Instance &I = mesh->inst[instance];
+    info->order = I.order;
+    info->n_cells = I.nc;
+    info->cell_offset = I.cell_off;
+    info->u_offset = I.u_off;
+    info->trace_offset = I.tr_off;
+    info->fside_offset = I.fs_off;
+    return ADG_OK;
+}
+
+adg_status adg_mesh_cells(const adg_mesh *mesh, int32_t *cells)
+{
+    if (!valid_mesh(mesh) || !cells) {
+        set_error("adg_mesh_cells: null argument");
+        return ADG_ERR_INVALID_ARG;
+    }
+    for (const auto &I : mesh->inst)
+        for (int64_t c = 0; c < I.nc; ++c) {
+            int32_t *o = cells + 4 * (I.cell_off + c);
+            o[0] = I.hm.level[c];
+            o[1] = I.hm.ijk[3 * c];
+            o[2] = I.hm.ijk[3 * c + 1];
+            o[3] = I.hm.ijk[3 * c + 2];
+        }
+    return ADG_OK;
+}
+
+adg_status adg_node_coords(const adg_mesh *mesh, double *xyz, hipStream_t stream)
+{
+    if (!valid_mesh(mesh) || !xyz) {
+        set_error("adg_node_coords: null argument");
+        return ADG_ERR_INVALID_ARG;
+    }
+    for (const auto &I : mesh->inst)
+        ADG_HIP(launch_node_coords(I.N, xyz + 3 * (I.u_off / NV), I.ijk, I.level, I.nc, I.geo, I.hm.lo, stream),
+                "node coords");
+    return ADG_OK;
+}
+
+adg_status adg_cfl(adg_mesh *mesh, const double *u, double *dt, hipStream_t stream)
+{
+    if (!valid_mesh(mesh) || !u || !dt) {
+        set_error("adg_cfl: null argument");
+        return ADG_ERR_INVALID_ARG;
+    }
+    return do_cfl(mesh, u, dt, nullptr, stream);
+}
+
+adg_status adg_predictor(adg_mesh *mesh, const double *u, const double *dt, double *ustar, void *traces,
+                         hipStream_t stream)
+{
+    if (!valid_mesh(mesh) || !u || !dt || !ustar || !traces) {
+        set_error("adg_predictor: null argument");
+        return ADG_ERR_INVALID_ARG;
+    }
+    if (mesh->prec == ADG_FP64)
+        return do_predictor<double>(mesh, u, dt, ustar, static_cast<double *>(traces), stream, stream, false);
+    return do_predictor<float>(mesh, u, dt, ustar, static_cast<float *>(traces), stream, stream, false);
+}
+
+adg_status adg_riemann(adg_mesh *mesh, const void *traces, void *fside, hipStream_t stream)
+{
+    if (!valid_mesh(mesh) || !traces || !fside) {
+        set_error("adg_riemann: null argument");
+        return ADG_ERR_INVALID_ARG;
+    }
+    adg_status st;
+    if (mesh->prec == ADG_FP64) {
+        st = do_conforming<double>(mesh, static_cast<const double *>(traces), static_cast<double *>(fside), stream);
+        if (st == ADG_OK)
+            st = do_hanging<double>(mesh, static_cast<const double *>(traces), static_cast<double *>(fside), stream);
+    } else {
+        st = do_conforming<float>(mesh, static_cast<const float *>(traces), static_cast<float *>(fside), stream);
+        if (st == ADG_OK)
+            st = do_hanging<float>(mesh, static_cast<const float *>(traces), static_cast<float *>(fside), stream);
+    }
+    return st;
+}
+
+adg_status adg_corrector(adg_mesh *mesh, const double *ustar, const void *fside, const double *dt, double *uout,
+                         hipStream_t stream)
+{
+    if (!valid_mesh(mesh) || !ustar || !fside || !dt || !uout) {
+        set_error("adg_corrector: null argument");
+        return ADG_ERR_INVALID_ARG;
+    }
+    if (mesh->prec == ADG_FP64)
+        return do_corrector<double>(mesh, ustar, static_cast<const double *>(fside), dt, uout, stream);
+    return do_corrector<float>(mesh, ustar, static_cast<const float *>(fside), dt, uout, stream);
+}
+
+adg_status adg_step(adg_mesh *mesh, double *u, int32_t n_steps, double *dt_hist, void *ws, hipStream_t s_skel,
+                    hipStream_t s_encl)
+{
+    if (!valid_mesh(mesh) || !u || !ws || n_steps < 0) {
+        set_error("adg_step: null argument or negative step count");
+        return ADG_ERR_INVALID_ARG;
+    }
+    if (reinterpret_cast<uintptr_t>(ws) % ALIGN != 0) {
+        set_error("adg_step: workspace must be 256-byte aligned");
+        return ADG_ERR_WORKSPACE;
+    }
+    if (mesh->prec == ADG_FP64) return step_impl<double>(mesh, u, n_steps, dt_hist, ws, s_skel, s_encl);
+    return step_impl<float>(mesh, u, n_steps, dt_hist, ws, s_skel, s_encl);
+}
+
+adg_status adg_get_status(adg_mesh *mesh)
+{
+    if (!valid_mesh(mesh)) return ADG_ERR_INVALID_ARG;
+    ADG_HIP(hipDeviceSynchronize(), "synchronize");
+    int flag = 0;
+    ADG_HIP(hipMemcpy(&flag, mesh->status_dev, sizeof(int), hipMemcpyDeviceToHost), "status read");
+    if (flag) {
+        int zero = 0;
+        ADG_HIP(hipMemcpy(mesh->status_dev, &zero, sizeof(int), hipMemcpyHostToDevice), "status reset");
+        set_error("non-physical state (rho <= 0, p <= 0 or non-finite) met on the device");
+        return ADG_ERR_NONPHYSICAL;
+    }
+    return ADG_OK;
+}
+
+}  // extern "C"

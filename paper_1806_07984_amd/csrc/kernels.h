@@ -1,0 +1,53 @@
+// Launch wrappers of the HIP kernels (kernels.hip).  Every wrapper enqueues on
+// the given stream and returns the launch status; none synchronises.
+#pragma once
+
+#include "adg_internal.h"
+
+namespace adg {
+
+constexpr int CFL_MAX_BLOCKS = 2048;
+
+// Hanging child face as the kernels read it.
+struct HangDev {
+    int32_t fine, coarse;
+    int8_t d, fine_minus, dl, s1, s2, pad[3];
+};
+
+// first transfer block of level jump dl (blocks of 2 N^2 doubles: P then Rm,
+// one per sub-position s < 3^dl)
+__host__ __device__ constexpr int transfer_base(int dl)
+{
+    return dl == 1 ? 0 : (dl == 2 ? 3 : 12);
+}
+constexpr int TRANSFER_BLOCKS = 3 + 9 + 27;
+
+hipError_t upload_basis(const DevBasis *tab);
+
+template <typename T>
+hipError_t launch_predictor(int N, const double *u, double *ustar, T *traces, const int32_t *list,
+                            int64_t nlist, int64_t nc, const int8_t *level, const Geo &geo,
+                            const double *dt, double gamma, int npic, hipStream_t st);
+template <typename T>
+hipError_t launch_riemann(int N, const T *traces, T *fside, const int32_t *fm, const int32_t *fp,
+                          int64_t nf, int d, int64_t nc, double gamma, int *status, hipStream_t st);
+template <typename T>
+hipError_t launch_hang(int N, const T *traces, T *fside, const HangDev *hang, int64_t nh, int64_t nc,
+                       const double *ptab, double gamma, int *status, hipStream_t st);
+template <typename T>
+hipError_t launch_restrict(int N, T *fside, const HangDev *hang, const int32_t *ccell, const int8_t *cside,
+                           const int32_t *cptr, const int32_t *cchild, int64_t ncs, int64_t nc,
+                           const double *ptab, hipStream_t st);
+template <typename T>
+hipError_t launch_corrector(int N, const double *ustar, const T *fside, const double *dt, double *uout,
+                            int64_t nc, const int8_t *level, const Geo &geo, hipStream_t st);
+
+int cfl_blocks(int N, int64_t nc);
+// factor = cfl / (2p + 1); writes dt_out[0] (and hist[0] if not null)
+hipError_t launch_cfl(int N, const double *u, int64_t nc, const int8_t *level, const Geo &geo, double gamma,
+                      double factor, double *partial, int *status, double *dt_out, double *hist,
+                      hipStream_t st);
+hipError_t launch_node_coords(int N, double *xyz, const int32_t *ijk, const int8_t *level, int64_t nc,
+                              const Geo &geo, const double *lo, hipStream_t st);
+
+}  // namespace adg

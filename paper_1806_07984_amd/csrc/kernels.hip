@@ -1,0 +1,696 @@
+// HIP kernels of the ADER-DG step for gfx950 (MI355X).
+//
+// Data layouts are the ones documented in include/adg.h (structure of arrays:
+// variable-major, then cell, then node), so that consecutive lanes touch
+// consecutive doubles in every global load and store.
+//
+// Kernels (template parameters: real type T, N = p + 1):
+//   k_predictor   C_STP by Picard iterations + time averages + volume term +
+//                 face projections (paper Eq. 3-4, Sec. 2.1-2.2).  One lane per
+//                 spatial node holds the whole time history of its node in
+//                 registers; flux values are exchanged through LDS once per
+//                 time node for the three derivative contractions.
+//   k_riemann     Rusanov solve on conforming faces (Alg. 1, Sec. 2.4).
+//   k_hang        virtual-cell face data (interpolation of the coarse cell's
+//                 face projection) + Rusanov on hanging child faces (Sec. 2.3).
+//   k_restrict    restriction of child face results into the coarse side, in
+//                 a fixed order (no atomics).
+//   k_corrector   C_Corr (Eq. 4), FP64 accumulation.
+//   k_cfl_*       global time step size: block maxima then one final block.
+#include <cmath>
+
+#include "adg_internal.h"
+#include "kernels.h"
+
+namespace adg {
+
+__constant__ DevBasis c_basis[NMAX + 1];
+
+namespace {
+
+template <typename T>
+__device__ __forceinline__ T rcp(T x) { return T(1) / x; }
+
+// Euler fluxes along the three axes of the state q.
+template <typename T>
+__device__ __forceinline__ void euler_flux3(T gm1, const T q[NV], T f[3][NV])
+{
+    const T inv = rcp(q[0]);
+    const T ke = T(0.5) * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) * inv;
+    const T p = gm1 * (q[4] - ke);
+    const T Ep = q[4] + p;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const T vd = q[1 + d] * inv;
+        f[d][0] = q[1 + d];
+        f[d][1] = vd * q[1];
+        f[d][2] = vd * q[2];
+        f[d][3] = vd * q[3];
+        f[d][1 + d] += p;
+        f[d][4] = vd * Ep;
+    }
+}
+
+// |u_d| + c and a physical-state check.
+template <typename T>
+__device__ __forceinline__ T wave_speed(T gamma, T gm1, const T q[NV], int d, bool &bad)
+{
+    const T inv = rcp(q[0]);
+    const T p = gm1 * (q[4] - T(0.5) * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) * inv);
+    bool ok = q[0] > T(0) && p > T(0);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ok = ok && isfinite(q[v]);
+    bad = !ok;
+    return fabs(q[1 + d] * inv) + sqrt(gamma * p * inv);
+}
+
+// volume node index from (index e along axis d, face index b)
+template <int N>
+__device__ __forceinline__ int node_from_face(int d, int e, int b)
+{
+    const int b1 = b % N, b2 = b / N;
+    if (d == 0) return e + N * b1 + N * N * b2;
+    if (d == 1) return b1 + N * e + N * N * b2;
+    return b1 + N * b2 + N * N * e;
+}
+
+constexpr int round64(int x) { return (x + 63) / 64 * 64; }
+
+}  // namespace
+
+// cells per block for the predictor, chosen so one block is close to a
+// multiple of 64 lanes
+template <int N> struct PredCfg;
+template <> struct PredCfg<1> { static constexpr int CPB = 64; };
+template <> struct PredCfg<2> { static constexpr int CPB = 32; };
+template <> struct PredCfg<3> { static constexpr int CPB = 9; };
+template <> struct PredCfg<4> { static constexpr int CPB = 4; };
+template <> struct PredCfg<5> { static constexpr int CPB = 2; };
+template <> struct PredCfg<6> { static constexpr int CPB = 1; };
+template <> struct PredCfg<7> { static constexpr int CPB = 1; };
+
+template <typename T, int N>
+__global__ void __launch_bounds__(round64(PredCfg<N>::CPB * N * N * N))
+k_predictor(const double *__restrict__ u, double *__restrict__ ustar, T *__restrict__ traces,
+            const int32_t *__restrict__ list, int64_t nlist, int64_t nc,
+            const int8_t *__restrict__ level, Geo geo, const double *__restrict__ dt_dev,
+            double gamma, int npic)
+{
+    constexpr int CPB = PredCfg<N>::CPB;
+    constexpr int N2 = N * N, N3 = N2 * N, NT = CPB * N3;
+    __shared__ T lds[CPB * 15 * N3];
+    const DevBasis &B = c_basis[N];
+
+    const int tid = threadIdx.x;
+    const int cl = tid / N3, a = tid % N3;
+    const int64_t idx = int64_t(blockIdx.x) * CPB + cl;
+    const bool lane_ok = tid < NT;
+    const bool active = lane_ok && idx < nlist;
+    const int64_t c = active ? (list ? int64_t(list[idx]) : idx) : 0;
+    const int a0 = a % N, a1 = (a / N) % N, a2 = a / N2;
+
+    const double dt = dt_dev[0];
+    const int lev = level ? level[c] : 0;
+    const T cx = T(dt * geo.inv_dx[lev][0]);
+    const T cy = T(dt * geo.inv_dx[lev][1]);
+    const T cz = T(dt * geo.inv_dx[lev][2]);
+    const T gm1 = T(gamma - 1.0);
+
+    double ud[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ud[v] = active ? u[(int64_t(v) * nc + c) * N3 + a] : (v == 0 ? 1.0 : (v == 4 ? 2.5 : 0.0));
+    T uu[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) uu[v] = T(ud[v]);
+
+    // derivative rows of this lane's node along each axis
+    T Dx[N], Dy[N], Dz[N];
+#pragma unroll
+    for (int e = 0; e < N; ++e) {
+        Dx[e] = T(B.D[a0 * N + e]);
+        Dy[e] = T(B.D[a1 * N + e]);
+        Dz[e] = T(B.D[a2 * N + e]);
+    }
+
+    T q[N][NV];
+#pragma unroll
+    for (int l = 0; l < N; ++l)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) q[l][v] = uu[v];
+
+    T *my = lds + (lane_ok ? cl : 0) * 15 * N3;
+    const int bx = N * a1 + N2 * a2, by = a0 + N2 * a2, bz = a0 + N * a1;
+
+    for (int it = 0; it < npic; ++it) {
+        T acc[N][NV];
+#pragma unroll
+        for (int l = 0; l < N; ++l)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[l][v] = T(0);
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            T f[3][NV];
+            euler_flux3(gm1, q[j], f);
+            __syncthreads();
+            if (lane_ok) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) my[(d * NV + v) * N3 + a] = f[d][v];
+            }
+            __syncthreads();
+            if (lane_ok) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    T gx = T(0), gy = T(0), gz = T(0);
+#pragma unroll
+                    for (int e = 0; e < N; ++e) {
+                        gx += Dx[e] * my[(0 * NV + v) * N3 + e + bx];
+                        gy += Dy[e] * my[(1 * NV + v) * N3 + N * e + by];
+                        gz += Dz[e] * my[(2 * NV + v) * N3 + N2 * e + bz];
+                    }
+                    const T G = cx * gx + cy * gy + cz * gz;
+#pragma unroll
+                    for (int l = 0; l < N; ++l) acc[l][v] += T(B.KW[l * N + j]) * G;
+                }
+            }
+        }
+#pragma unroll
+        for (int l = 0; l < N; ++l)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) q[l][v] = uu[v] - acc[l][v];
+    }
+
+    // time averages of the state and of the fluxes of the final iterate
+    T qb[NV], Fb[3][NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        qb[v] = T(0);
+        Fb[0][v] = Fb[1][v] = Fb[2][v] = T(0);
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        T f[3][NV];
+        euler_flux3(gm1, q[j], f);
+        const T wj = T(B.w[j]);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            qb[v] += wj * q[j][v];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) Fb[d][v] += wj * f[d][v];
+        }
+    }
+    __syncthreads();
+    if (lane_ok) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) my[(d * NV + v) * N3 + a] = Fb[d][v];
+    }
+    __syncthreads();
+
+    // volume term of the corrector: u* = u + sum_d (dt/dx_d)/w_{a_d} sum_e Kw[a_d][e] Fbar_d
+    if (active) {
+        const T sx = cx * T(B.winv[a0]), sy = cy * T(B.winv[a1]), sz = cz * T(B.winv[a2]);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            T vx = T(0), vy = T(0), vz = T(0);
+#pragma unroll
+            for (int e = 0; e < N; ++e) {
+                vx += T(B.Kw[a0 * N + e]) * my[(0 * NV + v) * N3 + e + bx];
+                vy += T(B.Kw[a1 * N + e]) * my[(1 * NV + v) * N3 + N * e + by];
+                vz += T(B.Kw[a2 * N + e]) * my[(2 * NV + v) * N3 + N2 * e + bz];
+            }
+            const T V = sx * vx + sy * vy + sz * vz;
+            ustar[(int64_t(v) * nc + c) * N3 + a] = ud[v] + double(V);
+        }
+    }
+
+    // face projections: normal flux component (arr 1), then the state (arr 0)
+    const int64_t base = int64_t(blockIdx.x) * CPB;
+    constexpr int ITEMS = 6 * NV * CPB * N2;
+    for (int arr = 1; arr >= 0; --arr) {
+        if (arr == 0) {
+            __syncthreads();
+            if (lane_ok) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) my[v * N3 + a] = qb[v];
+            }
+            __syncthreads();
+        }
+        for (int t = tid; t < ITEMS; t += blockDim.x) {
+            const int inner = t % (CPB * N2), sv = t / (CPB * N2);
+            const int s = sv / NV, v = sv % NV, cl2 = inner / N2, b = inner % N2;
+            const int64_t idx2 = base + cl2;
+            if (idx2 >= nlist) continue;
+            const int64_t c2 = list ? int64_t(list[idx2]) : idx2;
+            const int d = s >> 1;
+            const double *E = (s & 1) ? B.R : B.L;
+            const T *src = lds + cl2 * 15 * N3 + (arr == 1 ? (d * NV + v) : v) * N3;
+            T accv = T(0);
+#pragma unroll
+            for (int e = 0; e < N; ++e) accv += T(E[e]) * src[node_from_face<N>(d, e, b)];
+            traces[((int64_t(s * 2 + arr) * NV + v) * nc + c2) * N2 + b] = accv;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Riemann solves on conforming faces of one axis
+// ---------------------------------------------------------------------------
+
+template <int N> struct FaceCfg {
+    static constexpr int FPB = (256 / (N * N)) > 0 ? 256 / (N * N) : 1;
+    static constexpr int THREADS = round64(FPB * N * N);
+};
+
+template <typename T, int N>
+__global__ void __launch_bounds__(FaceCfg<N>::THREADS)
+k_riemann(const T *__restrict__ traces, T *__restrict__ fside, const int32_t *__restrict__ fm,
+          const int32_t *__restrict__ fp, int64_t nf, int d, int64_t nc, double gamma,
+          int *__restrict__ status)
+{
+    constexpr int N2 = N * N, FPB = FaceCfg<N>::FPB;
+    __shared__ T smax[FPB * N2];
+    const int tid = threadIdx.x;
+    const int fl = tid / N2, b = tid % N2;
+    const int64_t f = int64_t(blockIdx.x) * FPB + fl;
+    const bool lane_ok = tid < FPB * N2;
+    const bool active = lane_ok && f < nf;
+    const T g = T(gamma), gm1 = T(gamma - 1.0);
+    const int sL = 2 * d + 1, sR = 2 * d;
+    T QL[NV], FL[NV], QR[NV], FR[NV];
+    int64_t cL = 0, cR = 0;
+    T lam = T(0);
+    if (active) {
+        cL = fm[f];
+        cR = fp[f];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            QL[v] = traces[((int64_t(sL * 2 + 0) * NV + v) * nc + cL) * N2 + b];
+            FL[v] = traces[((int64_t(sL * 2 + 1) * NV + v) * nc + cL) * N2 + b];
+            QR[v] = traces[((int64_t(sR * 2 + 0) * NV + v) * nc + cR) * N2 + b];
+            FR[v] = traces[((int64_t(sR * 2 + 1) * NV + v) * nc + cR) * N2 + b];
+        }
+        bool badL, badR;
+        const T lL = wave_speed(g, gm1, QL, d, badL);
+        const T lR = wave_speed(g, gm1, QR, d, badR);
+        lam = fmax(lL, lR);
+        if (badL || badR) *status = 1;
+    }
+    if (lane_ok) smax[tid] = lam;
+    __syncthreads();
+    if (!active) return;
+    T s = T(0);
+    for (int k = 0; k < N2; ++k) s = fmax(s, smax[fl * N2 + k]);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const T F = T(0.5) * (FL[v] + FR[v]) - T(0.5) * s * (QR[v] - QL[v]);
+        fside[(int64_t(sL * NV + v) * nc + cL) * N2 + b] = F;
+        fside[(int64_t(sR * NV + v) * nc + cR) * N2 + b] = F;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Hanging faces: virtual-cell data by interpolation, Rusanov on the child face
+// ---------------------------------------------------------------------------
+
+template <typename T, int N>
+__global__ void __launch_bounds__(FaceCfg<N>::THREADS)
+k_hang(const T *__restrict__ traces, T *__restrict__ fside, const HangDev *__restrict__ hang,
+       int64_t nh, int64_t nc, const double *__restrict__ ptab, double gamma,
+       int *__restrict__ status)
+{
+    constexpr int N2 = N * N, FPB = FaceCfg<N>::FPB;
+    __shared__ T smax[FPB * N2];
+    const int tid = threadIdx.x;
+    const int fl = tid / N2, b = tid % N2;
+    const int64_t h = int64_t(blockIdx.x) * FPB + fl;
+    const bool lane_ok = tid < FPB * N2;
+    const bool active = lane_ok && h < nh;
+    const T g = T(gamma), gm1 = T(gamma - 1.0);
+    T Qf[NV], Ff[NV], Qv[NV], Fv[NV];
+    T lam = T(0);
+    int64_t fine = 0;
+    int sf = 0, d = 0, fine_minus = 0;
+    if (active) {
+        const HangDev H = hang[h];
+        fine = H.fine;
+        d = H.d;
+        fine_minus = H.fine_minus;
+        sf = 2 * d + (fine_minus ? 1 : 0);
+        const int sc = 2 * d + (fine_minus ? 0 : 1);
+        const double *P1 = ptab + (transfer_base(H.dl) + H.s1) * 2 * N2;  // P block
+        const double *P2 = ptab + (transfer_base(H.dl) + H.s2) * 2 * N2;
+        const int k1 = b % N, k2 = b / N;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            Qf[v] = traces[((int64_t(sf * 2 + 0) * NV + v) * nc + fine) * N2 + b];
+            Ff[v] = traces[((int64_t(sf * 2 + 1) * NV + v) * nc + fine) * N2 + b];
+            const T *cq = traces + ((int64_t(sc * 2 + 0) * NV + v) * nc + H.coarse) * N2;
+            const T *cf = traces + ((int64_t(sc * 2 + 1) * NV + v) * nc + H.coarse) * N2;
+            T sq = T(0), sfl = T(0);
+#pragma unroll
+            for (int e2 = 0; e2 < N; ++e2) {
+                T rq = T(0), rf = T(0);
+#pragma unroll
+                for (int e1 = 0; e1 < N; ++e1) {
+                    const T p1 = T(P1[k1 * N + e1]);
+                    rq += p1 * cq[e1 + N * e2];
+                    rf += p1 * cf[e1 + N * e2];
+                }
+                const T p2 = T(P2[k2 * N + e2]);
+                sq += p2 * rq;
+                sfl += p2 * rf;
+            }
+            Qv[v] = sq;
+            Fv[v] = sfl;
+        }
+        bool b1, b2;
+        lam = fmax(wave_speed(g, gm1, Qf, d, b1), wave_speed(g, gm1, Qv, d, b2));
+        if (b1 || b2) *status = 1;
+    }
+    if (lane_ok) smax[tid] = lam;
+    __syncthreads();
+    if (!active) return;
+    T s = T(0);
+    for (int k = 0; k < N2; ++k) s = fmax(s, smax[fl * N2 + k]);
+    const T *QL = fine_minus ? Qf : Qv, *FL = fine_minus ? Ff : Fv;
+    const T *QR = fine_minus ? Qv : Qf, *FR = fine_minus ? Fv : Ff;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const T F = T(0.5) * (FL[v] + FR[v]) - T(0.5) * s * (QR[v] - QL[v]);
+        fside[(int64_t(sf * NV + v) * nc + fine) * N2 + b] = F;
+    }
+}
+
+// Restriction into coarse sides: F_C[k] = sum_children (R1 x R2) F_child,
+// children in increasing fine-cell order, FP64 accumulation.
+template <typename T, int N>
+__global__ void __launch_bounds__(256)
+k_restrict(T *__restrict__ fside, const HangDev *__restrict__ hang, const int32_t *__restrict__ ccell,
+           const int8_t *__restrict__ cside, const int32_t *__restrict__ cptr,
+           const int32_t *__restrict__ cchild, int64_t ncs, int64_t nc, const double *__restrict__ ptab)
+{
+    constexpr int N2 = N * N;
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= ncs * N2) return;
+    const int64_t i = t / N2;
+    const int k = int(t % N2), k1 = k % N, k2 = k / N;
+    const int64_t C = ccell[i];
+    const int s = cside[i];
+    double acc[NV] = {0, 0, 0, 0, 0};
+    for (int q = cptr[i]; q < cptr[i + 1]; ++q) {
+        const HangDev H = hang[cchild[q]];
+        const int sf = 2 * H.d + (H.fine_minus ? 1 : 0);
+        const double *R1 = ptab + (transfer_base(H.dl) + H.s1) * 2 * N2 + N2;  // R block
+        const double *R2 = ptab + (transfer_base(H.dl) + H.s2) * 2 * N2 + N2;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const T *src = fside + (int64_t(sf * NV + v) * nc + H.fine) * N2;
+            double sum = 0.0;
+#pragma unroll
+            for (int e2 = 0; e2 < N; ++e2) {
+                double r = 0.0;
+#pragma unroll
+                for (int e1 = 0; e1 < N; ++e1) r += R1[k1 * N + e1] * double(src[e1 + N * e2]);
+                sum += R2[k2 * N + e2] * r;
+            }
+            acc[v] += sum;
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) fside[(int64_t(s * NV + v) * nc + C) * N2 + k] = T(acc[v]);
+}
+
+// ---------------------------------------------------------------------------
+// Corrector
+// ---------------------------------------------------------------------------
+
+template <typename T, int N>
+__global__ void __launch_bounds__(256)
+k_corrector(const double *__restrict__ ustar, const T *__restrict__ fside, const double *__restrict__ dt_dev,
+            double *__restrict__ uout, int64_t nc, const int8_t *__restrict__ level, Geo geo)
+{
+    constexpr int N2 = N * N, N3 = N2 * N;
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= nc * N3) return;
+    const int64_t c = t / N3;
+    const int a = int(t % N3), a0 = a % N, a1 = (a / N) % N, a2 = a / N2;
+    const DevBasis &B = c_basis[N];
+    const double dt = dt_dev[0];
+    const int lev = level ? level[c] : 0;
+    const double sx = dt * geo.inv_dx[lev][0] * B.winv[a0];
+    const double sy = dt * geo.inv_dx[lev][1] * B.winv[a1];
+    const double sz = dt * geo.inv_dx[lev][2] * B.winv[a2];
+    const int bx = a1 + N * a2, by = a0 + N * a2, bz = a0 + N * a1;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const double fxm = fside[(int64_t(0 * NV + v) * nc + c) * N2 + bx];
+        const double fxp = fside[(int64_t(1 * NV + v) * nc + c) * N2 + bx];
+        const double fym = fside[(int64_t(2 * NV + v) * nc + c) * N2 + by];
+        const double fyp = fside[(int64_t(3 * NV + v) * nc + c) * N2 + by];
+        const double fzm = fside[(int64_t(4 * NV + v) * nc + c) * N2 + bz];
+        const double fzp = fside[(int64_t(5 * NV + v) * nc + c) * N2 + bz];
+        const double s = sx * (B.R[a0] * fxp - B.L[a0] * fxm) + sy * (B.R[a1] * fyp - B.L[a1] * fym) +
+                         sz * (B.R[a2] * fzp - B.L[a2] * fzm);
+        const int64_t o = (int64_t(v) * nc + c) * N3 + a;
+        uout[o] = ustar[o] - s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Time step size
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double block_max(double x, double *sh)
+{
+    for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off));
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) sh[wv] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = sh[0];
+        for (int i = 1; i < int(blockDim.x >> 6); ++i) m = fmax(m, sh[i]);
+        sh[0] = m;
+    }
+    __syncthreads();
+    return sh[0];
+}
+
+template <int N>
+__global__ void __launch_bounds__(256)
+k_cfl_partial(const double *__restrict__ u, int64_t nc, const int8_t *__restrict__ level, Geo geo,
+              double gamma, double *__restrict__ partial, int *__restrict__ status)
+{
+    constexpr int N3 = N * N * N;
+    __shared__ double sh[4];
+    const double gm1 = gamma - 1.0;
+    double m = 0.0;
+    const int64_t total = nc * N3;
+    for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
+         t += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t c = t / N3;
+        const int a = int(t % N3);
+        double q[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) q[v] = u[(int64_t(v) * nc + c) * N3 + a];
+        const int lev = level ? level[c] : 0;
+        bool bad = false, b2;
+        double s = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            s += wave_speed(gamma, gm1, q, d, b2) * geo.inv_dx[lev][d];
+            bad = bad || b2;
+        }
+        if (bad) {
+            *status = 1;
+            s = INFINITY;
+        }
+        m = fmax(m, s);
+    }
+    m = block_max(m, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = m;
+}
+
+__global__ void __launch_bounds__(256)
+k_cfl_final(const double *__restrict__ partial, int nparts, double factor, double *__restrict__ dt_out,
+            double *__restrict__ hist)
+{
+    __shared__ double sh[4];
+    double m = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) m = fmax(m, partial[i]);
+    m = block_max(m, sh);
+    if (threadIdx.x == 0) {
+        const double dt = (m > 0.0 && m < INFINITY) ? factor / m : 0.0;
+        dt_out[0] = dt;
+        if (hist) hist[0] = dt;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Node coordinates
+// ---------------------------------------------------------------------------
+
+template <int N>
+__global__ void __launch_bounds__(256)
+k_node_coords(double *__restrict__ xyz, const int32_t *__restrict__ ijk, const int8_t *__restrict__ level,
+              int64_t nc, Geo geo, double lo0, double lo1, double lo2)
+{
+    constexpr int N3 = N * N * N;
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= nc * N3) return;
+    const int64_t c = t / N3;
+    const int a = int(t % N3);
+    const int aa[3] = {a % N, (a / N) % N, a / (N * N)};
+    const double lo[3] = {lo0, lo1, lo2};
+    const int lev = level ? level[c] : 0;
+    const DevBasis &B = c_basis[N];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        xyz[(int64_t(d) * nc + c) * N3 + a] = lo[d] + (double(ijk[3 * c + d]) + B.xi[aa[d]]) / geo.inv_dx[lev][d];
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+#define ADG_DISPATCH_N(N_, ...)                      \
+    switch (N_) {                                    \
+    case 1: { constexpr int NN = 1; __VA_ARGS__; } break; \
+    case 2: { constexpr int NN = 2; __VA_ARGS__; } break; \
+    case 3: { constexpr int NN = 3; __VA_ARGS__; } break; \
+    case 4: { constexpr int NN = 4; __VA_ARGS__; } break; \
+    case 5: { constexpr int NN = 5; __VA_ARGS__; } break; \
+    case 6: { constexpr int NN = 6; __VA_ARGS__; } break; \
+    case 7: { constexpr int NN = 7; __VA_ARGS__; } break; \
+    default: return hipErrorInvalidValue;            \
+    }
+
+hipError_t upload_basis(const DevBasis *tab)
+{
+    return hipMemcpyToSymbol(HIP_SYMBOL(c_basis), tab, sizeof(DevBasis) * (NMAX + 1));
+}
+
+template <typename T>
+hipError_t launch_predictor(int N, const double *u, double *ustar, T *traces, const int32_t *list,
+                            int64_t nlist, int64_t nc, const int8_t *level, const Geo &geo,
+                            const double *dt, double gamma, int npic, hipStream_t st)
+{
+    if (nlist <= 0) return hipSuccess;
+    ADG_DISPATCH_N(N, {
+        constexpr int CPB = PredCfg<NN>::CPB;
+        const int64_t blocks = (nlist + CPB - 1) / CPB;
+        hipLaunchKernelGGL((k_predictor<T, NN>), dim3(unsigned(blocks)), dim3(round64(CPB * NN * NN * NN)), 0, st,
+                           u, ustar, traces, list, nlist, nc, level, geo, dt, gamma, npic);
+    });
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_riemann(int N, const T *traces, T *fside, const int32_t *fm, const int32_t *fp,
+                          int64_t nf, int d, int64_t nc, double gamma, int *status, hipStream_t st)
+{
+    if (nf <= 0) return hipSuccess;
+    ADG_DISPATCH_N(N, {
+        constexpr int FPB = FaceCfg<NN>::FPB;
+        const int64_t blocks = (nf + FPB - 1) / FPB;
+        hipLaunchKernelGGL((k_riemann<T, NN>), dim3(unsigned(blocks)), dim3(FaceCfg<NN>::THREADS), 0, st,
+                           traces, fside, fm, fp, nf, d, nc, gamma, status);
+    });
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_hang(int N, const T *traces, T *fside, const HangDev *hang, int64_t nh, int64_t nc,
+                       const double *ptab, double gamma, int *status, hipStream_t st)
+{
+    if (nh <= 0) return hipSuccess;
+    ADG_DISPATCH_N(N, {
+        constexpr int FPB = FaceCfg<NN>::FPB;
+        const int64_t blocks = (nh + FPB - 1) / FPB;
+        hipLaunchKernelGGL((k_hang<T, NN>), dim3(unsigned(blocks)), dim3(FaceCfg<NN>::THREADS), 0, st,
+                           traces, fside, hang, nh, nc, ptab, gamma, status);
+    });
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_restrict(int N, T *fside, const HangDev *hang, const int32_t *ccell, const int8_t *cside,
+                           const int32_t *cptr, const int32_t *cchild, int64_t ncs, int64_t nc,
+                           const double *ptab, hipStream_t st)
+{
+    if (ncs <= 0) return hipSuccess;
+    ADG_DISPATCH_N(N, {
+        const int64_t blocks = (ncs * NN * NN + 255) / 256;
+        hipLaunchKernelGGL((k_restrict<T, NN>), dim3(unsigned(blocks)), dim3(256), 0, st,
+                           fside, hang, ccell, cside, cptr, cchild, ncs, nc, ptab);
+    });
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_corrector(int N, const double *ustar, const T *fside, const double *dt, double *uout,
+                            int64_t nc, const int8_t *level, const Geo &geo, hipStream_t st)
+{
+    if (nc <= 0) return hipSuccess;
+    ADG_DISPATCH_N(N, {
+        const int64_t blocks = (nc * NN * NN * NN + 255) / 256;
+        hipLaunchKernelGGL((k_corrector<T, NN>), dim3(unsigned(blocks)), dim3(256), 0, st,
+                           ustar, fside, dt, uout, nc, level, geo);
+    });
+    return hipGetLastError();
+}
+
+int cfl_blocks(int N, int64_t nc)
+{
+    const int64_t total = nc * int64_t(N) * N * N;
+    int64_t b = (total + 255) / 256;
+    if (b > CFL_MAX_BLOCKS) b = CFL_MAX_BLOCKS;
+    if (b < 1) b = 1;
+    return int(b);
+}
+
+hipError_t launch_cfl(int N, const double *u, int64_t nc, const int8_t *level, const Geo &geo, double gamma,
+                      double factor, double *partial, int *status, double *dt_out, double *hist,
+                      hipStream_t st)
+{
+    const int nb = cfl_blocks(N, nc);
+    ADG_DISPATCH_N(N, {
+        hipLaunchKernelGGL((k_cfl_partial<NN>), dim3(nb), dim3(256), 0, st, u, nc, level, geo, gamma, partial,
+                           status);
+    });
+    hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(256), 0, st, partial, nb, factor, dt_out, hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_node_coords(int N, double *xyz, const int32_t *ijk, const int8_t *level, int64_t nc,
+                              const Geo &geo, const double *lo, hipStream_t st)
+{
+    if (nc <= 0) return hipSuccess;
+    ADG_DISPATCH_N(N, {
+        const int64_t blocks = (nc * NN * NN * NN + 255) / 256;
+        hipLaunchKernelGGL((k_node_coords<NN>), dim3(unsigned(blocks)), dim3(256), 0, st, xyz, ijk, level, nc,
+                           geo, lo[0], lo[1], lo[2]);
+    });
+    return hipGetLastError();
+}
+
+#define ADG_INSTANTIATE(T)                                                                              \
+    template hipError_t launch_predictor<T>(int, const double *, double *, T *, const int32_t *, int64_t,  \
+                                            int64_t, const int8_t *, const Geo &, const double *, double, \
+                                            int, hipStream_t);                                           \
+    template hipError_t launch_riemann<T>(int, const T *, T *, const int32_t *, const int32_t *, int64_t, \
+                                          int, int64_t, double, int *, hipStream_t);                     \
+    template hipError_t launch_hang<T>(int, const T *, T *, const HangDev *, int64_t, int64_t,           \
+                                       const double *, double, int *, hipStream_t);                      \
+    template hipError_t launch_restrict<T>(int, T *, const HangDev *, const int32_t *, const int8_t *,   \
+                                           const int32_t *, const int32_t *, int64_t, int64_t,           \
+                                           const double *, hipStream_t);                                 \
+    template hipError_t launch_corrector<T>(int, const double *, const T *, const double *, double *,    \
+                                            int64_t, const int8_t *, const Geo &, hipStream_t);
+
+ADG_INSTANTIATE(double)
+ADG_INSTANTIATE(float)
+
+}  // namespace adg
