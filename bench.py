@@ -1,0 +1,194 @@
+"""Benchmark of the ADER-DG step on one MI355X.
+
+Workload: 3-D compressible Euler, p = 3 (4^3 Gauss-Legendre nodes per cell),
+uniform periodic 81^3 mesh (531,441 cells, 170,061,120 DoFs), density wave
+rho = 1 + 0.2 sin(2 pi (x+y+z)), velocity (1,1,1), pressure 1, plus seeded
+U[-0.01, 0.01] noise on the nodal density; CFL 0.4, Rusanov faces.
+
+The timed region runs K whole steps through adg_step (CFL reduction,
+predictor, Riemann, corrector, all on the device; dt never leaves the GPU) for
+the FP32 form (predictor, face data and Riemann in FP32; u, u*, dt and the
+corrector accumulation in FP64) and for the plain FP64 path.  `value` is the
+FP32 form's DoF-updates/s; the FP64 path is reported beside it.  Per-kernel
+durations come from HIP events the library records around every launch on
+the launch's own stream during the timed region.
+
+Prints ONE JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N_BASE = 81
+ORDER = 3
+SEED = 2026
+PEAK = {"hbm_GBs": 8000.0, "fp64_TFs": 78.6, "fp32_TFs": 157.3}
+
+
+def predictor_flops_per_node(N, npic):
+    """Algorithmic flops of the predictor per spatial node (FMA = 2 flops,
+    division = 1): npic Picard iterations of [N flux evaluations (29 flops)
+    + 3 derivative contractions (2N each) per variable and time node + the
+    time solve (2N per variable, time node)], the epilogue (N flux evaluations,
+    time averages of the state and the 3 fluxes, volume term) and the face
+    projections (12 arrays x 5 variables x N^2 face nodes x 2N per cell)."""
+    per_iter = N * (29 + 5 * (3 * 2 * N + 5 + 2 * N)) + 5 * N
+    epilogue = N * (29 + 5 * 2 + 15 * 2) + 5 * (3 * 2 * N + 6)
+    traces = 12 * 5 * N * N * 2 * N / N ** 3
+    return npic * per_iter + epilogue + traces
+
+
+def predictor_bytes_per_cell(N, real_bytes):
+    """HBM bytes of the predictor per cell: read u, write u* (FP64), write the
+    face projections (12 arrays x 5 variables x N^2 reals)."""
+    return 2 * 5 * N ** 3 * 8 + 12 * 5 * N ** 2 * real_bytes
+
+
+def cpu_baseline(budget_s=12.0):
+    """The oracle (plain FP64 C, OpenMP over cells) on a bounded sample of the
+    same workload: 27^3 cells, p = 3, same initial state recipe."""
+    import oracle
+    from paper_1806_07984_amd import inputs
+    n = 27
+    om = oracle.Mesh(ORDER, (n, n, n))
+    u = inputs.density_wave_noisy(om.node_coords(), seed=SEED, noise=0.01)
+    dofs = om.nc * 5 * (ORDER + 1) ** 3
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        u, _, rc = om.run(u, 1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if rc != 0 or el >= budget_s:
+            break
+    return {"value": dofs * steps / el, "unit": "DoF-updates/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{steps} step(s) of a 27^3 periodic mesh, p=3, density wave + node noise "
+                      f"({dofs} DoFs/step), {el:.1f} s"}
+
+
+def load_traffic(kernel_name):
+    """HBM traffic of a kernel from committed rocprofv3 --pmc summaries, if
+    they were taken on the current kernel source (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f).get(kernel_name)
+    if not rec:
+        return None
+    src = open(os.path.join(ROOT, "paper_1806_07984_amd", "csrc", "kernels.hip"), "rb").read()
+    if hashlib.sha256(src).hexdigest()[:16] != rec.get("kernels_sha"):
+        return None
+    return rec["bytes_per_launch"]
+
+
+def run_path(A, precision, u0, steps, warmup):
+    import torch
+    mesh = A.Mesh(A.instance(ORDER, (N_BASE,) * 3), precision)
+    u = u0.clone()
+    ws = mesh.empty_workspace()
+    s = torch.cuda.current_stream()
+    mesh.step(u, warmup, ws, stream_skeleton=s, stream_enclave=s)
+    torch.cuda.synchronize()
+    mesh.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mesh.step(u, steps, ws, stream_skeleton=s, stream_enclave=s)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = mesh.profile_read()
+    mesh.profile(False)
+    mesh.status()
+    ms_step = (t1 - t0) * 1e3 / steps
+    dofs = mesh.info["n_dofs"]
+    N = ORDER + 1
+    pm, pc = prof["predictor"]
+    avg = pm / max(pc, 1)
+    nc = mesh.info["n_cells"]
+    flops = predictor_flops_per_node(N, N) * nc * N ** 3
+    res = {
+        "value": dofs * steps / (t1 - t0),
+        "ms_per_step": ms_step,
+        "phases_ms_per_step": {k: v[0] / steps for k, v in prof.items()},
+        "predictor": {"avg_ms": avg, "flops_per_launch": flops, "tflops": flops / (avg * 1e-3) / 1e12,
+                      "bytes_per_launch": predictor_bytes_per_cell(N, mesh.info["real_bytes"]) * nc},
+    }
+    mesh.close()
+    del ws, u
+    torch.cuda.empty_cache()
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["fp64", "fp32"], default=None,
+                    help="run one path only (for profiling runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU decomposition is a design, not a measured path.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1806_07984_amd as A
+    from paper_1806_07984_amd import inputs
+
+    A.load()
+    # initial state: node coordinates from the library, analytic state + seeded noise on the host
+    probe = A.Mesh(A.instance(ORDER, (N_BASE,) * 3), "fp64")
+    xyz = probe.node_coords().cpu().numpy().reshape(3, -1)
+    probe.close()
+    u0 = torch.from_numpy(inputs.density_wave_noisy(xyz, seed=SEED, noise=0.01).reshape(-1)).cuda()
+    del xyz
+
+    paths = ["fp32", "fp64"] if args.only is None else [args.only]
+    res = {p: run_path(A, p, u0, args.steps, args.warmup) for p in paths}
+    head = res.get("fp32", res.get("fp64"))
+    head_prec = "fp32" if "fp32" in res else "fp64"
+    pr = head["predictor"]
+    if head_prec == "fp32":
+        bound, peak = "alu", PEAK["fp32_TFs"]
+    else:
+        bound, peak = "alu", PEAK["fp64_TFs"]
+    traffic = load_traffic(f"predictor_{head_prec}")
+    out = {
+        "metric": "DoF-updates/s, 3D Euler ADER-DG p=3-5: FP64 plain vs FP32-MFMA batched; % roofline",
+        "value": head["value"],
+        "unit": "DoF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if head_prec == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "euler3d_aderdg_p3_periodic_81cubed_density_wave_noise", "order": ORDER,
+                   "cells": N_BASE ** 3, "dofs": 5 * N_BASE ** 3 * (ORDER + 1) ** 3, "path": head_prec,
+                   "parallelism": "single-gpu"},
+        "roofline": {"bound": bound, "achieved": pr["tflops"], "peak": peak, "unit": "TFLOP/s",
+                     "frac": pr["tflops"] / peak, "traffic": traffic, "kernel": f"k_predictor ({head_prec})",
+                     "avg_launch_ms": pr["avg_ms"],
+                     "hbm_GBs_algorithmic": pr["bytes_per_launch"] / (pr["avg_ms"] * 1e-3) / 1e9},
+        "paths": {k: {"value": v["value"], "ms_per_step": v["ms_per_step"],
+                      "phases_ms_per_step": v["phases_ms_per_step"],
+                      "predictor_tflops": v["predictor"]["tflops"]} for k, v in res.items()},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -162,6 +162,18 @@ adg_status adg_corrector(adg_mesh *mesh, const double *ustar_dev, const void *fs
 adg_status adg_step(adg_mesh *mesh, double *u_dev, int32_t n_steps, double *dt_hist_dev,
                     void *ws_dev, hipStream_t stream_skeleton, hipStream_t stream_enclave);
 
+/* Phase timing for measurement.  While enabled, every launch made by the
+ * handle's calls is bracketed by HIP events recorded on the stream the launch
+ * goes to.  adg_profile(mesh, 1) enables and clears the accumulators,
+ * adg_profile(mesh, 0) disables.  adg_profile_read synchronises on the
+ * recorded events and returns, per phase (ADG_PHASE_*), the summed kernel
+ * time in milliseconds and the number of launches (arrays of ADG_NPHASES).
+ * Enabling adds an event pair per launch; results are unchanged. */
+enum { ADG_PHASE_CFL = 0, ADG_PHASE_PREDICTOR = 1, ADG_PHASE_HANGING = 2, ADG_PHASE_RIEMANN = 3,
+       ADG_PHASE_CORRECTOR = 4, ADG_NPHASES = 5 };
+adg_status adg_profile(adg_mesh *mesh, int32_t enable);
+adg_status adg_profile_read(adg_mesh *mesh, double *ms, int64_t *launches);
+
 /* Synchronises the handle's device work and returns ADG_ERR_NONPHYSICAL if a
  * non-physical state was met since the last call (then clears the latch). */
 adg_status adg_get_status(adg_mesh *mesh);

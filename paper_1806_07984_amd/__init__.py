@@ -21,7 +21,8 @@ STATUS = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "OOM", 4: "HIP", 5: "N
 
 EXPORTS = ["adg_init_mesh", "adg_free_mesh", "adg_mesh_info", "adg_instance_info", "adg_mesh_cells",
            "adg_node_coords", "adg_cfl", "adg_predictor", "adg_riemann", "adg_corrector", "adg_step",
-           "adg_get_status", "adg_last_error"]
+           "adg_profile", "adg_profile_read", "adg_get_status", "adg_last_error"]
+PHASES = ["cfl", "predictor", "hanging", "riemann", "corrector"]
 
 
 class AdgError(RuntimeError):
@@ -75,6 +76,8 @@ def load():
         "adg_corrector": [P, P, P, P, P, P],
         "adg_step": [P, P, I32, P, P, P, P],
         "adg_get_status": [P],
+        "adg_profile": [P, I32],
+        "adg_profile_read": [P, P, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -243,6 +246,18 @@ class Mesh:
             raise ValueError("workspace too small")
         _check(load().adg_step(self._h, _ptr(u, torch.float64, self.info["u_elems"], "u"), int(n_steps), hist,
                                ctypes.c_void_p(ws.data_ptr()), s1, s2))
+
+    def profile(self, enable):
+        """Enable (and clear) or disable per-phase HIP-event timing."""
+        _check(load().adg_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{phase: (milliseconds summed over launches, launch count)}; synchronises."""
+        ms = np.zeros(len(PHASES))
+        cnt = np.zeros(len(PHASES), dtype=np.int64)
+        _check(load().adg_profile_read(self._h, ms.ctypes.data_as(ctypes.c_void_p),
+                                       cnt.ctypes.data_as(ctypes.c_void_p)))
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(PHASES)}
 
     def status(self):
         """Synchronises; raises AdgError(NONPHYSICAL) if a bad state was met."""

@@ -49,6 +49,12 @@ struct adg_mesh {
     double *dt_dev = nullptr;  // one per instance
     hipEvent_t ev_dt = nullptr, ev_skel = nullptr, ev_encl = nullptr;
     adg_info info{};
+    // phase timing (adg_profile)
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    struct Rec { int phase; hipEvent_t a, b; };
+    std::vector<Rec> recs;
 };
 
 namespace adg {
@@ -134,7 +140,41 @@ void free_all(adg_mesh *m)
     if (m->ev_dt) (void)hipEventDestroy(m->ev_dt);
     if (m->ev_skel) (void)hipEventDestroy(m->ev_skel);
     if (m->ev_encl) (void)hipEventDestroy(m->ev_encl);
+    for (hipEvent_t e : m->ev_pool) (void)hipEventDestroy(e);
+    m->ev_pool.clear();
 }
+
+// Event pair around the launches of one phase on one stream (no-op unless
+// profiling is enabled).
+struct PhaseTimer {
+    adg_mesh *m;
+    int phase;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    PhaseTimer(adg_mesh *m_, int phase_, hipStream_t st_) : m(m_), phase(phase_), st(st_)
+    {
+        if (!m->prof) return;
+        a = take();
+        if (a) (void)hipEventRecord(a, st);
+    }
+    ~PhaseTimer()
+    {
+        if (!a) return;
+        hipEvent_t b = take();
+        if (!b) return;
+        (void)hipEventRecord(b, st);
+        m->recs.push_back({phase, a, b});
+    }
+    hipEvent_t take()
+    {
+        if (m->ev_used == m->ev_pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            m->ev_pool.push_back(e);
+        }
+        return m->ev_pool[m->ev_used++];
+    }
+};
 
 bool valid_mesh(const adg_mesh *m)
 {
@@ -155,11 +195,16 @@ adg_status do_predictor(adg_mesh *m, const double *u, const double *dt, double *
         double *usi = ustar + I.u_off;
         T *tri = traces + I.tr_off;
         if (split && I.nskel > 0) {
-            ADG_HIP(launch_predictor<T>(I.N, ui, usi, tri, I.skel, I.nskel, I.nc, I.level, I.geo, dt + i,
-                                        I.gamma, I.npic, st_skel), "predictor (skeleton)");
+            {
+                PhaseTimer tm(m, ADG_PHASE_PREDICTOR, st_skel);
+                ADG_HIP(launch_predictor<T>(I.N, ui, usi, tri, I.skel, I.nskel, I.nc, I.level, I.geo, dt + i,
+                                            I.gamma, I.npic, st_skel), "predictor (skeleton)");
+            }
+            PhaseTimer tm(m, ADG_PHASE_PREDICTOR, st_encl);
             ADG_HIP(launch_predictor<T>(I.N, ui, usi, tri, I.encl, I.nencl, I.nc, I.level, I.geo, dt + i,
                                         I.gamma, I.npic, st_encl), "predictor (enclave)");
         } else {
+            PhaseTimer tm(m, ADG_PHASE_PREDICTOR, st_encl);
             ADG_HIP(launch_predictor<T>(I.N, ui, usi, tri, nullptr, I.nc, I.nc, I.level, I.geo, dt + i, I.gamma,
                                         I.npic, st_encl), "predictor");
         }
@@ -172,6 +217,7 @@ adg_status do_hanging(adg_mesh *m, const T *traces, T *fside, hipStream_t st)
 {
     for (auto &I : m->inst) {
         if (I.nh == 0) continue;
+        PhaseTimer tm(m, ADG_PHASE_HANGING, st);
         ADG_HIP(launch_hang<T>(I.N, traces + I.tr_off, fside + I.fs_off, I.hang, I.nh, I.nc, I.ptab, I.gamma,
                                m->status_dev, st), "hanging faces");
         ADG_HIP(launch_restrict<T>(I.N, fside + I.fs_off, I.hang, I.ccell, I.cside, I.cptr, I.cchild, I.ncs, I.nc,
@@ -183,6 +229,7 @@ adg_status do_hanging(adg_mesh *m, const T *traces, T *fside, hipStream_t st)
 template <typename T>
 adg_status do_conforming(adg_mesh *m, const T *traces, T *fside, hipStream_t st)
 {
+    PhaseTimer tm(m, ADG_PHASE_RIEMANN, st);
     for (auto &I : m->inst)
         for (int d = 0; d < 3; ++d)
             ADG_HIP(launch_riemann<T>(I.N, traces + I.tr_off, fside + I.fs_off, I.face_m[d], I.face_p[d], I.nf[d],
@@ -194,6 +241,7 @@ template <typename T>
 adg_status do_corrector(adg_mesh *m, const double *ustar, const T *fside, const double *dt, double *uout,
                         hipStream_t st)
 {
+    PhaseTimer tm(m, ADG_PHASE_CORRECTOR, st);
     for (size_t i = 0; i < m->inst.size(); ++i) {
         Instance &I = m->inst[i];
         ADG_HIP(launch_corrector<T>(I.N, ustar + I.u_off, fside + I.fs_off, dt + i, uout + I.u_off, I.nc, I.level,
@@ -204,6 +252,7 @@ adg_status do_corrector(adg_mesh *m, const double *ustar, const T *fside, const 
 
 adg_status do_cfl(adg_mesh *m, const double *u, double *dt, double *hist, hipStream_t st)
 {
+    PhaseTimer tm(m, ADG_PHASE_CFL, st);
     for (size_t i = 0; i < m->inst.size(); ++i) {
         Instance &I = m->inst[i];
         const double factor = I.cfl / (2.0 * I.order + 1.0);
@@ -534,6 +583,38 @@ adg_status adg_step(adg_mesh *mesh, double *u, int32_t n_steps, double *dt_hist,
     }
     if (mesh->prec == ADG_FP64) return step_impl<double>(mesh, u, n_steps, dt_hist, ws, s_skel, s_encl);
     return step_impl<float>(mesh, u, n_steps, dt_hist, ws, s_skel, s_encl);
+}
+
+adg_status adg_profile(adg_mesh *mesh, int32_t enable)
+{
+    if (!valid_mesh(mesh)) return ADG_ERR_INVALID_ARG;
+    if (enable) {
+        ADG_HIP(hipDeviceSynchronize(), "synchronize");
+        mesh->recs.clear();
+        mesh->ev_used = 0;
+    }
+    mesh->prof = enable != 0;
+    return ADG_OK;
+}
+
+adg_status adg_profile_read(adg_mesh *mesh, double *ms, int64_t *launches)
+{
+    if (!valid_mesh(mesh) || !ms || !launches) {
+        set_error("adg_profile_read: null argument");
+        return ADG_ERR_INVALID_ARG;
+    }
+    for (int k = 0; k < ADG_NPHASES; ++k) {
+        ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    for (const auto &r : mesh->recs) {
+        ADG_HIP(hipEventSynchronize(r.b), "event synchronize");
+        float t = 0.0f;
+        ADG_HIP(hipEventElapsedTime(&t, r.a, r.b), "event elapsed");
+        ms[r.phase] += double(t);
+        launches[r.phase] += 1;
+    }
+    return ADG_OK;
 }
 
 adg_status adg_get_status(adg_mesh *mesh)
