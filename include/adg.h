@@ -162,6 +162,24 @@ adg_status adg_corrector(adg_mesh *mesh, const double *ustar_dev, const void *fs
 adg_status adg_step(adg_mesh *mesh, double *u_dev, int32_t n_steps, double *dt_hist_dev,
                     void *ws_dev, hipStream_t stream_skeleton, hipStream_t stream_enclave);
 
+/* Batched handles (more than one instance, none with hanging faces) run the
+ * predictors of all instances and orders in ONE persistent launch whose work
+ * items are groups of cells; the cells per group of each order come from a
+ * table that adg_autotune fills by timing every candidate on the handle's
+ * largest instance of that order (u_dev is the state to time on, ws_dev a
+ * workspace of workspace_bytes; both are only read/overwritten as scratch;
+ * synchronises).  adg_tuning returns the cells per group chosen for
+ * N = 1..8 (8 int32).  Results do not depend on the choice. */
+adg_status adg_autotune(adg_mesh *mesh, const double *u_dev, void *ws_dev, hipStream_t stream);
+adg_status adg_tuning(const adg_mesh *mesh, int32_t *cells_per_block);
+
+/* use_graph = 1 (default): adg_step captures one step into a hipGraph on
+ * the handle's own streams and replays it (re-captured when u_dev or ws_dev
+ * change); 0: plain launches.  batched = 1 selects the one-launch batched
+ * predictor (default for handles with more than one instance and no hanging
+ * faces), 0 the per-instance launches.  Results are identical either way. */
+adg_status adg_set_options(adg_mesh *mesh, int32_t use_graph, int32_t batched);
+
 /* Phase timing for measurement.  While enabled, every launch made by the
  * handle's calls is bracketed by HIP events recorded on the stream the launch
  * goes to.  adg_profile(mesh, 1) enables and clears the accumulators,

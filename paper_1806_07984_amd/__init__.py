@@ -21,7 +21,8 @@ STATUS = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "OOM", 4: "HIP", 5: "N
 
 EXPORTS = ["adg_init_mesh", "adg_free_mesh", "adg_mesh_info", "adg_instance_info", "adg_mesh_cells",
            "adg_node_coords", "adg_cfl", "adg_predictor", "adg_riemann", "adg_corrector", "adg_step",
-           "adg_profile", "adg_profile_read", "adg_get_status", "adg_last_error"]
+           "adg_profile", "adg_profile_read", "adg_get_status", "adg_last_error", "adg_autotune",
+           "adg_tuning", "adg_set_options"]
 PHASES = ["cfl", "predictor", "hanging", "riemann", "corrector"]
 
 
@@ -78,6 +79,9 @@ def load():
         "adg_get_status": [P],
         "adg_profile": [P, I32],
         "adg_profile_read": [P, P, P],
+        "adg_autotune": [P, P, P, P],
+        "adg_tuning": [P, P],
+        "adg_set_options": [P, I32, I32],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -246,6 +250,22 @@ class Mesh:
             raise ValueError("workspace too small")
         _check(load().adg_step(self._h, _ptr(u, torch.float64, self.info["u_elems"], "u"), int(n_steps), hist,
                                ctypes.c_void_p(ws.data_ptr()), s1, s2))
+
+    def autotune(self, u, ws, stream=None):
+        """Pick the cells per work item of every order by timing (adg_autotune)."""
+        import torch
+        _check(load().adg_autotune(self._h, _ptr(u, torch.float64, self.info["u_elems"], "u"),
+                                   ctypes.c_void_p(ws.data_ptr()), _stream(stream)))
+
+    def tuning(self):
+        out = np.zeros(8, dtype=np.int32)
+        _check(load().adg_tuning(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return {N: int(out[N - 1]) for N in range(1, 9)}
+
+    def set_options(self, use_graph=True, batched=None):
+        if batched is None:
+            batched = self.n_instances > 1 and self.info["n_hanging_faces"] == 0
+        _check(load().adg_set_options(self._h, 1 if use_graph else 0, 1 if batched else 0))
 
     def profile(self, enable):
         """Enable (and clear) or disable per-phase HIP-event timing."""

@@ -55,6 +55,23 @@ struct adg_mesh {
     size_t ev_used = 0;
     struct Rec { int phase; hipEvent_t a, b; };
     std::vector<Rec> recs;
+    // batched predictor: every instance in one persistent launch (handles
+    // without hanging faces and with more than one instance)
+    bool batched = false;
+    int codes[adg::NMAX + 1] = {0};  // predictor variant per N
+    adg::PredInst *insts_dev = nullptr;
+    adg::PredItem *items_dev = nullptr;
+    int64_t nitems = 0;
+    int batch_threads = 0, batch_grid = 0, n_cu = 0;
+    bool autotuned = false;
+    // captured step (hipGraph) replayed by adg_step
+    bool use_graph = true;
+    hipStream_t gs_a = nullptr, gs_b = nullptr;
+    hipEvent_t ev_in = nullptr, ev_in2 = nullptr, ev_out = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    const void *gkey_u = nullptr, *gkey_ws = nullptr;
+    bool gkey_two = false;
 };
 
 namespace adg {
@@ -133,8 +150,26 @@ adg_status hip_fail(hipError_t e, const char *what)
         if (e_ != hipSuccess) return hip_fail(e_, what); \
     } while (0)
 
+void drop_graph(adg_mesh *m)
+{
+    if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
+    if (m->graph) (void)hipGraphDestroy(m->graph);
+    m->gexec = nullptr;
+    m->graph = nullptr;
+    m->gkey_u = m->gkey_ws = nullptr;
+}
+
 void free_all(adg_mesh *m)
 {
+    drop_graph(m);
+    if (m->items_dev) (void)hipFree(m->items_dev);
+    if (m->insts_dev) (void)hipFree(m->insts_dev);
+    m->items_dev = nullptr;
+    m->insts_dev = nullptr;
+    for (hipEvent_t *e : {&m->ev_in, &m->ev_in2, &m->ev_out})
+        if (*e) (void)hipEventDestroy(*e);
+    if (m->gs_a) (void)hipStreamDestroy(m->gs_a);
+    if (m->gs_b) (void)hipStreamDestroy(m->gs_b);
     for (void *p : m->allocs) (void)hipFree(p);
     m->allocs.clear();
     if (m->ev_dt) (void)hipEventDestroy(m->ev_dt);
@@ -185,10 +220,68 @@ bool valid_mesh(const adg_mesh *m)
     return true;
 }
 
+// default predictor variant per N (cells per block as PredCfg)
+int default_code(int N)
+{
+    static const int tab[NMAX + 1] = {0, 0, 2, 5, 8, 11, 13, 15, 15};
+    return tab[N];
+}
+
+int variant_threads(int code)
+{
+    int N, CPB;
+    pred_variant_shape(code, &N, &CPB);
+    int t = CPB * N * N * N;
+    return (t + 63) / 64 * 64;
+}
+
+// (Re)build the work items of the batched predictor from m->codes: one item
+// per CPB cells of every instance, ordered by decreasing cost per item so
+// that the static round-robin of the persistent grid balances the load.
+adg_status build_batch(adg_mesh *m)
+{
+    std::vector<PredItem> items;
+    int threads = 64;
+    for (size_t i = 0; i < m->inst.size(); ++i) {
+        const Instance &I = m->inst[i];
+        const int code = m->codes[I.N];
+        int N, CPB;
+        pred_variant_shape(code, &N, &CPB);
+        threads = std::max(threads, variant_threads(code));
+        for (int64_t c = 0; c < I.nc; c += CPB) items.push_back(PredItem{int32_t(i), code, c});
+    }
+    auto cost = [&](const PredItem &w) {
+        int N, CPB;
+        pred_variant_shape(w.code, &N, &CPB);
+        return double(CPB) * N * N * N * N;
+    };
+    std::stable_sort(items.begin(), items.end(),
+                     [&](const PredItem &a, const PredItem &b) { return cost(a) > cost(b); });
+    if (m->items_dev) (void)hipFree(m->items_dev);
+    m->items_dev = nullptr;
+    ADG_HIP(hipMalloc(&m->items_dev, sizeof(PredItem) * std::max<size_t>(items.size(), 1)), "batch items");
+    ADG_HIP(hipMemcpy(m->items_dev, items.data(), sizeof(PredItem) * items.size(), hipMemcpyHostToDevice),
+            "batch items upload");
+    m->nitems = int64_t(items.size());
+    m->batch_threads = threads;
+    const int occ = m->prec == ADG_FP64 ? predictor_batch_occupancy<double>(threads)
+                                        : predictor_batch_occupancy<float>(threads);
+    const int64_t grid = std::min<int64_t>(m->nitems, int64_t(occ) * m->n_cu);
+    m->batch_grid = int(std::max<int64_t>(grid, 1));
+    drop_graph(m);
+    return ADG_OK;
+}
+
 template <typename T>
 adg_status do_predictor(adg_mesh *m, const double *u, const double *dt, double *ustar, T *traces,
                         hipStream_t st_skel, hipStream_t st_encl, bool split)
 {
+    if (m->batched) {
+        PhaseTimer tm(m, ADG_PHASE_PREDICTOR, st_encl);
+        ADG_HIP(launch_predictor_batch<T>(m->items_dev, m->nitems, m->insts_dev, u, ustar, traces, dt,
+                                          m->batch_threads, m->batch_grid, st_encl), "batched predictor");
+        return ADG_OK;
+    }
     for (size_t i = 0; i < m->inst.size(); ++i) {
         Instance &I = m->inst[i];
         const double *ui = u + I.u_off;
@@ -262,9 +355,9 @@ adg_status do_cfl(adg_mesh *m, const double *u, double *dt, double *hist, hipStr
     return ADG_OK;
 }
 
+// Enqueues one whole step (CFL, predictor, faces, corrector) on the streams.
 template <typename T>
-adg_status step_impl(adg_mesh *m, double *u, int32_t n_steps, double *hist, void *ws, hipStream_t s_skel,
-                     hipStream_t s_encl)
+adg_status enqueue_step(adg_mesh *m, double *u, double *hist, void *ws, hipStream_t s_skel, hipStream_t s_encl)
 {
     char *w = static_cast<char *>(ws);
     double *ustar = reinterpret_cast<double *>(w);
@@ -273,9 +366,8 @@ adg_status step_impl(adg_mesh *m, double *u, int32_t n_steps, double *hist, void
     w += align_up(sizeof(T) * m->info.trace_elems);
     T *fside = reinterpret_cast<T *>(w);
     const bool two = s_skel != s_encl;
-    const int ni = int(m->inst.size());
-    for (int n = 0; n < n_steps; ++n) {
-        adg_status st = do_cfl(m, u, m->dt_dev, hist ? hist + int64_t(n) * ni : nullptr, s_skel);
+    {
+        adg_status st = do_cfl(m, u, m->dt_dev, hist, s_skel);
         if (st != ADG_OK) return st;
         if (two) {
             ADG_HIP(hipEventRecord(m->ev_dt, s_skel), "event record");
@@ -294,12 +386,150 @@ adg_status step_impl(adg_mesh *m, double *u, int32_t n_steps, double *hist, void
         st = do_corrector<T>(m, ustar, fside, m->dt_dev, u, s_skel);
         if (st != ADG_OK) return st;
     }
-    if (two) {
+    return ADG_OK;
+}
+
+template <typename T>
+adg_status step_eager(adg_mesh *m, double *u, int32_t n_steps, double *hist, void *ws, hipStream_t s_skel,
+                      hipStream_t s_encl)
+{
+    const int ni = int(m->inst.size());
+    for (int n = 0; n < n_steps; ++n) {
+        adg_status st = enqueue_step<T>(m, u, hist ? hist + int64_t(n) * ni : nullptr, ws, s_skel, s_encl);
+        if (st != ADG_OK) return st;
+    }
+    if (s_skel != s_encl) {
         // leave both streams ordered after the last corrector
         ADG_HIP(hipEventRecord(m->ev_skel, s_skel), "event record");
         ADG_HIP(hipStreamWaitEvent(s_encl, m->ev_skel, 0), "stream wait");
     }
     return ADG_OK;
+}
+
+// Captures one step into a hipGraph on the handle's private streams (default
+// priority) and replays it n_steps times; the caller's streams are joined by
+// events before and after.  dt stays on the device; the history, if asked
+// for, is copied after each replay.
+template <typename T>
+adg_status step_graph(adg_mesh *m, double *u, int32_t n_steps, double *hist, void *ws, hipStream_t s_skel,
+                      hipStream_t s_encl)
+{
+    const bool two = s_skel != s_encl;
+    hipStream_t A = m->gs_a, B = two ? m->gs_b : m->gs_a;
+    ADG_HIP(hipEventRecord(m->ev_in, s_skel), "event record");
+    ADG_HIP(hipStreamWaitEvent(A, m->ev_in, 0), "stream wait");
+    if (two) {
+        ADG_HIP(hipEventRecord(m->ev_in2, s_encl), "event record");
+        ADG_HIP(hipStreamWaitEvent(A, m->ev_in2, 0), "stream wait");
+    }
+    if (!m->gexec || m->gkey_u != u || m->gkey_ws != ws || m->gkey_two != two) {
+        drop_graph(m);
+        ADG_HIP(hipStreamBeginCapture(A, hipStreamCaptureModeThreadLocal), "begin capture");
+        adg_status st = enqueue_step<T>(m, u, nullptr, ws, A, B);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(A, &g);
+        if (st != ADG_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return hip_fail(e, "end capture");
+        m->graph = g;
+        ADG_HIP(hipGraphInstantiate(&m->gexec, m->graph, nullptr, nullptr, 0), "graph instantiate");
+        m->gkey_u = u;
+        m->gkey_ws = ws;
+        m->gkey_two = two;
+    }
+    const int ni = int(m->inst.size());
+    for (int n = 0; n < n_steps; ++n) {
+        ADG_HIP(hipGraphLaunch(m->gexec, A), "graph launch");
+        if (hist)
+            ADG_HIP(hipMemcpyAsync(hist + int64_t(n) * ni, m->dt_dev, sizeof(double) * ni, hipMemcpyDeviceToDevice, A),
+                    "dt history copy");
+    }
+    ADG_HIP(hipEventRecord(m->ev_out, A), "event record");
+    ADG_HIP(hipStreamWaitEvent(s_skel, m->ev_out, 0), "stream wait");
+    if (two) ADG_HIP(hipStreamWaitEvent(s_encl, m->ev_out, 0), "stream wait");
+    return ADG_OK;
+}
+
+template <typename T>
+adg_status step_impl(adg_mesh *m, double *u, int32_t n_steps, double *hist, void *ws, hipStream_t s_skel,
+                     hipStream_t s_encl)
+{
+    if (n_steps == 0) return ADG_OK;
+    if (m->use_graph && !m->prof) return step_graph<T>(m, u, n_steps, hist, ws, s_skel, s_encl);
+    return step_eager<T>(m, u, n_steps, hist, ws, s_skel, s_encl);
+}
+
+// Times one predictor variant on one instance (the batched kernel restricted
+// to that instance); returns milliseconds per cell, or a negative value.
+template <typename T>
+double time_variant(adg_mesh *m, int inst, int code, const double *u, double *ustar, T *traces, hipStream_t st)
+{
+    const Instance &I = m->inst[inst];
+    int N, CPB;
+    pred_variant_shape(code, &N, &CPB);
+    std::vector<PredItem> items;
+    for (int64_t c = 0; c < I.nc; c += CPB) items.push_back(PredItem{int32_t(inst), code, c});
+    PredItem *dev = nullptr;
+    if (hipMalloc(&dev, sizeof(PredItem) * items.size()) != hipSuccess) return -1.0;
+    double best = -1.0;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipMemcpy(dev, items.data(), sizeof(PredItem) * items.size(), hipMemcpyHostToDevice) == hipSuccess &&
+        hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) {
+        const int threads = variant_threads(code);
+        const int occ = predictor_batch_occupancy<T>(threads);
+        const int grid = int(std::max<int64_t>(1, std::min<int64_t>(int64_t(items.size()), int64_t(occ) * m->n_cu)));
+        for (int rep = 0; rep < 4; ++rep) {
+            (void)hipEventRecord(a, st);
+            (void)launch_predictor_batch<T>(dev, int64_t(items.size()), m->insts_dev, u, ustar, traces, m->dt_dev,
+                                            threads, grid, st);
+            (void)hipEventRecord(b, st);
+            (void)hipEventSynchronize(b);
+            float ms = 0.0f;
+            if (rep > 0 && hipEventElapsedTime(&ms, a, b) == hipSuccess) {
+                const double per = double(ms) / double(I.nc);
+                if (best < 0.0 || per < best) best = per;
+            }
+        }
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    (void)hipFree(dev);
+    return best;
+}
+
+template <typename T>
+adg_status autotune_impl(adg_mesh *m, const double *u, void *ws, hipStream_t st)
+{
+    char *w = static_cast<char *>(ws);
+    double *ustar = reinterpret_cast<double *>(w);
+    w += align_up(sizeof(double) * m->info.u_elems);
+    T *traces = reinterpret_cast<T *>(w);
+    // dt for the trials: the CFL value of the current state
+    adg_status s0 = do_cfl(m, u, m->dt_dev, nullptr, st);
+    if (s0 != ADG_OK) return s0;
+    for (int N = 1; N <= NMAX; ++N) {
+        int rep = -1;  // the largest instance of this order stands for it
+        for (size_t i = 0; i < m->inst.size(); ++i)
+            if (m->inst[i].N == N && (rep < 0 || m->inst[i].nc > m->inst[rep].nc)) rep = int(i);
+        if (rep < 0) continue;
+        double best = -1.0;
+        int best_code = default_code(N);
+        for (int code = 0; code < PRED_VARIANTS; ++code) {
+            int vn, cpb;
+            pred_variant_shape(code, &vn, &cpb);
+            if (vn != N) continue;
+            const double t = time_variant<T>(m, rep, code, u, ustar, traces, st);
+            if (t > 0.0 && (best < 0.0 || t < best)) {
+                best = t;
+                best_code = code;
+            }
+        }
+        m->codes[N] = best_code;
+    }
+    m->autotuned = true;
+    return build_batch(m);
 }
 
 }  // namespace
@@ -424,6 +654,31 @@ adg_status adg_init_mesh(const adg_instance_desc *desc, int32_t n_instances, adg
         }
     }
     ok = ok && dev_alloc(m, m->status_dev, 1) && dev_alloc(m, m->dt_dev, size_t(n_instances));
+    if (ok) {
+        hipDeviceProp_t prop;
+        ok = hipGetDeviceProperties(&prop, m->device) == hipSuccess;
+        m->n_cu = ok ? prop.multiProcessorCount : 1;
+        ok = ok && hipStreamCreateWithFlags(&m->gs_a, hipStreamNonBlocking) == hipSuccess &&
+             hipStreamCreateWithFlags(&m->gs_b, hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&m->ev_in, hipEventDisableTiming) == hipSuccess &&
+             hipEventCreateWithFlags(&m->ev_in2, hipEventDisableTiming) == hipSuccess &&
+             hipEventCreateWithFlags(&m->ev_out, hipEventDisableTiming) == hipSuccess;
+    }
+    if (ok) {
+        // batched predictor table (used when there is more than one instance
+        // and no instance has hanging faces)
+        bool any_skel = false;
+        std::vector<PredInst> pis;
+        for (auto &I : m->inst) {
+            any_skel = any_skel || I.nskel > 0;
+            pis.push_back(PredInst{I.u_off, I.tr_off, I.nc, I.level, I.gamma, int32_t(I.npic), int32_t(I.N), I.geo});
+        }
+        for (int N = 0; N <= NMAX; ++N) m->codes[N] = default_code(N);
+        m->batched = n_instances > 1 && !any_skel;
+        ok = hipMalloc(&m->insts_dev, sizeof(PredInst) * pis.size()) == hipSuccess &&
+             hipMemcpy(m->insts_dev, pis.data(), sizeof(PredInst) * pis.size(), hipMemcpyHostToDevice) == hipSuccess;
+        ok = ok && (!any_skel ? build_batch(m) == ADG_OK : true);
+    }
     if (ok) {
         int zero = 0;
         ok = hipMemcpy(m->status_dev, &zero, sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
@@ -583,6 +838,47 @@ adg_status adg_step(adg_mesh *mesh, double *u, int32_t n_steps, double *dt_hist,
     }
     if (mesh->prec == ADG_FP64) return step_impl<double>(mesh, u, n_steps, dt_hist, ws, s_skel, s_encl);
     return step_impl<float>(mesh, u, n_steps, dt_hist, ws, s_skel, s_encl);
+}
+
+adg_status adg_autotune(adg_mesh *mesh, const double *u, void *ws, hipStream_t stream)
+{
+    if (!valid_mesh(mesh) || !u || !ws) {
+        set_error("adg_autotune: null argument");
+        return ADG_ERR_INVALID_ARG;
+    }
+    if (mesh->nitems == 0) {
+        set_error("adg_autotune: the handle has hanging faces; only uniform instances are batched");
+        return ADG_ERR_UNSUPPORTED;
+    }
+    if (mesh->prec == ADG_FP64) return autotune_impl<double>(mesh, u, ws, stream);
+    return autotune_impl<float>(mesh, u, ws, stream);
+}
+
+adg_status adg_tuning(const adg_mesh *mesh, int32_t *cells_per_block)
+{
+    if (!valid_mesh(mesh) || !cells_per_block) {
+        set_error("adg_tuning: null argument");
+        return ADG_ERR_INVALID_ARG;
+    }
+    for (int N = 1; N <= NMAX; ++N) {
+        int vn, cpb;
+        pred_variant_shape(mesh->codes[N], &vn, &cpb);
+        cells_per_block[N - 1] = cpb;
+    }
+    return ADG_OK;
+}
+
+adg_status adg_set_options(adg_mesh *mesh, int32_t use_graph, int32_t batched)
+{
+    if (!valid_mesh(mesh)) return ADG_ERR_INVALID_ARG;
+    if (batched && mesh->nitems == 0) {
+        set_error("adg_set_options: batching needs instances without hanging faces");
+        return ADG_ERR_UNSUPPORTED;
+    }
+    mesh->use_graph = use_graph != 0;
+    mesh->batched = batched != 0;
+    drop_graph(mesh);
+    return ADG_OK;
 }
 
 adg_status adg_profile(adg_mesh *mesh, int32_t enable)

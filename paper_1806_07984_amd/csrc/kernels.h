@@ -24,6 +24,30 @@ constexpr int TRANSFER_BLOCKS = 3 + 9 + 27;
 
 hipError_t upload_basis(const DevBasis *tab);
 
+// Batched predictor: one work item = CPB cells of one instance.
+struct PredItem {
+    int32_t inst;   // index into the PredInst table
+    int32_t code;   // (N, CPB) variant, see pred_variant_shape
+    int64_t first;  // first cell of the item
+};
+// per instance: offsets into the concatenated u / u* / traces arrays
+struct PredInst {
+    int64_t u_off, tr_off, nc;
+    const int8_t *level;
+    double gamma;
+    int32_t npic, N;
+    Geo geo;
+};
+constexpr int PRED_VARIANTS = 16;
+int pred_variant_count();
+void pred_variant_shape(int code, int *N, int *CPB);
+template <typename T>
+hipError_t launch_predictor_batch(const PredItem *items, int64_t nitems, const PredInst *insts, const double *u,
+                                  double *ustar, T *traces, const double *dt, int threads, int grid,
+                                  hipStream_t st);
+template <typename T>
+int predictor_batch_occupancy(int threads);
+
 template <typename T>
 hipError_t launch_predictor(int N, const double *u, double *ustar, T *traces, const int32_t *list,
                             int64_t nlist, int64_t nc, const int8_t *level, const Geo &geo,

@@ -17,6 +17,7 @@
 //                 a fixed order (no atomics).
 //   k_corrector   C_Corr (Eq. 4), FP64 accumulation.
 //   k_cfl_*       global time step size: block maxima then one final block.
+#include <algorithm>
 #include <cmath>
 
 #include "adg_internal.h"
@@ -78,8 +79,8 @@ constexpr int round64(int x) { return (x + 63) / 64 * 64; }
 
 }  // namespace
 
-// cells per block for the predictor, chosen so one block is close to a
-// multiple of 64 lanes
+// Default cells per block of the per-order predictor kernel, chosen so one
+// block is close to a multiple of 64 lanes (the autotuner may pick others).
 template <int N> struct PredCfg;
 template <> struct PredCfg<1> { static constexpr int CPB = 64; };
 template <> struct PredCfg<2> { static constexpr int CPB = 32; };
@@ -89,27 +90,26 @@ template <> struct PredCfg<5> { static constexpr int CPB = 2; };
 template <> struct PredCfg<6> { static constexpr int CPB = 1; };
 template <> struct PredCfg<7> { static constexpr int CPB = 1; };
 
-template <typename T, int N>
-__global__ void __launch_bounds__(round64(PredCfg<N>::CPB * N * N * N))
-k_predictor(const double *__restrict__ u, double *__restrict__ ustar, T *__restrict__ traces,
-            const int32_t *__restrict__ list, int64_t nlist, int64_t nc,
-            const int8_t *__restrict__ level, Geo geo, const double *__restrict__ dt_dev,
-            double gamma, int npic)
+// Predictor of CPB cells (list entries first .. first+CPB-1) by one block of
+// at least CPB * N^3 threads; lds holds CPB * 15 * N^3 reals.
+template <typename T, int N, int CPB>
+__device__ __forceinline__ void predictor_body(T *__restrict__ lds, const double *__restrict__ u,
+                                               double *__restrict__ ustar, T *__restrict__ traces,
+                                               const int32_t *__restrict__ list, int64_t nlist, int64_t nc,
+                                               const int8_t *__restrict__ level, const Geo &geo, double dt,
+                                               double gamma, int npic, int64_t first)
 {
-    constexpr int CPB = PredCfg<N>::CPB;
     constexpr int N2 = N * N, N3 = N2 * N, NT = CPB * N3;
-    __shared__ T lds[CPB * 15 * N3];
     const DevBasis &B = c_basis[N];
 
     const int tid = threadIdx.x;
     const int cl = tid / N3, a = tid % N3;
-    const int64_t idx = int64_t(blockIdx.x) * CPB + cl;
+    const int64_t idx = first + cl;
     const bool lane_ok = tid < NT;
     const bool active = lane_ok && idx < nlist;
     const int64_t c = active ? (list ? int64_t(list[idx]) : idx) : 0;
     const int a0 = a % N, a1 = (a / N) % N, a2 = a / N2;
 
-    const double dt = dt_dev[0];
     const int lev = level ? level[c] : 0;
     const T cx = T(dt * geo.inv_dx[lev][0]);
     const T cy = T(dt * geo.inv_dx[lev][1]);
@@ -227,7 +227,7 @@ k_predictor(const double *__restrict__ u, double *__restrict__ ustar, T *__restr
     }
 
     // face projections: normal flux component (arr 1), then the state (arr 0)
-    const int64_t base = int64_t(blockIdx.x) * CPB;
+    const int64_t base = first;
     constexpr int ITEMS = 6 * NV * CPB * N2;
     for (int arr = 1; arr >= 0; --arr) {
         if (arr == 0) {
@@ -252,6 +252,55 @@ k_predictor(const double *__restrict__ u, double *__restrict__ ustar, T *__restr
             for (int e = 0; e < N; ++e) accv += T(E[e]) * src[node_from_face<N>(d, e, b)];
             traces[((int64_t(s * 2 + arr) * NV + v) * nc + c2) * N2 + b] = accv;
         }
+    }
+}
+
+
+template <typename T, int N, int CPB>
+__global__ void __launch_bounds__(round64(CPB * N * N * N))
+k_predictor(const double *__restrict__ u, double *__restrict__ ustar, T *__restrict__ traces,
+            const int32_t *__restrict__ list, int64_t nlist, int64_t nc,
+            const int8_t *__restrict__ level, Geo geo, const double *__restrict__ dt_dev,
+            double gamma, int npic)
+{
+    __shared__ T lds[CPB * 15 * N * N * N];
+    predictor_body<T, N, CPB>(lds, u, ustar, traces, list, nlist, nc, level, geo, dt_dev[0], gamma, npic,
+                              int64_t(blockIdx.x) * CPB);
+}
+
+// Predictor variants compiled into the batched kernel: (N, CPB) per code.
+#define ADG_PRED_VARIANTS(X) \
+    X(0, 1, 64) X(1, 2, 16) X(2, 2, 32) X(3, 2, 64) X(4, 3, 4) X(5, 3, 9) X(6, 3, 18) \
+    X(7, 4, 2) X(8, 4, 4) X(9, 4, 8) X(10, 5, 1) X(11, 5, 2) X(12, 5, 4) X(13, 6, 1) X(14, 6, 2) \
+    X(15, 7, 1)
+
+// One persistent launch over the work items of many instances of any order:
+// block b processes items b, b + gridDim, ... ; each item is CPB cells of one
+// instance, run by the (N, CPB) variant its code names.
+template <typename T>
+__global__ void __launch_bounds__(512)
+k_predictor_batch(const PredItem *__restrict__ items, int64_t nitems, const PredInst *__restrict__ insts,
+                  const double *__restrict__ u, double *__restrict__ ustar, T *__restrict__ traces,
+                  const double *__restrict__ dt)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *lds = reinterpret_cast<T *>(smem);
+    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const PredItem w = items[it];
+        const PredInst &I = insts[w.inst];
+        const double dti = dt[w.inst];
+        switch (w.code) {
+#define ADG_CASE(code, NN, CC)                                                                                  \
+    case code:                                                                                                  \
+        predictor_body<T, NN, CC>(lds, u + I.u_off, ustar + I.u_off, traces + I.tr_off, nullptr, I.nc, I.nc,   \
+                                  I.level, I.geo, dti, I.gamma, I.npic, w.first);                               \
+        break;
+            ADG_PRED_VARIANTS(ADG_CASE)
+#undef ADG_CASE
+        default:
+            break;
+        }
+        __syncthreads();
     }
 }
 
@@ -581,8 +630,8 @@ hipError_t launch_predictor(int N, const double *u, double *ustar, T *traces, co
     ADG_DISPATCH_N(N, {
         constexpr int CPB = PredCfg<NN>::CPB;
         const int64_t blocks = (nlist + CPB - 1) / CPB;
-        hipLaunchKernelGGL((k_predictor<T, NN>), dim3(unsigned(blocks)), dim3(round64(CPB * NN * NN * NN)), 0, st,
-                           u, ustar, traces, list, nlist, nc, level, geo, dt, gamma, npic);
+        hipLaunchKernelGGL((k_predictor<T, NN, CPB>), dim3(unsigned(blocks)), dim3(round64(CPB * NN * NN * NN)), 0,
+                           st, u, ustar, traces, list, nlist, nc, level, geo, dt, gamma, npic);
     });
     return hipGetLastError();
 }
@@ -642,6 +691,51 @@ hipError_t launch_corrector(int N, const double *ustar, const T *fside, const do
     return hipGetLastError();
 }
 
+int pred_variant_count() { return PRED_VARIANTS; }
+
+void pred_variant_shape(int code, int *N, int *CPB)
+{
+    switch (code) {
+#define ADG_SHAPE(code_, NN, CC) \
+    case code_: *N = NN; *CPB = CC; return;
+        ADG_PRED_VARIANTS(ADG_SHAPE)
+#undef ADG_SHAPE
+    default: *N = 0; *CPB = 0;
+    }
+}
+
+template <typename T>
+hipError_t launch_predictor_batch(const PredItem *items, int64_t nitems, const PredInst *insts, const double *u,
+                                  double *ustar, T *traces, const double *dt, int threads, int grid,
+                                  hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    size_t lds = 0;
+    for (int c = 0; c < PRED_VARIANTS; ++c) {
+        int N, CPB;
+        pred_variant_shape(c, &N, &CPB);
+        if (round64(CPB * N * N * N) <= threads) lds = std::max(lds, size_t(CPB) * 15 * N * N * N * sizeof(T));
+    }
+    hipLaunchKernelGGL(k_predictor_batch<T>, dim3(grid), dim3(threads), lds, st, items, nitems, insts, u, ustar,
+                       traces, dt);
+    return hipGetLastError();
+}
+
+template <typename T>
+int predictor_batch_occupancy(int threads)
+{
+    size_t lds = 0;
+    for (int c = 0; c < PRED_VARIANTS; ++c) {
+        int N, CPB;
+        pred_variant_shape(c, &N, &CPB);
+        if (round64(CPB * N * N * N) <= threads) lds = std::max(lds, size_t(CPB) * 15 * N * N * N * sizeof(T));
+    }
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_predictor_batch<T>, threads, lds) != hipSuccess)
+        return 1;
+    return blocks > 0 ? blocks : 1;
+}
+
 int cfl_blocks(int N, int64_t nc)
 {
     const int64_t total = nc * int64_t(N) * N * N;
@@ -692,5 +786,11 @@ hipError_t launch_node_coords(int N, double *xyz, const int32_t *ijk, const int8
 
 ADG_INSTANTIATE(double)
 ADG_INSTANTIATE(float)
+template hipError_t launch_predictor_batch<double>(const PredItem *, int64_t, const PredInst *, const double *,
+                                                  double *, double *, const double *, int, int, hipStream_t);
+template hipError_t launch_predictor_batch<float>(const PredItem *, int64_t, const PredInst *, const double *,
+                                                 double *, float *, const double *, int, int, hipStream_t);
+template int predictor_batch_occupancy<double>(int);
+template int predictor_batch_occupancy<float>(int);
 
 }  // namespace adg

@@ -1,0 +1,112 @@
+"""Batched instances of uneven size and order in one persistent predictor
+launch, the autotuned cells-per-item table and the hipGraph-captured step.
+
+Each instance of a batch must match the oracle run of that instance alone
+(relative L2 <= 1e-12 FP64, <= 2e-5 FP32); batched vs per-instance launches,
+autotuned vs default tiling and graph replays vs plain launches must agree
+bit for bit (they run the same per-cell arithmetic)."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1806_07984_amd as A
+from paper_1806_07984_amd import inputs
+from helpers import rel_l2_per_var, solution_weights
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 2e-5}
+
+# (order, base cells, amplitude): every order 2..6, ragged sizes
+SMALL_BATCH = [(2, (5, 3, 4), 0.05), (3, (4, 4, 4), 0.3), (4, (3, 5, 2), 0.1), (5, (2, 3, 3), 0.2),
+               (6, (2, 2, 3), 0.15), (3, (7, 2, 3), 0.25)]
+
+
+def batch_state(gm, descs):
+    """Density waves of the given amplitudes at the library's node coordinates."""
+    xyz = gm.node_coords().cpu().numpy()
+    u = np.zeros(gm.info["u_elems"])
+    for g, (_, _, amp) in zip(gm.instances, descs):
+        n = g["n_cells"] * (g["order"] + 1) ** 3
+        x = xyz[3 * g["u_offset"] // 5: 3 * g["u_offset"] // 5 + 3 * n].reshape(3, n)
+        u[g["u_offset"]: g["u_offset"] + 5 * n] = inputs.density_wave(x, amp=amp).reshape(-1)
+    return u
+
+
+def run(gm, u0, steps, ws=None):
+    u = torch.from_numpy(u0.copy()).cuda()
+    ws = gm.empty_workspace() if ws is None else ws
+    hist = torch.zeros(steps * gm.n_instances, dtype=torch.float64, device="cuda")
+    gm.step(u, steps, ws, hist)
+    torch.cuda.synchronize()
+    gm.status()
+    return u, hist
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_matches_oracle_per_instance(precision):
+    descs = SMALL_BATCH
+    gm = A.Mesh([A.instance(p, n) for p, n, _ in descs], precision)
+    assert gm.n_instances == len(descs)
+    u0 = batch_state(gm, descs)
+    steps = 3
+    u, hist = run(gm, u0, steps)
+    u = u.cpu().numpy()
+    hist = hist.cpu().numpy().reshape(steps, -1)
+    for i, ((p, n, amp), g) in enumerate(zip(descs, gm.instances)):
+        print(f"[batch] instance {i} p={p} n={n} {precision}", flush=True)
+        om = oracle.Mesh(p, n)
+        size = 5 * g["n_cells"] * (p + 1) ** 3
+        ui0 = u0[g["u_offset"]: g["u_offset"] + size].reshape(5, g["n_cells"], -1)
+        ref, h_ref, rc = om.run(ui0, steps)
+        assert rc == 0
+        e = rel_l2_per_var(u[g["u_offset"]: g["u_offset"] + size], ref, solution_weights(om, n))
+        assert e.max() <= TOL[precision], (i, e)
+        assert np.abs(hist[:, i] / h_ref - 1).max() <= (1e-12 if precision == "fp64" else 1e-5)
+
+
+def test_batched_graph_autotune_are_bitwise_neutral():
+    descs = SMALL_BATCH
+    gm = A.Mesh([A.instance(p, n) for p, n, _ in descs], "fp32")
+    u0 = batch_state(gm, descs)
+    steps = 4
+    # reference: per-instance launches, no graph
+    gm.set_options(use_graph=False, batched=False)
+    ref, _ = run(gm, u0, steps)
+    # one persistent batched launch, no graph
+    gm.set_options(use_graph=False, batched=True)
+    b, _ = run(gm, u0, steps)
+    assert torch.equal(b, ref)
+    # graph replays, with eager work and synchronisation between replays
+    gm.set_options(use_graph=True, batched=True)
+    u = torch.from_numpy(u0.copy()).cuda()
+    ws = gm.empty_workspace()
+    for k in range(steps):
+        gm.step(u, 1, ws)
+        junk = torch.ones(1000, device="cuda").sum()  # unrelated eager work between replays
+        torch.cuda.synchronize()
+        assert junk.item() == 1000.0
+    assert torch.equal(u, ref)
+    # autotuned tiling
+    gm.autotune(torch.from_numpy(u0.copy()).cuda(), ws)
+    print("tuning:", gm.tuning(), flush=True)
+    t, _ = run(gm, u0, steps, ws)
+    assert torch.equal(t, ref)
+
+
+def test_single_instance_graph_matches_eager():
+    n = (6, 5, 4)
+    gm = A.Mesh(A.instance(3, n), "fp64")
+    om = oracle.Mesh(3, n)
+    u0 = inputs.density_wave_noisy(om.node_coords(), seed=4, noise=0.02).reshape(-1)
+    gm.set_options(use_graph=False, batched=False)
+    ref, _ = run(gm, u0, 5)
+    gm.set_options(use_graph=True, batched=False)
+    u = torch.from_numpy(u0.copy()).cuda()
+    ws = gm.empty_workspace()
+    gm.step(u, 2, ws)
+    torch.cuda.synchronize()
+    gm.step(u, 3, ws)  # replays of the same captured graph
+    torch.cuda.synchronize()
+    assert torch.equal(u, ref)
