@@ -126,6 +126,85 @@ def run_path(A, precision, u0, steps, warmup):
     return res
 
 
+def run_amr(A, steps=50):
+    """Adaptive mesh: 27^3 base cells, two levels of 3:1 refinement in the
+    sphere |x - c| <= 0.25 (1,074,035 cells), p = 4, blast wave with its
+    interface smoothed over one finest cell, FP32 form; skeleton predictor on
+    one stream, enclave predictor on another (default priorities)."""
+    import torch
+    from paper_1806_07984_amd import inputs
+    n = (27, 27, 27)
+    ref = inputs.sphere_refine_list(n, 2, radius=0.25)
+    mesh = A.Mesh(A.instance(4, n, max_level=2, refine=ref), "fp32")
+    xyz = mesh.node_coords().cpu().numpy().reshape(3, -1)
+    u = torch.from_numpy(inputs.blast_smooth(xyz, width=1.0 / (27 * 9)).reshape(-1)).cuda()
+    del xyz
+    ws = mesh.empty_workspace()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    s1.wait_stream(torch.cuda.current_stream())
+    mesh.step(u, 1, ws, stream_skeleton=s1, stream_enclave=s2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mesh.step(u, steps, ws, stream_skeleton=s1, stream_enclave=s2)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    mesh.status()
+    info = mesh.info
+    out = {"value": info["n_dofs"] * steps / el, "unit": "DoF-updates/s", "ms_per_step": el * 1e3 / steps,
+           "steps": steps, "cells": info["n_cells"], "dofs": info["n_dofs"],
+           "hanging_faces": info["n_hanging_faces"], "skeleton_cells": info["n_skeleton_cells"],
+           "path": "fp32, graph, skeleton/enclave streams"}
+    mesh.close()
+    del u, ws
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_batch(A, steps=10, seed=0):
+    """64 periodic instances, edges in {9,15,21,27,45} and orders 2..6 drawn
+    from a seed, density waves with amplitudes in [0.05, 0.3]; FP32 form,
+    one persistent predictor launch over all instances, autotuned cells per
+    work item, hipGraph-captured step."""
+    import torch
+    from paper_1806_07984_amd import inputs
+    draws = inputs.batch_instances(64, seed=seed)
+    mesh = A.Mesh([A.instance(d["order"], (d["edge"],) * 3) for d in draws], "fp32")
+    xyz = mesh.node_coords().cpu().numpy()
+    u0 = np.zeros(mesh.info["u_elems"])
+    for g, d in zip(mesh.instances, draws):
+        nn = g["n_cells"] * (g["order"] + 1) ** 3
+        x = xyz[3 * g["u_offset"] // 5: 3 * g["u_offset"] // 5 + 3 * nn].reshape(3, nn)
+        u0[g["u_offset"]: g["u_offset"] + 5 * nn] = inputs.density_wave(x, amp=d["amp"]).reshape(-1)
+    del xyz
+    u = torch.from_numpy(u0).cuda()
+    del u0
+    ws = mesh.empty_workspace()
+    mesh.autotune(u, ws)
+    res = {}
+    for mode, name in ((1, "one persistent predictor launch per order"),
+                       (2, "one persistent predictor launch for all orders")):
+        mesh.set_options(use_graph=True, batched=mode)
+        mesh.step(u, 1, ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mesh.step(u, steps, ws)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        mesh.status()
+        res[mode] = (el, name)
+    best = min(res, key=lambda k: res[k][0])
+    el = res[best][0]
+    out = {"value": mesh.info["n_dofs"] * steps / el, "unit": "DoF-updates/s", "ms_per_step": el * 1e3 / steps,
+           "steps": steps, "instances": 64, "dofs": mesh.info["n_dofs"],
+           "tuning_cells_per_item": {f"p={N - 1}": c for N, c in mesh.tuning().items() if 3 <= N <= 7},
+           "path": "fp32, graph, " + res[best][1],
+           "ms_per_step_by_mode": {v[1]: v[0] * 1e3 / steps for v in res.values()}}
+    mesh.close()
+    del u, ws
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,7 +213,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["fp64", "fp32"], default=None,
                     help="run one path only (for profiling runs)")
+    ap.add_argument("--no-extra", action="store_true", help="skip the AMR and batch workloads")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy a 1 GiB buffer 3 times (calibrates HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": 2 * a.numel() * 8, "launches": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU decomposition is a design, not a measured path.", file=sys.stderr)
@@ -185,6 +276,9 @@ def main():
                       "phases_ms_per_step": v["phases_ms_per_step"],
                       "predictor_tflops": v["predictor"]["tflops"]} for k, v in res.items()},
     }
+    if not args.no_extra:
+        out["other_workloads"] = {"amr_blast_p4_27cubed_2levels": run_amr(A),
+                                  "batch64_p2to6_seed0": run_batch(A)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

@@ -163,9 +163,11 @@ adg_status adg_step(adg_mesh *mesh, double *u_dev, int32_t n_steps, double *dt_h
                     void *ws_dev, hipStream_t stream_skeleton, hipStream_t stream_enclave);
 
 /* Batched handles (more than one instance, none with hanging faces) run the
- * predictors of all instances and orders in ONE persistent launch whose work
- * items are groups of cells; the cells per group of each order come from a
- * table that adg_autotune fills by timing every candidate on the handle's
+ * predictors of all instances from a work list whose items are groups of
+ * cells of one instance: either one persistent launch per order over the
+ * items of all instances of that order (default), or ONE persistent launch
+ * over all items of all orders.  The cells per item of each order come from
+ * a table that adg_autotune fills by timing every candidate on the handle's
  * largest instance of that order (u_dev is the state to time on, ws_dev a
  * workspace of workspace_bytes; both are only read/overwritten as scratch;
  * synchronises).  adg_tuning returns the cells per group chosen for
@@ -175,9 +177,10 @@ adg_status adg_tuning(const adg_mesh *mesh, int32_t *cells_per_block);
 
 /* use_graph = 1 (default): adg_step captures one step into a hipGraph on
  * the handle's own streams and replays it (re-captured when u_dev or ws_dev
- * change); 0: plain launches.  batched = 1 selects the one-launch batched
- * predictor (default for handles with more than one instance and no hanging
- * faces), 0 the per-instance launches.  Results are identical either way. */
+ * change); 0: plain launches.  batched = 0: one predictor launch per
+ * instance; 1: one persistent launch per order (default for handles with
+ * more than one instance and no hanging faces); 2: one persistent launch for
+ * all orders.  Results are identical either way. */
 adg_status adg_set_options(adg_mesh *mesh, int32_t use_graph, int32_t batched);
 
 /* Phase timing for measurement.  While enabled, every launch made by the

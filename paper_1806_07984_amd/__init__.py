@@ -263,9 +263,11 @@ class Mesh:
         return {N: int(out[N - 1]) for N in range(1, 9)}
 
     def set_options(self, use_graph=True, batched=None):
+        """batched: 0 per-instance launches, 1 one persistent launch per order,
+        2 one persistent launch for all orders (None: 1 if the handle can batch)."""
         if batched is None:
-            batched = self.n_instances > 1 and self.info["n_hanging_faces"] == 0
-        _check(load().adg_set_options(self._h, 1 if use_graph else 0, 1 if batched else 0))
+            batched = 1 if (self.n_instances > 1 and self.info["n_hanging_faces"] == 0) else 0
+        _check(load().adg_set_options(self._h, 1 if use_graph else 0, int(batched)))
 
     def profile(self, enable):
         """Enable (and clear) or disable per-phase HIP-event timing."""

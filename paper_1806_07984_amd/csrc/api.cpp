@@ -57,8 +57,10 @@ struct adg_mesh {
     std::vector<Rec> recs;
     // batched predictor: every instance in one persistent launch (handles
     // without hanging faces and with more than one instance)
-    bool batched = false;
+    int batched = 0;                  // 0 per instance, 1 per order, 2 one launch
     int codes[adg::NMAX + 1] = {0};  // predictor variant per N
+    int64_t order_begin[adg::NMAX + 2] = {0};  // first item of every N (items grouped by N)
+    int64_t order_count[adg::NMAX + 2] = {0};
     adg::PredInst *insts_dev = nullptr;
     adg::PredItem *items_dev = nullptr;
     int64_t nitems = 0;
@@ -255,8 +257,27 @@ adg_status build_batch(adg_mesh *m)
         pred_variant_shape(w.code, &N, &CPB);
         return double(CPB) * N * N * N * N;
     };
+    // grouped by order (largest first), each group in instance order; the
+    // per-order launches take contiguous ranges, the single launch the whole
+    // list (cost per item decreases along it)
     std::stable_sort(items.begin(), items.end(),
                      [&](const PredItem &a, const PredItem &b) { return cost(a) > cost(b); });
+    std::stable_sort(items.begin(), items.end(), [&](const PredItem &a, const PredItem &b) {
+        return m->inst[a.inst].N > m->inst[b.inst].N;
+    });
+    for (int N = 0; N <= NMAX + 1; ++N) m->order_begin[N] = 0;
+    {
+        // order_begin[N] .. order_begin[N] + count: items of order N
+        std::vector<int64_t> cnt(NMAX + 2, 0);
+        for (const auto &w : items) cnt[m->inst[w.inst].N]++;
+        int64_t pos = 0;
+        for (int N = NMAX; N >= 1; --N) {
+            m->order_begin[N] = pos;
+            pos += cnt[N];
+        }
+        m->order_begin[NMAX + 1] = pos;  // unused sentinel
+        for (int N = 1; N <= NMAX; ++N) m->order_count[N] = cnt[N];
+    }
     if (m->items_dev) (void)hipFree(m->items_dev);
     m->items_dev = nullptr;
     ADG_HIP(hipMalloc(&m->items_dev, sizeof(PredItem) * std::max<size_t>(items.size(), 1)), "batch items");
@@ -276,10 +297,20 @@ template <typename T>
 adg_status do_predictor(adg_mesh *m, const double *u, const double *dt, double *ustar, T *traces,
                         hipStream_t st_skel, hipStream_t st_encl, bool split)
 {
-    if (m->batched) {
+    if (m->batched == 2) {
         PhaseTimer tm(m, ADG_PHASE_PREDICTOR, st_encl);
         ADG_HIP(launch_predictor_batch<T>(m->items_dev, m->nitems, m->insts_dev, u, ustar, traces, dt,
                                           m->batch_threads, m->batch_grid, st_encl), "batched predictor");
+        return ADG_OK;
+    }
+    if (m->batched == 1) {
+        PhaseTimer tm(m, ADG_PHASE_PREDICTOR, st_encl);
+        for (int N = NMAX; N >= 1; --N) {
+            if (m->order_count[N] == 0) continue;
+            ADG_HIP(launch_predictor_order<T>(m->codes[N], m->items_dev + m->order_begin[N], m->order_count[N],
+                                              m->insts_dev, u, ustar, traces, dt, m->n_cu, st_encl),
+                    "per-order batched predictor");
+        }
         return ADG_OK;
     }
     for (size_t i = 0; i < m->inst.size(); ++i) {
@@ -461,8 +492,9 @@ adg_status step_impl(adg_mesh *m, double *u, int32_t n_steps, double *hist, void
     return step_eager<T>(m, u, n_steps, hist, ws, s_skel, s_encl);
 }
 
-// Times one predictor variant on one instance (the batched kernel restricted
-// to that instance); returns milliseconds per cell, or a negative value.
+// Times one predictor variant on one instance (the per-order persistent
+// kernel restricted to that instance); returns milliseconds per cell, or a
+// negative value.
 template <typename T>
 double time_variant(adg_mesh *m, int inst, int code, const double *u, double *ustar, T *traces, hipStream_t st)
 {
@@ -477,13 +509,10 @@ double time_variant(adg_mesh *m, int inst, int code, const double *u, double *us
     hipEvent_t a = nullptr, b = nullptr;
     if (hipMemcpy(dev, items.data(), sizeof(PredItem) * items.size(), hipMemcpyHostToDevice) == hipSuccess &&
         hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) {
-        const int threads = variant_threads(code);
-        const int occ = predictor_batch_occupancy<T>(threads);
-        const int grid = int(std::max<int64_t>(1, std::min<int64_t>(int64_t(items.size()), int64_t(occ) * m->n_cu)));
         for (int rep = 0; rep < 4; ++rep) {
             (void)hipEventRecord(a, st);
-            (void)launch_predictor_batch<T>(dev, int64_t(items.size()), m->insts_dev, u, ustar, traces, m->dt_dev,
-                                            threads, grid, st);
+            (void)launch_predictor_order<T>(code, dev, int64_t(items.size()), m->insts_dev, u, ustar, traces,
+                                            m->dt_dev, m->n_cu, st);
             (void)hipEventRecord(b, st);
             (void)hipEventSynchronize(b);
             float ms = 0.0f;
@@ -674,7 +703,7 @@ adg_status adg_init_mesh(const adg_instance_desc *desc, int32_t n_instances, adg
             pis.push_back(PredInst{I.u_off, I.tr_off, I.nc, I.level, I.gamma, int32_t(I.npic), int32_t(I.N), I.geo});
         }
         for (int N = 0; N <= NMAX; ++N) m->codes[N] = default_code(N);
-        m->batched = n_instances > 1 && !any_skel;
+        m->batched = (n_instances > 1 && !any_skel) ? 1 : 0;
         ok = hipMalloc(&m->insts_dev, sizeof(PredInst) * pis.size()) == hipSuccess &&
              hipMemcpy(m->insts_dev, pis.data(), sizeof(PredInst) * pis.size(), hipMemcpyHostToDevice) == hipSuccess;
         ok = ok && (!any_skel ? build_batch(m) == ADG_OK : true);
@@ -871,12 +900,16 @@ adg_status adg_tuning(const adg_mesh *mesh, int32_t *cells_per_block)
 adg_status adg_set_options(adg_mesh *mesh, int32_t use_graph, int32_t batched)
 {
     if (!valid_mesh(mesh)) return ADG_ERR_INVALID_ARG;
+    if (batched < 0 || batched > 2) {
+        set_error("adg_set_options: batched must be 0, 1 or 2");
+        return ADG_ERR_INVALID_ARG;
+    }
     if (batched && mesh->nitems == 0) {
         set_error("adg_set_options: batching needs instances without hanging faces");
         return ADG_ERR_UNSUPPORTED;
     }
     mesh->use_graph = use_graph != 0;
-    mesh->batched = batched != 0;
+    mesh->batched = batched;
     drop_graph(mesh);
     return ADG_OK;
 }

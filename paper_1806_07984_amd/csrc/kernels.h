@@ -47,6 +47,11 @@ hipError_t launch_predictor_batch(const PredItem *items, int64_t nitems, const P
                                   hipStream_t st);
 template <typename T>
 int predictor_batch_occupancy(int threads);
+// persistent predictor over the items of one order (variant code)
+template <typename T>
+hipError_t launch_predictor_order(int code, const PredItem *items, int64_t nitems, const PredInst *insts,
+                                  const double *u, double *ustar, T *traces, const double *dt, int n_cu,
+                                  hipStream_t st);
 
 template <typename T>
 hipError_t launch_predictor(int N, const double *u, double *ustar, T *traces, const int32_t *list,

@@ -268,6 +268,33 @@ k_predictor(const double *__restrict__ u, double *__restrict__ ustar, T *__restr
                               int64_t(blockIdx.x) * CPB);
 }
 
+// One variant of the batched predictor on one work item.
+template <typename T, int N, int CPB>
+__device__ __forceinline__ void predictor_item(T *lds, const double *u, double *ustar, T *traces, int64_t nc,
+                                            const int8_t *level, const Geo *geo, double dt, double gamma,
+                                            int npic, int64_t first)
+{
+    predictor_body<T, N, CPB>(lds, u, ustar, traces, nullptr, nc, nc, level, *geo, dt, gamma, npic, first);
+}
+
+// Persistent predictor over the work items of ONE order (all instances of
+// that order): block b processes items b, b + gridDim, ...
+template <typename T, int N, int CPB>
+__global__ void __launch_bounds__(round64(CPB * N * N * N))
+k_predictor_order(const PredItem *__restrict__ items, int64_t nitems, const PredInst *__restrict__ insts,
+                  const double *__restrict__ u, double *__restrict__ ustar, T *__restrict__ traces,
+                  const double *__restrict__ dt)
+{
+    __shared__ T lds[CPB * 15 * N * N * N];
+    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const PredItem w = items[it];
+        const PredInst &I = insts[w.inst];
+        predictor_body<T, N, CPB>(lds, u + I.u_off, ustar + I.u_off, traces + I.tr_off, nullptr, I.nc, I.nc, I.level,
+                                  I.geo, dt[w.inst], I.gamma, I.npic, w.first);
+        __syncthreads();
+    }
+}
+
 // Predictor variants compiled into the batched kernel: (N, CPB) per code.
 #define ADG_PRED_VARIANTS(X) \
     X(0, 1, 64) X(1, 2, 16) X(2, 2, 32) X(3, 2, 64) X(4, 3, 4) X(5, 3, 9) X(6, 3, 18) \
@@ -290,10 +317,10 @@ k_predictor_batch(const PredItem *__restrict__ items, int64_t nitems, const Pred
         const PredInst &I = insts[w.inst];
         const double dti = dt[w.inst];
         switch (w.code) {
-#define ADG_CASE(code, NN, CC)                                                                                  \
-    case code:                                                                                                  \
-        predictor_body<T, NN, CC>(lds, u + I.u_off, ustar + I.u_off, traces + I.tr_off, nullptr, I.nc, I.nc,   \
-                                  I.level, I.geo, dti, I.gamma, I.npic, w.first);                               \
+#define ADG_CASE(code, NN, CC)                                                                                \
+    case code:                                                                                                \
+        predictor_item<T, NN, CC>(lds, u + I.u_off, ustar + I.u_off, traces + I.tr_off, I.nc, I.level, &I.geo, \
+                                  dti, I.gamma, I.npic, w.first);                                             \
         break;
             ADG_PRED_VARIANTS(ADG_CASE)
 #undef ADG_CASE
@@ -722,6 +749,33 @@ hipError_t launch_predictor_batch(const PredItem *items, int64_t nitems, const P
 }
 
 template <typename T>
+hipError_t launch_predictor_order(int code, const PredItem *items, int64_t nitems, const PredInst *insts,
+                                  const double *u, double *ustar, T *traces, const double *dt, int n_cu,
+                                  hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    switch (code) {
+#define ADG_ORDER_CASE(code_, NN, CC)                                                                            \
+    case code_: {                                                                                                \
+        constexpr int TH = round64(CC * NN * NN * NN);                                                           \
+        int occ = 0;                                                                                             \
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_predictor_order<T, NN, CC>, TH, 0) != hipSuccess \
+            || occ < 1)                                                                                          \
+            occ = 1;                                                                                             \
+        const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(nitems, int64_t(occ) * n_cu));              \
+        hipLaunchKernelGGL((k_predictor_order<T, NN, CC>), dim3(unsigned(grid)), dim3(TH), 0, st, items, nitems, \
+                           insts, u, ustar, traces, dt);                                                         \
+        break;                                                                                                   \
+    }
+        ADG_PRED_VARIANTS(ADG_ORDER_CASE)
+#undef ADG_ORDER_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
 int predictor_batch_occupancy(int threads)
 {
     size_t lds = 0;
@@ -791,6 +845,10 @@ template hipError_t launch_predictor_batch<double>(const PredItem *, int64_t, co
 template hipError_t launch_predictor_batch<float>(const PredItem *, int64_t, const PredInst *, const double *,
                                                  double *, float *, const double *, int, int, hipStream_t);
 template int predictor_batch_occupancy<double>(int);
+template hipError_t launch_predictor_order<double>(int, const PredItem *, int64_t, const PredInst *, const double *,
+                                                  double *, double *, const double *, int, hipStream_t);
+template hipError_t launch_predictor_order<float>(int, const PredItem *, int64_t, const PredInst *, const double *,
+                                                 double *, float *, const double *, int, hipStream_t);
 template int predictor_batch_occupancy<float>(int);
 
 }  // namespace adg

@@ -74,12 +74,13 @@ def test_batched_graph_autotune_are_bitwise_neutral():
     # reference: per-instance launches, no graph
     gm.set_options(use_graph=False, batched=False)
     ref, _ = run(gm, u0, steps)
-    # one persistent batched launch, no graph
-    gm.set_options(use_graph=False, batched=True)
-    b, _ = run(gm, u0, steps)
-    assert torch.equal(b, ref)
+    # one persistent launch per order, then one launch for all orders, no graph
+    for mode in (1, 2):
+        gm.set_options(use_graph=False, batched=mode)
+        b, _ = run(gm, u0, steps)
+        assert torch.equal(b, ref), mode
     # graph replays, with eager work and synchronisation between replays
-    gm.set_options(use_graph=True, batched=True)
+    gm.set_options(use_graph=True, batched=1)
     u = torch.from_numpy(u0.copy()).cuda()
     ws = gm.empty_workspace()
     for k in range(steps):
