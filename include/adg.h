@@ -93,6 +93,7 @@ typedef struct {
     int64_t workspace_bytes;  /* device bytes adg_step needs in ws                */
     int64_t n_conforming_faces, n_hanging_faces, n_skeleton_cells;
     int32_t real_bytes;       /* 8 (FP64) or 4 (FP32_MFMA)                        */
+    int64_t adjoint_workspace_bytes;  /* device bytes adg_step_adjoint needs      */
 } adg_info;
 
 typedef struct {
@@ -194,6 +195,42 @@ enum { ADG_PHASE_CFL = 0, ADG_PHASE_PREDICTOR = 1, ADG_PHASE_HANGING = 2, ADG_PH
        ADG_PHASE_CORRECTOR = 4, ADG_NPHASES = 5 };
 adg_status adg_profile(adg_mesh *mesh, int32_t enable);
 adg_status adg_profile_read(adg_mesh *mesh, double *ms, int64_t *launches);
+
+/* Vector-Jacobian product of one step at a FIXED time step size:
+ * ubar_n = (d u_{n+1} / d u_n)^T ubar_np1, where u_{n+1} = corrector(riemann(
+ * predictor(u_n, dt)), dt) with dt_dev[i] held constant (the CFL reduction is
+ * not differentiated).  The transposes run in reverse order: corrector,
+ * Rusanov (the face speed s takes the subgradient of the max at its first
+ * maximiser in (node, minus side first) order; |x|' = 0 at 0), then the
+ * predictor (time averages, volume term and face projections, then the
+ * Picard iterations in reverse, with the forward iterates recomputed and
+ * stored in ws_dev).  FP64 handles with uniform meshes only
+ * (ADG_ERR_UNSUPPORTED otherwise).  ws_dev holds adjoint_workspace_bytes;
+ * ubar_n_dev must not alias ubar_np1_dev. */
+adg_status adg_step_adjoint(adg_mesh *mesh, const double *u_n_dev, const double *dt_dev,
+                            const double *ubar_np1_dev, double *ubar_n_dev, void *ws_dev,
+                            hipStream_t stream);
+
+/* Switch tape of the Rusanov face speed on conforming faces (for checking
+ * derivatives of the piecewise-smooth step).  mode 1 (record): every
+ * following adg_riemann stores, per conforming face, the first maximiser of
+ * |u_d| + c in (node, minus side first) order as 2*node + side into tape_dev;
+ * mode 2 (replay): the face speed is taken at the stored maximiser instead of
+ * the maximum; mode 0: off (tape_dev may be NULL).  tape_dev holds
+ * n_conforming_faces int16 (faces of axis 0, 1, 2 per instance, instances in
+ * order) and must stay valid while the mode is on. */
+adg_status adg_set_switch_tape(adg_mesh *mesh, int16_t *tape_dev, int32_t mode);
+
+/* Point values of the density of a single-instance uniform handle:
+ * out_dev[s] = sum_a rho_{c,a} phi_a0(xi0) phi_a1(xi1) phi_a2(xi2), where c
+ * is the cell containing pts_dev[3s..3s+2] (floor of the cell coordinate,
+ * clamped into the grid, so a point on a face goes to the upper cell).
+ * adg_sample_adjoint ADDS wbar_dev[s] phi_a(x_s) into the density part of
+ * ubar_dev, point by point in order (deterministic). */
+adg_status adg_sample(adg_mesh *mesh, const double *u_dev, const double *pts_dev, int64_t n_pts,
+                      double *out_dev, hipStream_t stream);
+adg_status adg_sample_adjoint(adg_mesh *mesh, const double *pts_dev, const double *wbar_dev, int64_t n_pts,
+                              double *ubar_dev, hipStream_t stream);
 
 /* Synchronises the handle's device work and returns ADG_ERR_NONPHYSICAL if a
  * non-physical state was met since the last call (then clears the latch). */

@@ -60,6 +60,10 @@ def lib():
         L.orc_run.restype = ctypes.c_int
         L.orc_run.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_double,
                               ctypes.c_double, P, ctypes.c_int, P]
+        L.orc_run_sched.restype = ctypes.c_int
+        L.orc_run_sched.argtypes = [P, ctypes.c_double, ctypes.c_int, P, P, ctypes.c_int]
+        L.orc_sample.restype = ctypes.c_int
+        L.orc_sample.argtypes = [P, P, P, ctypes.c_long, P]
         L.orc_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -165,6 +169,28 @@ class Mesh:
         rc = lib().orc_run(self._h, gamma, cfl, int(npic), float(dt_fixed), float(t_end), _p(u),
                            int(nsteps), _p(hist))
         return u, hist[:nsteps], int(rc)
+
+
+def _run_sched(self, u, dt_sched, gamma=1.4, npic=None):
+    """Steps with a prescribed dt per step; returns (u_final, status)."""
+    u = np.array(u, dtype=np.float64, copy=True, order="C")
+    dts = np.ascontiguousarray(dt_sched, dtype=np.float64)
+    npic = self.N if npic is None else npic
+    rc = lib().orc_run_sched(self._h, gamma, int(npic), _p(dts), _p(u), int(dts.shape[0]))
+    return u, int(rc)
+
+
+def _sample(self, u, pts):
+    """Density at points [n, 3] (base-level meshes)."""
+    u = _f64(u)
+    pts = np.ascontiguousarray(pts, dtype=np.float64)
+    out = np.zeros(pts.shape[0])
+    assert lib().orc_sample(self._h, _p(u), _p(pts), pts.shape[0], _p(out)) == 0
+    return out
+
+
+Mesh.run_sched = _run_sched
+Mesh.sample = _sample
 
 
 def num_threads():

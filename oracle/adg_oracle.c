@@ -862,6 +862,57 @@ int orc_run(const orc_mesh *m, double g, double cfl, int npic, double dt_fixed, 
     return rc;
 }
 
+/* Runs nsteps steps with a prescribed dt per step (dt_sched[n]); the CFL
+ * reduction is skipped.  Returns 0, or 1 if an unphysical state was met. */
+int orc_run_sched(const orc_mesh *m, double g, int npic, const double *dt_sched, double *u, int nsteps)
+{
+    int N = m->N, N2 = N * N, N3 = N2 * N;
+    long nc = m->nc;
+    double *us = (double *)malloc(sizeof(double) * NV * nc * N3);
+    double *tr = (double *)malloc(sizeof(double) * 6 * 2 * NV * nc * N2);
+    double *fs = (double *)malloc(sizeof(double) * 6 * NV * nc * N2);
+    if (!us || !tr || !fs) { free(us); free(tr); free(fs); return 2; }
+    int rc = 0;
+    for (int n = 0; n < nsteps; ++n) {
+        orc_predictor(m, g, npic, dt_sched[n], u, us, tr);
+        if (orc_riemann(m, g, tr, fs)) { rc = 1; break; }
+        orc_corrector(m, dt_sched[n], us, fs, u);
+    }
+    free(us); free(tr); free(fs);
+    return rc;
+}
+
+/* Density of the discrete solution at points (base-level meshes only):
+ * rho_h(x) = sum_a rho_{c,a} phi_a0(xi0) phi_a1(xi1) phi_a2(xi2) with c the
+ * cell containing x (floor of the cell coordinate, clamped into the grid). */
+int orc_sample(const orc_mesh *m, const double *u, const double *pts, long n, double *out)
+{
+    if (m->max_level != 0) return 1;
+    int N = m->N, N3 = N * N * N;
+    double xi[MAXN], w[MAXN];
+    orc_gauss_legendre(N, xi, w);
+    for (long s = 0; s < n; ++s) {
+        int ijk[3];
+        double phi[3][MAXN];
+        for (int d = 0; d < 3; ++d) {
+            double y = (pts[3 * s + d] - m->lo[d]) / (m->hi[d] - m->lo[d]) * m->n[d];
+            int i = (int)floor(y);
+            if (i < 0) i = 0;
+            if (i >= m->n[d]) i = m->n[d] - 1;
+            ijk[d] = i;
+            for (int e = 0; e < N; ++e) phi[d][e] = lagrange(N, xi, e, y - i);
+        }
+        long c = ijk[0] + (long)m->n[0] * (ijk[1] + (long)m->n[1] * ijk[2]);
+        double acc = 0.0;
+        for (int a2 = 0; a2 < N; ++a2)
+            for (int a1 = 0; a1 < N; ++a1)
+                for (int a0 = 0; a0 < N; ++a0)
+                    acc += u[c * N3 + a0 + N * a1 + N * N * a2] * phi[0][a0] * phi[1][a1] * phi[2][a2];
+        out[s] = acc;
+    }
+    return 0;
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

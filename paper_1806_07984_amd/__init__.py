@@ -22,7 +22,8 @@ STATUS = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "OOM", 4: "HIP", 5: "N
 EXPORTS = ["adg_init_mesh", "adg_free_mesh", "adg_mesh_info", "adg_instance_info", "adg_mesh_cells",
            "adg_node_coords", "adg_cfl", "adg_predictor", "adg_riemann", "adg_corrector", "adg_step",
            "adg_profile", "adg_profile_read", "adg_get_status", "adg_last_error", "adg_autotune",
-           "adg_tuning", "adg_set_options"]
+           "adg_tuning", "adg_set_options", "adg_step_adjoint", "adg_sample", "adg_sample_adjoint",
+           "adg_set_switch_tape"]
 PHASES = ["cfl", "predictor", "hanging", "riemann", "corrector"]
 
 
@@ -44,7 +45,7 @@ class Info(ctypes.Structure):
                 ("u_elems", ctypes.c_int64), ("trace_elems", ctypes.c_int64), ("fside_elems", ctypes.c_int64),
                 ("workspace_bytes", ctypes.c_int64), ("n_conforming_faces", ctypes.c_int64),
                 ("n_hanging_faces", ctypes.c_int64), ("n_skeleton_cells", ctypes.c_int64),
-                ("real_bytes", ctypes.c_int32)]
+                ("real_bytes", ctypes.c_int32), ("adjoint_workspace_bytes", ctypes.c_int64)]
 
 
 class InstanceGeom(ctypes.Structure):
@@ -82,6 +83,10 @@ def load():
         "adg_autotune": [P, P, P, P],
         "adg_tuning": [P, P],
         "adg_set_options": [P, I32, I32],
+        "adg_step_adjoint": [P, P, P, P, P, P, P],
+        "adg_set_switch_tape": [P, P, I32],
+        "adg_sample": [P, P, P, I64, P, P],
+        "adg_sample_adjoint": [P, P, P, I64, P, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -280,6 +285,43 @@ class Mesh:
         _check(load().adg_profile_read(self._h, ms.ctypes.data_as(ctypes.c_void_p),
                                        cnt.ctypes.data_as(ctypes.c_void_p)))
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(PHASES)}
+
+    def set_switch_tape(self, tape, mode):
+        """mode 0 off, 1 record, 2 replay; tape: int16 tensor of n_conforming_faces."""
+        import torch
+        ptr = ctypes.c_void_p(0) if tape is None else _ptr(tape, torch.int16, self.info["n_conforming_faces"], "tape")
+        _check(load().adg_set_switch_tape(self._h, ptr, int(mode)))
+
+    def empty_adjoint_workspace(self, device="cuda"):
+        import torch
+        return torch.empty(self.info["adjoint_workspace_bytes"], dtype=torch.uint8, device=device)
+
+    def step_adjoint(self, u, dt, ubar_next, ubar, ws, stream=None):
+        """ubar = (d step(u; dt) / du)^T ubar_next at fixed dt (adg_step_adjoint)."""
+        import torch
+        n = self.info["u_elems"]
+        if ws.numel() < self.info["adjoint_workspace_bytes"]:
+            raise ValueError("adjoint workspace too small")
+        _check(load().adg_step_adjoint(self._h, _ptr(u, torch.float64, n, "u"),
+                                       _ptr(dt, torch.float64, self.n_instances, "dt"),
+                                       _ptr(ubar_next, torch.float64, n, "ubar_next"),
+                                       _ptr(ubar, torch.float64, n, "ubar"), ctypes.c_void_p(ws.data_ptr()),
+                                       _stream(stream)))
+
+    def sample(self, u, pts, out, stream=None):
+        """Density at points pts [n, 3] (adg_sample)."""
+        import torch
+        _check(load().adg_sample(self._h, _ptr(u, torch.float64, self.info["u_elems"], "u"),
+                                 _ptr(pts, torch.float64, None, "pts"), pts.shape[0],
+                                 _ptr(out, torch.float64, pts.shape[0], "out"), _stream(stream)))
+
+    def sample_adjoint(self, pts, wbar, ubar, stream=None):
+        """ubar[density] += sum_s wbar[s] phi(x_s) (adg_sample_adjoint)."""
+        import torch
+        _check(load().adg_sample_adjoint(self._h, _ptr(pts, torch.float64, None, "pts"),
+                                         _ptr(wbar, torch.float64, pts.shape[0], "wbar"), pts.shape[0],
+                                         _ptr(ubar, torch.float64, self.info["u_elems"], "ubar"),
+                                         _stream(stream)))
 
     def status(self):
         """Synchronises; raises AdgError(NONPHYSICAL) if a bad state was met."""

@@ -66,6 +66,9 @@ struct adg_mesh {
     int64_t nitems = 0;
     int batch_threads = 0, batch_grid = 0, n_cu = 0;
     bool autotuned = false;
+    // Rusanov switch tape (conforming faces, axis-major per instance)
+    int16_t *tape = nullptr;
+    int tape_mode = 0;
     // captured step (hipGraph) replayed by adg_step
     bool use_graph = true;
     hipStream_t gs_a = nullptr, gs_b = nullptr;
@@ -354,10 +357,15 @@ template <typename T>
 adg_status do_conforming(adg_mesh *m, const T *traces, T *fside, hipStream_t st)
 {
     PhaseTimer tm(m, ADG_PHASE_RIEMANN, st);
+    int64_t toff = 0;
     for (auto &I : m->inst)
-        for (int d = 0; d < 3; ++d)
+        for (int d = 0; d < 3; ++d) {
             ADG_HIP(launch_riemann<T>(I.N, traces + I.tr_off, fside + I.fs_off, I.face_m[d], I.face_p[d], I.nf[d],
-                                      d, I.nc, I.gamma, m->status_dev, st), "riemann");
+                                      d, I.nc, I.gamma, m->status_dev, st, m->tape ? m->tape + toff : nullptr,
+                                      m->tape ? m->tape_mode : 0),
+                    "riemann");
+            toff += I.nf[d];
+        }
     return ADG_OK;
 }
 
@@ -488,7 +496,7 @@ adg_status step_impl(adg_mesh *m, double *u, int32_t n_steps, double *hist, void
                      hipStream_t s_encl)
 {
     if (n_steps == 0) return ADG_OK;
-    if (m->use_graph && !m->prof) return step_graph<T>(m, u, n_steps, hist, ws, s_skel, s_encl);
+    if (m->use_graph && !m->prof && m->tape_mode == 0) return step_graph<T>(m, u, n_steps, hist, ws, s_skel, s_encl);
     return step_eager<T>(m, u, n_steps, hist, ws, s_skel, s_encl);
 }
 
@@ -735,6 +743,14 @@ adg_status adg_init_mesh(const adg_instance_desc *desc, int32_t n_instances, adg
     inf.n_hanging_faces = nhang;
     inf.n_skeleton_cells = nskel;
     inf.real_bytes = rb;
+    {
+        // adjoint workspace: u*, traces, their adjoint, face-flux adjoint (FP64), Picard iterates
+        int64_t iters = 0;
+        for (auto &I : m->inst) iters += int64_t(I.npic) * I.N * NV * I.nc * I.N * I.N * I.N;
+        inf.adjoint_workspace_bytes =
+            int64_t(align_up(sizeof(double) * u_off) + 2 * align_up(sizeof(double) * tr_off) +
+                    align_up(sizeof(double) * fs_off) + align_up(sizeof(double) * std::max<int64_t>(iters, 1)));
+    }
     *out = m;
     return ADG_OK;
 }
@@ -943,6 +959,106 @@ adg_status adg_profile_read(adg_mesh *mesh, double *ms, int64_t *launches)
         ms[r.phase] += double(t);
         launches[r.phase] += 1;
     }
+    return ADG_OK;
+}
+
+adg_status adg_set_switch_tape(adg_mesh *mesh, int16_t *tape, int32_t mode)
+{
+    if (!valid_mesh(mesh) || mode < 0 || mode > 2 || (mode != 0 && !tape)) {
+        set_error("adg_set_switch_tape: bad argument");
+        return ADG_ERR_INVALID_ARG;
+    }
+    mesh->tape = mode ? tape : nullptr;
+    mesh->tape_mode = mode;
+    drop_graph(mesh);
+    return ADG_OK;
+}
+
+adg_status adg_step_adjoint(adg_mesh *mesh, const double *u, const double *dt, const double *ubar_next,
+                            double *ubar, void *ws, hipStream_t stream)
+{
+    if (!valid_mesh(mesh) || !u || !dt || !ubar_next || !ubar || !ws) {
+        set_error("adg_step_adjoint: null argument");
+        return ADG_ERR_INVALID_ARG;
+    }
+    if (ubar == ubar_next) {
+        set_error("adg_step_adjoint: ubar_n must not alias ubar_np1");
+        return ADG_ERR_INVALID_ARG;
+    }
+    if (mesh->prec != ADG_FP64) {
+        set_error("adg_step_adjoint: needs an FP64 handle");
+        return ADG_ERR_UNSUPPORTED;
+    }
+    for (const auto &I : mesh->inst)
+        if (I.hm.max_level > 0) {
+            set_error("adg_step_adjoint: adaptive meshes are not supported");
+            return ADG_ERR_UNSUPPORTED;
+        }
+    char *w = static_cast<char *>(ws);
+    double *ustar = reinterpret_cast<double *>(w);
+    w += align_up(sizeof(double) * mesh->info.u_elems);
+    double *traces = reinterpret_cast<double *>(w);
+    w += align_up(sizeof(double) * mesh->info.trace_elems);
+    double *tbar = reinterpret_cast<double *>(w);
+    w += align_up(sizeof(double) * mesh->info.trace_elems);
+    double *fbar = reinterpret_cast<double *>(w);
+    w += align_up(sizeof(double) * mesh->info.fside_elems);
+    double *iters = reinterpret_cast<double *>(w);
+    for (size_t i = 0; i < mesh->inst.size(); ++i) {
+        Instance &I = mesh->inst[i];
+        const int32_t *fm[3] = {I.face_m[0], I.face_m[1], I.face_m[2]};
+        const int32_t *fp[3] = {I.face_p[0], I.face_p[1], I.face_p[2]};
+        ADG_HIP(launch_adjoint_step(I.N, u + I.u_off, dt + i, ubar_next + I.u_off, ubar + I.u_off, ustar + I.u_off,
+                                    traces + I.tr_off, tbar + I.tr_off, fbar + I.fs_off, iters, fm, fp, I.nf, I.nc,
+                                    I.geo, I.gamma, I.npic, stream),
+                "adjoint step");
+        iters += int64_t(I.npic) * I.N * NV * I.nc * I.N * I.N * I.N;
+    }
+    return ADG_OK;
+}
+
+static adg_status sample_geo(adg_mesh *mesh, SampleGeo &sg)
+{
+    if (mesh->inst.size() != 1 || mesh->inst[0].hm.max_level > 0) {
+        set_error("point sampling needs a single-instance uniform handle");
+        return ADG_ERR_UNSUPPORTED;
+    }
+    const Instance &I = mesh->inst[0];
+    for (int d = 0; d < 3; ++d) {
+        sg.n[d] = I.hm.n[d];
+        sg.lo[d] = I.hm.lo[d];
+        sg.inv_h[d] = I.geo.inv_dx[0][d];
+    }
+    return ADG_OK;
+}
+
+adg_status adg_sample(adg_mesh *mesh, const double *u, const double *pts, int64_t n_pts, double *out,
+                      hipStream_t stream)
+{
+    if (!valid_mesh(mesh) || !u || (n_pts > 0 && (!pts || !out)) || n_pts < 0) {
+        set_error("adg_sample: bad argument");
+        return ADG_ERR_INVALID_ARG;
+    }
+    SampleGeo sg;
+    adg_status st = sample_geo(mesh, sg);
+    if (st != ADG_OK) return st;
+    const Instance &I = mesh->inst[0];
+    ADG_HIP(launch_sample(I.N, u, I.nc, sg, pts, n_pts, out, stream), "sample");
+    return ADG_OK;
+}
+
+adg_status adg_sample_adjoint(adg_mesh *mesh, const double *pts, const double *wbar, int64_t n_pts, double *ubar,
+                              hipStream_t stream)
+{
+    if (!valid_mesh(mesh) || !ubar || (n_pts > 0 && (!pts || !wbar)) || n_pts < 0) {
+        set_error("adg_sample_adjoint: bad argument");
+        return ADG_ERR_INVALID_ARG;
+    }
+    SampleGeo sg;
+    adg_status st = sample_geo(mesh, sg);
+    if (st != ADG_OK) return st;
+    const Instance &I = mesh->inst[0];
+    ADG_HIP(launch_sample_adjoint(I.N, pts, wbar, n_pts, sg, ubar, stream), "sample adjoint");
     return ADG_OK;
 }
 

@@ -56,10 +56,14 @@ hipError_t launch_predictor_order(int code, const PredItem *items, int64_t nitem
 template <typename T>
 hipError_t launch_predictor(int N, const double *u, double *ustar, T *traces, const int32_t *list,
                             int64_t nlist, int64_t nc, const int8_t *level, const Geo &geo,
-                            const double *dt, double gamma, int npic, hipStream_t st);
+                            const double *dt, double gamma, int npic, hipStream_t st, T *iters = nullptr);
+// Rusanov switch tape: TAPE_RECORD stores each face's maximiser (2 node +
+// side) of the wave speed, TAPE_REPLAY uses the stored one instead of the max.
+enum { TAPE_OFF = 0, TAPE_RECORD = 1, TAPE_REPLAY = 2 };
 template <typename T>
 hipError_t launch_riemann(int N, const T *traces, T *fside, const int32_t *fm, const int32_t *fp,
-                          int64_t nf, int d, int64_t nc, double gamma, int *status, hipStream_t st);
+                          int64_t nf, int d, int64_t nc, double gamma, int *status, hipStream_t st,
+                          int16_t *tape = nullptr, int tape_mode = TAPE_OFF);
 template <typename T>
 hipError_t launch_hang(int N, const T *traces, T *fside, const HangDev *hang, int64_t nh, int64_t nc,
                        const double *ptab, double gamma, int *status, hipStream_t st);
@@ -76,6 +80,22 @@ int cfl_blocks(int N, int64_t nc);
 hipError_t launch_cfl(int N, const double *u, int64_t nc, const int8_t *level, const Geo &geo, double gamma,
                       double factor, double *partial, int *status, double *dt_out, double *hist,
                       hipStream_t st);
+// Geometry of a uniform mesh for point location.
+struct SampleGeo {
+    int n[3];
+    double lo[3], inv_h[3];
+};
+
+// One adjoint step (FP64, uniform mesh): recomputes the predictor storing its
+// iterates, then applies the transposed corrector, Riemann and predictor.
+hipError_t launch_adjoint_step(int N, const double *u, const double *dt, const double *ubar_next, double *ubar,
+                               double *ustar, double *traces, double *tbar, double *fbar, double *iters,
+                               const int32_t *const fm[3], const int32_t *const fp[3], const int64_t nf[3],
+                               int64_t nc, const Geo &geo, double gamma, int npic, hipStream_t st);
+hipError_t launch_sample(int N, const double *u, int64_t nc, const SampleGeo &sg, const double *pts, int64_t npts,
+                         double *out, hipStream_t st);
+hipError_t launch_sample_adjoint(int N, const double *pts, const double *wbar, int64_t npts, const SampleGeo &sg,
+                                 double *ubar, hipStream_t st);
 hipError_t launch_node_coords(int N, double *xyz, const int32_t *ijk, const int8_t *level, int64_t nc,
                               const Geo &geo, const double *lo, hipStream_t st);
 

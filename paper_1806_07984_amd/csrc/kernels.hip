@@ -97,7 +97,8 @@ __device__ __forceinline__ void predictor_body(T *__restrict__ lds, const double
                                                double *__restrict__ ustar, T *__restrict__ traces,
                                                const int32_t *__restrict__ list, int64_t nlist, int64_t nc,
                                                const int8_t *__restrict__ level, const Geo &geo, double dt,
-                                               double gamma, int npic, int64_t first)
+                                               double gamma, int npic, int64_t first,
+                                               T *__restrict__ iters = nullptr)
 {
     constexpr int N2 = N * N, N3 = N2 * N, NT = CPB * N3;
     const DevBasis &B = c_basis[N];
@@ -179,6 +180,14 @@ __device__ __forceinline__ void predictor_body(T *__restrict__ lds, const double
         for (int l = 0; l < N; ++l)
 #pragma unroll
             for (int v = 0; v < NV; ++v) q[l][v] = uu[v] - acc[l][v];
+        if (iters && active) {
+            // iterate it+1, kept for the adjoint: [slot][l][v][cell][N^3]
+#pragma unroll
+            for (int l = 0; l < N; ++l)
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+                    iters[(((int64_t(it) * N + l) * NV + v) * nc + c) * N3 + a] = q[l][v];
+        }
     }
 
     // time averages of the state and of the fluxes of the final iterate
@@ -261,11 +270,11 @@ __global__ void __launch_bounds__(round64(CPB * N * N * N))
 k_predictor(const double *__restrict__ u, double *__restrict__ ustar, T *__restrict__ traces,
             const int32_t *__restrict__ list, int64_t nlist, int64_t nc,
             const int8_t *__restrict__ level, Geo geo, const double *__restrict__ dt_dev,
-            double gamma, int npic)
+            double gamma, int npic, T *__restrict__ iters)
 {
     __shared__ T lds[CPB * 15 * N * N * N];
     predictor_body<T, N, CPB>(lds, u, ustar, traces, list, nlist, nc, level, geo, dt_dev[0], gamma, npic,
-                              int64_t(blockIdx.x) * CPB);
+                              int64_t(blockIdx.x) * CPB, iters);
 }
 
 // One variant of the batched predictor on one work item.
@@ -344,10 +353,10 @@ template <typename T, int N>
 __global__ void __launch_bounds__(FaceCfg<N>::THREADS)
 k_riemann(const T *__restrict__ traces, T *__restrict__ fside, const int32_t *__restrict__ fm,
           const int32_t *__restrict__ fp, int64_t nf, int d, int64_t nc, double gamma,
-          int *__restrict__ status)
+          int *__restrict__ status, int16_t *__restrict__ tape, int tape_mode)
 {
     constexpr int N2 = N * N, FPB = FaceCfg<N>::FPB;
-    __shared__ T smax[FPB * N2];
+    __shared__ T slam[FPB * N2 * 2];
     const int tid = threadIdx.x;
     const int fl = tid / N2, b = tid % N2;
     const int64_t f = int64_t(blockIdx.x) * FPB + fl;
@@ -357,7 +366,7 @@ k_riemann(const T *__restrict__ traces, T *__restrict__ fside, const int32_t *__
     const int sL = 2 * d + 1, sR = 2 * d;
     T QL[NV], FL[NV], QR[NV], FR[NV];
     int64_t cL = 0, cR = 0;
-    T lam = T(0);
+    T lL = T(0), lR = T(0);
     if (active) {
         cL = fm[f];
         cR = fp[f];
@@ -369,16 +378,33 @@ k_riemann(const T *__restrict__ traces, T *__restrict__ fside, const int32_t *__
             FR[v] = traces[((int64_t(sR * 2 + 1) * NV + v) * nc + cR) * N2 + b];
         }
         bool badL, badR;
-        const T lL = wave_speed(g, gm1, QL, d, badL);
-        const T lR = wave_speed(g, gm1, QR, d, badR);
-        lam = fmax(lL, lR);
+        lL = wave_speed(g, gm1, QL, d, badL);
+        lR = wave_speed(g, gm1, QR, d, badR);
         if (badL || badR) *status = 1;
     }
-    if (lane_ok) smax[tid] = lam;
+    if (lane_ok) {
+        slam[2 * tid] = lL;
+        slam[2 * tid + 1] = lR;
+    }
     __syncthreads();
     if (!active) return;
-    T s = T(0);
-    for (int k = 0; k < N2; ++k) s = fmax(s, smax[fl * N2 + k]);
+    // s = the largest speed over (node, side); its first maximiser in
+    // (node, minus side first) order can be recorded or replayed
+    T s;
+    if (tape_mode == TAPE_REPLAY) {
+        s = slam[2 * fl * N2 + tape[f]];
+    } else {
+        s = T(-1);
+        int arg = 0;
+        for (int k = 0; k < 2 * N2; ++k) {
+            const T x = slam[2 * fl * N2 + k];
+            if (x > s) {
+                s = x;
+                arg = k;
+            }
+        }
+        if (tape_mode == TAPE_RECORD && b == 0) tape[f] = int16_t(arg);
+    }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         const T F = T(0.5) * (FL[v] + FR[v]) - T(0.5) * s * (QR[v] - QL[v]);
@@ -627,6 +653,371 @@ k_node_coords(double *__restrict__ xyz, const int32_t *__restrict__ ijk, const i
         xyz[(int64_t(d) * nc + c) * N3 + a] = lo[d] + (double(ijk[3 * c + d]) + B.xi[aa[d]]) / geo.inv_dx[lev][d];
 }
 
+
+// ---------------------------------------------------------------------------
+// Discrete adjoint of one step at a fixed time step size (FP64, uniform
+// meshes).  Forward: u* = u + V(Fbar(q)), traces = E(qbar, Fbar), F* =
+// Rusanov(traces), u_next = u* - C(F*).  The kernels apply the transposes in
+// reverse order: k_corrector_adj, k_riemann_adj, k_predictor_adj.
+// ---------------------------------------------------------------------------
+
+// qbar += (df_d/dq)^T fbar for the Euler flux along d at state q.
+__device__ __forceinline__ void flux_vjp(double gm1, const double q[NV], int d, const double fb[NV], double qb[NV])
+{
+    const double inv = 1.0 / q[0];
+    const double v[3] = {q[1] * inv, q[2] * inv, q[3] * inv};
+    const double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    const double p = gm1 * (q[4] - 0.5 * q[0] * v2);
+    const double H = (q[4] + p) * inv;  // (E + p)/rho
+    // partials of p
+    const double dp_r = gm1 * 0.5 * v2;
+    const double dp_m[3] = {-gm1 * v[0], -gm1 * v[1], -gm1 * v[2]};
+    const double dp_E = gm1;
+    const double vd = v[d];
+    // f0 = m_d
+    qb[1 + d] += fb[0];
+    // f_k = m_d m_k / rho + delta_kd p
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double g = fb[1 + k];
+        qb[0] += g * (-vd * v[k] + (k == d ? dp_r : 0.0));
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            double dm = (j == d ? v[k] : 0.0) + (j == k ? vd : 0.0) + (k == d ? dp_m[j] : 0.0);
+            qb[1 + j] += g * dm;
+        }
+        if (k == d) qb[4] += g * dp_E;
+    }
+    // f4 = m_d (E + p) / rho
+    const double g4 = fb[4];
+    qb[0] += g4 * (-vd * H + vd * dp_r);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) qb[1 + j] += g4 * ((j == d ? H : 0.0) + vd * dp_m[j]);
+    qb[4] += g4 * vd * (1.0 + dp_E);
+}
+
+// qbar += sbar * d(|u_d| + c)/dq  (abs'(0) = 0)
+__device__ __forceinline__ void speed_vjp(double gamma, const double q[NV], int d, double sbar, double qb[NV])
+{
+    const double gm1 = gamma - 1.0;
+    const double inv = 1.0 / q[0];
+    const double v[3] = {q[1] * inv, q[2] * inv, q[3] * inv};
+    const double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    const double p = gm1 * (q[4] - 0.5 * q[0] * v2);
+    const double c = sqrt(gamma * p * inv);
+    const double sg = v[d] > 0.0 ? 1.0 : (v[d] < 0.0 ? -1.0 : 0.0);
+    // |v_d|
+    qb[0] += sbar * (-sg * v[d] * inv);
+    qb[1 + d] += sbar * sg * inv;
+    // c = sqrt(gamma p / rho): dc = gamma/(2 c rho) (dp - p/rho drho)
+    const double k = gamma / (2.0 * c * q[0]);
+    qb[0] += sbar * k * (gm1 * 0.5 * v2 - p * inv);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) qb[1 + j] += sbar * k * (-gm1 * v[j]);
+    qb[4] += sbar * k * gm1;
+}
+
+// fbar of every cell side from the corrector: u_next = u* - sum_d s_d(a)
+// [R_{a_d} F_{d+}(b) - L_{a_d} F_{d-}(b)], s_d(a) = dt/dx_d/w_{a_d}.
+template <int N>
+__global__ void __launch_bounds__(256)
+k_corrector_adj(const double *__restrict__ ubar, double *__restrict__ fbar, const double *__restrict__ dt_dev,
+                int64_t nc, Geo geo)
+{
+    constexpr int N2 = N * N, N3 = N2 * N;
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= 6 * NV * nc * N2) return;
+    const int b = int(t % N2);
+    const int64_t c = (t / N2) % nc;
+    const int sv = int(t / (N2 * nc));
+    const int s = sv / NV, v = sv % NV, d = s >> 1;
+    const DevBasis &B = c_basis[N];
+    const double sc = dt_dev[0] * geo.inv_dx[0][d];
+    const double *E = (s & 1) ? B.R : B.L;
+    const double sign = (s & 1) ? -1.0 : 1.0;
+    double acc = 0.0;
+#pragma unroll
+    for (int e = 0; e < N; ++e)
+        acc += B.winv[e] * E[e] * ubar[(int64_t(v) * nc + c) * N3 + node_from_face<N>(d, e, b)];
+    fbar[t] = sign * sc * acc;
+}
+
+// Transpose of the Rusanov solve on the conforming faces of one axis: writes
+// the adjoint of both cells' face projections (state and normal flux).
+template <int N>
+__global__ void __launch_bounds__(FaceCfg<N>::THREADS)
+k_riemann_adj(const double *__restrict__ traces, const double *__restrict__ fbar, double *__restrict__ tbar,
+              const int32_t *__restrict__ fm, const int32_t *__restrict__ fp, int64_t nf, int d, int64_t nc,
+              double gamma)
+{
+    constexpr int N2 = N * N, FPB = FaceCfg<N>::FPB;
+    __shared__ double lam[FPB * N2 * 2];
+    __shared__ double part[FPB * N2];
+    const int tid = threadIdx.x;
+    const int fl = tid / N2, b = tid % N2;
+    const int64_t f = int64_t(blockIdx.x) * FPB + fl;
+    const bool lane_ok = tid < FPB * N2;
+    const bool active = lane_ok && f < nf;
+    const double gm1 = gamma - 1.0;
+    const int sL = 2 * d + 1, sR = 2 * d;
+    double QL[NV], FL[NV], QR[NV], FR[NV], Fb[NV];
+    int64_t cL = 0, cR = 0;
+    double lL = 0.0, lR = 0.0, sb = 0.0;
+    bool dummy;
+    if (active) {
+        cL = fm[f];
+        cR = fp[f];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            QL[v] = traces[((int64_t(sL * 2 + 0) * NV + v) * nc + cL) * N2 + b];
+            FL[v] = traces[((int64_t(sL * 2 + 1) * NV + v) * nc + cL) * N2 + b];
+            QR[v] = traces[((int64_t(sR * 2 + 0) * NV + v) * nc + cR) * N2 + b];
+            FR[v] = traces[((int64_t(sR * 2 + 1) * NV + v) * nc + cR) * N2 + b];
+            Fb[v] = fbar[(int64_t(sL * NV + v) * nc + cL) * N2 + b] + fbar[(int64_t(sR * NV + v) * nc + cR) * N2 + b];
+            sb += -0.5 * (QR[v] - QL[v]) * Fb[v];
+        }
+        lL = wave_speed(gamma, gm1, QL, d, dummy);
+        lR = wave_speed(gamma, gm1, QR, d, dummy);
+    }
+    if (lane_ok) {
+        lam[2 * tid] = lL;
+        lam[2 * tid + 1] = lR;
+        part[tid] = sb;
+    }
+    __syncthreads();
+    if (!active) return;
+    // s and its (lowest-index) argmax over (node, side), and sbar of the face
+    double s = -1.0, sbar = 0.0;
+    int arg = 0;
+    for (int k = 0; k < 2 * N2; ++k) {
+        const double x = lam[2 * fl * N2 + k];
+        if (x > s) {
+            s = x;
+            arg = k;
+        }
+    }
+    for (int k = 0; k < N2; ++k) sbar += part[fl * N2 + k];
+    double QLb[NV], QRb[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        QLb[v] = 0.5 * s * Fb[v];
+        QRb[v] = -0.5 * s * Fb[v];
+    }
+    if (arg / 2 == b) {
+        if (arg % 2 == 0) speed_vjp(gamma, QL, d, sbar, QLb);
+        else speed_vjp(gamma, QR, d, sbar, QRb);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        tbar[((int64_t(sL * 2 + 0) * NV + v) * nc + cL) * N2 + b] = QLb[v];
+        tbar[((int64_t(sL * 2 + 1) * NV + v) * nc + cL) * N2 + b] = 0.5 * Fb[v];
+        tbar[((int64_t(sR * 2 + 0) * NV + v) * nc + cR) * N2 + b] = QRb[v];
+        tbar[((int64_t(sR * 2 + 1) * NV + v) * nc + cR) * N2 + b] = 0.5 * Fb[v];
+    }
+}
+
+// Transpose of the predictor (Picard iterations, time averages, volume term,
+// face projections).  One lane per node as in the forward kernel; iterates
+// come from the forward run (iters, slots 0..npic-1 = iterates 1..npic).
+template <int N, int CPB>
+__global__ void __launch_bounds__(round64(CPB * N * N * N))
+k_predictor_adj(const double *__restrict__ u, const double *__restrict__ iters, const double *__restrict__ ubar_next,
+                const double *__restrict__ tbar, const double *__restrict__ dt_dev, double *__restrict__ ubar,
+                int64_t nc, Geo geo, double gamma, int npic)
+{
+    constexpr int N2 = N * N, N3 = N2 * N, NT = CPB * N3;
+    __shared__ double lds[CPB * NV * N3];
+    const DevBasis &B = c_basis[N];
+    const int tid = threadIdx.x;
+    const int cl = tid / N3, a = tid % N3;
+    const int64_t c = int64_t(blockIdx.x) * CPB + cl;
+    const bool lane_ok = tid < NT;
+    const bool active = lane_ok && c < nc;
+    const int aa[3] = {a % N, (a / N) % N, a / N2};
+    const int bf[3] = {aa[1] + N * aa[2], aa[0] + N * aa[2], aa[0] + N * aa[1]};
+    const double dt = dt_dev[0];
+    const double cd[3] = {dt * geo.inv_dx[0][0], dt * geo.inv_dx[0][1], dt * geo.inv_dx[0][2]};
+    const double gm1 = gamma - 1.0;
+    double *my = lds + (lane_ok ? cl : 0) * NV * N3;
+    auto node_with = [&](int d, int k) {
+        return d == 0 ? k + N * aa[1] + N2 * aa[2] : (d == 1 ? aa[0] + N * k + N2 * aa[2] : aa[0] + N * aa[1] + N2 * k);
+    };
+    auto load_q = [&](int r, int j, double q[NV]) {  // iterate r (0 = u) at time node j
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            q[v] = !active ? (v == 0 ? 1.0 : (v == 4 ? 2.5 : 0.0))
+                 : (r == 0 ? u[(int64_t(v) * nc + c) * N3 + a]
+                           : iters[(((int64_t(r - 1) * N + j) * NV + v) * nc + c) * N3 + a]);
+    };
+
+    // adjoint of u* (identity part and the volume term)
+    double ub[NV], acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        ub[v] = active ? ubar_next[(int64_t(v) * nc + c) * N3 + a] : 0.0;
+        acc[v] = ub[v];
+    }
+    if (lane_ok)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) my[v * N3 + a] = ub[v];
+    __syncthreads();
+    double Fbb[3][NV], qbb[NV];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double sacc = 0.0;
+#pragma unroll
+            for (int k = 0; k < N; ++k) sacc += B.winv[k] * B.Kw[k * N + aa[d]] * my[v * N3 + node_with(d, k)];
+            Fbb[d][v] = cd[d] * sacc;
+        }
+    // adjoint of the face projections
+#pragma unroll
+    for (int v = 0; v < NV; ++v) qbb[v] = 0.0;
+    if (active) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int sm = 2 * d, sp = 2 * d + 1;
+            const double Lk = B.L[aa[d]], Rk = B.R[aa[d]];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                qbb[v] += Lk * tbar[((int64_t(sm * 2 + 0) * NV + v) * nc + c) * N2 + bf[d]] +
+                          Rk * tbar[((int64_t(sp * 2 + 0) * NV + v) * nc + c) * N2 + bf[d]];
+                Fbb[d][v] += Lk * tbar[((int64_t(sm * 2 + 1) * NV + v) * nc + c) * N2 + bf[d]] +
+                             Rk * tbar[((int64_t(sp * 2 + 1) * NV + v) * nc + c) * N2 + bf[d]];
+            }
+        }
+    }
+    // adjoint of the time averages of the final iterate
+    double qbar[N][NV];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        double q[NV];
+        load_q(npic, j, q);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) qbar[j][v] = B.w[j] * qbb[v];
+        double fbw[NV];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) fbw[v] = B.w[j] * Fbb[d][v];
+            flux_vjp(gm1, q, d, fbw, qbar[j]);
+        }
+    }
+    // Picard iterations in reverse: q^(r) = u - sum_j KW[l][j] G_j(q^(r-1))
+    for (int r = npic; r >= 1; --r) {
+        double Gb[N][NV];
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                double sacc = 0.0;
+#pragma unroll
+                for (int l = 0; l < N; ++l) sacc += B.KW[l * N + j] * qbar[l][v];
+                Gb[j][v] = -sacc;
+            }
+#pragma unroll
+        for (int l = 0; l < N; ++l)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[v] += qbar[l][v];
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            __syncthreads();
+            if (lane_ok)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) my[v * N3 + a] = Gb[j][v];
+            __syncthreads();
+            double q[NV];
+            load_q(r - 1, j, q);
+            double nb[NV] = {0, 0, 0, 0, 0};
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                double fb[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    double sacc = 0.0;
+#pragma unroll
+                    for (int k = 0; k < N; ++k) sacc += B.D[k * N + aa[d]] * my[v * N3 + node_with(d, k)];
+                    fb[v] = cd[d] * sacc;
+                }
+                flux_vjp(gm1, q, d, fb, nb);
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) qbar[j][v] = nb[v];
+        }
+    }
+    // q^(0) = u at every time node
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] += qbar[j][v];
+    if (active)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) ubar[(int64_t(v) * nc + c) * N3 + a] = acc[v];
+}
+
+// ---------------------------------------------------------------------------
+// Point sampling of the density and its adjoint (uniform meshes)
+// ---------------------------------------------------------------------------
+
+template <int N>
+__device__ __forceinline__ void locate(const double *x, const int *n, const double *lo, const double *inv_h,
+                                       int64_t &cell, double phi[3][N])
+{
+    const DevBasis &B = c_basis[N];
+    int ijk[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double y = (x[d] - lo[d]) * inv_h[d];
+        int i = int(floor(y));
+        i = i < 0 ? 0 : (i >= n[d] ? n[d] - 1 : i);
+        ijk[d] = i;
+        const double xi = y - i;
+#pragma unroll
+        for (int e = 0; e < N; ++e) {
+            double p = 1.0;
+#pragma unroll
+            for (int m = 0; m < N; ++m)
+                if (m != e) p *= (xi - B.xi[m]) / (B.xi[e] - B.xi[m]);
+            phi[d][e] = p;
+        }
+    }
+    cell = ijk[0] + int64_t(n[0]) * (ijk[1] + int64_t(n[1]) * ijk[2]);
+}
+
+template <int N>
+__global__ void __launch_bounds__(256)
+k_sample(const double *__restrict__ u, int64_t nc, SampleGeo sg, const double *__restrict__ pts, int64_t npts,
+         double *__restrict__ out)
+{
+    constexpr int N3 = N * N * N;
+    const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s >= npts) return;
+    int64_t cell;
+    double phi[3][N];
+    locate<N>(pts + 3 * s, sg.n, sg.lo, sg.inv_h, cell, phi);
+    double acc = 0.0;
+    for (int a = 0; a < N3; ++a) acc += u[cell * N3 + a] * phi[0][a % N] * phi[1][(a / N) % N] * phi[2][a / (N * N)];
+    out[s] = acc;
+}
+
+// ubar_rho[cell(s)][a] += wbar[s] phi_a(x_s), points in order (deterministic)
+template <int N>
+__global__ void __launch_bounds__(round64(N * N * N))
+k_sample_adj(const double *__restrict__ pts, const double *__restrict__ wbar, int64_t npts, SampleGeo sg,
+             double *__restrict__ ubar)
+{
+    constexpr int N3 = N * N * N;
+    const int a = threadIdx.x;
+    if (a >= N3) return;
+    for (int64_t s = 0; s < npts; ++s) {
+        int64_t cell;
+        double phi[3][N];
+        locate<N>(pts + 3 * s, sg.n, sg.lo, sg.inv_h, cell, phi);
+        ubar[cell * N3 + a] += wbar[s] * phi[0][a % N] * phi[1][(a / N) % N] * phi[2][a / (N * N)];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
@@ -651,28 +1042,29 @@ hipError_t upload_basis(const DevBasis *tab)
 template <typename T>
 hipError_t launch_predictor(int N, const double *u, double *ustar, T *traces, const int32_t *list,
                             int64_t nlist, int64_t nc, const int8_t *level, const Geo &geo,
-                            const double *dt, double gamma, int npic, hipStream_t st)
+                            const double *dt, double gamma, int npic, hipStream_t st, T *iters)
 {
     if (nlist <= 0) return hipSuccess;
     ADG_DISPATCH_N(N, {
         constexpr int CPB = PredCfg<NN>::CPB;
         const int64_t blocks = (nlist + CPB - 1) / CPB;
         hipLaunchKernelGGL((k_predictor<T, NN, CPB>), dim3(unsigned(blocks)), dim3(round64(CPB * NN * NN * NN)), 0,
-                           st, u, ustar, traces, list, nlist, nc, level, geo, dt, gamma, npic);
+                           st, u, ustar, traces, list, nlist, nc, level, geo, dt, gamma, npic, iters);
     });
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_riemann(int N, const T *traces, T *fside, const int32_t *fm, const int32_t *fp,
-                          int64_t nf, int d, int64_t nc, double gamma, int *status, hipStream_t st)
+                          int64_t nf, int d, int64_t nc, double gamma, int *status, hipStream_t st,
+                          int16_t *tape, int tape_mode)
 {
     if (nf <= 0) return hipSuccess;
     ADG_DISPATCH_N(N, {
         constexpr int FPB = FaceCfg<NN>::FPB;
         const int64_t blocks = (nf + FPB - 1) / FPB;
         hipLaunchKernelGGL((k_riemann<T, NN>), dim3(unsigned(blocks)), dim3(FaceCfg<NN>::THREADS), 0, st,
-                           traces, fside, fm, fp, nf, d, nc, gamma, status);
+                           traces, fside, fm, fp, nf, d, nc, gamma, status, tape, tape_mode);
     });
     return hipGetLastError();
 }
@@ -824,12 +1216,62 @@ hipError_t launch_node_coords(int N, double *xyz, const int32_t *ijk, const int8
     return hipGetLastError();
 }
 
+
+hipError_t launch_adjoint_step(int N, const double *u, const double *dt, const double *ubar_next, double *ubar,
+                               double *ustar, double *traces, double *tbar, double *fbar, double *iters,
+                               const int32_t *const fm[3], const int32_t *const fp[3], const int64_t nf[3],
+                               int64_t nc, const Geo &geo, double gamma, int npic, hipStream_t st)
+{
+    hipError_t e = launch_predictor<double>(N, u, ustar, traces, nullptr, nc, nc, nullptr, geo, dt, gamma, npic, st,
+                                            iters);
+    if (e != hipSuccess) return e;
+    ADG_DISPATCH_N(N, {
+        constexpr int N2 = NN * NN;
+        const int64_t items = 6 * int64_t(NV) * nc * N2;
+        hipLaunchKernelGGL((k_corrector_adj<NN>), dim3(unsigned((items + 255) / 256)), dim3(256), 0, st, ubar_next,
+                           fbar, dt, nc, geo);
+        for (int d = 0; d < 3; ++d) {
+            if (nf[d] <= 0) continue;
+            constexpr int FPB = FaceCfg<NN>::FPB;
+            hipLaunchKernelGGL((k_riemann_adj<NN>), dim3(unsigned((nf[d] + FPB - 1) / FPB)), dim3(FaceCfg<NN>::THREADS),
+                               0, st, traces, fbar, tbar, fm[d], fp[d], nf[d], d, nc, gamma);
+        }
+        constexpr int CPB = PredCfg<NN>::CPB;
+        hipLaunchKernelGGL((k_predictor_adj<NN, CPB>), dim3(unsigned((nc + CPB - 1) / CPB)),
+                           dim3(round64(CPB * NN * NN * NN)), 0, st, u, iters, ubar_next, tbar, dt, ubar, nc, geo,
+                           gamma, npic);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_sample(int N, const double *u, int64_t nc, const SampleGeo &sg, const double *pts, int64_t npts,
+                         double *out, hipStream_t st)
+{
+    if (npts <= 0) return hipSuccess;
+    ADG_DISPATCH_N(N, {
+        hipLaunchKernelGGL((k_sample<NN>), dim3(unsigned((npts + 255) / 256)), dim3(256), 0, st, u, nc, sg, pts, npts,
+                           out);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_sample_adjoint(int N, const double *pts, const double *wbar, int64_t npts, const SampleGeo &sg,
+                                 double *ubar, hipStream_t st)
+{
+    if (npts <= 0) return hipSuccess;
+    ADG_DISPATCH_N(N, {
+        hipLaunchKernelGGL((k_sample_adj<NN>), dim3(1), dim3(round64(NN * NN * NN)), 0, st, pts, wbar, npts, sg,
+                           ubar);
+    });
+    return hipGetLastError();
+}
+
 #define ADG_INSTANTIATE(T)                                                                              \
     template hipError_t launch_predictor<T>(int, const double *, double *, T *, const int32_t *, int64_t,  \
                                             int64_t, const int8_t *, const Geo &, const double *, double, \
-                                            int, hipStream_t);                                           \
+                                            int, hipStream_t, T *);                                      \
     template hipError_t launch_riemann<T>(int, const T *, T *, const int32_t *, const int32_t *, int64_t, \
-                                          int, int64_t, double, int *, hipStream_t);                     \
+                                          int, int64_t, double, int *, hipStream_t, int16_t *, int);     \
     template hipError_t launch_hang<T>(int, const T *, T *, const HangDev *, int64_t, int64_t,           \
                                        const double *, double, int *, hipStream_t);                      \
     template hipError_t launch_restrict<T>(int, T *, const HangDev *, const int32_t *, const int8_t *,   \

@@ -1,0 +1,195 @@
+"""Hand-written adjoint of the ADER-DG step (adg_step_adjoint), the point
+sampling and its transpose, and the checkpointed differentiable rollout.
+
+The Rusanov face speed is a maximum, so the step is only piecewise smooth: a
+finite-difference interval that crosses a switch of the maximiser measures the
+average of two one-sided slopes, not a derivative (in smooth regions the two
+sides' projections at the maximising node differ only by the scheme's jump, so
+at 27^3 x 20 steps almost every interval crosses some switch).  As the time
+step is frozen for differentiation, the GPU finite differences therefore also
+freeze the maximiser of every face and step to the one of the unperturbed run
+(adg_set_switch_tape: record, then replay), and differentiate exactly the
+branch the adjoint differentiates.  The plain finite differences of the
+non-smooth map are reported beside them.  The oracle has no such switch, so its
+differences use a small step taken at two sizes (eps, eps/4).  A direction
+whose two values disagree crossed a switch and is excluded, and at most a
+quarter of the directions may be excluded.
+
+Pins: the vector-Jacobian product of one step against central finite
+differences of the forward step at the same fixed dt; the full gradient of the
+sampled density misfit after 20 steps on the 27^3, p = 3 mesh against central
+finite differences on 32 seeded directions (relative error <= 1e-6); the
+directional derivative against central finite differences of the ORACLE's
+forward run (an independent FP64 CPU reference); the Taylor remainder's second
+order; checkpoint-interval neutrality."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1806_07984_amd as A
+from paper_1806_07984_amd import inputs, rollout
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.float64)).reshape(-1)).cuda()
+
+
+def setup(order, n, seed=1, noise=0.01):
+    om = oracle.Mesh(order, n)
+    gm = A.Mesh(A.instance(order, n), "fp64")
+    u0 = inputs.density_wave_noisy(om.node_coords(), seed=seed, noise=noise)
+    return om, gm, u0
+
+
+def fd_check(F, u, v, ad, tag, rel_eps=1e-6):
+    """Central differences at eps and eps/4; returns (rel error, smooth?)."""
+    eps = rel_eps * float(u.norm() / v.norm())
+    fd1 = (F(u + eps * v) - F(u - eps * v)) / (2 * eps)
+    fd2 = (F(u + 0.25 * eps * v) - F(u - 0.25 * eps * v)) / (0.5 * eps)
+    smooth = abs(fd1 - fd2) <= 5e-7 * abs(fd1)
+    rel = abs(fd1 - ad) / abs(ad)
+    print(f"{tag} fd={fd1:.12e} fd/4={fd2:.12e} ad={ad:.12e} rel={rel:.2e} smooth={smooth}", flush=True)
+    return rel, smooth
+
+
+def judge(res, tol):
+    smooth = [r for r, ok in res if ok]
+    assert len(smooth) >= 0.75 * len(res), f"too many directions cross a switch of the face maximum: {res}"
+    assert max(smooth) <= tol, res
+
+
+def test_sample_matches_oracle_and_is_transposed():
+    om, gm, u0 = setup(3, (5, 4, 3))
+    pts = inputs.sample_points(300, seed=5)
+    pts[0] = (0.0, 0.0, 0.0)
+    pts[1] = (1.0, 1.0, 1.0)
+    out = torch.empty(300, dtype=torch.float64, device="cuda")
+    gm.sample(dev(u0), dev(pts).reshape(-1, 3).contiguous(), out)
+    assert np.allclose(out.cpu().numpy(), om.sample(u0, pts), atol=1e-13, rtol=0)
+    # <S u, w> = <u, S^T w>
+    w = np.random.Generator(np.random.PCG64(6)).standard_normal(300)
+    ub = torch.zeros(gm.info["u_elems"], dtype=torch.float64, device="cuda")
+    gm.sample_adjoint(dev(pts).reshape(-1, 3).contiguous(), dev(w), ub)
+    lhs = float((out.cpu().numpy() * w).sum())
+    rhs = float((u0.reshape(-1) * ub.cpu().numpy()).sum())
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0)
+
+
+@pytest.mark.parametrize("order", [1, 2, 3, 4])
+def test_step_adjoint_against_finite_differences(order):
+    """<ubar_n, v> = d/de <ubar_{n+1}, step(u + e v)> at fixed dt."""
+    n = (4, 3, 5)
+    om, gm, u0 = setup(order, n, seed=10 + order, noise=0.05)
+    u = dev(u0)
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    gm.cfl(u, dt)
+    rng = np.random.Generator(np.random.PCG64(100 + order))
+    wbar = dev(rng.standard_normal(u.numel()))
+    vs = [dev(rng.standard_normal(u.numel())) for _ in range(8)]
+    ws = gm.empty_adjoint_workspace()
+    ubar = torch.empty_like(u)
+    gm.step_adjoint(u, dt, wbar, ubar, ws)
+    bufs = rollout._Buffers(gm)
+    sched = dt.clone()
+    tape = rollout.record_switches(gm, u, sched, 1)[0]
+
+    def F(x):
+        y = x.clone()
+        gm.set_switch_tape(tape, 2)
+        rollout.advance_fixed(gm, y, sched, 0, 1, bufs)
+        gm.set_switch_tape(None, 0)
+        return float((y * wbar).sum())
+    res = [fd_check(F, u, v, float((ubar * v).sum()), f"[vjp] p={order} dir={k}") for k, v in enumerate(vs)]
+    assert max(r for r, _ in res) <= 1e-6, res
+    gm.status()
+
+
+def config5(n=27, steps=20, n_pts=512):
+    om, gm, u0 = setup(3, (n, n, n), seed=7, noise=0.01)
+    pts = dev(inputs.sample_points(n_pts, seed=1)).reshape(-1, 3).contiguous()
+    target = dev(inputs.sample_targets(n_pts, seed=2))
+    return om, gm, dev(u0), pts, target, steps
+
+
+def test_gradient_27cubed_20_steps_against_finite_differences():
+    """Config of the differentiation workload: 27^3 cells, p = 3, 20 steps,
+    512 sample points, checkpoint every 5 steps, 32 seeded directions."""
+    om, gm, u0, pts, target, steps = config5()
+    J, g, sched = rollout.loss_and_grad(gm, u0, pts, target, steps, k=5)
+    assert np.isfinite(float(J)) and float(g.norm()) > 0
+    dirs = inputs.directions((u0.numel(),), 32, seed=3)
+    tapes = rollout.record_switches(gm, u0, sched, steps)
+
+    def F(x):
+        return rollout.loss_fixed(gm, x, pts, target, sched, steps, tapes=tapes)
+
+    def F_plain(x):
+        return rollout.loss_fixed(gm, x, pts, target, sched, steps)
+    worst_plain = 0.0
+    res = []
+    for k in range(32):
+        v = dev(dirs[k])
+        ad = float((g * v).sum())
+        res.append(fd_check(F, u0, v, ad, f"[fd frozen switches] dir={k:2d}"))
+        eps = 1e-6 * float(u0.norm() / v.norm())
+        plain = (F_plain(u0 + eps * v) - F_plain(u0 - eps * v)) / (2 * eps)
+        worst_plain = max(worst_plain, abs(plain - ad) / abs(ad))
+    print(f"[fd] plain central differences of the non-smooth map: worst relative error {worst_plain:.2e}",
+          flush=True)
+    assert max(r for r, _ in res) <= 1e-6, res
+    assert worst_plain <= 1e-4
+    # checkpoint interval does not change the gradient (bit for bit)
+    _, g1, _ = rollout.loss_and_grad(gm, u0, pts, target, steps, k=1, dt_sched=sched)
+    _, g20, _ = rollout.loss_and_grad(gm, u0, pts, target, steps, k=20, dt_sched=sched)
+    assert torch.equal(g1, g) and torch.equal(g20, g)
+    # Taylor remainder |J(u+hv) - J(u) - h<g,v>| is second order in h
+    v = dev(dirs[0])
+    h0 = 1e-3 * float(u0.norm() / v.norm())
+    J0 = rollout.loss_fixed(gm, u0, pts, target, sched, steps)
+    gv = float((g * v).sum())
+    rem = [abs(rollout.loss_fixed(gm, u0 + h * v, pts, target, sched, steps) - J0 - h * gv)
+           for h in (h0, h0 / 2, h0 / 4)]
+    slopes = [np.log2(rem[i] / rem[i + 1]) for i in range(2)]
+    print("[taylor] remainders", rem, "slopes", slopes, flush=True)
+    assert min(slopes) > 1.8, slopes
+
+
+def test_gradient_against_oracle_finite_differences():
+    """Directional derivatives of the same loss by central differences of the
+    oracle's forward run (FP64 CPU, same frozen dt schedule)."""
+    n, steps, n_pts = 6, 5, 64
+    om, gm, u0 = setup(3, (n, n, n), seed=12, noise=0.02)
+    pts_np = inputs.sample_points(n_pts, seed=21)
+    tgt_np = inputs.sample_targets(n_pts, seed=22)
+    pts, target = dev(pts_np).reshape(-1, 3).contiguous(), dev(tgt_np)
+    J, g, sched = rollout.loss_and_grad(gm, dev(u0), pts, target, steps, k=2)
+    sched_np = sched.cpu().numpy()
+    g = g.cpu().numpy()
+
+    def J_oracle(x):
+        y, rc = om.run_sched(x.reshape(u0.shape), sched_np)
+        assert rc == 0
+        r = om.sample(y, pts_np) - tgt_np
+        return 0.5 * float((r * r).sum())
+    assert abs(J_oracle(u0) - float(J)) <= 1e-12 * abs(float(J))
+    dirs = inputs.directions((u0.size,), 8, seed=23)
+    u_flat = torch.from_numpy(u0.reshape(-1).copy())
+
+    def F(x):
+        return J_oracle(x.numpy())
+    res = [fd_check(F, u_flat, torch.from_numpy(dirs[k]), float((g * dirs[k]).sum()), f"[oracle fd] dir={k}",
+                    rel_eps=1e-7) for k in range(8)]
+    judge(res, 1e-6)
+
+
+def test_adjoint_rejects_unsupported_handles():
+    gm = A.Mesh(A.instance(2, (3, 3, 3)), "fp32")
+    u = gm.empty_u()
+    dt = torch.ones(1, dtype=torch.float64, device="cuda")
+    with pytest.raises(A.AdgError) as e:
+        gm.step_adjoint(u, dt, u.clone(), torch.empty_like(u), torch.empty(gm.info["adjoint_workspace_bytes"],
+                                                                            dtype=torch.uint8, device="cuda"))
+    assert e.value.code == 2

@@ -370,3 +370,27 @@ def test_sharp_blast_is_flagged_unphysical():
     assert tr[:, 0, 0].min() < 0.0
     assert m.riemann(tr)[1] == 1
     assert m.run(u0, 1)[2] == 1
+
+
+def test_sample_reproduces_polynomials():
+    """Point values of the discrete solution are exact for data that is a
+    polynomial of degree <= p along each axis inside every cell."""
+    p, n = 3, (3, 2, 4)
+    m = oracle.Mesh(p, n)
+    xyz = m.node_coords()
+    poly = lambda x, y, z: 1.0 + 0.3 * x ** 3 - 0.2 * x * y ** 2 + 0.1 * z ** 3 * y
+    u = np.zeros((5, m.nc, m.N ** 3))
+    u[0] = poly(*xyz)
+    rng = np.random.Generator(np.random.PCG64(17))
+    pts = rng.uniform(0.0, 1.0, size=(200, 3))
+    pts[0] = (0.0, 0.0, 0.0)
+    pts[1] = (1.0, 1.0, 1.0)
+    assert np.allclose(m.sample(u, pts), poly(pts[:, 0], pts[:, 1], pts[:, 2]), atol=1e-13, rtol=0)
+
+
+def test_run_sched_matches_fixed_dt():
+    m = oracle.Mesh(2, (3, 3, 3))
+    u0 = inputs.density_wave_noisy(m.node_coords(), seed=8, noise=0.02)
+    a, _, _ = m.run(u0, 3, dt_fixed=2e-3)
+    b, rc = m.run_sched(u0, [2e-3] * 3)
+    assert rc == 0 and np.array_equal(a, b)
