@@ -24,6 +24,9 @@ constexpr int TRANSFER_BLOCKS = 3 + 9 + 27;
 
 hipError_t upload_basis(const DevBasis *tab);
 
+// FP32, N = 4: use the LDS-free DPP/MFMA predictor (default) or the generic one
+extern bool g_pred4_mfma;
+
 // Batched predictor: one work item = CPB cells of one instance.
 struct PredItem {
     int32_t inst;   // index into the PredInst table

@@ -19,6 +19,7 @@
 //   k_cfl_*       global time step size: block maxima then one final block.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "adg_internal.h"
 #include "kernels.h"
@@ -90,9 +91,17 @@ template <> struct PredCfg<5> { static constexpr int CPB = 2; };
 template <> struct PredCfg<6> { static constexpr int CPB = 1; };
 template <> struct PredCfg<7> { static constexpr int CPB = 1; };
 
+// wavefront-per-cell FP32 predictor for N = 4 (defined below)
+__device__ __forceinline__ void pred4_wave(const double *__restrict__ u, double *__restrict__ ustar,
+                                           float *__restrict__ traces, int64_t c, int64_t nc, int lev,
+                                           const Geo &geo, double dt, double gamma, int npic);
+// the LDS-free N = 4 FP32 kernels are always used (kept as a constant so the
+// generic path stays compiled for the FP64 form and other orders)
+constexpr bool g_pred4_mfma_dev = true;
+
 // Predictor of CPB cells (list entries first .. first+CPB-1) by one block of
 // at least CPB * N^3 threads; lds holds CPB * 15 * N^3 reals.
-template <typename T, int N, int CPB>
+template <typename T, int N, int CPB, bool STORE = false>
 __device__ __forceinline__ void predictor_body(T *__restrict__ lds, const double *__restrict__ u,
                                                double *__restrict__ ustar, T *__restrict__ traces,
                                                const int32_t *__restrict__ list, int64_t nlist, int64_t nc,
@@ -180,7 +189,7 @@ __device__ __forceinline__ void predictor_body(T *__restrict__ lds, const double
         for (int l = 0; l < N; ++l)
 #pragma unroll
             for (int v = 0; v < NV; ++v) q[l][v] = uu[v] - acc[l][v];
-        if (iters && active) {
+        if (STORE && active) {
             // iterate it+1, kept for the adjoint: [slot][l][v][cell][N^3]
 #pragma unroll
             for (int l = 0; l < N; ++l)
@@ -265,7 +274,7 @@ __device__ __forceinline__ void predictor_body(T *__restrict__ lds, const double
 }
 
 
-template <typename T, int N, int CPB>
+template <typename T, int N, int CPB, bool STORE>
 __global__ void __launch_bounds__(round64(CPB * N * N * N))
 k_predictor(const double *__restrict__ u, double *__restrict__ ustar, T *__restrict__ traces,
             const int32_t *__restrict__ list, int64_t nlist, int64_t nc,
@@ -273,8 +282,8 @@ k_predictor(const double *__restrict__ u, double *__restrict__ ustar, T *__restr
             double gamma, int npic, T *__restrict__ iters)
 {
     __shared__ T lds[CPB * 15 * N * N * N];
-    predictor_body<T, N, CPB>(lds, u, ustar, traces, list, nlist, nc, level, geo, dt_dev[0], gamma, npic,
-                              int64_t(blockIdx.x) * CPB, iters);
+    predictor_body<T, N, CPB, STORE>(lds, u, ustar, traces, list, nlist, nc, level, geo, dt_dev[0], gamma, npic,
+                                     int64_t(blockIdx.x) * CPB, iters);
 }
 
 // One variant of the batched predictor on one work item.
@@ -283,6 +292,17 @@ __device__ __forceinline__ void predictor_item(T *lds, const double *u, double *
                                             const int8_t *level, const Geo *geo, double dt, double gamma,
                                             int npic, int64_t first)
 {
+    if constexpr (std::is_same<T, float>::value && N == 4) {
+        // the FP32 N = 4 items use the same wavefront-per-cell kernel as the
+        // other launch modes (results identical across modes)
+        if (g_pred4_mfma_dev) {
+            for (int k = int(threadIdx.x >> 6); k < CPB; k += int(blockDim.x >> 6)) {
+                if (first + k >= nc) break;
+                pred4_wave(u, ustar, traces, first + k, nc, level ? level[first + k] : 0, *geo, dt, gamma, npic);
+            }
+            return;
+        }
+    }
     predictor_body<T, N, CPB>(lds, u, ustar, traces, nullptr, nc, nc, level, *geo, dt, gamma, npic, first);
 }
 
@@ -337,6 +357,253 @@ k_predictor_batch(const PredItem *__restrict__ items, int64_t nitems, const Pred
             break;
         }
         __syncthreads();
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+// Predictor for N = 4 in FP32 on one wavefront per cell, without LDS.
+// Lane l holds node a = l (a0 = l%4, a1 = (l/4)%4, a2 = l/16) and the whole
+// time history of that node in registers.
+//   x contraction: the x fibre is a lane quad -> DPP quad broadcasts fused
+//                  into the FMAs;
+//   y contraction: the y fibre is lanes a0 + 4 k of a 16-lane row -> DPP row
+//                  rotations by 4 k;
+//   z contraction: the z fibre is the four 16-lane row groups, which is the
+//                  K dimension of v_mfma_f32_16x16x4f32 (A row 4t carries
+//                  dt/dx_z D[t][k], other rows zero; the result for this
+//                  lane's node lands in accumulator register 0);
+//   time solve:    q_l -= sum_j KW[l][j] G_j is a register-axis contraction,
+//                  done by v_mfma_f32_4x4x1f32 (16 blocks of 4 lanes: lane
+//                  4b+i supplies KW[i][j], every lane its own G_j; register
+//                  l of every lane accumulates KW[l][j] G_j).
+// ---------------------------------------------------------------------------
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Fused DPP multiply-adds: acc += c[k] * x(from the lane selected by the
+// DPP pattern).  The compiler does not fold DPP moves into v_fmac_f32 here,
+// so the fused forms are written directly.  The hazard recognizer does not
+// look inside the block, so it carries its own wait states: s_nop 1 before
+// (a DPP read after a VALU write of its source) and s_nop 4 after (the next
+// consumer may be an MFMA reading acc).  The blocks are volatile so that
+// they are never moved into a branch with a partial EXEC mask.
+//
+// x fibre (a lane quad): c[k] multiplies x from the lane with a0' = (a0+k)&3.
+__device__ __forceinline__ float quad_sum(const float c[4], float x, float acc)
+{
+    acc = fmaf(c[0], x, acc);
+    asm volatile("s_nop 1\n\t"
+        "v_fmac_f32_dpp %0, %1, %2 quad_perm:[1,2,3,0] row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %3 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %4 quad_perm:[3,0,1,2] row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 4"
+        : "+v"(acc)
+        : "v"(x), "v"(c[1]), "v"(c[2]), "v"(c[3]));
+    return acc;
+}
+
+// y fibre (lanes a0 + 4 a1 of a 16-lane row): c[k] multiplies x from the lane
+// with a1' = (a1 - k)&3 (row rotation by 4 k lanes).
+__device__ __forceinline__ float row_sum(const float c[4], float x, float acc)
+{
+    acc = fmaf(c[0], x, acc);
+    asm volatile("s_nop 1\n\t"
+        "v_fmac_f32_dpp %0, %1, %2 row_ror:4 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %3 row_ror:8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %4 row_ror:12 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 4"
+        : "+v"(acc)
+        : "v"(x), "v"(c[1]), "v"(c[2]), "v"(c[3]));
+    return acc;
+}
+
+// z fibre through MFMA: returns acc + sum_k A-row(t = a2)[k] * x(lane with a2 = k)
+__device__ __forceinline__ f32x4 z_mfma(float a, float x, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, x, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ void euler_flux3_fast(float gm1, const float q[NV], float f[3][NV])
+{
+    const float inv = __builtin_amdgcn_rcpf(q[0]);
+    const float ke = 0.5f * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) * inv;
+    const float p = gm1 * (q[4] - ke);
+    const float Ep = q[4] + p;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const float vd = q[1 + d] * inv;
+        f[d][0] = q[1 + d];
+        f[d][1] = vd * q[1];
+        f[d][2] = vd * q[2];
+        f[d][3] = vd * q[3];
+        f[d][1 + d] += p;
+        f[d][4] = vd * Ep;
+    }
+}
+
+// One cell per wavefront; work item w covers cells first + w.
+__device__ __forceinline__ void pred4_wave(const double *__restrict__ u, double *__restrict__ ustar,
+                                           float *__restrict__ traces, int64_t c, int64_t nc, int lev,
+                                           const Geo &geo, double dt, double gamma, int npic)
+{
+    constexpr int N = 4, N2 = 16, N3 = 64;
+    const DevBasis &B = c_basis[N];
+    const int l = threadIdx.x & 63;
+    const int a0 = l & 3, a1 = (l >> 2) & 3, a2 = l >> 4;
+    const float cx = float(dt * geo.inv_dx[lev][0]);
+    const float cy = float(dt * geo.inv_dx[lev][1]);
+    const float cz = float(dt * geo.inv_dx[lev][2]);
+    const float gm1 = float(gamma - 1.0);
+
+    float uu[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) uu[v] = float(u[(int64_t(v) * nc + c) * N3 + l]);
+
+    // per-lane coefficients
+    float Cx[4], Cy[4], KWa[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        Cx[e] = cx * float(B.D[a0 * N + ((a0 + e) & 3)]);
+        Cy[e] = cy * float(B.D[a1 * N + ((a1 - e) & 3)]);
+        KWa[e] = float(B.KW[a0 * N + e]);  // lane 4b+i supplies KW[i][j], i = a0
+    }
+    const float Az = (a0 == 0) ? cz * float(B.D[a1 * N + a2]) : 0.0f;  // A[row = l%16][k = l/16]
+    const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
+
+    float q[N][NV];
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) q[j][v] = uu[v];
+
+    for (int it = 0; it < npic; ++it) {
+        f32x4 acc[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            float f[3][NV];
+            euler_flux3_fast(gm1, q[j], f);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const f32x4 g4 = z_mfma(Az, f[2][v], zero4);
+                float G = quad_sum(Cx, f[0][v], g4[0]);
+                G = row_sum(Cy, f[1][v], G);
+                acc[v] = __builtin_amdgcn_mfma_f32_4x4x1f32(KWa[j], G, acc[v], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int j = 0; j < N; ++j) q[j][v] = uu[v] - acc[v][j];
+    }
+
+    // time averages of the final iterate
+    float qb[NV], Fb[3][NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        qb[v] = 0.f;
+        Fb[0][v] = Fb[1][v] = Fb[2][v] = 0.f;
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        float f[3][NV];
+        euler_flux3_fast(gm1, q[j], f);
+        const float wj = float(B.w[j]);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            qb[v] = fmaf(wj, q[j][v], qb[v]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) Fb[d][v] = fmaf(wj, f[d][v], Fb[d][v]);
+        }
+    }
+
+    // volume term with the weak stiffness Kw (same three mechanisms)
+    {
+        float Vx[4], Vy[4];
+        const float sx = cx * float(B.winv[a0]), sy = cy * float(B.winv[a1]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            Vx[e] = sx * float(B.Kw[a0 * N + ((a0 + e) & 3)]);
+            Vy[e] = sy * float(B.Kw[a1 * N + ((a1 - e) & 3)]);
+        }
+        const float Avz = (a0 == 0) ? cz * float(B.winv[a1]) * float(B.Kw[a1 * N + a2]) : 0.0f;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const f32x4 r = z_mfma(Avz, Fb[2][v], zero4);
+            float V = quad_sum(Vx, Fb[0][v], r[0]);
+            V = row_sum(Vy, Fb[1][v], V);
+            const int64_t o = (int64_t(v) * nc + c) * N3 + l;
+            ustar[o] = u[o] + double(V);
+        }
+    }
+
+    // face projections: L (minus) and R (plus) along each axis
+    {
+        float Lx[4], Rx[4], Ly[4], Ry[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            Lx[e] = float(B.L[(a0 + e) & 3]);
+            Rx[e] = float(B.R[(a0 + e) & 3]);
+            Ly[e] = float(B.L[(a1 - e) & 3]);
+            Ry[e] = float(B.R[(a1 - e) & 3]);
+        }
+        // z: A row 4t + 0 carries L[k], row 4t + 1 carries R[k]
+        const float Ap = (a0 == 0) ? float(B.L[a2]) : ((a0 == 1) ? float(B.R[a2]) : 0.0f);
+        const int bx = a1 + 4 * a2, by = a0 + 4 * a2, bz = a0 + 4 * a1;
+        auto put = [&](int s, int arr, int v, int b, float x) {
+            traces[((int64_t(s * 2 + arr) * NV + v) * nc + c) * N2 + b] = x;
+        };
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+#pragma unroll
+            for (int arr = 0; arr < 2; ++arr) {
+                // x faces: state or normal flux Fx
+                const float xv = arr == 0 ? qb[v] : Fb[0][v];
+                const float pxl = quad_sum(Lx, xv, 0.f), pxr = quad_sum(Rx, xv, 0.f);
+                if (a0 == 0) put(0, arr, v, bx, pxl);
+                if (a0 == 3) put(1, arr, v, bx, pxr);
+                const float yv = arr == 0 ? qb[v] : Fb[1][v];
+                const float pyl = row_sum(Ly, yv, 0.f), pyr = row_sum(Ry, yv, 0.f);
+                if (a1 == 0) put(2, arr, v, by, pyl);
+                if (a1 == 3) put(3, arr, v, by, pyr);
+                const float zv = arr == 0 ? qb[v] : Fb[2][v];
+                const f32x4 r = z_mfma(Ap, zv, zero4);
+                if (a2 == 0) put(4, arr, v, bz, r[0]);
+                if (a2 == 3) put(5, arr, v, bz, r[1]);
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_predictor4_mfma(const double *__restrict__ u, double *__restrict__ ustar, float *__restrict__ traces,
+                  const int32_t *__restrict__ list, int64_t nlist, int64_t nc, const int8_t *__restrict__ level,
+                  Geo geo, const double *__restrict__ dt_dev, double gamma, int npic)
+{
+    const int64_t idx = int64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (idx >= nlist) return;  // whole wavefront leaves together
+    const int64_t c = list ? int64_t(list[idx]) : idx;
+    pred4_wave(u, ustar, traces, c, nc, level ? level[c] : 0, geo, dt_dev[0], gamma, npic);
+}
+
+// persistent form over batched work items of order 4 (items of CPB cells)
+__global__ void __launch_bounds__(256)
+k_predictor4_mfma_order(const PredItem *__restrict__ items, int64_t nitems, const PredInst *__restrict__ insts,
+                        const double *__restrict__ u, double *__restrict__ ustar, float *__restrict__ traces,
+                        const double *__restrict__ dt, int cpb)
+{
+    const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const PredItem w = items[it];
+        const PredInst &I = insts[w.inst];
+        for (int k = wave; k < cpb; k += nwaves) {
+            const int64_t c = w.first + k;
+            if (c >= I.nc) break;
+            pred4_wave(u + I.u_off, ustar + I.u_off, traces + I.tr_off, c, I.nc, I.level ? I.level[c] : 0, I.geo,
+                       dt[w.inst], I.gamma, I.npic);
+        }
     }
 }
 
@@ -1034,6 +1301,8 @@ k_sample_adj(const double *__restrict__ pts, const double *__restrict__ wbar, in
     default: return hipErrorInvalidValue;            \
     }
 
+bool g_pred4_mfma = true;
+
 hipError_t upload_basis(const DevBasis *tab)
 {
     return hipMemcpyToSymbol(HIP_SYMBOL(c_basis), tab, sizeof(DevBasis) * (NMAX + 1));
@@ -1045,11 +1314,25 @@ hipError_t launch_predictor(int N, const double *u, double *ustar, T *traces, co
                             const double *dt, double gamma, int npic, hipStream_t st, T *iters)
 {
     if (nlist <= 0) return hipSuccess;
+    if constexpr (std::is_same<T, float>::value) {
+        if (N == 4 && iters == nullptr && g_pred4_mfma) {
+            const int64_t blocks = (nlist + 3) / 4;
+            hipLaunchKernelGGL(k_predictor4_mfma, dim3(unsigned(blocks)), dim3(256), 0, st, u, ustar, traces, list,
+                               nlist, nc, level, geo, dt, gamma, npic);
+            return hipGetLastError();
+        }
+    }
     ADG_DISPATCH_N(N, {
         constexpr int CPB = PredCfg<NN>::CPB;
         const int64_t blocks = (nlist + CPB - 1) / CPB;
-        hipLaunchKernelGGL((k_predictor<T, NN, CPB>), dim3(unsigned(blocks)), dim3(round64(CPB * NN * NN * NN)), 0,
-                           st, u, ustar, traces, list, nlist, nc, level, geo, dt, gamma, npic, iters);
+        if (iters)
+            hipLaunchKernelGGL((k_predictor<T, NN, CPB, true>), dim3(unsigned(blocks)),
+                               dim3(round64(CPB * NN * NN * NN)), 0, st, u, ustar, traces, list, nlist, nc, level, geo,
+                               dt, gamma, npic, iters);
+        else
+            hipLaunchKernelGGL((k_predictor<T, NN, CPB, false>), dim3(unsigned(blocks)),
+                               dim3(round64(CPB * NN * NN * NN)), 0, st, u, ustar, traces, list, nlist, nc, level, geo,
+                               dt, gamma, npic, iters);
     });
     return hipGetLastError();
 }
@@ -1146,6 +1429,20 @@ hipError_t launch_predictor_order(int code, const PredItem *items, int64_t nitem
                                   hipStream_t st)
 {
     if (nitems <= 0) return hipSuccess;
+    if constexpr (std::is_same<T, float>::value) {
+        int vn, cpb;
+        pred_variant_shape(code, &vn, &cpb);
+        if (vn == 4 && g_pred4_mfma) {
+            int occ = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_predictor4_mfma_order, 256, 0) != hipSuccess ||
+                occ < 1)
+                occ = 1;
+            const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(nitems, int64_t(occ) * n_cu));
+            hipLaunchKernelGGL(k_predictor4_mfma_order, dim3(unsigned(grid)), dim3(256), 0, st, items, nitems, insts,
+                               u, ustar, traces, dt, cpb);
+            return hipGetLastError();
+        }
+    }
     switch (code) {
 #define ADG_ORDER_CASE(code_, NN, CC)                                                                            \
     case code_: {                                                                                                \
