@@ -369,15 +369,18 @@ adg_status do_conforming(adg_mesh *m, const T *traces, T *fside, hipStream_t st)
     return ADG_OK;
 }
 
+// fuse_cfl: the corrector also leaves the block maxima of the new state's
+// CFL rate in each instance's partial buffer (consumed by do_cfl_fused).
 template <typename T>
 adg_status do_corrector(adg_mesh *m, const double *ustar, const T *fside, const double *dt, double *uout,
-                        hipStream_t st)
+                        hipStream_t st, bool fuse_cfl = false)
 {
     PhaseTimer tm(m, ADG_PHASE_CORRECTOR, st);
     for (size_t i = 0; i < m->inst.size(); ++i) {
         Instance &I = m->inst[i];
         ADG_HIP(launch_corrector<T>(I.N, ustar + I.u_off, fside + I.fs_off, dt + i, uout + I.u_off, I.nc, I.level,
-                                    I.geo, st), "corrector");
+                                    I.geo, st, I.gamma, fuse_cfl ? I.partial : nullptr, m->status_dev),
+                "corrector");
     }
     return ADG_OK;
 }
@@ -394,7 +397,33 @@ adg_status do_cfl(adg_mesh *m, const double *u, double *dt, double *hist, hipStr
     return ADG_OK;
 }
 
+// Block maxima of the CFL rate of u in the corrector's layout (starts a run
+// of fused steps).
+adg_status do_cfl_prime(adg_mesh *m, const double *u, hipStream_t st)
+{
+    PhaseTimer tm(m, ADG_PHASE_CFL, st);
+    for (auto &I : m->inst)
+        ADG_HIP(launch_cfl_prime(I.N, u + I.u_off, I.nc, I.level, I.geo, I.gamma, I.partial, m->status_dev, st),
+                "cfl block maxima");
+    return ADG_OK;
+}
+
+// dt from the block maxima left by do_cfl_prime or the previous corrector.
+adg_status do_cfl_fused(adg_mesh *m, double *dt, double *hist, hipStream_t st)
+{
+    PhaseTimer tm(m, ADG_PHASE_CFL, st);
+    for (size_t i = 0; i < m->inst.size(); ++i) {
+        Instance &I = m->inst[i];
+        ADG_HIP(launch_cfl_final(I.partial, corrector_blocks(I.N, I.nc), I.cfl / (2.0 * I.order + 1.0), dt + i,
+                                 hist ? hist + i : nullptr, st),
+                "cfl final");
+    }
+    return ADG_OK;
+}
+
 // Enqueues one whole step (CFL, predictor, faces, corrector) on the streams.
+// The block maxima of the CFL rate must be current (do_cfl_prime, or the
+// previous step's corrector); the corrector leaves them for the next step.
 template <typename T>
 adg_status enqueue_step(adg_mesh *m, double *u, double *hist, void *ws, hipStream_t s_skel, hipStream_t s_encl)
 {
@@ -406,7 +435,7 @@ adg_status enqueue_step(adg_mesh *m, double *u, double *hist, void *ws, hipStrea
     T *fside = reinterpret_cast<T *>(w);
     const bool two = s_skel != s_encl;
     {
-        adg_status st = do_cfl(m, u, m->dt_dev, hist, s_skel);
+        adg_status st = do_cfl_fused(m, m->dt_dev, hist, s_skel);
         if (st != ADG_OK) return st;
         if (two) {
             ADG_HIP(hipEventRecord(m->ev_dt, s_skel), "event record");
@@ -422,7 +451,7 @@ adg_status enqueue_step(adg_mesh *m, double *u, double *hist, void *ws, hipStrea
         }
         st = do_conforming<T>(m, traces, fside, s_skel);
         if (st != ADG_OK) return st;
-        st = do_corrector<T>(m, ustar, fside, m->dt_dev, u, s_skel);
+        st = do_corrector<T>(m, ustar, fside, m->dt_dev, u, s_skel, true);
         if (st != ADG_OK) return st;
     }
     return ADG_OK;
@@ -433,6 +462,8 @@ adg_status step_eager(adg_mesh *m, double *u, int32_t n_steps, double *hist, voi
                       hipStream_t s_encl)
 {
     const int ni = int(m->inst.size());
+    adg_status st0 = do_cfl_prime(m, u, s_skel);
+    if (st0 != ADG_OK) return st0;
     for (int n = 0; n < n_steps; ++n) {
         adg_status st = enqueue_step<T>(m, u, hist ? hist + int64_t(n) * ni : nullptr, ws, s_skel, s_encl);
         if (st != ADG_OK) return st;
@@ -460,6 +491,10 @@ adg_status step_graph(adg_mesh *m, double *u, int32_t n_steps, double *hist, voi
     if (two) {
         ADG_HIP(hipEventRecord(m->ev_in2, s_encl), "event record");
         ADG_HIP(hipStreamWaitEvent(A, m->ev_in2, 0), "stream wait");
+    }
+    {
+        adg_status st0 = do_cfl_prime(m, u, A);
+        if (st0 != ADG_OK) return st0;
     }
     if (!m->gexec || m->gkey_u != u || m->gkey_ws != ws || m->gkey_two != two) {
         drop_graph(m);
@@ -683,7 +718,7 @@ adg_status adg_init_mesh(const adg_instance_desc *desc, int32_t n_instances, adg
             }
         }
         ok = ok && upload(m, I.ptab, pt.data(), pt.size());
-        ok = ok && dev_alloc(m, I.partial, CFL_MAX_BLOCKS);
+        ok = ok && dev_alloc(m, I.partial, size_t(std::max(CFL_MAX_BLOCKS, corrector_blocks(I.N, I.nc))));
         // the host copy of the cell table is kept (adg_mesh_cells); face lists are not needed
         for (int a = 0; a < 3; ++a) {
             std::vector<int32_t>().swap(h.face_m[a]);

@@ -7,6 +7,7 @@
 namespace adg {
 
 constexpr int CFL_MAX_BLOCKS = 2048;
+constexpr int CORRECTOR_MAX_BLOCKS = 4096;
 
 // Hanging child face as the kernels read it.
 struct HangDev {
@@ -74,9 +75,18 @@ template <typename T>
 hipError_t launch_restrict(int N, T *fside, const HangDev *hang, const int32_t *ccell, const int8_t *cside,
                            const int32_t *cptr, const int32_t *cchild, int64_t ncs, int64_t nc,
                            const double *ptab, hipStream_t st);
+// partial != nullptr: also write the CFL maximum of the new state per block
+// (corrector_blocks(N, nc) values) for the next step's launch_cfl_final.
 template <typename T>
 hipError_t launch_corrector(int N, const double *ustar, const T *fside, const double *dt, double *uout,
-                            int64_t nc, const int8_t *level, const Geo &geo, hipStream_t st);
+                            int64_t nc, const int8_t *level, const Geo &geo, hipStream_t st, double gamma = 0.0,
+                            double *partial = nullptr, int *status = nullptr);
+int corrector_blocks(int N, int64_t nc);
+// block maxima of the CFL rate of u in the corrector's block layout
+hipError_t launch_cfl_prime(int N, const double *u, int64_t nc, const int8_t *level, const Geo &geo, double gamma,
+                            double *partial, int *status, hipStream_t st);
+hipError_t launch_cfl_final(const double *partial, int nparts, double factor, double *dt_out, double *hist,
+                            hipStream_t st);
 
 int cfl_blocks(int N, int64_t nc);
 // factor = cfl / (2p + 1); writes dt_out[0] (and hist[0] if not null)

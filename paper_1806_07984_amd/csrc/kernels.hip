@@ -796,35 +796,74 @@ k_restrict(T *__restrict__ fside, const HangDev *__restrict__ hang, const int32_
 // Corrector
 // ---------------------------------------------------------------------------
 
-template <typename T, int N>
+__device__ __forceinline__ double block_max(double x, double *sh);
+
+// Sum over the axes of (|u_d| + c)/dx_d at one node; +inf (and the status
+// flag) for a non-physical state.  Shared by the CFL kernels and the fused
+// corrector epilogue, so both give the same bits.
+__device__ __forceinline__ double cfl_rate(double gamma, const double q[NV], const Geo &geo, int lev,
+                                           int *__restrict__ status)
+{
+    const double gm1 = gamma - 1.0;
+    bool bad = false, b2;
+    double s = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        s += wave_speed(gamma, gm1, q, d, b2) * geo.inv_dx[lev][d];
+        bad = bad || b2;
+    }
+    if (bad) {
+        *status = 1;
+        s = INFINITY;
+    }
+    return s;
+}
+
+// FUSE: also reduce the CFL rate of the new state to one maximum per block
+// (partial[blockIdx.x]), which the next step's k_cfl_final consumes.
+template <typename T, int N, bool FUSE>
 __global__ void __launch_bounds__(256)
 k_corrector(const double *__restrict__ ustar, const T *__restrict__ fside, const double *__restrict__ dt_dev,
-            double *__restrict__ uout, int64_t nc, const int8_t *__restrict__ level, Geo geo)
+            double *__restrict__ uout, int64_t nc, const int8_t *__restrict__ level, Geo geo, double gamma,
+            double *__restrict__ partial, int *__restrict__ status)
 {
     constexpr int N2 = N * N, N3 = N2 * N;
-    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= nc * N3) return;
-    const int64_t c = t / N3;
-    const int a = int(t % N3), a0 = a % N, a1 = (a / N) % N, a2 = a / N2;
     const DevBasis &B = c_basis[N];
     const double dt = dt_dev[0];
-    const int lev = level ? level[c] : 0;
-    const double sx = dt * geo.inv_dx[lev][0] * B.winv[a0];
-    const double sy = dt * geo.inv_dx[lev][1] * B.winv[a1];
-    const double sz = dt * geo.inv_dx[lev][2] * B.winv[a2];
-    const int bx = a1 + N * a2, by = a0 + N * a2, bz = a0 + N * a1;
+    double rate = 0.0;
+    const int64_t total = nc * N3;
+    // grid-stride over nodes (the grid is capped so that the fused CFL
+    // leaves few block maxima)
+    for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
+         t += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t c = t / N3;
+        const int a = int(t % N3), a0 = a % N, a1 = (a / N) % N, a2 = a / N2;
+        const int lev = level ? level[c] : 0;
+        const double sx = dt * geo.inv_dx[lev][0] * B.winv[a0];
+        const double sy = dt * geo.inv_dx[lev][1] * B.winv[a1];
+        const double sz = dt * geo.inv_dx[lev][2] * B.winv[a2];
+        const int bx = a1 + N * a2, by = a0 + N * a2, bz = a0 + N * a1;
+        double q[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        const double fxm = fside[(int64_t(0 * NV + v) * nc + c) * N2 + bx];
-        const double fxp = fside[(int64_t(1 * NV + v) * nc + c) * N2 + bx];
-        const double fym = fside[(int64_t(2 * NV + v) * nc + c) * N2 + by];
-        const double fyp = fside[(int64_t(3 * NV + v) * nc + c) * N2 + by];
-        const double fzm = fside[(int64_t(4 * NV + v) * nc + c) * N2 + bz];
-        const double fzp = fside[(int64_t(5 * NV + v) * nc + c) * N2 + bz];
-        const double s = sx * (B.R[a0] * fxp - B.L[a0] * fxm) + sy * (B.R[a1] * fyp - B.L[a1] * fym) +
-                         sz * (B.R[a2] * fzp - B.L[a2] * fzm);
-        const int64_t o = (int64_t(v) * nc + c) * N3 + a;
-        uout[o] = ustar[o] - s;
+        for (int v = 0; v < NV; ++v) {
+            const double fxm = fside[(int64_t(0 * NV + v) * nc + c) * N2 + bx];
+            const double fxp = fside[(int64_t(1 * NV + v) * nc + c) * N2 + bx];
+            const double fym = fside[(int64_t(2 * NV + v) * nc + c) * N2 + by];
+            const double fyp = fside[(int64_t(3 * NV + v) * nc + c) * N2 + by];
+            const double fzm = fside[(int64_t(4 * NV + v) * nc + c) * N2 + bz];
+            const double fzp = fside[(int64_t(5 * NV + v) * nc + c) * N2 + bz];
+            const double s = sx * (B.R[a0] * fxp - B.L[a0] * fxm) + sy * (B.R[a1] * fyp - B.L[a1] * fym) +
+                             sz * (B.R[a2] * fzp - B.L[a2] * fzm);
+            const int64_t o = (int64_t(v) * nc + c) * N3 + a;
+            q[v] = ustar[o] - s;
+            uout[o] = q[v];
+        }
+        if (FUSE) rate = fmax(rate, cfl_rate(gamma, q, geo, lev, status));
+    }
+    if (FUSE) {
+        __shared__ double sh[4];
+        rate = block_max(rate, sh);
+        if (threadIdx.x == 0) partial[blockIdx.x] = rate;
     }
 }
 
@@ -854,7 +893,6 @@ k_cfl_partial(const double *__restrict__ u, int64_t nc, const int8_t *__restrict
 {
     constexpr int N3 = N * N * N;
     __shared__ double sh[4];
-    const double gm1 = gamma - 1.0;
     double m = 0.0;
     const int64_t total = nc * N3;
     for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
@@ -864,19 +902,7 @@ k_cfl_partial(const double *__restrict__ u, int64_t nc, const int8_t *__restrict
         double q[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) q[v] = u[(int64_t(v) * nc + c) * N3 + a];
-        const int lev = level ? level[c] : 0;
-        bool bad = false, b2;
-        double s = 0.0;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            s += wave_speed(gamma, gm1, q, d, b2) * geo.inv_dx[lev][d];
-            bad = bad || b2;
-        }
-        if (bad) {
-            *status = 1;
-            s = INFINITY;
-        }
-        m = fmax(m, s);
+        m = fmax(m, cfl_rate(gamma, q, geo, level ? level[c] : 0, status));
     }
     m = block_max(m, sh);
     if (threadIdx.x == 0) partial[blockIdx.x] = m;
@@ -1382,13 +1408,18 @@ hipError_t launch_restrict(int N, T *fside, const HangDev *hang, const int32_t *
 
 template <typename T>
 hipError_t launch_corrector(int N, const double *ustar, const T *fside, const double *dt, double *uout,
-                            int64_t nc, const int8_t *level, const Geo &geo, hipStream_t st)
+                            int64_t nc, const int8_t *level, const Geo &geo, hipStream_t st, double gamma,
+                            double *partial, int *status)
 {
     if (nc <= 0) return hipSuccess;
     ADG_DISPATCH_N(N, {
-        const int64_t blocks = (nc * NN * NN * NN + 255) / 256;
-        hipLaunchKernelGGL((k_corrector<T, NN>), dim3(unsigned(blocks)), dim3(256), 0, st,
-                           ustar, fside, dt, uout, nc, level, geo);
+        const int64_t blocks = corrector_blocks(NN, nc);
+        if (partial)
+            hipLaunchKernelGGL((k_corrector<T, NN, true>), dim3(unsigned(blocks)), dim3(256), 0, st, ustar, fside, dt,
+                               uout, nc, level, geo, gamma, partial, status);
+        else
+            hipLaunchKernelGGL((k_corrector<T, NN, false>), dim3(unsigned(blocks)), dim3(256), 0, st, ustar, fside,
+                               dt, uout, nc, level, geo, gamma, partial, status);
     });
     return hipGetLastError();
 }
@@ -1501,6 +1532,30 @@ hipError_t launch_cfl(int N, const double *u, int64_t nc, const int8_t *level, c
     return hipGetLastError();
 }
 
+int corrector_blocks(int N, int64_t nc)
+{
+    const int64_t b = (nc * N * N * N + 255) / 256;
+    return int(std::max<int64_t>(1, std::min<int64_t>(b, CORRECTOR_MAX_BLOCKS)));
+}
+
+hipError_t launch_cfl_prime(int N, const double *u, int64_t nc, const int8_t *level, const Geo &geo, double gamma,
+                            double *partial, int *status, hipStream_t st)
+{
+    const int nb = corrector_blocks(N, nc);
+    ADG_DISPATCH_N(N, {
+        hipLaunchKernelGGL((k_cfl_partial<NN>), dim3(nb), dim3(256), 0, st, u, nc, level, geo, gamma, partial,
+                           status);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_cfl_final(const double *partial, int nparts, double factor, double *dt_out, double *hist,
+                            hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(256), 0, st, partial, nparts, factor, dt_out, hist);
+    return hipGetLastError();
+}
+
 hipError_t launch_node_coords(int N, double *xyz, const int32_t *ijk, const int8_t *level, int64_t nc,
                               const Geo &geo, const double *lo, hipStream_t st)
 {
@@ -1575,7 +1630,8 @@ hipError_t launch_sample_adjoint(int N, const double *pts, const double *wbar, i
                                            const int32_t *, const int32_t *, int64_t, int64_t,           \
                                            const double *, hipStream_t);                                 \
     template hipError_t launch_corrector<T>(int, const double *, const T *, const double *, double *,    \
-                                            int64_t, const int8_t *, const Geo &, hipStream_t);
+                                            int64_t, const int8_t *, const Geo &, hipStream_t, double,    \
+                                            double *, int *);
 
 ADG_INSTANTIATE(double)
 ADG_INSTANTIATE(float)
