@@ -214,6 +214,8 @@ def main():
     ap.add_argument("--only", choices=["fp64", "fp32"], default=None,
                     help="run one path only (for profiling runs)")
     ap.add_argument("--no-extra", action="store_true", help="skip the AMR and batch workloads")
+    ap.add_argument("--extra-only", choices=["amr", "batch"], default=None,
+                    help="run only one of the other workloads and print its JSON (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB buffer 3 times (calibrates HBM byte counters) and exit")
     args = ap.parse_args()
@@ -235,6 +237,10 @@ def main():
     from paper_1806_07984_amd import inputs
 
     A.load()
+    if args.extra_only:
+        res = run_amr(A) if args.extra_only == "amr" else run_batch(A)
+        print(json.dumps({"workload": args.extra_only, **res}))
+        return
     # initial state: node coordinates from the library, analytic state + seeded noise on the host
     probe = A.Mesh(A.instance(ORDER, (N_BASE,) * 3), "fp64")
     xyz = probe.node_coords().cpu().numpy().reshape(3, -1)
