@@ -7,7 +7,7 @@
 namespace adg {
 
 constexpr int CFL_MAX_BLOCKS = 2048;
-constexpr int CORRECTOR_MAX_BLOCKS = 4096;
+constexpr int CORRECTOR_MAX_BLOCKS = 16384;
 
 // Hanging child face as the kernels read it.
 struct HangDev {

@@ -385,9 +385,10 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // DPP pattern).  The compiler does not fold DPP moves into v_fmac_f32 here,
 // so the fused forms are written directly.  The hazard recognizer does not
 // look inside the block, so it carries its own wait states: s_nop 1 before
-// (a DPP read after a VALU write of its source) and s_nop 4 after (the next
-// consumer may be an MFMA reading acc).  The blocks are volatile so that
-// they are never moved into a branch with a partial EXEC mask.
+// (a DPP read after a VALU write of its source), and s_nop 2 after row_sum,
+// whose result an MFMA reads next (quad_sum's result only feeds VALU
+// instructions).  The blocks are volatile so that they are never moved into
+// a branch with a partial EXEC mask.
 //
 // x fibre (a lane quad): c[k] multiplies x from the lane with a0' = (a0+k)&3.
 __device__ __forceinline__ float quad_sum(const float c[4], float x, float acc)
@@ -396,8 +397,7 @@ __device__ __forceinline__ float quad_sum(const float c[4], float x, float acc)
     asm volatile("s_nop 1\n\t"
         "v_fmac_f32_dpp %0, %1, %2 quad_perm:[1,2,3,0] row_mask:0xf bank_mask:0xf\n\t"
         "v_fmac_f32_dpp %0, %1, %3 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %0, %1, %4 quad_perm:[3,0,1,2] row_mask:0xf bank_mask:0xf\n\t"
-        "s_nop 4"
+        "v_fmac_f32_dpp %0, %1, %4 quad_perm:[3,0,1,2] row_mask:0xf bank_mask:0xf"
         : "+v"(acc)
         : "v"(x), "v"(c[1]), "v"(c[2]), "v"(c[3]));
     return acc;
@@ -412,7 +412,7 @@ __device__ __forceinline__ float row_sum(const float c[4], float x, float acc)
         "v_fmac_f32_dpp %0, %1, %2 row_ror:4 row_mask:0xf bank_mask:0xf\n\t"
         "v_fmac_f32_dpp %0, %1, %3 row_ror:8 row_mask:0xf bank_mask:0xf\n\t"
         "v_fmac_f32_dpp %0, %1, %4 row_ror:12 row_mask:0xf bank_mask:0xf\n\t"
-        "s_nop 4"
+        "s_nop 2"
         : "+v"(acc)
         : "v"(x), "v"(c[1]), "v"(c[2]), "v"(c[3]));
     return acc;
@@ -908,11 +908,11 @@ k_cfl_partial(const double *__restrict__ u, int64_t nc, const int8_t *__restrict
     if (threadIdx.x == 0) partial[blockIdx.x] = m;
 }
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
 k_cfl_final(const double *__restrict__ partial, int nparts, double factor, double *__restrict__ dt_out,
             double *__restrict__ hist)
 {
-    __shared__ double sh[4];
+    __shared__ double sh[16];
     double m = 0.0;
     for (int i = threadIdx.x; i < nparts; i += blockDim.x) m = fmax(m, partial[i]);
     m = block_max(m, sh);
@@ -1528,7 +1528,7 @@ hipError_t launch_cfl(int N, const double *u, int64_t nc, const int8_t *level, c
         hipLaunchKernelGGL((k_cfl_partial<NN>), dim3(nb), dim3(256), 0, st, u, nc, level, geo, gamma, partial,
                            status);
     });
-    hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(256), 0, st, partial, nb, factor, dt_out, hist);
+    hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(1024), 0, st, partial, nb, factor, dt_out, hist);
     return hipGetLastError();
 }
 
@@ -1552,7 +1552,7 @@ hipError_t launch_cfl_prime(int N, const double *u, int64_t nc, const int8_t *le
 hipError_t launch_cfl_final(const double *partial, int nparts, double factor, double *dt_out, double *hist,
                             hipStream_t st)
 {
-    hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(256), 0, st, partial, nparts, factor, dt_out, hist);
+    hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(1024), 0, st, partial, nparts, factor, dt_out, hist);
     return hipGetLastError();
 }
 
