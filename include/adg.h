@@ -63,8 +63,10 @@ typedef enum {
 
 typedef enum {
     ADG_FP64 = 0,       /* every step in FP64                                    */
-    ADG_FP32_MFMA = 1   /* predictor, traces, Riemann in FP32 (contractions on
-                           MFMA); u, u*, dt and the corrector accumulation FP64 */
+    ADG_FP32_MFMA = 1   /* predictor, traces, Riemann in FP32; for p = 3 the
+                           predictor's z contraction and time solve run on MFMA
+                           (other orders on the vector units); u, u*, dt and the
+                           corrector accumulation stay FP64                        */
 } adg_precision;
 
 /* One periodic box with an optional static 3:1 refinement (Assumption 1). */

@@ -99,8 +99,40 @@ __device__ __forceinline__ void pred4_wave(const double *__restrict__ u, double 
 // generic path stays compiled for the FP64 form and other orders)
 constexpr bool g_pred4_mfma_dev = true;
 
+// LDS layout of the generic predictor, per cell: the 15 values (3 axes x 5
+// variables) of every node in node order.  A wave's writes are consecutive;
+// a fibre read is a broadcast across the lanes that share the fibre (cheaper
+// in LDS bandwidth than wide loads, which move all their bytes per lane).
+template <typename T, int N> struct Fib {
+    static constexpr int PER_CELL = 15 * N * N * N;
+};
+
+// Euler fluxes; the FP32 form uses the hardware reciprocal for 1/rho
+template <typename T>
+__device__ __forceinline__ void flux3(T gm1, const T q[NV], T f[3][NV])
+{
+    if constexpr (std::is_same<T, float>::value) {
+        const float inv = __builtin_amdgcn_rcpf(q[0]);
+        const float ke = 0.5f * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) * inv;
+        const float p = gm1 * (q[4] - ke);
+        const float Ep = q[4] + p;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const float vd = q[1 + d] * inv;
+            f[d][0] = q[1 + d];
+            f[d][1] = vd * q[1];
+            f[d][2] = vd * q[2];
+            f[d][3] = vd * q[3];
+            f[d][1 + d] += p;
+            f[d][4] = vd * Ep;
+        }
+    } else {
+        euler_flux3(gm1, q, f);
+    }
+}
+
 // Predictor of CPB cells (list entries first .. first+CPB-1) by one block of
-// at least CPB * N^3 threads; lds holds CPB * 15 * N^3 reals.
+// at least CPB * N^3 threads; lds holds CPB * Fib<T, N>::PER_CELL reals.
 template <typename T, int N, int CPB, bool STORE = false>
 __device__ __forceinline__ void predictor_body(T *__restrict__ lds, const double *__restrict__ u,
                                                double *__restrict__ ustar, T *__restrict__ traces,
@@ -110,6 +142,7 @@ __device__ __forceinline__ void predictor_body(T *__restrict__ lds, const double
                                                T *__restrict__ iters = nullptr)
 {
     constexpr int N2 = N * N, N3 = N2 * N, NT = CPB * N3;
+    constexpr int PC = Fib<T, N>::PER_CELL;
     const DevBasis &B = c_basis[N];
 
     const int tid = threadIdx.x;
@@ -118,12 +151,11 @@ __device__ __forceinline__ void predictor_body(T *__restrict__ lds, const double
     const bool lane_ok = tid < NT;
     const bool active = lane_ok && idx < nlist;
     const int64_t c = active ? (list ? int64_t(list[idx]) : idx) : 0;
-    const int a0 = a % N, a1 = (a / N) % N, a2 = a / N2;
+    const int aa[3] = {a % N, (a / N) % N, a / N2};
+    const int bf[3] = {aa[1] + N * aa[2], aa[0] + N * aa[2], aa[0] + N * aa[1]};  // fibre (= face) index per axis
 
     const int lev = level ? level[c] : 0;
-    const T cx = T(dt * geo.inv_dx[lev][0]);
-    const T cy = T(dt * geo.inv_dx[lev][1]);
-    const T cz = T(dt * geo.inv_dx[lev][2]);
+    const double cdd[3] = {dt * geo.inv_dx[lev][0], dt * geo.inv_dx[lev][1], dt * geo.inv_dx[lev][2]};
     const T gm1 = T(gamma - 1.0);
 
     double ud[NV];
@@ -133,14 +165,12 @@ __device__ __forceinline__ void predictor_body(T *__restrict__ lds, const double
 #pragma unroll
     for (int v = 0; v < NV; ++v) uu[v] = T(ud[v]);
 
-    // derivative rows of this lane's node along each axis
-    T Dx[N], Dy[N], Dz[N];
+    // derivative rows of this lane's node along each axis, scaled by dt/dx_d
+    T Dc[3][N];
 #pragma unroll
-    for (int e = 0; e < N; ++e) {
-        Dx[e] = T(B.D[a0 * N + e]);
-        Dy[e] = T(B.D[a1 * N + e]);
-        Dz[e] = T(B.D[a2 * N + e]);
-    }
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int e = 0; e < N; ++e) Dc[d][e] = T(cdd[d] * B.D[aa[d] * N + e]);
 
     T q[N][NV];
 #pragma unroll
@@ -148,8 +178,15 @@ __device__ __forceinline__ void predictor_body(T *__restrict__ lds, const double
 #pragma unroll
         for (int v = 0; v < NV; ++v) q[l][v] = uu[v];
 
-    T *my = lds + (lane_ok ? cl : 0) * 15 * N3;
-    const int bx = N * a1 + N2 * a2, by = a0 + N2 * a2, bz = a0 + N * a1;
+    T *my = lds + (lane_ok ? cl : 0) * PC;
+    // address of (axis d, variable v) at this lane's node
+    auto put_at = [&](int d, int v) { return (d * NV + v) * N3 + a; };
+    // the N values of the fibre with face index b along d
+    auto fibre = [&](const T *cellbase, int d, int v, int b, T out[N]) {
+        const T *src = cellbase + (d * NV + v) * N3;
+#pragma unroll
+        for (int e = 0; e < N; ++e) out[e] = src[node_from_face<N>(d, e, b)];
+    };
 
     for (int it = 0; it < npic; ++it) {
         T acc[N][NV];
@@ -160,26 +197,26 @@ __device__ __forceinline__ void predictor_body(T *__restrict__ lds, const double
 #pragma unroll
         for (int j = 0; j < N; ++j) {
             T f[3][NV];
-            euler_flux3(gm1, q[j], f);
+            flux3(gm1, q[j], f);
             __syncthreads();
             if (lane_ok) {
 #pragma unroll
                 for (int d = 0; d < 3; ++d)
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) my[(d * NV + v) * N3 + a] = f[d][v];
+                    for (int v = 0; v < NV; ++v) my[put_at(d, v)] = f[d][v];
             }
             __syncthreads();
             if (lane_ok) {
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
-                    T gx = T(0), gy = T(0), gz = T(0);
+                    T G = T(0);
 #pragma unroll
-                    for (int e = 0; e < N; ++e) {
-                        gx += Dx[e] * my[(0 * NV + v) * N3 + e + bx];
-                        gy += Dy[e] * my[(1 * NV + v) * N3 + N * e + by];
-                        gz += Dz[e] * my[(2 * NV + v) * N3 + N2 * e + bz];
+                    for (int d = 0; d < 3; ++d) {
+                        T fib[N];
+                        fibre(my, d, v, bf[d], fib);
+#pragma unroll
+                        for (int e = 0; e < N; ++e) G += Dc[d][e] * fib[e];
                     }
-                    const T G = cx * gx + cy * gy + cz * gz;
 #pragma unroll
                     for (int l = 0; l < N; ++l) acc[l][v] += T(B.KW[l * N + j]) * G;
                 }
@@ -209,7 +246,7 @@ __device__ __forceinline__ void predictor_body(T *__restrict__ lds, const double
 #pragma unroll
     for (int j = 0; j < N; ++j) {
         T f[3][NV];
-        euler_flux3(gm1, q[j], f);
+        flux3(gm1, q[j], f);
         const T wj = T(B.w[j]);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -223,28 +260,33 @@ __device__ __forceinline__ void predictor_body(T *__restrict__ lds, const double
 #pragma unroll
         for (int d = 0; d < 3; ++d)
 #pragma unroll
-            for (int v = 0; v < NV; ++v) my[(d * NV + v) * N3 + a] = Fb[d][v];
+            for (int v = 0; v < NV; ++v) my[put_at(d, v)] = Fb[d][v];
     }
     __syncthreads();
 
     // volume term of the corrector: u* = u + sum_d (dt/dx_d)/w_{a_d} sum_e Kw[a_d][e] Fbar_d
     if (active) {
-        const T sx = cx * T(B.winv[a0]), sy = cy * T(B.winv[a1]), sz = cz * T(B.winv[a2]);
+        T Kc[3][N];
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int e = 0; e < N; ++e) Kc[d][e] = T(cdd[d] * B.winv[aa[d]] * B.Kw[aa[d] * N + e]);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            T vx = T(0), vy = T(0), vz = T(0);
+            T V = T(0);
 #pragma unroll
-            for (int e = 0; e < N; ++e) {
-                vx += T(B.Kw[a0 * N + e]) * my[(0 * NV + v) * N3 + e + bx];
-                vy += T(B.Kw[a1 * N + e]) * my[(1 * NV + v) * N3 + N * e + by];
-                vz += T(B.Kw[a2 * N + e]) * my[(2 * NV + v) * N3 + N2 * e + bz];
+            for (int d = 0; d < 3; ++d) {
+                T fib[N];
+                fibre(my, d, v, bf[d], fib);
+#pragma unroll
+                for (int e = 0; e < N; ++e) V += Kc[d][e] * fib[e];
             }
-            const T V = sx * vx + sy * vy + sz * vz;
             ustar[(int64_t(v) * nc + c) * N3 + a] = ud[v] + double(V);
         }
     }
 
-    // face projections: normal flux component (arr 1), then the state (arr 0)
+    // face projections: normal flux component (arr 1), then the state (arr 0,
+    // stored along all three axes)
     const int64_t base = first;
     constexpr int ITEMS = 6 * NV * CPB * N2;
     for (int arr = 1; arr >= 0; --arr) {
@@ -252,7 +294,9 @@ __device__ __forceinline__ void predictor_body(T *__restrict__ lds, const double
             __syncthreads();
             if (lane_ok) {
 #pragma unroll
-                for (int v = 0; v < NV; ++v) my[v * N3 + a] = qb[v];
+                for (int d = 0; d < 3; ++d)
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) my[put_at(d, v)] = qb[v];
             }
             __syncthreads();
         }
@@ -264,15 +308,15 @@ __device__ __forceinline__ void predictor_body(T *__restrict__ lds, const double
             const int64_t c2 = list ? int64_t(list[idx2]) : idx2;
             const int d = s >> 1;
             const double *E = (s & 1) ? B.R : B.L;
-            const T *src = lds + cl2 * 15 * N3 + (arr == 1 ? (d * NV + v) : v) * N3;
+            T fib[N];
+            fibre(lds + cl2 * PC, d, v, b, fib);
             T accv = T(0);
 #pragma unroll
-            for (int e = 0; e < N; ++e) accv += T(E[e]) * src[node_from_face<N>(d, e, b)];
+            for (int e = 0; e < N; ++e) accv += T(E[e]) * fib[e];
             traces[((int64_t(s * 2 + arr) * NV + v) * nc + c2) * N2 + b] = accv;
         }
     }
 }
-
 
 template <typename T, int N, int CPB, bool STORE>
 __global__ void __launch_bounds__(round64(CPB * N * N * N))
@@ -281,7 +325,7 @@ k_predictor(const double *__restrict__ u, double *__restrict__ ustar, T *__restr
             const int8_t *__restrict__ level, Geo geo, const double *__restrict__ dt_dev,
             double gamma, int npic, T *__restrict__ iters)
 {
-    __shared__ T lds[CPB * 15 * N * N * N];
+    __shared__ __align__(16) T lds[CPB * Fib<T, N>::PER_CELL];
     predictor_body<T, N, CPB, STORE>(lds, u, ustar, traces, list, nlist, nc, level, geo, dt_dev[0], gamma, npic,
                                      int64_t(blockIdx.x) * CPB, iters);
 }
@@ -314,7 +358,7 @@ k_predictor_order(const PredItem *__restrict__ items, int64_t nitems, const Pred
                   const double *__restrict__ u, double *__restrict__ ustar, T *__restrict__ traces,
                   const double *__restrict__ dt)
 {
-    __shared__ T lds[CPB * 15 * N * N * N];
+    __shared__ __align__(16) T lds[CPB * Fib<T, N>::PER_CELL];
     for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         const PredItem w = items[it];
         const PredInst &I = insts[w.inst];
@@ -1438,6 +1482,12 @@ void pred_variant_shape(int code, int *N, int *CPB)
 }
 
 template <typename T>
+size_t fib_per_cell(int N)
+{
+    return size_t(15) * N * N * N;
+}
+
+template <typename T>
 hipError_t launch_predictor_batch(const PredItem *items, int64_t nitems, const PredInst *insts, const double *u,
                                   double *ustar, T *traces, const double *dt, int threads, int grid,
                                   hipStream_t st)
@@ -1447,7 +1497,7 @@ hipError_t launch_predictor_batch(const PredItem *items, int64_t nitems, const P
     for (int c = 0; c < PRED_VARIANTS; ++c) {
         int N, CPB;
         pred_variant_shape(c, &N, &CPB);
-        if (round64(CPB * N * N * N) <= threads) lds = std::max(lds, size_t(CPB) * 15 * N * N * N * sizeof(T));
+        if (round64(CPB * N * N * N) <= threads) lds = std::max(lds, size_t(CPB) * fib_per_cell<T>(N) * sizeof(T));
     }
     hipLaunchKernelGGL(k_predictor_batch<T>, dim3(grid), dim3(threads), lds, st, items, nitems, insts, u, ustar,
                        traces, dt);
@@ -1502,7 +1552,7 @@ int predictor_batch_occupancy(int threads)
     for (int c = 0; c < PRED_VARIANTS; ++c) {
         int N, CPB;
         pred_variant_shape(c, &N, &CPB);
-        if (round64(CPB * N * N * N) <= threads) lds = std::max(lds, size_t(CPB) * 15 * N * N * N * sizeof(T));
+        if (round64(CPB * N * N * N) <= threads) lds = std::max(lds, size_t(CPB) * fib_per_cell<T>(N) * sizeof(T));
     }
     int blocks = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_predictor_batch<T>, threads, lds) != hipSuccess)
