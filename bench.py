@@ -34,15 +34,21 @@ PEAK = {"hbm_GBs": 8000.0, "fp64_TFs": 78.6, "fp32_TFs": 157.3}
 
 def predictor_flops_per_node(N, npic):
     """Algorithmic flops of the predictor per spatial node (FMA = 2 flops,
-    division = 1): npic Picard iterations of [N flux evaluations (29 flops)
-    + 3 derivative contractions (2N each) per variable and time node + the
-    time solve (2N per variable, time node)], the epilogue (N flux evaluations,
-    time averages of the state and the 3 fluxes, volume term) and the face
-    projections (12 arrays x 5 variables x N^2 face nodes x 2N per cell)."""
+    division = 1).  A Picard iteration from a general iterate costs N flux
+    evaluations (29 flops) + 3 derivative contractions (2N each) per variable
+    and time node + the time solve (2N per variable and time node).  The first
+    iteration starts from the time-constant state u, so its N time nodes share
+    one flux evaluation and one set of contractions, and the time solve
+    reduces to the row sums of the time matrix (2 flops per variable and time
+    node).  Then the epilogue (N flux evaluations, time averages of the state
+    and the 3 fluxes, volume term) and the face projections (12 arrays x 5
+    variables x N^2 face nodes x 2N per cell)."""
     per_iter = N * (29 + 5 * (3 * 2 * N + 5 + 2 * N)) + 5 * N
+    first_iter = 29 + 5 * (3 * 2 * N + 5) + 5 * 2 * N
     epilogue = N * (29 + 5 * 2 + 15 * 2) + 5 * (3 * 2 * N + 6)
     traces = 12 * 5 * N * N * 2 * N / N ** 3
-    return npic * per_iter + epilogue + traces
+    iters = first_iter + (npic - 1) * per_iter if npic > 0 else 0
+    return iters + epilogue + traces
 
 
 def predictor_bytes_per_cell(N, real_bytes):

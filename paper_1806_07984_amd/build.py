@@ -20,6 +20,10 @@ FLAGS = [
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
     # no packed FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in ordinary VGPRs: the FP32 predictor feeds every MFMA
+    # result straight into VALU work, and AGPR operands would cost a
+    # v_accvgpr_read per element
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wno-unused-command-line-argument",
 ]
 

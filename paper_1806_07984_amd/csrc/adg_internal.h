@@ -38,6 +38,7 @@ struct DevBasis {
     double KW[NMAX * NMAX];
     double Kw[NMAX * NMAX];
     double w[NMAX], winv[NMAX], L[NMAX], R[NMAX], xi[NMAX];
+    double KWsum[NMAX];  // row sums sum_j KW[l][j] (time solve from a time-constant state)
 };
 
 // Per-mesh geometry passed to kernels by value.

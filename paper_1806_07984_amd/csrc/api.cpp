@@ -133,6 +133,9 @@ adg_status ensure_basis(int device)
             tab[N].L[e] = b.L[e];
             tab[N].R[e] = b.R[e];
             tab[N].xi[e] = b.xi[e];
+            double rs = 0.0;
+            for (int j = 0; j < N && e < N; ++j) rs += b.KW[e * N + j];
+            tab[N].KWsum[e] = rs;
         }
     }
     if (upload_basis(tab) != hipSuccess) {

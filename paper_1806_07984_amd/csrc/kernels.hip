@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <cmath>
 #include <type_traits>
+#include <vector>
 
 #include "adg_internal.h"
 #include "kernels.h"
@@ -27,6 +28,20 @@
 namespace adg {
 
 __constant__ DevBasis c_basis[NMAX + 1];
+
+// Per-lane coefficient rows of the N = 4 FP32 predictor (one wavefront per
+// cell, lane l = node a0 + 4 a1 + 16 a2), LANE4 floats per lane, in the order
+// the rotations of the x (quad), y (row) and z (row group) sums visit them:
+//   [0,4)   D[a0][(a0+e)&3]          [4,8)   D[a1][(a1-e)&3]
+//   [8,12)  D[a2][(a2+k)&3]          [12,16) KW[a0][e]
+//   [16,20) Kw[a0][(a0+e)&3]/w[a0]   [20,24) Kw[a1][(a1-e)&3]/w[a1]
+//   [24,28) Kw[a2][(a2+k)&3]/w[a2]
+//   [28,32) P(a0)[(a0+e)&3], [32,36) P(a1)[(a1-e)&3], [36,40) P(a2)[(a2+k)&3]
+//           with P(t) = L for t = 0, R otherwise (only the face lanes store)
+constexpr int LANE4 = 40;
+__constant__ float c_lane4[64 * LANE4];
+// row sums sum_l KW[j][l] of the N = 4 time solve (first Picard iteration)
+__constant__ float c_kwsum4[4];
 
 namespace {
 
@@ -37,20 +52,16 @@ __device__ __forceinline__ T rcp(T x) { return T(1) / x; }
 template <typename T>
 __device__ __forceinline__ void euler_flux3(T gm1, const T q[NV], T f[3][NV])
 {
+    // velocities once; the momentum flux m_de = rho v_d v_e is symmetric
     const T inv = rcp(q[0]);
-    const T ke = T(0.5) * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) * inv;
-    const T p = gm1 * (q[4] - ke);
+    const T v0 = q[1] * inv, v1 = q[2] * inv, v2 = q[3] * inv;
+    const T m00 = v0 * q[1], m11 = v1 * q[2], m22 = v2 * q[3];
+    const T m01 = v0 * q[2], m02 = v0 * q[3], m12 = v1 * q[3];
+    const T p = gm1 * (q[4] - T(0.5) * (m00 + m11 + m22));
     const T Ep = q[4] + p;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const T vd = q[1 + d] * inv;
-        f[d][0] = q[1 + d];
-        f[d][1] = vd * q[1];
-        f[d][2] = vd * q[2];
-        f[d][3] = vd * q[3];
-        f[d][1 + d] += p;
-        f[d][4] = vd * Ep;
-    }
+    f[0][0] = q[1]; f[0][1] = m00 + p; f[0][2] = m01; f[0][3] = m02; f[0][4] = v0 * Ep;
+    f[1][0] = q[2]; f[1][1] = m01; f[1][2] = m11 + p; f[1][3] = m12; f[1][4] = v1 * Ep;
+    f[2][0] = q[3]; f[2][1] = m02; f[2][2] = m12; f[2][3] = m22 + p; f[2][4] = v2 * Ep;
 }
 
 // |u_d| + c and a physical-state check.
@@ -107,28 +118,30 @@ template <typename T, int N> struct Fib {
     static constexpr int PER_CELL = 15 * N * N * N;
 };
 
-// Euler fluxes; the FP32 form uses the hardware reciprocal for 1/rho
+// Euler fluxes in FP32: hardware reciprocal for 1/rho, and the symmetric
+// momentum flux formed once
+__device__ __forceinline__ void euler_flux3_fast(float gm1, const float q[NV], float f[3][NV])
+{
+    // velocities once; the momentum flux m_de = rho v_d v_e is symmetric
+    const float inv = __builtin_amdgcn_rcpf(q[0]);
+    const float v0 = q[1] * inv, v1 = q[2] * inv, v2 = q[3] * inv;
+    const float m00 = v0 * q[1], m11 = v1 * q[2], m22 = v2 * q[3];
+    const float m01 = v0 * q[2], m02 = v0 * q[3], m12 = v1 * q[3];
+    // p = (gamma - 1) (E - rho |v|^2 / 2)
+    const float p = fmaf(-0.5f * gm1, m00 + m11 + m22, gm1 * q[4]);
+    const float Ep = q[4] + p;
+    f[0][0] = q[1]; f[0][1] = m00 + p; f[0][2] = m01; f[0][3] = m02; f[0][4] = v0 * Ep;
+    f[1][0] = q[2]; f[1][1] = m01; f[1][2] = m11 + p; f[1][3] = m12; f[1][4] = v1 * Ep;
+    f[2][0] = q[3]; f[2][1] = m02; f[2][2] = m12; f[2][3] = m22 + p; f[2][4] = v2 * Ep;
+}
+
 template <typename T>
 __device__ __forceinline__ void flux3(T gm1, const T q[NV], T f[3][NV])
 {
-    if constexpr (std::is_same<T, float>::value) {
-        const float inv = __builtin_amdgcn_rcpf(q[0]);
-        const float ke = 0.5f * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) * inv;
-        const float p = gm1 * (q[4] - ke);
-        const float Ep = q[4] + p;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const float vd = q[1 + d] * inv;
-            f[d][0] = q[1 + d];
-            f[d][1] = vd * q[1];
-            f[d][2] = vd * q[2];
-            f[d][3] = vd * q[3];
-            f[d][1 + d] += p;
-            f[d][4] = vd * Ep;
-        }
-    } else {
+    if constexpr (std::is_same<T, float>::value)
+        euler_flux3_fast(gm1, q, f);
+    else
         euler_flux3(gm1, q, f);
-    }
 }
 
 // Predictor of CPB cells (list entries first .. first+CPB-1) by one block of
@@ -188,7 +201,56 @@ __device__ __forceinline__ void predictor_body(T *__restrict__ lds, const double
         for (int e = 0; e < N; ++e) out[e] = src[node_from_face<N>(d, e, b)];
     };
 
-    for (int it = 0; it < npic; ++it) {
+    // scaled divergence sum_d (dt/dx_d) D_d F_d(qn) at this lane's node
+    auto divergence = [&](const T qn[NV], T G[NV]) {
+        T f[3][NV];
+        flux3(gm1, qn, f);
+        __syncthreads();
+        if (lane_ok) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) my[put_at(d, v)] = f[d][v];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            G[v] = T(0);
+            if (lane_ok) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    T fib[N];
+                    fibre(my, d, v, bf[d], fib);
+#pragma unroll
+                    for (int e = 0; e < N; ++e) G[v] += Dc[d][e] * fib[e];
+                }
+            }
+        }
+    };
+    // iterate it+1, kept for the adjoint: [slot][l][v][cell][N^3]
+    auto store_iterate = [&](int it) {
+        if (STORE && active) {
+#pragma unroll
+            for (int l = 0; l < N; ++l)
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+                    iters[(((int64_t(it) * N + l) * NV + v) * nc + c) * N3 + a] = q[l][v];
+        }
+    };
+
+    if (npic > 0) {
+        // first iteration from q = u at every time node: one flux and one
+        // divergence serve all time nodes, and the row sums of KW finish the
+        // time solve
+        T G[NV];
+        divergence(uu, G);
+#pragma unroll
+        for (int l = 0; l < N; ++l)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) q[l][v] = uu[v] - T(B.KWsum[l]) * G[v];
+        store_iterate(0);
+    }
+    for (int it = 1; it < npic; ++it) {
         T acc[N][NV];
 #pragma unroll
         for (int l = 0; l < N; ++l)
@@ -196,44 +258,18 @@ __device__ __forceinline__ void predictor_body(T *__restrict__ lds, const double
             for (int v = 0; v < NV; ++v) acc[l][v] = T(0);
 #pragma unroll
         for (int j = 0; j < N; ++j) {
-            T f[3][NV];
-            flux3(gm1, q[j], f);
-            __syncthreads();
-            if (lane_ok) {
+            T G[NV];
+            divergence(q[j], G);
 #pragma unroll
-                for (int d = 0; d < 3; ++d)
+            for (int v = 0; v < NV; ++v)
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) my[put_at(d, v)] = f[d][v];
-            }
-            __syncthreads();
-            if (lane_ok) {
-#pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    T G = T(0);
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        T fib[N];
-                        fibre(my, d, v, bf[d], fib);
-#pragma unroll
-                        for (int e = 0; e < N; ++e) G += Dc[d][e] * fib[e];
-                    }
-#pragma unroll
-                    for (int l = 0; l < N; ++l) acc[l][v] += T(B.KW[l * N + j]) * G;
-                }
-            }
+                for (int l = 0; l < N; ++l) acc[l][v] += T(B.KW[l * N + j]) * G[v];
         }
 #pragma unroll
         for (int l = 0; l < N; ++l)
 #pragma unroll
             for (int v = 0; v < NV; ++v) q[l][v] = uu[v] - acc[l][v];
-        if (STORE && active) {
-            // iterate it+1, kept for the adjoint: [slot][l][v][cell][N^3]
-#pragma unroll
-            for (int l = 0; l < N; ++l)
-#pragma unroll
-                for (int v = 0; v < NV; ++v)
-                    iters[(((int64_t(it) * N + l) * NV + v) * nc + c) * N3 + a] = q[l][v];
-        }
+        store_iterate(it);
     }
 
     // time averages of the state and of the fluxes of the final iterate
@@ -413,10 +449,13 @@ k_predictor_batch(const PredItem *__restrict__ items, int64_t nitems, const Pred
 //                  into the FMAs;
 //   y contraction: the y fibre is lanes a0 + 4 k of a 16-lane row -> DPP row
 //                  rotations by 4 k;
-//   z contraction: the z fibre is the four 16-lane row groups, which is the
-//                  K dimension of v_mfma_f32_16x16x4f32 (A row 4t carries
-//                  dt/dx_z D[t][k], other rows zero; the result for this
-//                  lane's node lands in accumulator register 0);
+//   z contraction: the z fibre is the four 16-lane row groups; DPP does not
+//                  cross rows, so the three other values come through
+//                  ds_bpermute (the LDS crossbar, which issues beside the
+//                  VALU) and plain FMAs.  (A 16x16x4 MFMA with three of four
+//                  A rows zero does the same sum, but matrix-core and VALU
+//                  work do not overlap here, and it costs 32 cycles against
+//                  16 for the FMAs);
 //   time solve:    q_l -= sum_j KW[l][j] G_j is a register-axis contraction,
 //                  done by v_mfma_f32_4x4x1f32 (16 blocks of 4 lanes: lane
 //                  4b+i supplies KW[i][j], every lane its own G_j; register
@@ -429,10 +468,9 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // DPP pattern).  The compiler does not fold DPP moves into v_fmac_f32 here,
 // so the fused forms are written directly.  The hazard recognizer does not
 // look inside the block, so it carries its own wait states: s_nop 1 before
-// (a DPP read after a VALU write of its source), and s_nop 2 after row_sum,
-// whose result an MFMA reads next (quad_sum's result only feeds VALU
-// instructions).  The blocks are volatile so that they are never moved into
-// a branch with a partial EXEC mask.
+// (a DPP read after a VALU write of its source).  Results feed ordinary VALU
+// code or stores only, never an MFMA directly.  The blocks are volatile so
+// that they are never moved into a branch with a partial EXEC mask.
 //
 // x fibre (a lane quad): c[k] multiplies x from the lane with a0' = (a0+k)&3.
 __device__ __forceinline__ float quad_sum(const float c[4], float x, float acc)
@@ -455,35 +493,79 @@ __device__ __forceinline__ float row_sum(const float c[4], float x, float acc)
     asm volatile("s_nop 1\n\t"
         "v_fmac_f32_dpp %0, %1, %2 row_ror:4 row_mask:0xf bank_mask:0xf\n\t"
         "v_fmac_f32_dpp %0, %1, %3 row_ror:8 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %0, %1, %4 row_ror:12 row_mask:0xf bank_mask:0xf\n\t"
-        "s_nop 2"
+        "v_fmac_f32_dpp %0, %1, %4 row_ror:12 row_mask:0xf bank_mask:0xf"
         : "+v"(acc)
         : "v"(x), "v"(c[1]), "v"(c[2]), "v"(c[3]));
     return acc;
 }
 
-// z fibre through MFMA: returns acc + sum_k A-row(t = a2)[k] * x(lane with a2 = k)
-__device__ __forceinline__ f32x4 z_mfma(float a, float x, f32x4 c)
+// x and y derivative sums of the five flux components of one time node.  On
+// entry G[v] holds the lane's own x term; adds the lane's own y term, then the
+// three neighbour terms of x (quad rotations) and of y (row rotations by 4, 8,
+// 12 lanes).  The five plain FMAs ahead of the first DPP read give the DPP
+// sources their required distance from any earlier write.  G is read next by
+// ordinary (compiler-scheduled) VALU code only.
+__device__ __forceinline__ void xy_sums5(float G[NV], const float fx[NV], const float fy[NV], const float Cx[4],
+                                         const float Cy[4])
 {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, x, c, 0, 0, 0);
+    asm volatile(
+        "v_fmac_f32 %0, %10, %15\n\t"
+        "v_fmac_f32 %1, %11, %15\n\t"
+        "v_fmac_f32 %2, %12, %15\n\t"
+        "v_fmac_f32 %3, %13, %15\n\t"
+        "v_fmac_f32 %4, %14, %15\n\t"
+        "v_fmac_f32_dpp %0, %5, %16 quad_perm:[1,2,3,0] row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %6, %16 quad_perm:[1,2,3,0] row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, %7, %16 quad_perm:[1,2,3,0] row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, %8, %16 quad_perm:[1,2,3,0] row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %4, %9, %16 quad_perm:[1,2,3,0] row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %5, %17 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %6, %17 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, %7, %17 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, %8, %17 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %4, %9, %17 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %5, %18 quad_perm:[3,0,1,2] row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %6, %18 quad_perm:[3,0,1,2] row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, %7, %18 quad_perm:[3,0,1,2] row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, %8, %18 quad_perm:[3,0,1,2] row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %4, %9, %18 quad_perm:[3,0,1,2] row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %10, %19 row_ror:4 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %11, %19 row_ror:4 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, %12, %19 row_ror:4 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, %13, %19 row_ror:4 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %4, %14, %19 row_ror:4 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %10, %20 row_ror:8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %11, %20 row_ror:8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, %12, %20 row_ror:8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, %13, %20 row_ror:8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %4, %14, %20 row_ror:8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %10, %21 row_ror:12 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %11, %21 row_ror:12 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, %12, %21 row_ror:12 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, %13, %21 row_ror:12 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %4, %14, %21 row_ror:12 row_mask:0xf bank_mask:0xf"
+        : "+v"(G[0]), "+v"(G[1]), "+v"(G[2]), "+v"(G[3]), "+v"(G[4])
+        : "v"(fx[0]), "v"(fx[1]), "v"(fx[2]), "v"(fx[3]), "v"(fx[4]), "v"(fy[0]), "v"(fy[1]), "v"(fy[2]),
+          "v"(fy[3]), "v"(fy[4]), "v"(Cy[0]), "v"(Cx[1]), "v"(Cx[2]), "v"(Cx[3]), "v"(Cy[1]), "v"(Cy[2]),
+          "v"(Cy[3]));
 }
 
-__device__ __forceinline__ void euler_flux3_fast(float gm1, const float q[NV], float f[3][NV])
+// x of the lane whose byte address (4 x lane index) is addr, through the LDS
+// crossbar (no LDS memory is used)
+__device__ __forceinline__ float from_row(int addr, float x)
 {
-    const float inv = __builtin_amdgcn_rcpf(q[0]);
-    const float ke = 0.5f * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) * inv;
-    const float p = gm1 * (q[4] - ke);
-    const float Ep = q[4] + p;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const float vd = q[1 + d] * inv;
-        f[d][0] = q[1 + d];
-        f[d][1] = vd * q[1];
-        f[d][2] = vd * q[2];
-        f[d][3] = vd * q[3];
-        f[d][1 + d] += p;
-        f[d][4] = vd * Ep;
-    }
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(x)));
+}
+
+// base + byte offset, with the offset a 32-bit unsigned value: a wave-uniform
+// base then stays in scalar registers and the access uses scalar-base addressing
+template <typename T> __device__ __forceinline__ T *lane_at(T *base, unsigned byte_off)
+{
+    return reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off);
+}
+template <typename T> __device__ __forceinline__ const T *lane_at(const T *base, unsigned byte_off)
+{
+    return reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
 }
 
 // One cell per wavefront; work item w covers cells first + w.
@@ -500,42 +582,76 @@ __device__ __forceinline__ void pred4_wave(const double *__restrict__ u, double 
     const float cz = float(dt * geo.inv_dx[lev][2]);
     const float gm1 = float(gamma - 1.0);
 
+    // wave-uniform bases plus a 32-bit lane byte offset (scalar-base addressing)
+    const unsigned lu = unsigned(l) * unsigned(sizeof(double));
     float uu[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) uu[v] = float(u[(int64_t(v) * nc + c) * N3 + l]);
+    for (int v = 0; v < NV; ++v) uu[v] = float(*lane_at(u + (int64_t(v) * nc + c) * N3, lu));
 
-    // per-lane coefficients
-    float Cx[4], Cy[4], KWa[4];
+    // per-lane coefficients (one scalar base, one lane offset)
+    const float *Tl = lane_at(static_cast<const float *>(c_lane4), unsigned(l) * unsigned(LANE4 * sizeof(float)));
+    float Cx[4], Cy[4], Cz[4], KWa[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        Cx[e] = cx * float(B.D[a0 * N + ((a0 + e) & 3)]);
-        Cy[e] = cy * float(B.D[a1 * N + ((a1 - e) & 3)]);
-        KWa[e] = float(B.KW[a0 * N + e]);  // lane 4b+i supplies KW[i][j], i = a0
+        Cx[e] = cx * Tl[e];
+        Cy[e] = cy * Tl[4 + e];
+        Cz[e] = cz * Tl[8 + e];
+        KWa[e] = Tl[12 + e];  // lane 4b+i supplies KW[i][j], i = a0
     }
-    const float Az = (a0 == 0) ? cz * float(B.D[a1 * N + a2]) : 0.0f;  // A[row = l%16][k = l/16]
-    const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
+    // z neighbours come through the LDS crossbar: from_row(pz[k], x) is x of
+    // the lane with a2' = (a2 + k) & 3 (same a0, a1)
+    int pz[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pz[k] = ((l + 16 * k) & 63) * 4;
+
+    // scaled divergence sum_d (dt/dx_d) D_d F_d(qn) at this lane's node
+    auto spatial = [&](const float qn[NV], float g[NV]) {
+        float f[3][NV];
+        euler_flux3_fast(gm1, qn, f);
+        float zn[3][NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int k = 1; k < 4; ++k) zn[k - 1][v] = from_row(pz[k], f[2][v]);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) g[v] = Cx[0] * f[0][v];
+        xy_sums5(g, f[0], f[1], Cx, Cy);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            g[v] = fmaf(Cz[0], f[2][v], g[v]);
+#pragma unroll
+            for (int k = 1; k < 4; ++k) g[v] = fmaf(Cz[k], zn[k - 1][v], g[v]);
+        }
+    };
 
     float q[N][NV];
+    if (npic > 0) {
+        // first iteration from q = u at every time node: one flux and one
+        // spatial sum serve all time nodes, and the row sums of KW finish
+        // the time solve
+        float g[NV];
+        spatial(uu, g);
 #pragma unroll
-    for (int j = 0; j < N; ++j)
+        for (int j = 0; j < N; ++j)
 #pragma unroll
-        for (int v = 0; v < NV; ++v) q[j][v] = uu[v];
+            for (int v = 0; v < NV; ++v) q[j][v] = fmaf(-c_kwsum4[j], g[v], uu[v]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) q[j][v] = uu[v];
+    }
 
-    for (int it = 0; it < npic; ++it) {
+    for (int it = 1; it < npic; ++it) {
         f32x4 acc[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[v] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int j = 0; j < N; ++j) {
-            float f[3][NV];
-            euler_flux3_fast(gm1, q[j], f);
+            float g[NV];
+            spatial(q[j], g);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                const f32x4 g4 = z_mfma(Az, f[2][v], zero4);
-                float G = quad_sum(Cx, f[0][v], g4[0]);
-                G = row_sum(Cy, f[1][v], G);
-                acc[v] = __builtin_amdgcn_mfma_f32_4x4x1f32(KWa[j], G, acc[v], 0, 0, 0);
-            }
+            for (int v = 0; v < NV; ++v) acc[v] = __builtin_amdgcn_mfma_f32_4x4x1f32(KWa[j], g[v], acc[v], 0, 0, 0);
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v)
@@ -565,80 +681,93 @@ __device__ __forceinline__ void pred4_wave(const double *__restrict__ u, double 
 
     // volume term with the weak stiffness Kw (same three mechanisms)
     {
-        float Vx[4], Vy[4];
-        const float sx = cx * float(B.winv[a0]), sy = cy * float(B.winv[a1]);
+        float Vx[4], Vy[4], Vz[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            Vx[e] = sx * float(B.Kw[a0 * N + ((a0 + e) & 3)]);
-            Vy[e] = sy * float(B.Kw[a1 * N + ((a1 - e) & 3)]);
+            Vx[e] = cx * Tl[16 + e];
+            Vy[e] = cy * Tl[20 + e];
+            Vz[e] = cz * Tl[24 + e];
         }
-        const float Avz = (a0 == 0) ? cz * float(B.winv[a1]) * float(B.Kw[a1 * N + a2]) : 0.0f;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            const f32x4 r = z_mfma(Avz, Fb[2][v], zero4);
-            float V = quad_sum(Vx, Fb[0][v], r[0]);
+            float V = Vz[0] * Fb[2][v];
+#pragma unroll
+            for (int k = 1; k < 4; ++k) V = fmaf(Vz[k], from_row(pz[k], Fb[2][v]), V);
+            V = quad_sum(Vx, Fb[0][v], V);
             V = row_sum(Vy, Fb[1][v], V);
-            const int64_t o = (int64_t(v) * nc + c) * N3 + l;
-            ustar[o] = u[o] + double(V);
+            const int64_t o = (int64_t(v) * nc + c) * N3;
+            *lane_at(ustar + o, lu) = *lane_at(u + o, lu) + double(V);
         }
     }
 
-    // face projections: L (minus) and R (plus) along each axis
+    // face projections: L (minus) and R (plus) along each axis.  The x sum
+    // runs with L weights in lanes a0 = 0 and R weights in the other lanes, so
+    // lane a0 = 0 holds the minus-face value and lane a0 = 3 the plus-face
+    // value of one sum (y likewise over a1).  Stores go through 64-byte raw
+    // buffer views of one face plane each; lanes that do not store get an
+    // offset beyond the view, which buffer range checking drops.
     {
-        float Lx[4], Rx[4], Ly[4], Ry[4];
+        float Px[4], Py[4], Pz[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            Lx[e] = float(B.L[(a0 + e) & 3]);
-            Rx[e] = float(B.R[(a0 + e) & 3]);
-            Ly[e] = float(B.L[(a1 - e) & 3]);
-            Ry[e] = float(B.R[(a1 - e) & 3]);
+            Px[e] = Tl[28 + e];
+            Py[e] = Tl[32 + e];
+            Pz[e] = Tl[36 + e];
         }
-        // z: A row 4t + 0 carries L[k], row 4t + 1 carries R[k]
-        const float Ap = (a0 == 0) ? float(B.L[a2]) : ((a0 == 1) ? float(B.R[a2]) : 0.0f);
-        const int bx = a1 + 4 * a2, by = a0 + 4 * a2, bz = a0 + 4 * a1;
-        auto put = [&](int s, int arr, int v, int b, float x) {
-            traces[((int64_t(s * 2 + arr) * NV + v) * nc + c) * N2 + b] = x;
+        constexpr unsigned F = sizeof(float), OUT = 0x80000000u;
+        const unsigned bx = (a1 + 4 * a2) * F, by = (a0 + 4 * a2) * F, bz = (a0 + 4 * a1) * F;
+        const unsigned o0 = a0 == 0 ? bx : OUT, o1 = a0 == 3 ? bx : OUT;
+        const unsigned o2 = a1 == 0 ? by : OUT, o3 = a1 == 3 ? by : OUT;
+        const unsigned o4 = a2 == 0 ? bz : OUT, o5 = a2 == 3 ? bz : OUT;
+        auto put = [&](int s, int arr, int v, unsigned off, float x) {
+            float *plane = traces + ((int64_t(s * 2 + arr) * NV + v) * nc + c) * N2;
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x),
+                                                  __builtin_amdgcn_make_buffer_rsrc(plane, 0, N2 * F, 0x00020000),
+                                                  off, 0, 0);
         };
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
 #pragma unroll
             for (int arr = 0; arr < 2; ++arr) {
                 // x faces: state or normal flux Fx
-                const float xv = arr == 0 ? qb[v] : Fb[0][v];
-                const float pxl = quad_sum(Lx, xv, 0.f), pxr = quad_sum(Rx, xv, 0.f);
-                if (a0 == 0) put(0, arr, v, bx, pxl);
-                if (a0 == 3) put(1, arr, v, bx, pxr);
-                const float yv = arr == 0 ? qb[v] : Fb[1][v];
-                const float pyl = row_sum(Ly, yv, 0.f), pyr = row_sum(Ry, yv, 0.f);
-                if (a1 == 0) put(2, arr, v, by, pyl);
-                if (a1 == 3) put(3, arr, v, by, pyr);
+                const float px = quad_sum(Px, arr == 0 ? qb[v] : Fb[0][v], 0.f);
+                put(0, arr, v, o0, px);
+                put(1, arr, v, o1, px);
+                const float py = row_sum(Py, arr == 0 ? qb[v] : Fb[1][v], 0.f);
+                put(2, arr, v, o2, py);
+                put(3, arr, v, o3, py);
                 const float zv = arr == 0 ? qb[v] : Fb[2][v];
-                const f32x4 r = z_mfma(Ap, zv, zero4);
-                if (a2 == 0) put(4, arr, v, bz, r[0]);
-                if (a2 == 3) put(5, arr, v, bz, r[1]);
+                float pz_ = Pz[0] * zv;
+#pragma unroll
+                for (int k = 1; k < 4; ++k) pz_ = fmaf(Pz[k], from_row(pz[k], zv), pz_);
+                put(4, arr, v, o4, pz_);
+                put(5, arr, v, o5, pz_);
             }
         }
     }
 }
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_predictor4_mfma(const double *__restrict__ u, double *__restrict__ ustar, float *__restrict__ traces,
                   const int32_t *__restrict__ list, int64_t nlist, int64_t nc, const int8_t *__restrict__ level,
                   Geo geo, const double *__restrict__ dt_dev, double gamma, int npic)
 {
-    const int64_t idx = int64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    // the wave index is uniform across the wavefront: saying so keeps the cell
+    // index and every address derived from it in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const int64_t idx = int64_t(blockIdx.x) * (blockDim.x >> 6) + wave;
     if (idx >= nlist) return;  // whole wavefront leaves together
     const int64_t c = list ? int64_t(list[idx]) : idx;
     pred4_wave(u, ustar, traces, c, nc, level ? level[c] : 0, geo, dt_dev[0], gamma, npic);
 }
 
 // persistent form over batched work items of order 4 (items of CPB cells)
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_predictor4_mfma_order(const PredItem *__restrict__ items, int64_t nitems, const PredInst *__restrict__ insts,
                         const double *__restrict__ u, double *__restrict__ ustar, float *__restrict__ traces,
                         const double *__restrict__ dt, int cpb)
 {
-    const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)), nwaves = blockDim.x >> 6;
     for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         const PredItem w = items[it];
         const PredInst &I = insts[w.inst];
@@ -1375,7 +1504,35 @@ bool g_pred4_mfma = true;
 
 hipError_t upload_basis(const DevBasis *tab)
 {
-    return hipMemcpyToSymbol(HIP_SYMBOL(c_basis), tab, sizeof(DevBasis) * (NMAX + 1));
+    hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_basis), tab, sizeof(DevBasis) * (NMAX + 1));
+    if (e != hipSuccess) return e;
+    // lane rows of the N = 4 FP32 predictor (layout at c_lane4)
+    const DevBasis &B = tab[4];
+    constexpr int N = 4;
+    std::vector<float> lane(64 * LANE4);
+    for (int l = 0; l < 64; ++l) {
+        const int a[3] = {l & 3, (l >> 2) & 3, l >> 4};
+        float *r = &lane[l * LANE4];
+        for (int e = 0; e < 4; ++e) {
+            // neighbour visited at step e of each axis' rotation
+            const int nx = (a[0] + e) & 3, ny = (a[1] - e) & 3, nz = (a[2] + e) & 3;
+            r[e] = float(B.D[a[0] * N + nx]);
+            r[4 + e] = float(B.D[a[1] * N + ny]);
+            r[8 + e] = float(B.D[a[2] * N + nz]);
+            r[12 + e] = float(B.KW[a[0] * N + e]);
+            r[16 + e] = float(B.Kw[a[0] * N + nx] * B.winv[a[0]]);
+            r[20 + e] = float(B.Kw[a[1] * N + ny] * B.winv[a[1]]);
+            r[24 + e] = float(B.Kw[a[2] * N + nz] * B.winv[a[2]]);
+            r[28 + e] = float(a[0] == 0 ? B.L[nx] : B.R[nx]);
+            r[32 + e] = float(a[1] == 0 ? B.L[ny] : B.R[ny]);
+            r[36 + e] = float(a[2] == 0 ? B.L[nz] : B.R[nz]);
+        }
+    }
+    e = hipMemcpyToSymbol(HIP_SYMBOL(c_lane4), lane.data(), sizeof(float) * lane.size());
+    if (e != hipSuccess) return e;
+    float kws[4];
+    for (int j = 0; j < 4; ++j) kws[j] = float(B.KWsum[j]);
+    return hipMemcpyToSymbol(HIP_SYMBOL(c_kwsum4), kws, sizeof(kws));
 }
 
 template <typename T>
