@@ -42,6 +42,9 @@ constexpr int LANE4 = 40;
 __constant__ float c_lane4[64 * LANE4];
 // row sums sum_l KW[j][l] of the N = 4 time solve (first Picard iteration)
 __constant__ float c_kwsum4[4];
+// lift weights of the N = 4 corrector per lane (node): R[a_d]/w[a_d] for
+// d = 0, 1, 2, then L[a_d]/w[a_d]
+__constant__ double c_corr4[64 * 6];
 
 namespace {
 
@@ -550,6 +553,36 @@ __device__ __forceinline__ void xy_sums5(float G[NV], const float fx[NV], const 
           "v"(Cy[3]));
 }
 
+// Raw buffer views: a wave-uniform base (in scalar registers) of a given byte
+// size, addressed by a 32-bit lane offset.  Offsets beyond the size read as
+// zero and drop stores (buffer range checking), which is also how lanes skip
+// a store without a branch.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_view(const void *base, int bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, bytes, 0x00020000);
+}
+__device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, unsigned off, float)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ double buf_ld(__amdgpu_buffer_rsrc_t r, unsigned off, double)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned off, float x)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned off, double x)
+{
+    using b64 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(b64, x), r, off, 0, 0);
+}
+
+#ifndef SCHED_SPLIT
+#define SCHED_SPLIT() __builtin_amdgcn_sched_barrier(0)
+#endif
+
 // x of the lane whose byte address (4 x lane index) is addr, through the LDS
 // crossbar (no LDS memory is used)
 __device__ __forceinline__ float from_row(int addr, float x)
@@ -613,6 +646,7 @@ __device__ __forceinline__ void pred4_wave(const double *__restrict__ u, double 
         for (int v = 0; v < NV; ++v)
 #pragma unroll
             for (int k = 1; k < 4; ++k) zn[k - 1][v] = from_row(pz[k], f[2][v]);
+        SCHED_SPLIT();
 #pragma unroll
         for (int v = 0; v < NV; ++v) g[v] = Cx[0] * f[0][v];
         xy_sums5(g, f[0], f[1], Cx, Cy);
@@ -652,6 +686,7 @@ __device__ __forceinline__ void pred4_wave(const double *__restrict__ u, double 
             spatial(q[j], g);
 #pragma unroll
             for (int v = 0; v < NV; ++v) acc[v] = __builtin_amdgcn_mfma_f32_4x4x1f32(KWa[j], g[v], acc[v], 0, 0, 0);
+            SCHED_SPLIT();
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v)
@@ -784,12 +819,33 @@ k_predictor4_mfma_order(const PredItem *__restrict__ items, int64_t nitems, cons
 // Riemann solves on conforming faces of one axis
 // ---------------------------------------------------------------------------
 
+// maximum over the 16 lanes of each DPP row, in every lane (rotations by 8,
+// 4, 2, 1 lanes); doubles move as two 32-bit halves
+template <int K> __device__ __forceinline__ float ror_max(float x)
+{
+    return fmaxf(x, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x120 + K, 0xf, 0xf, false)));
+}
+template <int K> __device__ __forceinline__ double ror_max(double x)
+{
+    const long long bits = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, int(bits & 0xffffffff), 0x120 + K, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, int(bits >> 32), 0x120 + K, 0xf, 0xf, false);
+    return fmax(x, __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo)));
+}
+template <typename T> __device__ __forceinline__ T row_max16(T x)
+{
+    return ror_max<1>(ror_max<2>(ror_max<4>(ror_max<8>(x))));
+}
+
 template <int N> struct FaceCfg {
     static constexpr int FPB = (256 / (N * N)) > 0 ? 256 / (N * N) : 1;
     static constexpr int THREADS = round64(FPB * N * N);
 };
 
-template <typename T, int N>
+// B32: every trace and face plane (one side, array and variable over all
+// cells) is below 2 GiB, so accesses are buffer loads and stores from a
+// scalar plane base with a 32-bit per-lane offset
+template <typename T, int N, bool B32>
 __global__ void __launch_bounds__(FaceCfg<N>::THREADS)
 k_riemann(const T *__restrict__ traces, T *__restrict__ fside, const int32_t *__restrict__ fm,
           const int32_t *__restrict__ fp, int64_t nf, int d, int64_t nc, double gamma,
@@ -810,18 +866,41 @@ k_riemann(const T *__restrict__ traces, T *__restrict__ fside, const int32_t *__
     if (active) {
         cL = fm[f];
         cR = fp[f];
+        if constexpr (B32) {
+            const int pb = int(nc * N2 * int64_t(sizeof(T)));
+            const unsigned oL = unsigned(cL * N2 + b) * unsigned(sizeof(T));
+            const unsigned oR = unsigned(cR * N2 + b) * unsigned(sizeof(T));
+            auto plane = [&](int side, int arr, int v) {
+                return buf_view(traces + (int64_t(side * 2 + arr) * NV + v) * nc * N2, pb);
+            };
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            QL[v] = traces[((int64_t(sL * 2 + 0) * NV + v) * nc + cL) * N2 + b];
-            FL[v] = traces[((int64_t(sL * 2 + 1) * NV + v) * nc + cL) * N2 + b];
-            QR[v] = traces[((int64_t(sR * 2 + 0) * NV + v) * nc + cR) * N2 + b];
-            FR[v] = traces[((int64_t(sR * 2 + 1) * NV + v) * nc + cR) * N2 + b];
+            for (int v = 0; v < NV; ++v) {
+                QL[v] = buf_ld(plane(sL, 0, v), oL, T(0));
+                FL[v] = buf_ld(plane(sL, 1, v), oL, T(0));
+                QR[v] = buf_ld(plane(sR, 0, v), oR, T(0));
+                FR[v] = buf_ld(plane(sR, 1, v), oR, T(0));
+            }
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                QL[v] = traces[((int64_t(sL * 2 + 0) * NV + v) * nc + cL) * N2 + b];
+                FL[v] = traces[((int64_t(sL * 2 + 1) * NV + v) * nc + cL) * N2 + b];
+                QR[v] = traces[((int64_t(sR * 2 + 0) * NV + v) * nc + cR) * N2 + b];
+                FR[v] = traces[((int64_t(sR * 2 + 1) * NV + v) * nc + cR) * N2 + b];
+            }
         }
         bool badL, badR;
         lL = wave_speed(g, gm1, QL, d, badL);
         lR = wave_speed(g, gm1, QR, d, badR);
         if (badL || badR) *status = 1;
     }
+    T s;
+    if (N2 == 16 && tape_mode == TAPE_OFF) {
+        // one face per 16-lane row: the maximum over (node, side) by row
+        // rotations (a maximum is exact, so this equals the serial scan)
+        s = row_max16(lL > lR ? lL : lR);  // speeds are >= 0 and finite unless flagged
+        if (!active) return;
+    } else {
     if (lane_ok) {
         slam[2 * tid] = lL;
         slam[2 * tid + 1] = lR;
@@ -830,7 +909,6 @@ k_riemann(const T *__restrict__ traces, T *__restrict__ fside, const int32_t *__
     if (!active) return;
     // s = the largest speed over (node, side); its first maximiser in
     // (node, minus side first) order can be recorded or replayed
-    T s;
     if (tape_mode == TAPE_REPLAY) {
         s = slam[2 * fl * N2 + tape[f]];
     } else {
@@ -845,11 +923,18 @@ k_riemann(const T *__restrict__ traces, T *__restrict__ fside, const int32_t *__
         }
         if (tape_mode == TAPE_RECORD && b == 0) tape[f] = int16_t(arg);
     }
+    }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         const T F = T(0.5) * (FL[v] + FR[v]) - T(0.5) * s * (QR[v] - QL[v]);
-        fside[(int64_t(sL * NV + v) * nc + cL) * N2 + b] = F;
-        fside[(int64_t(sR * NV + v) * nc + cR) * N2 + b] = F;
+        if constexpr (B32) {
+            const int pb = int(nc * N2 * int64_t(sizeof(T)));
+            buf_st(buf_view(fside + (int64_t(sL) * NV + v) * nc * N2, pb), unsigned(cL * N2 + b) * unsigned(sizeof(T)), F);
+            buf_st(buf_view(fside + (int64_t(sR) * NV + v) * nc * N2, pb), unsigned(cR * N2 + b) * unsigned(sizeof(T)), F);
+        } else {
+            fside[(int64_t(sL * NV + v) * nc + cL) * N2 + b] = F;
+            fside[(int64_t(sR * NV + v) * nc + cR) * N2 + b] = F;
+        }
     }
 }
 
@@ -1057,6 +1142,54 @@ __device__ __forceinline__ double block_max(double x, double *sh)
     }
     __syncthreads();
     return sh[0];
+}
+
+// N = 4: one wavefront per cell (lane = node), so the cell index is uniform
+// and every address is a scalar base plus a 32-bit lane offset.  Grid-stride
+// over cells with the same block count as the generic form.
+template <typename T, bool FUSE>
+__global__ void __launch_bounds__(256)
+k_corrector4(const double *__restrict__ ustar, const T *__restrict__ fside, const double *__restrict__ dt_dev,
+             double *__restrict__ uout, int64_t nc, const int8_t *__restrict__ level, Geo geo, double gamma,
+             double *__restrict__ partial, int *__restrict__ status)
+{
+    constexpr int N2 = 16, N3 = 64;
+    const int l = threadIdx.x & 63;
+    const int a0 = l & 3, a1 = (l >> 2) & 3, a2 = l >> 4;
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const unsigned lu = unsigned(l) * unsigned(sizeof(double));
+    const unsigned bx = unsigned(a1 + 4 * a2) * unsigned(sizeof(T)), by = unsigned(a0 + 4 * a2) * unsigned(sizeof(T)),
+                   bz = unsigned(a0 + 4 * a1) * unsigned(sizeof(T));
+    const double *Wl = lane_at(static_cast<const double *>(c_corr4), unsigned(l) * unsigned(6 * sizeof(double)));
+    const double Rx = Wl[0], Ry = Wl[1], Rz = Wl[2], Lx = Wl[3], Ly = Wl[4], Lz = Wl[5];
+    const double dt = dt_dev[0];
+    double rate = 0.0;
+    for (int64_t c = int64_t(blockIdx.x) * (blockDim.x >> 6) + wave; c < nc;
+         c += int64_t(gridDim.x) * (blockDim.x >> 6)) {
+        const int lev = level ? __builtin_amdgcn_readfirstlane(int(level[c])) : 0;
+        const double cx = dt * geo.inv_dx[lev][0], cy = dt * geo.inv_dx[lev][1], cz = dt * geo.inv_dx[lev][2];
+        double q[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            auto face = [&](int side, unsigned off) {
+                return double(buf_ld(buf_view(fside + ((int64_t(side) * NV + v) * nc + c) * N2, N2 * sizeof(T)), off,
+                                     T(0)));
+            };
+            const double fxm = face(0, bx), fxp = face(1, bx);
+            const double fym = face(2, by), fyp = face(3, by);
+            const double fzm = face(4, bz), fzp = face(5, bz);
+            const double sv = cx * (Rx * fxp - Lx * fxm) + cy * (Ry * fyp - Ly * fym) + cz * (Rz * fzp - Lz * fzm);
+            const int64_t o = (int64_t(v) * nc + c) * N3;
+            q[v] = buf_ld(buf_view(ustar + o, N3 * sizeof(double)), lu, 0.0) - sv;
+            buf_st(buf_view(uout + o, N3 * sizeof(double)), lu, q[v]);
+        }
+        if (FUSE) rate = fmax(rate, cfl_rate(gamma, q, geo, lev, status));
+    }
+    if (FUSE) {
+        __shared__ double sh[4];
+        rate = block_max(rate, sh);
+        if (threadIdx.x == 0) partial[blockIdx.x] = rate;
+    }
 }
 
 template <int N>
@@ -1532,7 +1665,17 @@ hipError_t upload_basis(const DevBasis *tab)
     if (e != hipSuccess) return e;
     float kws[4];
     for (int j = 0; j < 4; ++j) kws[j] = float(B.KWsum[j]);
-    return hipMemcpyToSymbol(HIP_SYMBOL(c_kwsum4), kws, sizeof(kws));
+    e = hipMemcpyToSymbol(HIP_SYMBOL(c_kwsum4), kws, sizeof(kws));
+    if (e != hipSuccess) return e;
+    std::vector<double> corr(64 * 6);
+    for (int l = 0; l < 64; ++l) {
+        const int a[3] = {l & 3, (l >> 2) & 3, l >> 4};
+        for (int d = 0; d < 3; ++d) {
+            corr[l * 6 + d] = B.R[a[d]] * B.winv[a[d]];
+            corr[l * 6 + 3 + d] = B.L[a[d]] * B.winv[a[d]];
+        }
+    }
+    return hipMemcpyToSymbol(HIP_SYMBOL(c_corr4), corr.data(), sizeof(double) * corr.size());
 }
 
 template <typename T>
@@ -1573,8 +1716,12 @@ hipError_t launch_riemann(int N, const T *traces, T *fside, const int32_t *fm, c
     ADG_DISPATCH_N(N, {
         constexpr int FPB = FaceCfg<NN>::FPB;
         const int64_t blocks = (nf + FPB - 1) / FPB;
-        hipLaunchKernelGGL((k_riemann<T, NN>), dim3(unsigned(blocks)), dim3(FaceCfg<NN>::THREADS), 0, st,
-                           traces, fside, fm, fp, nf, d, nc, gamma, status, tape, tape_mode);
+        if (nc * NN * NN * int64_t(sizeof(T)) < (int64_t(1) << 31))
+            hipLaunchKernelGGL((k_riemann<T, NN, true>), dim3(unsigned(blocks)), dim3(FaceCfg<NN>::THREADS), 0, st,
+                               traces, fside, fm, fp, nf, d, nc, gamma, status, tape, tape_mode);
+        else
+            hipLaunchKernelGGL((k_riemann<T, NN, false>), dim3(unsigned(blocks)), dim3(FaceCfg<NN>::THREADS), 0, st,
+                               traces, fside, fm, fp, nf, d, nc, gamma, status, tape, tape_mode);
     });
     return hipGetLastError();
 }
@@ -1613,6 +1760,16 @@ hipError_t launch_corrector(int N, const double *ustar, const T *fside, const do
                             double *partial, int *status)
 {
     if (nc <= 0) return hipSuccess;
+    if (N == 4) {
+        const int64_t blocks = corrector_blocks(4, nc);
+        if (partial)
+            hipLaunchKernelGGL((k_corrector4<T, true>), dim3(unsigned(blocks)), dim3(256), 0, st, ustar, fside, dt,
+                               uout, nc, level, geo, gamma, partial, status);
+        else
+            hipLaunchKernelGGL((k_corrector4<T, false>), dim3(unsigned(blocks)), dim3(256), 0, st, ustar, fside, dt,
+                               uout, nc, level, geo, gamma, partial, status);
+        return hipGetLastError();
+    }
     ADG_DISPATCH_N(N, {
         const int64_t blocks = corrector_blocks(NN, nc);
         if (partial)
