@@ -281,7 +281,8 @@ def main():
                    "cells": N_BASE ** 3, "dofs": 5 * N_BASE ** 3 * (ORDER + 1) ** 3, "path": head_prec,
                    "parallelism": "single-gpu"},
         "roofline": {"bound": bound, "achieved": pr["tflops"], "peak": peak, "unit": "TFLOP/s",
-                     "frac": pr["tflops"] / peak, "traffic": traffic, "kernel": f"k_predictor ({head_prec})",
+                     "frac": pr["tflops"] / peak, "traffic": traffic,
+                     "kernel": "adg::k_predictor4_mfma" if head_prec == "fp32" else "adg::k_predictor<double, 4, 4, false>",
                      "avg_launch_ms": pr["avg_ms"],
                      "hbm_GBs_algorithmic": pr["bytes_per_launch"] / (pr["avg_ms"] * 1e-3) / 1e9},
         "paths": {k: {"value": v["value"], "ms_per_step": v["ms_per_step"],
