@@ -186,6 +186,21 @@ adg_status adg_tuning(const adg_mesh *mesh, int32_t *cells_per_block);
  * all orders.  Results are identical either way. */
 adg_status adg_set_options(adg_mesh *mesh, int32_t use_graph, int32_t batched);
 
+/* Pipelined step for a handle with a single instance and no hanging faces
+ * (off by default).  The cells form 8 contiguous chunks;
+ * adg_step runs the predictors chunk by chunk on one of the handle's streams
+ * and, on the other, the Riemann solves of the faces whose two cells are
+ * done, followed by the correctors of chunks whose faces are all solved, so
+ * the bandwidth-bound face and corrector work overlaps the compute-bound
+ * predictor.  The per-cell and per-face arithmetic is unchanged, so results
+ * are identical with the pipeline on or off.  The caller's streams are joined
+ * by events before and after.  ADG_ERR_UNSUPPORTED for other handles when
+ * enable != 0.  Waits for the device before switching.  On one MI355X at
+ * 81^3, p = 3 it is slower than the sequential step (3.40 against 3.28 ms):
+ * the face and corrector kernels also issue VALU work, and running beside
+ * the VALU-bound predictor they slow it by about as much as they save. */
+adg_status adg_set_pipeline(adg_mesh *mesh, int32_t enable);
+
 /* Phase timing for measurement.  While enabled, every launch made by the
  * handle's calls is bracketed by HIP events recorded on the stream the launch
  * goes to.  adg_profile(mesh, 1) enables and clears the accumulators,

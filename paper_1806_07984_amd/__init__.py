@@ -23,7 +23,7 @@ EXPORTS = ["adg_init_mesh", "adg_free_mesh", "adg_mesh_info", "adg_instance_info
            "adg_node_coords", "adg_cfl", "adg_predictor", "adg_riemann", "adg_corrector", "adg_step",
            "adg_profile", "adg_profile_read", "adg_get_status", "adg_last_error", "adg_autotune",
            "adg_tuning", "adg_set_options", "adg_step_adjoint", "adg_sample", "adg_sample_adjoint",
-           "adg_set_switch_tape"]
+           "adg_set_switch_tape", "adg_set_pipeline"]
 PHASES = ["cfl", "predictor", "hanging", "riemann", "corrector"]
 
 
@@ -83,6 +83,7 @@ def load():
         "adg_autotune": [P, P, P, P],
         "adg_tuning": [P, P],
         "adg_set_options": [P, I32, I32],
+        "adg_set_pipeline": [P, I32],
         "adg_step_adjoint": [P, P, P, P, P, P, P],
         "adg_set_switch_tape": [P, P, I32],
         "adg_sample": [P, P, P, I64, P, P],
@@ -273,6 +274,10 @@ class Mesh:
         if batched is None:
             batched = 1 if (self.n_instances > 1 and self.info["n_hanging_faces"] == 0) else 0
         _check(load().adg_set_options(self._h, 1 if use_graph else 0, int(batched)))
+
+    def set_pipeline(self, enable):
+        """Pipelined step over cell chunks (single instance, no hanging faces)."""
+        _check(load().adg_set_pipeline(self._h, 1 if enable else 0))
 
     def profile(self, enable):
         """Enable (and clear) or disable per-phase HIP-event timing."""

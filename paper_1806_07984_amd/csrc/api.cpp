@@ -16,6 +16,9 @@ void set_error(const std::string &msg) { g_last_error = msg; }
 
 namespace {
 
+// pipelined step: number of cell chunks (off by default: measured slower)
+constexpr int PIPE_CHUNKS = 8;
+
 struct Instance {
     HostMesh hm;
     int N = 0, order = 0, npic = 0;
@@ -35,6 +38,15 @@ struct Instance {
     int64_t nskel = 0, nencl = 0;
     double *ptab = nullptr;
     double *partial = nullptr;
+    // pipelined step (one instance without hanging faces): the cells form ps
+    // contiguous chunks and the faces of every axis are sorted by owner
+    // chunk, the later chunk of their two cells
+    int ps = 0;                            // chunks (0: not available)
+    std::vector<int64_t> pcb;              // [ps + 1] chunk cell boundaries
+    std::vector<int64_t> pfo[3];           // [ps + 1] face offsets per axis
+    std::vector<std::vector<int>> pcorr;   // chunks whose corrector follows chunk k's faces
+    std::vector<int64_t> ppoff;            // [ps + 1] offsets of the chunks' CFL block maxima
+    int32_t *ident = nullptr;              // cell list 0 .. nc-1
 };
 
 }  // namespace
@@ -77,6 +89,11 @@ struct adg_mesh {
     hipGraphExec_t gexec = nullptr;
     const void *gkey_u = nullptr, *gkey_ws = nullptr;
     bool gkey_two = false;
+    // pipelined step: predictors chunk by chunk on one stream, the faces and
+    // correctors of finished chunks on another
+    bool pipeline = false;
+    std::vector<hipEvent_t> ev_chunk;
+    hipEvent_t ev_join = nullptr;
 };
 
 namespace adg {
@@ -174,8 +191,11 @@ void free_all(adg_mesh *m)
     if (m->insts_dev) (void)hipFree(m->insts_dev);
     m->items_dev = nullptr;
     m->insts_dev = nullptr;
-    for (hipEvent_t *e : {&m->ev_in, &m->ev_in2, &m->ev_out})
+    for (hipEvent_t *e : {&m->ev_in, &m->ev_in2, &m->ev_out, &m->ev_join})
         if (*e) (void)hipEventDestroy(*e);
+    for (hipEvent_t e : m->ev_chunk)
+        if (e) (void)hipEventDestroy(e);
+    m->ev_chunk.clear();
     if (m->gs_a) (void)hipStreamDestroy(m->gs_a);
     if (m->gs_b) (void)hipStreamDestroy(m->gs_b);
     for (void *p : m->allocs) (void)hipFree(p);
@@ -388,6 +408,12 @@ adg_status do_corrector(adg_mesh *m, const double *ustar, const T *fside, const 
     return ADG_OK;
 }
 
+// number of CFL block maxima the corrector leaves for the next step
+int nparts(const adg_mesh *m, const Instance &I)
+{
+    return m->pipeline && I.ps > 0 ? int(I.ppoff[I.ps]) : corrector_blocks(I.N, I.nc);
+}
+
 adg_status do_cfl(adg_mesh *m, const double *u, double *dt, double *hist, hipStream_t st)
 {
     PhaseTimer tm(m, ADG_PHASE_CFL, st);
@@ -406,7 +432,8 @@ adg_status do_cfl_prime(adg_mesh *m, const double *u, hipStream_t st)
 {
     PhaseTimer tm(m, ADG_PHASE_CFL, st);
     for (auto &I : m->inst)
-        ADG_HIP(launch_cfl_prime(I.N, u + I.u_off, I.nc, I.level, I.geo, I.gamma, I.partial, m->status_dev, st),
+        ADG_HIP(launch_cfl_prime(I.N, u + I.u_off, I.nc, I.level, I.geo, I.gamma, I.partial, nparts(m, I),
+                                 m->status_dev, st),
                 "cfl block maxima");
     return ADG_OK;
 }
@@ -417,11 +444,55 @@ adg_status do_cfl_fused(adg_mesh *m, double *dt, double *hist, hipStream_t st)
     PhaseTimer tm(m, ADG_PHASE_CFL, st);
     for (size_t i = 0; i < m->inst.size(); ++i) {
         Instance &I = m->inst[i];
-        ADG_HIP(launch_cfl_final(I.partial, corrector_blocks(I.N, I.nc), I.cfl / (2.0 * I.order + 1.0), dt + i,
+        ADG_HIP(launch_cfl_final(I.partial, nparts(m, I), I.cfl / (2.0 * I.order + 1.0), dt + i,
                                  hist ? hist + i : nullptr, st),
                 "cfl final");
     }
     return ADG_OK;
+}
+
+// Chunks of the pipelined step: ps contiguous cell ranges; the faces of every
+// axis stably sorted by owner chunk (the later chunk of their two cells); the
+// corrector of chunk j follows the faces of the latest chunk that owns a face
+// of j; the CFL block maxima of chunk j start at ppoff[j].
+void build_chunks(Instance &I)
+{
+    HostMesh &h = I.hm;
+    const int S = PIPE_CHUNKS;
+    I.ps = S;
+    I.pcb.resize(S + 1);
+    for (int k = 0; k <= S; ++k) I.pcb[k] = h.nc * k / S;
+    auto chunk = [&](int32_t c) {
+        return int(std::upper_bound(I.pcb.begin(), I.pcb.end(), int64_t(c)) - I.pcb.begin()) - 1;
+    };
+    std::vector<int> dep(S);
+    for (int k = 0; k < S; ++k) dep[k] = k;
+    for (int a = 0; a < 3; ++a) {
+        const size_t nf = h.face_m[a].size();
+        std::vector<int> own(nf);
+        std::vector<int64_t> cnt(S + 1, 0);
+        for (size_t f = 0; f < nf; ++f) {
+            const int cm = chunk(h.face_m[a][f]), cp = chunk(h.face_p[a][f]);
+            own[f] = std::max(cm, cp);
+            dep[cm] = std::max(dep[cm], own[f]);
+            dep[cp] = std::max(dep[cp], own[f]);
+            ++cnt[own[f] + 1];
+        }
+        for (int k = 0; k < S; ++k) cnt[k + 1] += cnt[k];
+        I.pfo[a] = cnt;
+        std::vector<int32_t> fm(nf), fp(nf);
+        for (size_t f = 0; f < nf; ++f) {
+            const int64_t at = cnt[own[f]]++;
+            fm[size_t(at)] = h.face_m[a][f];
+            fp[size_t(at)] = h.face_p[a][f];
+        }
+        h.face_m[a].swap(fm);
+        h.face_p[a].swap(fp);
+    }
+    I.pcorr.assign(S, {});
+    for (int j = 0; j < S; ++j) I.pcorr[dep[j]].push_back(j);
+    I.ppoff.assign(S + 1, 0);
+    for (int j = 0; j < S; ++j) I.ppoff[j + 1] = I.ppoff[j] + corrector_blocks(I.N, I.pcb[j + 1] - I.pcb[j]);
 }
 
 // Enqueues one whole step (CFL, predictor, faces, corrector) on the streams.
@@ -460,10 +531,82 @@ adg_status enqueue_step(adg_mesh *m, double *u, double *hist, void *ws, hipStrea
     return ADG_OK;
 }
 
+// One whole step, pipelined over cell chunks (single instance, no hanging
+// faces).  Stream A: dt, then the predictor of chunk 0, 1, ...  Stream B: as
+// soon as chunk k's predictor is done, the faces chunk k owns (both cells'
+// predictors are then done), then the corrector of every chunk whose faces
+// are now all solved.  B joins A at the end.  Per-cell and per-face
+// arithmetic is that of enqueue_step, so the results are identical.
+template <typename T>
+adg_status enqueue_step_pipe(adg_mesh *m, double *u, double *hist, void *ws, hipStream_t A, hipStream_t B)
+{
+    char *w = static_cast<char *>(ws);
+    double *ustar = reinterpret_cast<double *>(w);
+    w += align_up(sizeof(double) * m->info.u_elems);
+    T *traces = reinterpret_cast<T *>(w);
+    w += align_up(sizeof(T) * m->info.trace_elems);
+    T *fside = reinterpret_cast<T *>(w);
+    Instance &I = m->inst[0];
+    const int S = I.ps;
+    adg_status st = do_cfl_fused(m, m->dt_dev, hist, A);
+    if (st != ADG_OK) return st;
+    ADG_HIP(hipEventRecord(m->ev_dt, A), "event record");
+    ADG_HIP(hipStreamWaitEvent(B, m->ev_dt, 0), "stream wait");
+    for (int k = 0; k < S; ++k) {
+        {
+            PhaseTimer tm(m, ADG_PHASE_PREDICTOR, A);
+            ADG_HIP(launch_predictor<T>(I.N, u, ustar, traces, I.ident + I.pcb[k], I.pcb[k + 1] - I.pcb[k], I.nc,
+                                        I.level, I.geo, m->dt_dev, I.gamma, I.npic, A),
+                    "predictor (chunk)");
+        }
+        ADG_HIP(hipEventRecord(m->ev_chunk[k], A), "event record");
+    }
+    for (int k = 0; k < S; ++k) {
+        ADG_HIP(hipStreamWaitEvent(B, m->ev_chunk[k], 0), "stream wait");
+        {
+            PhaseTimer tm(m, ADG_PHASE_RIEMANN, B);
+            for (int d = 0; d < 3; ++d)
+                ADG_HIP(launch_riemann<T>(I.N, traces, fside, I.face_m[d] + I.pfo[d][k], I.face_p[d] + I.pfo[d][k],
+                                          I.pfo[d][k + 1] - I.pfo[d][k], d, I.nc, I.gamma, m->status_dev, B),
+                        "riemann (chunk)");
+        }
+        for (int j : I.pcorr[k]) {
+            PhaseTimer tm(m, ADG_PHASE_CORRECTOR, B);
+            ADG_HIP(launch_corrector<T>(I.N, ustar, fside, m->dt_dev, u, I.nc, I.level, I.geo, B, I.gamma,
+                                        I.partial + I.ppoff[j], m->status_dev, I.pcb[j], I.pcb[j + 1]),
+                    "corrector (chunk)");
+        }
+    }
+    ADG_HIP(hipEventRecord(m->ev_join, B), "event record");
+    ADG_HIP(hipStreamWaitEvent(A, m->ev_join, 0), "stream wait");
+    return ADG_OK;
+}
+
 template <typename T>
 adg_status step_eager(adg_mesh *m, double *u, int32_t n_steps, double *hist, void *ws, hipStream_t s_skel,
                       hipStream_t s_encl)
 {
+    if (m->pipeline) {
+        // the handle's two streams, joined with the caller's before and after
+        hipStream_t A = m->gs_a, B = m->gs_b;
+        ADG_HIP(hipEventRecord(m->ev_in, s_skel), "event record");
+        ADG_HIP(hipStreamWaitEvent(A, m->ev_in, 0), "stream wait");
+        if (s_skel != s_encl) {
+            ADG_HIP(hipEventRecord(m->ev_in2, s_encl), "event record");
+            ADG_HIP(hipStreamWaitEvent(A, m->ev_in2, 0), "stream wait");
+        }
+        const int ni = int(m->inst.size());
+        adg_status st0 = do_cfl_prime(m, u, A);
+        if (st0 != ADG_OK) return st0;
+        for (int n = 0; n < n_steps; ++n) {
+            adg_status st = enqueue_step_pipe<T>(m, u, hist ? hist + int64_t(n) * ni : nullptr, ws, A, B);
+            if (st != ADG_OK) return st;
+        }
+        ADG_HIP(hipEventRecord(m->ev_out, A), "event record");
+        ADG_HIP(hipStreamWaitEvent(s_skel, m->ev_out, 0), "stream wait");
+        if (s_skel != s_encl) ADG_HIP(hipStreamWaitEvent(s_encl, m->ev_out, 0), "stream wait");
+        return ADG_OK;
+    }
     const int ni = int(m->inst.size());
     adg_status st0 = do_cfl_prime(m, u, s_skel);
     if (st0 != ADG_OK) return st0;
@@ -488,7 +631,7 @@ adg_status step_graph(adg_mesh *m, double *u, int32_t n_steps, double *hist, voi
                       hipStream_t s_encl)
 {
     const bool two = s_skel != s_encl;
-    hipStream_t A = m->gs_a, B = two ? m->gs_b : m->gs_a;
+    hipStream_t A = m->gs_a, B = (two || m->pipeline) ? m->gs_b : m->gs_a;
     ADG_HIP(hipEventRecord(m->ev_in, s_skel), "event record");
     ADG_HIP(hipStreamWaitEvent(A, m->ev_in, 0), "stream wait");
     if (two) {
@@ -502,7 +645,8 @@ adg_status step_graph(adg_mesh *m, double *u, int32_t n_steps, double *hist, voi
     if (!m->gexec || m->gkey_u != u || m->gkey_ws != ws || m->gkey_two != two) {
         drop_graph(m);
         ADG_HIP(hipStreamBeginCapture(A, hipStreamCaptureModeThreadLocal), "begin capture");
-        adg_status st = enqueue_step<T>(m, u, nullptr, ws, A, B);
+        adg_status st = m->pipeline ? enqueue_step_pipe<T>(m, u, nullptr, ws, A, B)
+                                    : enqueue_step<T>(m, u, nullptr, ws, A, B);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(A, &g);
         if (st != ADG_OK) {
@@ -684,8 +828,14 @@ adg_status adg_init_mesh(const adg_instance_desc *desc, int32_t n_instances, adg
     bool ok = true;
     for (auto &I : m->inst) {
         HostMesh &h = I.hm;
+        if (n_instances == 1 && h.hang.empty() && h.nc >= 2 * PIPE_CHUNKS) build_chunks(I);
         if (h.max_level > 0) ok = ok && upload(m, I.level, h.level.data(), h.level.size());
         ok = ok && upload(m, I.ijk, h.ijk.data(), h.ijk.size());
+        if (I.ps > 0) {
+            std::vector<int32_t> id(size_t(I.nc));
+            for (int64_t c = 0; c < I.nc; ++c) id[size_t(c)] = int32_t(c);
+            ok = ok && upload(m, I.ident, id.data(), id.size());
+        }
         for (int a = 0; a < 3; ++a) {
             I.nf[a] = int64_t(h.face_m[a].size());
             ok = ok && upload(m, I.face_m[a], h.face_m[a].data(), h.face_m[a].size());
@@ -721,7 +871,8 @@ adg_status adg_init_mesh(const adg_instance_desc *desc, int32_t n_instances, adg
             }
         }
         ok = ok && upload(m, I.ptab, pt.data(), pt.size());
-        ok = ok && dev_alloc(m, I.partial, size_t(std::max(CFL_MAX_BLOCKS, corrector_blocks(I.N, I.nc))));
+        ok = ok && dev_alloc(m, I.partial, size_t(std::max<int64_t>({CFL_MAX_BLOCKS, corrector_blocks(I.N, I.nc),
+                                                                      I.ps > 0 ? I.ppoff[I.ps] : 0})));
         // the host copy of the cell table is kept (adg_mesh_cells); face lists are not needed
         for (int a = 0; a < 3; ++a) {
             std::vector<int32_t>().swap(h.face_m[a]);
@@ -761,7 +912,12 @@ adg_status adg_init_mesh(const adg_instance_desc *desc, int32_t n_instances, adg
     if (ok)
         ok = hipEventCreateWithFlags(&m->ev_dt, hipEventDisableTiming) == hipSuccess &&
              hipEventCreateWithFlags(&m->ev_skel, hipEventDisableTiming) == hipSuccess &&
-             hipEventCreateWithFlags(&m->ev_encl, hipEventDisableTiming) == hipSuccess;
+             hipEventCreateWithFlags(&m->ev_encl, hipEventDisableTiming) == hipSuccess &&
+             hipEventCreateWithFlags(&m->ev_join, hipEventDisableTiming) == hipSuccess;
+    if (ok && m->inst[0].ps > 0) {
+        m->ev_chunk.assign(size_t(m->inst[0].ps), nullptr);
+        for (auto &e : m->ev_chunk) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+    }
     if (!ok) {
         set_error("device allocation or upload failed");
         free_all(m);
@@ -964,6 +1120,19 @@ adg_status adg_set_options(adg_mesh *mesh, int32_t use_graph, int32_t batched)
     }
     mesh->use_graph = use_graph != 0;
     mesh->batched = batched;
+    drop_graph(mesh);
+    return ADG_OK;
+}
+
+adg_status adg_set_pipeline(adg_mesh *mesh, int32_t enable)
+{
+    if (!valid_mesh(mesh)) return ADG_ERR_INVALID_ARG;
+    if (enable && mesh->inst[0].ps == 0) {
+        set_error("adg_set_pipeline: the pipelined step needs a single instance without hanging faces");
+        return ADG_ERR_UNSUPPORTED;
+    }
+    ADG_HIP(hipDeviceSynchronize(), "synchronize");
+    mesh->pipeline = enable != 0;
     drop_graph(mesh);
     return ADG_OK;
 }

@@ -75,16 +75,18 @@ template <typename T>
 hipError_t launch_restrict(int N, T *fside, const HangDev *hang, const int32_t *ccell, const int8_t *cside,
                            const int32_t *cptr, const int32_t *cchild, int64_t ncs, int64_t nc,
                            const double *ptab, hipStream_t st);
-// partial != nullptr: also write the CFL maximum of the new state per block
-// (corrector_blocks(N, nc) values) for the next step's launch_cfl_final.
+// Cells c0 .. c1-1 (c1 < 0: all nc cells).  partial != nullptr: also write
+// the CFL maximum of the new state per block (corrector_blocks(N, c1 - c0)
+// values) for the next step's launch_cfl_final.
 template <typename T>
 hipError_t launch_corrector(int N, const double *ustar, const T *fside, const double *dt, double *uout,
                             int64_t nc, const int8_t *level, const Geo &geo, hipStream_t st, double gamma = 0.0,
-                            double *partial = nullptr, int *status = nullptr);
+                            double *partial = nullptr, int *status = nullptr, int64_t c0 = 0, int64_t c1 = -1);
 int corrector_blocks(int N, int64_t nc);
-// block maxima of the CFL rate of u in the corrector's block layout
+// block maxima of the CFL rate of u, nb blocks (the number of maxima the next
+// launch_cfl_final reads)
 hipError_t launch_cfl_prime(int N, const double *u, int64_t nc, const int8_t *level, const Geo &geo, double gamma,
-                            double *partial, int *status, hipStream_t st);
+                            double *partial, int nb, int *status, hipStream_t st);
 hipError_t launch_cfl_final(const double *partial, int nparts, double factor, double *dt_out, double *hist,
                             hipStream_t st);
 

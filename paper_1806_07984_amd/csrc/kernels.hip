@@ -1083,16 +1083,16 @@ template <typename T, int N, bool FUSE>
 __global__ void __launch_bounds__(256)
 k_corrector(const double *__restrict__ ustar, const T *__restrict__ fside, const double *__restrict__ dt_dev,
             double *__restrict__ uout, int64_t nc, const int8_t *__restrict__ level, Geo geo, double gamma,
-            double *__restrict__ partial, int *__restrict__ status)
+            double *__restrict__ partial, int *__restrict__ status, int64_t c0, int64_t c1)
 {
     constexpr int N2 = N * N, N3 = N2 * N;
     const DevBasis &B = c_basis[N];
     const double dt = dt_dev[0];
     double rate = 0.0;
-    const int64_t total = nc * N3;
-    // grid-stride over nodes (the grid is capped so that the fused CFL
-    // leaves few block maxima)
-    for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
+    const int64_t total = c1 * N3;
+    // grid-stride over the nodes of cells c0 .. c1-1 (the grid is capped so
+    // that the fused CFL leaves few block maxima)
+    for (int64_t t = c0 * N3 + int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
          t += int64_t(gridDim.x) * blockDim.x) {
         const int64_t c = t / N3;
         const int a = int(t % N3), a0 = a % N, a1 = (a / N) % N, a2 = a / N2;
@@ -1151,7 +1151,7 @@ template <typename T, bool FUSE>
 __global__ void __launch_bounds__(256)
 k_corrector4(const double *__restrict__ ustar, const T *__restrict__ fside, const double *__restrict__ dt_dev,
              double *__restrict__ uout, int64_t nc, const int8_t *__restrict__ level, Geo geo, double gamma,
-             double *__restrict__ partial, int *__restrict__ status)
+             double *__restrict__ partial, int *__restrict__ status, int64_t c0, int64_t c1)
 {
     constexpr int N2 = 16, N3 = 64;
     const int l = threadIdx.x & 63;
@@ -1164,7 +1164,7 @@ k_corrector4(const double *__restrict__ ustar, const T *__restrict__ fside, cons
     const double Rx = Wl[0], Ry = Wl[1], Rz = Wl[2], Lx = Wl[3], Ly = Wl[4], Lz = Wl[5];
     const double dt = dt_dev[0];
     double rate = 0.0;
-    for (int64_t c = int64_t(blockIdx.x) * (blockDim.x >> 6) + wave; c < nc;
+    for (int64_t c = c0 + int64_t(blockIdx.x) * (blockDim.x >> 6) + wave; c < c1;
          c += int64_t(gridDim.x) * (blockDim.x >> 6)) {
         const int lev = level ? __builtin_amdgcn_readfirstlane(int(level[c])) : 0;
         const double cx = dt * geo.inv_dx[lev][0], cy = dt * geo.inv_dx[lev][1], cz = dt * geo.inv_dx[lev][2];
@@ -1187,6 +1187,65 @@ k_corrector4(const double *__restrict__ ustar, const T *__restrict__ fside, cons
     }
     if (FUSE) {
         __shared__ double sh[4];
+        rate = block_max(rate, sh);
+        if (threadIdx.x == 0) partial[blockIdx.x] = rate;
+    }
+}
+
+// N >= 5: a cell spans W = ceil(N^3 / 64) wavefronts (node a = 64 w + lane),
+// so the cell index is again uniform per wavefront and all accesses are
+// buffer accesses from scalar bases.  Lanes past N^3 use out-of-range offsets
+// (loads read zero, stores are dropped) and stay out of the CFL maximum.
+template <int N> struct CorrW {
+    static constexpr int W = (N * N * N + 63) / 64;
+    static constexpr int CPB = W >= 4 ? 1 : 4 / W;  // cells per block
+    static constexpr int THREADS = 64 * W * CPB;
+};
+
+template <typename T, int N, bool FUSE>
+__global__ void __launch_bounds__(CorrW<N>::THREADS)
+k_correctorW(const double *__restrict__ ustar, const T *__restrict__ fside, const double *__restrict__ dt_dev,
+             double *__restrict__ uout, int64_t nc, const int8_t *__restrict__ level, Geo geo, double gamma,
+             double *__restrict__ partial, int *__restrict__ status, int64_t c0, int64_t c1)
+{
+    constexpr int N2 = N * N, N3 = N2 * N, W = CorrW<N>::W, CPB = CorrW<N>::CPB;
+    constexpr unsigned OUT = 0x80000000u;
+    const DevBasis &B = c_basis[N];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const int a = (wave % W) * 64 + lane, cl = wave / W;
+    const bool node_ok = a < N3;
+    const int a0 = node_ok ? a % N : 0, a1 = node_ok ? (a / N) % N : 0, a2 = node_ok ? a / N2 : 0;
+    const unsigned lu = node_ok ? unsigned(a) * unsigned(sizeof(double)) : OUT;
+    const unsigned bx = node_ok ? unsigned(a1 + N * a2) * unsigned(sizeof(T)) : OUT;
+    const unsigned by = node_ok ? unsigned(a0 + N * a2) * unsigned(sizeof(T)) : OUT;
+    const unsigned bz = node_ok ? unsigned(a0 + N * a1) * unsigned(sizeof(T)) : OUT;
+    const double Rx = B.R[a0] * B.winv[a0], Ry = B.R[a1] * B.winv[a1], Rz = B.R[a2] * B.winv[a2];
+    const double Lx = B.L[a0] * B.winv[a0], Ly = B.L[a1] * B.winv[a1], Lz = B.L[a2] * B.winv[a2];
+    const double dt = dt_dev[0];
+    double rate = 0.0;
+    for (int64_t c = c0 + int64_t(blockIdx.x) * CPB + cl; c < c1; c += int64_t(gridDim.x) * CPB) {
+        const int lev = level ? __builtin_amdgcn_readfirstlane(int(level[c])) : 0;
+        const double cx = dt * geo.inv_dx[lev][0], cy = dt * geo.inv_dx[lev][1], cz = dt * geo.inv_dx[lev][2];
+        double q[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            auto face = [&](int side, unsigned off) {
+                return double(buf_ld(buf_view(fside + ((int64_t(side) * NV + v) * nc + c) * N2, N2 * sizeof(T)), off,
+                                     T(0)));
+            };
+            const double fxm = face(0, bx), fxp = face(1, bx);
+            const double fym = face(2, by), fyp = face(3, by);
+            const double fzm = face(4, bz), fzp = face(5, bz);
+            const double sv = cx * (Rx * fxp - Lx * fxm) + cy * (Ry * fyp - Ly * fym) + cz * (Rz * fzp - Lz * fzm);
+            const int64_t o = (int64_t(v) * nc + c) * N3;
+            q[v] = buf_ld(buf_view(ustar + o, N3 * sizeof(double)), lu, 0.0) - sv;
+            buf_st(buf_view(uout + o, N3 * sizeof(double)), lu, q[v]);
+        }
+        if (FUSE && node_ok) rate = fmax(rate, cfl_rate(gamma, q, geo, lev, status));
+    }
+    if (FUSE) {
+        __shared__ double sh[CorrW<N>::THREADS / 64];
         rate = block_max(rate, sh);
         if (threadIdx.x == 0) partial[blockIdx.x] = rate;
     }
@@ -1757,27 +1816,34 @@ hipError_t launch_restrict(int N, T *fside, const HangDev *hang, const int32_t *
 template <typename T>
 hipError_t launch_corrector(int N, const double *ustar, const T *fside, const double *dt, double *uout,
                             int64_t nc, const int8_t *level, const Geo &geo, hipStream_t st, double gamma,
-                            double *partial, int *status)
+                            double *partial, int *status, int64_t c0, int64_t c1)
 {
-    if (nc <= 0) return hipSuccess;
-    if (N == 4) {
-        const int64_t blocks = corrector_blocks(4, nc);
-        if (partial)
-            hipLaunchKernelGGL((k_corrector4<T, true>), dim3(unsigned(blocks)), dim3(256), 0, st, ustar, fside, dt,
-                               uout, nc, level, geo, gamma, partial, status);
-        else
-            hipLaunchKernelGGL((k_corrector4<T, false>), dim3(unsigned(blocks)), dim3(256), 0, st, ustar, fside, dt,
-                               uout, nc, level, geo, gamma, partial, status);
-        return hipGetLastError();
-    }
+    if (c1 < 0) c1 = nc;
+    if (c1 <= c0) return hipSuccess;
+    const int64_t blocks = corrector_blocks(N, c1 - c0);
     ADG_DISPATCH_N(N, {
-        const int64_t blocks = corrector_blocks(NN, nc);
-        if (partial)
-            hipLaunchKernelGGL((k_corrector<T, NN, true>), dim3(unsigned(blocks)), dim3(256), 0, st, ustar, fside, dt,
-                               uout, nc, level, geo, gamma, partial, status);
-        else
-            hipLaunchKernelGGL((k_corrector<T, NN, false>), dim3(unsigned(blocks)), dim3(256), 0, st, ustar, fside,
-                               dt, uout, nc, level, geo, gamma, partial, status);
+        if constexpr (NN == 4) {
+            if (partial)
+                hipLaunchKernelGGL((k_corrector4<T, true>), dim3(unsigned(blocks)), dim3(256), 0, st, ustar, fside,
+                                   dt, uout, nc, level, geo, gamma, partial, status, c0, c1);
+            else
+                hipLaunchKernelGGL((k_corrector4<T, false>), dim3(unsigned(blocks)), dim3(256), 0, st, ustar, fside,
+                                   dt, uout, nc, level, geo, gamma, partial, status, c0, c1);
+        } else if constexpr (NN >= 5) {
+            if (partial)
+                hipLaunchKernelGGL((k_correctorW<T, NN, true>), dim3(unsigned(blocks)), dim3(CorrW<NN>::THREADS), 0,
+                                   st, ustar, fside, dt, uout, nc, level, geo, gamma, partial, status, c0, c1);
+            else
+                hipLaunchKernelGGL((k_correctorW<T, NN, false>), dim3(unsigned(blocks)), dim3(CorrW<NN>::THREADS), 0,
+                                   st, ustar, fside, dt, uout, nc, level, geo, gamma, partial, status, c0, c1);
+        } else {
+            if (partial)
+                hipLaunchKernelGGL((k_corrector<T, NN, true>), dim3(unsigned(blocks)), dim3(256), 0, st, ustar,
+                                   fside, dt, uout, nc, level, geo, gamma, partial, status, c0, c1);
+            else
+                hipLaunchKernelGGL((k_corrector<T, NN, false>), dim3(unsigned(blocks)), dim3(256), 0, st, ustar,
+                                   fside, dt, uout, nc, level, geo, gamma, partial, status, c0, c1);
+        }
     });
     return hipGetLastError();
 }
@@ -1903,9 +1969,8 @@ int corrector_blocks(int N, int64_t nc)
 }
 
 hipError_t launch_cfl_prime(int N, const double *u, int64_t nc, const int8_t *level, const Geo &geo, double gamma,
-                            double *partial, int *status, hipStream_t st)
+                            double *partial, int nb, int *status, hipStream_t st)
 {
-    const int nb = corrector_blocks(N, nc);
     ADG_DISPATCH_N(N, {
         hipLaunchKernelGGL((k_cfl_partial<NN>), dim3(nb), dim3(256), 0, st, u, nc, level, geo, gamma, partial,
                            status);
@@ -1995,7 +2060,7 @@ hipError_t launch_sample_adjoint(int N, const double *pts, const double *wbar, i
                                            const double *, hipStream_t);                                 \
     template hipError_t launch_corrector<T>(int, const double *, const T *, const double *, double *,    \
                                             int64_t, const int8_t *, const Geo &, hipStream_t, double,    \
-                                            double *, int *);
+                                            double *, int *, int64_t, int64_t);
 
 ADG_INSTANTIATE(double)
 ADG_INSTANTIATE(float)

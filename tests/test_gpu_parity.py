@@ -121,7 +121,7 @@ def test_orders_ragged_mesh_fp64(p):
     check_run(om, gm, u0, n, "fp64", 3)
 
 
-@pytest.mark.parametrize("p", [2, 4, 6])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6])
 def test_orders_ragged_mesh_fp32(p):
     n = (4, 3, 5)
     om, gm = make_pair(p, n, "fp32")
@@ -131,7 +131,7 @@ def test_orders_ragged_mesh_fp32(p):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("p", [2, 4])
+@pytest.mark.parametrize("p", [2, 3, 4, 5])
 def test_amr_blast(p, precision):
     """3^3 base cells, two levels of 3:1 refinement in a sphere (level jumps
     of 1 and 2), smoothed blast wave; phases, runs, and the two-stream
