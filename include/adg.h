@@ -178,9 +178,11 @@ adg_status adg_step(adg_mesh *mesh, double *u_dev, int32_t n_steps, double *dt_h
 adg_status adg_autotune(adg_mesh *mesh, const double *u_dev, void *ws_dev, hipStream_t stream);
 adg_status adg_tuning(const adg_mesh *mesh, int32_t *cells_per_block);
 
-/* use_graph = 1 (default): adg_step captures one step into a hipGraph on
- * the handle's own streams and replays it (re-captured when u_dev or ws_dev
- * change); 0: plain launches.  batched = 0: one predictor launch per
+/* use_graph = 1 (default for handles with more than one instance):
+ * adg_step captures one step into a hipGraph on the handle's own streams and
+ * replays it (re-captured when u_dev or ws_dev change); 0 (default for a
+ * single instance, whose few large launches ran about 2 % faster without
+ * the graph at 81^3, p = 3): plain launches.  batched = 0: one predictor launch per
  * instance; 1: one persistent launch per order (default for handles with
  * more than one instance and no hanging faces); 2: one persistent launch for
  * all orders.  Results are identical either way. */
@@ -196,15 +198,19 @@ adg_status adg_set_options(adg_mesh *mesh, int32_t use_graph, int32_t batched);
  * are identical with the pipeline on or off.  The caller's streams are joined
  * by events before and after.  ADG_ERR_UNSUPPORTED for other handles when
  * enable != 0.  Waits for the device before switching.  On one MI355X at
- * 81^3, p = 3 it is slower than the sequential step (3.40 against 3.28 ms):
- * the face and corrector kernels also issue VALU work, and running beside
- * the VALU-bound predictor they slow it by about as much as they save. */
+ * 81^3, p = 3 it is not faster than the sequential step (3.21 against
+ * 3.19 ms, plain launches): the face and corrector kernels also issue VALU
+ * work, and running beside the VALU-bound predictor they slow it by about as
+ * much as they save.  enable = 2 runs the same chunk order on one stream
+ * (locality only); it is slower (3.26 ms). */
 adg_status adg_set_pipeline(adg_mesh *mesh, int32_t enable);
 
 /* Phase timing for measurement.  While enabled, every launch made by the
  * handle's calls is bracketed by HIP events recorded on the stream the launch
- * goes to.  adg_profile(mesh, 1) enables and clears the accumulators,
- * adg_profile(mesh, 0) disables.  adg_profile_read synchronises on the
+ * goes to.  adg_profile(mesh, 1) enables (every phase) and clears the
+ * accumulators, adg_profile(mesh, 2) likewise but records the predictor
+ * launches only (the fewest events in a timed run), adg_profile(mesh, 0)
+ * disables.  adg_profile_read synchronises on the
  * recorded events and returns, per phase (ADG_PHASE_*), the summed kernel
  * time in milliseconds and the number of launches (arrays of ADG_NPHASES).
  * Enabling adds an event pair per launch; results are unchanged. */

@@ -275,13 +275,15 @@ class Mesh:
             batched = 1 if (self.n_instances > 1 and self.info["n_hanging_faces"] == 0) else 0
         _check(load().adg_set_options(self._h, 1 if use_graph else 0, int(batched)))
 
-    def set_pipeline(self, enable):
-        """Pipelined step over cell chunks (single instance, no hanging faces)."""
-        _check(load().adg_set_pipeline(self._h, 1 if enable else 0))
+    def set_pipeline(self, mode):
+        """Pipelined step over cell chunks (single instance, no hanging faces):
+        0/False off, 1/True predictor and face/corrector streams, 2 one stream."""
+        _check(load().adg_set_pipeline(self._h, int(mode)))
 
-    def profile(self, enable):
-        """Enable (and clear) or disable per-phase HIP-event timing."""
-        _check(load().adg_profile(self._h, 1 if enable else 0))
+    def profile(self, enable, predictor_only=False):
+        """Enable (and clear) or disable HIP-event timing of every phase (or of
+        the predictor launches only)."""
+        _check(load().adg_profile(self._h, (2 if predictor_only else 1) if enable else 0))
 
     def profile_read(self):
         """{phase: (milliseconds summed over launches, launch count)}; synchronises."""

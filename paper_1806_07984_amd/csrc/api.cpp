@@ -62,7 +62,7 @@ struct adg_mesh {
     hipEvent_t ev_dt = nullptr, ev_skel = nullptr, ev_encl = nullptr;
     adg_info info{};
     // phase timing (adg_profile)
-    bool prof = false;
+    int prof = 0;  // 0 off, 1 every phase, 2 predictor launches only
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     struct Rec { int phase; hipEvent_t a, b; };
@@ -82,7 +82,7 @@ struct adg_mesh {
     int16_t *tape = nullptr;
     int tape_mode = 0;
     // captured step (hipGraph) replayed by adg_step
-    bool use_graph = true;
+    bool use_graph = false;  // set at init: on for handles with more than one instance
     hipStream_t gs_a = nullptr, gs_b = nullptr;
     hipEvent_t ev_in = nullptr, ev_in2 = nullptr, ev_out = nullptr;
     hipGraph_t graph = nullptr;
@@ -91,7 +91,7 @@ struct adg_mesh {
     bool gkey_two = false;
     // pipelined step: predictors chunk by chunk on one stream, the faces and
     // correctors of finished chunks on another
-    bool pipeline = false;
+    int pipeline = 0;                 // 0 off, 1 two streams, 2 one stream (chunk by chunk)
     std::vector<hipEvent_t> ev_chunk;
     hipEvent_t ev_join = nullptr;
 };
@@ -216,7 +216,7 @@ struct PhaseTimer {
     hipEvent_t a = nullptr;
     PhaseTimer(adg_mesh *m_, int phase_, hipStream_t st_) : m(m_), phase(phase_), st(st_)
     {
-        if (!m->prof) return;
+        if (!m->prof || (m->prof == 2 && phase != ADG_PHASE_PREDICTOR)) return;
         a = take();
         if (a) (void)hipEventRecord(a, st);
     }
@@ -550,8 +550,10 @@ adg_status enqueue_step_pipe(adg_mesh *m, double *u, double *hist, void *ws, hip
     const int S = I.ps;
     adg_status st = do_cfl_fused(m, m->dt_dev, hist, A);
     if (st != ADG_OK) return st;
-    ADG_HIP(hipEventRecord(m->ev_dt, A), "event record");
-    ADG_HIP(hipStreamWaitEvent(B, m->ev_dt, 0), "stream wait");
+    if (A != B) {
+        ADG_HIP(hipEventRecord(m->ev_dt, A), "event record");
+        ADG_HIP(hipStreamWaitEvent(B, m->ev_dt, 0), "stream wait");
+    }
     for (int k = 0; k < S; ++k) {
         {
             PhaseTimer tm(m, ADG_PHASE_PREDICTOR, A);
@@ -559,10 +561,10 @@ adg_status enqueue_step_pipe(adg_mesh *m, double *u, double *hist, void *ws, hip
                                         I.level, I.geo, m->dt_dev, I.gamma, I.npic, A),
                     "predictor (chunk)");
         }
-        ADG_HIP(hipEventRecord(m->ev_chunk[k], A), "event record");
-    }
-    for (int k = 0; k < S; ++k) {
-        ADG_HIP(hipStreamWaitEvent(B, m->ev_chunk[k], 0), "stream wait");
+        if (A != B) {
+            ADG_HIP(hipEventRecord(m->ev_chunk[k], A), "event record");
+            ADG_HIP(hipStreamWaitEvent(B, m->ev_chunk[k], 0), "stream wait");
+        }
         {
             PhaseTimer tm(m, ADG_PHASE_RIEMANN, B);
             for (int d = 0; d < 3; ++d)
@@ -577,8 +579,10 @@ adg_status enqueue_step_pipe(adg_mesh *m, double *u, double *hist, void *ws, hip
                     "corrector (chunk)");
         }
     }
-    ADG_HIP(hipEventRecord(m->ev_join, B), "event record");
-    ADG_HIP(hipStreamWaitEvent(A, m->ev_join, 0), "stream wait");
+    if (A != B) {
+        ADG_HIP(hipEventRecord(m->ev_join, B), "event record");
+        ADG_HIP(hipStreamWaitEvent(A, m->ev_join, 0), "stream wait");
+    }
     return ADG_OK;
 }
 
@@ -588,7 +592,7 @@ adg_status step_eager(adg_mesh *m, double *u, int32_t n_steps, double *hist, voi
 {
     if (m->pipeline) {
         // the handle's two streams, joined with the caller's before and after
-        hipStream_t A = m->gs_a, B = m->gs_b;
+        hipStream_t A = m->gs_a, B = m->pipeline == 2 ? m->gs_a : m->gs_b;
         ADG_HIP(hipEventRecord(m->ev_in, s_skel), "event record");
         ADG_HIP(hipStreamWaitEvent(A, m->ev_in, 0), "stream wait");
         if (s_skel != s_encl) {
@@ -631,7 +635,7 @@ adg_status step_graph(adg_mesh *m, double *u, int32_t n_steps, double *hist, voi
                       hipStream_t s_encl)
 {
     const bool two = s_skel != s_encl;
-    hipStream_t A = m->gs_a, B = (two || m->pipeline) ? m->gs_b : m->gs_a;
+    hipStream_t A = m->gs_a, B = (two || m->pipeline == 1) ? m->gs_b : m->gs_a;
     ADG_HIP(hipEventRecord(m->ev_in, s_skel), "event record");
     ADG_HIP(hipStreamWaitEvent(A, m->ev_in, 0), "stream wait");
     if (two) {
@@ -901,6 +905,7 @@ adg_status adg_init_mesh(const adg_instance_desc *desc, int32_t n_instances, adg
         }
         for (int N = 0; N <= NMAX; ++N) m->codes[N] = default_code(N);
         m->batched = (n_instances > 1 && !any_skel) ? 1 : 0;
+        m->use_graph = n_instances > 1;
         ok = hipMalloc(&m->insts_dev, sizeof(PredInst) * pis.size()) == hipSuccess &&
              hipMemcpy(m->insts_dev, pis.data(), sizeof(PredInst) * pis.size(), hipMemcpyHostToDevice) == hipSuccess;
         ok = ok && (!any_skel ? build_batch(m) == ADG_OK : true);
@@ -1131,8 +1136,12 @@ adg_status adg_set_pipeline(adg_mesh *mesh, int32_t enable)
         set_error("adg_set_pipeline: the pipelined step needs a single instance without hanging faces");
         return ADG_ERR_UNSUPPORTED;
     }
+    if (enable < 0 || enable > 2) {
+        set_error("adg_set_pipeline: mode must be 0, 1 or 2");
+        return ADG_ERR_INVALID_ARG;
+    }
     ADG_HIP(hipDeviceSynchronize(), "synchronize");
-    mesh->pipeline = enable != 0;
+    mesh->pipeline = enable;
     drop_graph(mesh);
     return ADG_OK;
 }
@@ -1145,7 +1154,11 @@ adg_status adg_profile(adg_mesh *mesh, int32_t enable)
         mesh->recs.clear();
         mesh->ev_used = 0;
     }
-    mesh->prof = enable != 0;
+    if (enable < 0 || enable > 2) {
+        set_error("adg_profile: enable must be 0, 1 or 2");
+        return ADG_ERR_INVALID_ARG;
+    }
+    mesh->prof = enable;
     return ADG_OK;
 }
 

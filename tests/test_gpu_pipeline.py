@@ -40,7 +40,7 @@ def test_pipelined_step_is_bitwise_identical(order, precision):
     gm.set_pipeline(False)
     gm.set_options(use_graph=False, batched=False)
     ref_u, ref_h = run(gm, u0, steps)
-    for pipe in (False, True):
+    for pipe in (0, 1, 2):
         for graph in (False, True):
             for two in (False, True):
                 print(f"[pipeline] p={order} {precision} pipe={pipe} graph={graph} two_streams={two}", flush=True)
