@@ -243,7 +243,7 @@ def main():
         print(json.dumps({"copy_bytes_per_launch": 2 * a.numel() * 8, "launches": 3}))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: measures one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU decomposition is a design, not a measured path.", file=sys.stderr)
         sys.exit(2)
     import torch

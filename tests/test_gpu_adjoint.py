@@ -55,7 +55,7 @@ def fd_check(F, u, v, ad, tag, rel_eps=1e-6):
     return rel, smooth
 
 
-def judge(res, tol):
+def check_fd(res, tol):
     smooth = [r for r, ok in res if ok]
     assert len(smooth) >= 0.75 * len(res), f"too many directions cross a switch of the face maximum: {res}"
     assert max(smooth) <= tol, res
@@ -182,7 +182,7 @@ def test_gradient_against_oracle_finite_differences():
         return J_oracle(x.numpy())
     res = [fd_check(F, u_flat, torch.from_numpy(dirs[k]), float((g * dirs[k]).sum()), f"[oracle fd] dir={k}",
                     rel_eps=1e-7) for k in range(8)]
-    judge(res, 1e-6)
+    check_fd(res, 1e-6)
 
 
 def test_adjoint_rejects_unsupported_handles():
