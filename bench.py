@@ -219,6 +219,43 @@ def run_batch(A, steps=10, seed=0):
     return out
 
 
+def run_adjoint(A, n=27, steps=20, k=5, n_pts=512):
+    """Differentiation workload: 27^3 cells, p = 3, FP64, 20 steps; loss =
+    sampled density misfit at 512 seeded points; gradient with respect to
+    the whole initial state through the hand-written adjoint, checkpoint
+    every 5 steps.  Reports the forward time (20 steps) and the gradient
+    time (forward with checkpoints, segment recomputation and the adjoint
+    steps) and their ratio."""
+    import torch
+    from paper_1806_07984_amd import inputs, rollout
+    mesh = A.Mesh(A.instance(ORDER, (n, n, n)), "fp64")
+    xyz = mesh.node_coords().cpu().numpy().reshape(3, -1)
+    u0 = torch.from_numpy(inputs.density_wave_noisy(xyz, seed=7, noise=0.01).reshape(-1)).cuda()
+    pts = torch.from_numpy(inputs.sample_points(n_pts, seed=1)).cuda().contiguous()
+    target = torch.from_numpy(inputs.sample_targets(n_pts, seed=2)).cuda()
+    sched = rollout.dt_schedule(mesh, u0, steps)  # also warms up
+    rollout.loss_and_grad(mesh, u0, pts, target, steps, k=k, dt_sched=sched)
+    torch.cuda.synchronize()
+    u = u0.clone()
+    ws = mesh.empty_workspace()
+    t0 = time.perf_counter()
+    mesh.step(u, steps, ws)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    J, g, _ = rollout.loss_and_grad(mesh, u0, pts, target, steps, k=k, dt_sched=sched)
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t0
+    mesh.status()
+    out = {"forward_ms": t_fwd * 1e3, "gradient_ms": t_grad * 1e3, "gradient_over_forward": t_grad / t_fwd,
+           "steps": steps, "checkpoint_every": k, "cells": n ** 3, "dofs": mesh.info["n_dofs"],
+           "loss": float(J), "path": "fp64"}
+    mesh.close()
+    del u, ws, g
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -228,7 +265,7 @@ def main():
     ap.add_argument("--only", choices=["fp64", "fp32"], default=None,
                     help="run one path only (for profiling runs)")
     ap.add_argument("--no-extra", action="store_true", help="skip the AMR and batch workloads")
-    ap.add_argument("--extra-only", choices=["amr", "batch"], default=None,
+    ap.add_argument("--extra-only", choices=["amr", "batch", "adjoint"], default=None,
                     help="run only one of the other workloads and print its JSON (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB buffer 3 times (calibrates HBM byte counters) and exit")
@@ -252,7 +289,7 @@ def main():
 
     A.load()
     if args.extra_only:
-        res = run_amr(A) if args.extra_only == "amr" else run_batch(A)
+        res = {"amr": run_amr, "batch": run_batch, "adjoint": run_adjoint}[args.extra_only](A)
         print(json.dumps({"workload": args.extra_only, **res}))
         return
     # initial state: node coordinates from the library, analytic state + seeded noise on the host
@@ -299,7 +336,8 @@ def main():
     }
     if not args.no_extra:
         out["other_workloads"] = {"amr_blast_p4_27cubed_2levels": run_amr(A),
-                                  "batch64_p2to6_seed0": run_batch(A)}
+                                  "batch64_p2to6_seed0": run_batch(A),
+                                  "adjoint_p3_27cubed_20steps": run_adjoint(A)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

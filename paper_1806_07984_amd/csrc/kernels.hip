@@ -1484,7 +1484,8 @@ k_predictor_adj(const double *__restrict__ u, const double *__restrict__ iters, 
                 int64_t nc, Geo geo, double gamma, int npic)
 {
     constexpr int N2 = N * N, N3 = N2 * N, NT = CPB * N3;
-    __shared__ double lds[CPB * NV * N3];
+    // per cell: the adjoint divergence inputs Gb_j of all N time nodes
+    __shared__ double lds[CPB * N * NV * N3];
     const DevBasis &B = c_basis[N];
     const int tid = threadIdx.x;
     const int cl = tid / N3, a = tid % N3;
@@ -1496,7 +1497,7 @@ k_predictor_adj(const double *__restrict__ u, const double *__restrict__ iters, 
     const double dt = dt_dev[0];
     const double cd[3] = {dt * geo.inv_dx[0][0], dt * geo.inv_dx[0][1], dt * geo.inv_dx[0][2]};
     const double gm1 = gamma - 1.0;
-    double *my = lds + (lane_ok ? cl : 0) * NV * N3;
+    double *my = lds + (lane_ok ? cl : 0) * N * NV * N3;
     auto node_with = [&](int d, int k) {
         return d == 0 ? k + N * aa[1] + N2 * aa[2] : (d == 1 ? aa[0] + N * k + N2 * aa[2] : aa[0] + N * aa[1] + N2 * k);
     };
@@ -1562,29 +1563,43 @@ k_predictor_adj(const double *__restrict__ u, const double *__restrict__ iters, 
             flux_vjp(gm1, q, d, fbw, qbar[j]);
         }
     }
-    // Picard iterations in reverse: q^(r) = u - sum_j KW[l][j] G_j(q^(r-1))
+    // Picard iterations in reverse: q^(r) = u - sum_j KW[l][j] G_j(q^(r-1)).
+    // Gb_j = -sum_l KW[l][j] qbar_l of every time node goes to LDS at once.
+    // At r = 1 every q^(0)_j is u, so the Gb_j are summed first and one
+    // transposed divergence and flux VJP serve all time nodes.
     for (int r = npic; r >= 1; --r) {
-        double Gb[N][NV];
+        const bool first = r == 1;
+        __syncthreads();
+        if (lane_ok) {
+            double gs[NV] = {0, 0, 0, 0, 0};
 #pragma unroll
-        for (int j = 0; j < N; ++j)
+            for (int j = 0; j < N; ++j)
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                double sacc = 0.0;
+                for (int v = 0; v < NV; ++v) {
+                    double sacc = 0.0;
 #pragma unroll
-                for (int l = 0; l < N; ++l) sacc += B.KW[l * N + j] * qbar[l][v];
-                Gb[j][v] = -sacc;
-            }
+                    for (int l = 0; l < N; ++l) sacc += B.KW[l * N + j] * qbar[l][v];
+                    if (first)
+                        gs[v] -= sacc;
+                    else
+                        my[(j * NV + v) * N3 + a] = -sacc;
+                }
+            if (first)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) my[v * N3 + a] = gs[v];
+        }
 #pragma unroll
         for (int l = 0; l < N; ++l)
 #pragma unroll
             for (int v = 0; v < NV; ++v) acc[v] += qbar[l][v];
+        __syncthreads();
 #pragma unroll
         for (int j = 0; j < N; ++j) {
-            __syncthreads();
-            if (lane_ok)
+            if (first && j > 0) {
 #pragma unroll
-                for (int v = 0; v < NV; ++v) my[v * N3 + a] = Gb[j][v];
-            __syncthreads();
+                for (int v = 0; v < NV; ++v) qbar[j][v] = 0.0;
+                continue;
+            }
             double q[NV];
             load_q(r - 1, j, q);
             double nb[NV] = {0, 0, 0, 0, 0};
@@ -1595,7 +1610,7 @@ k_predictor_adj(const double *__restrict__ u, const double *__restrict__ iters, 
                 for (int v = 0; v < NV; ++v) {
                     double sacc = 0.0;
 #pragma unroll
-                    for (int k = 0; k < N; ++k) sacc += B.D[k * N + aa[d]] * my[v * N3 + node_with(d, k)];
+                    for (int k = 0; k < N; ++k) sacc += B.D[k * N + aa[d]] * my[(j * NV + v) * N3 + node_with(d, k)];
                     fb[v] = cd[d] * sacc;
                 }
                 flux_vjp(gm1, q, d, fb, nb);

@@ -111,3 +111,42 @@ def test_single_instance_graph_matches_eager():
     gm.step(u, 3, ws)  # replays of the same captured graph
     torch.cuda.synchronize()
     assert torch.equal(u, ref)
+
+
+def test_seeded_batch_config_subset_matches_oracle():
+    """The benchmark's 64-instance batch (seed 0, edges in {9..45}, orders
+    2..6, FP32 form) runs two steps through the batched persistent path; one
+    9^3 instance of every order is compared with the oracle's run of that
+    instance alone."""
+    draws = inputs.batch_instances(64, seed=0)
+    gm = A.Mesh([A.instance(d["order"], (d["edge"],) * 3) for d in draws], "fp32")
+    xyz = gm.node_coords().cpu().numpy()
+    u0 = np.zeros(gm.info["u_elems"])
+    for g, d in zip(gm.instances, draws):
+        nn = g["n_cells"] * (g["order"] + 1) ** 3
+        x = xyz[3 * g["u_offset"] // 5: 3 * g["u_offset"] // 5 + 3 * nn].reshape(3, nn)
+        u0[g["u_offset"]: g["u_offset"] + 5 * nn] = inputs.density_wave(x, amp=d["amp"]).reshape(-1)
+    del xyz
+    steps = 2
+    u, hist = run(gm, u0, steps)
+    hist = hist.cpu().numpy().reshape(steps, -1)
+    picks = {}
+    for i, d in enumerate(draws):
+        if d["edge"] == 9 and d["order"] not in picks:
+            picks[d["order"]] = i
+    assert sorted(picks) == [2, 3, 4, 5, 6]
+    for p, i in sorted(picks.items()):
+        g, d = gm.instances[i], draws[i]
+        print(f"[batch config] instance {i} p={p} edge={d['edge']} amp={d['amp']:.3f}", flush=True)
+        n = (d["edge"],) * 3
+        om = oracle.Mesh(p, n)
+        size = 5 * g["n_cells"] * (p + 1) ** 3
+        ui0 = u0[g["u_offset"]: g["u_offset"] + size].reshape(5, g["n_cells"], -1)
+        ref, h_ref, rc = om.run(ui0, steps)
+        assert rc == 0
+        got = u[g["u_offset"]: g["u_offset"] + size].cpu().numpy()
+        e = rel_l2_per_var(got, ref, solution_weights(om, n))
+        print("   rel L2 per variable:", e, flush=True)
+        assert e.max() <= TOL["fp32"], (i, e)
+        assert np.abs(hist[:, i] / h_ref - 1).max() <= 1e-5
+    gm.close()
