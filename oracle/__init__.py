@@ -65,6 +65,10 @@ def lib():
         L.orc_sample.restype = ctypes.c_int
         L.orc_sample.argtypes = [P, P, P, ctypes.c_long, P]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_indicator.argtypes = [P, P, P]
+        L.orc_volume_transfer.restype = ctypes.c_int
+        L.orc_volume_transfer.argtypes = [P, P, P, P]
+        L.orc_integral.argtypes = [P, P, P]
         _lib = L
     return _lib
 
@@ -189,8 +193,59 @@ def _sample(self, u, pts):
     return out
 
 
+def _indicator(self, u):
+    """Refinement indicator per cell: max over nodes and axes of the density
+    derivative in the cell's reference coordinate (change across the cell)."""
+    u = _f64(u)
+    out = np.zeros(self.nc)
+    lib().orc_indicator(self._h, _p(u), _p(out))
+    return out
+
+
+def _transfer_to(self, u, other):
+    """Volumetric data of mesh `other` from this mesh's u (copy, evaluation of
+    a coarser cell's polynomial, or L2 projection of finer cells)."""
+    u = _f64(u)
+    out = np.zeros((5, other.nc, other.N ** 3))
+    rc = lib().orc_volume_transfer(self._h, _p(u), other._h, _p(out))
+    assert rc == 0, "a cell of the target mesh is only partly covered"
+    return out
+
+
+def _integral(self, u):
+    """Integral of every variable over the box."""
+    u = _f64(u)
+    out = np.zeros(5)
+    lib().orc_integral(self._h, _p(u), _p(out))
+    return out
+
+
 Mesh.run_sched = _run_sched
 Mesh.sample = _sample
+Mesh.indicator = _indicator
+Mesh.transfer_to = _transfer_to
+Mesh.integral = _integral
+
+
+def adapt_plan(cells, refine, eta, theta_refine, theta_coarsen, max_level):
+    """The next refine list (rows (level, i, j, k), sorted by (level, k, j, i))
+    from the current one, written out plainly (test reference).
+
+    cells: [nc, 4] (level, i, j, k) of the leaves; refine: rows of the current
+    mesh; eta: indicator per leaf.  A leaf with eta > theta_refine below
+    max_level is split; a parent whose 27 children are all leaves, none split
+    now, all with eta < theta_coarsen, is merged (its row is dropped)."""
+    rows = {tuple(int(x) for x in r) for r in np.asarray(refine, dtype=np.int64).reshape(-1, 4)}
+    leaf = {tuple(int(x) for x in c): i for i, c in enumerate(np.asarray(cells).reshape(-1, 4))}
+    split = {c for c, i in leaf.items() if eta[i] > theta_refine and c[0] < max_level}
+    merged = set()
+    for r in rows:
+        l, i, j, k = r
+        kids = [(l + 1, 3 * i + a, 3 * j + b, 3 * k + c) for c in range(3) for b in range(3) for a in range(3)]
+        if all(q in leaf and q not in split and eta[leaf[q]] < theta_coarsen for q in kids):
+            merged.add(r)
+    new = (rows - merged) | split
+    return np.array(sorted(new, key=lambda r: (r[0], r[3], r[2], r[1])), dtype=np.int32).reshape(-1, 4)
 
 
 def num_threads():

@@ -913,6 +913,164 @@ int orc_sample(const orc_mesh *m, const double *u, const double *pts, long n, do
     return 0;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Dynamic adaptivity: refinement indicator and volumetric transfer          */
+/* ------------------------------------------------------------------------- */
+
+/* Feature-based criterion read in the corrector's epilogue (Sec. 2.3,
+ * dynamic-adaptivity paragraph; Sec. 2.5: criteria study first or second
+ * derivatives of the solution, cell by cell).  Reading: the indicator of a
+ * cell is the largest change of the density across the cell along any axis,
+ *   eta_c = max_{nodes a, axes d} | d rho_h / d xi_d (x_a) |,
+ * the derivative in the cell's reference coordinate xi_d in [0,1] (so
+ * eta_c = dx_d * |d rho / dx_d| for a linear density). */
+void orc_indicator(const orc_mesh *m, const double *u, double *eta)
+{
+    int N = m->N, N3 = N * N * N;
+    double xi[MAXN], w[MAXN];
+    orc_gauss_legendre(N, xi, w);
+    for (long c = 0; c < m->nc; ++c) {
+        double best = 0.0;
+        for (int a = 0; a < N3; ++a) {
+            int aa[3] = { a % N, (a / N) % N, a / (N * N) };
+            for (int d = 0; d < 3; ++d) {
+                double g = 0.0;
+                for (int e = 0; e < N; ++e)
+                    g += lagrange_deriv(N, xi, e, xi[aa[d]]) * u[c * N3 + node_with(N, a, d, e)];
+                if (fabs(g) > best) best = fabs(g);
+            }
+        }
+        eta[c] = best;
+    }
+}
+
+/* Value of cell c's polynomial (all 5 variables) at reference point y. */
+static void eval_cell(const orc_mesh *m, const double *u, long c, const double *xi, const double y[3],
+                      double out[NV])
+{
+    int N = m->N, N3 = N * N * N;
+    for (int v = 0; v < NV; ++v) out[v] = 0.0;
+    for (int b = 0; b < N3; ++b) {
+        double phi = lagrange(N, xi, b % N, y[0]) * lagrange(N, xi, (b / N) % N, y[1]) *
+                     lagrange(N, xi, b / (N * N), y[2]);
+        for (int v = 0; v < NV; ++v) out[v] += phi * u[((long)v * m->nc + c) * N3 + b];
+    }
+}
+
+/* Accumulate into acc[v][a] the integral over the part of cell C (level lc,
+ * coordinates kc) covered by the leaves of `from` inside region (l, q) of
+ * the u_from polynomials times phi_a of C, in units of C's volume; the
+ * covered volume fraction goes to *vol.  Each leaf is integrated with its own
+ * Gauss rule, exact for the degree-2p integrands. */
+static void project_region(const orc_mesh *from, const double *u, int lc, const int *kc, int l, const int *q,
+                           const double *xi, const double *w, double *acc, double *vol)
+{
+    int N = from->N, N3 = N * N * N;
+    long f = find_cell(from, l, q);
+    if (f >= 0) {
+        double r = (double)ipow3(l - lc);
+        for (int b = 0; b < N3; ++b) {
+            int bb[3] = { b % N, (b / N) % N, b / (N * N) };
+            double wt = w[bb[0]] * w[bb[1]] * w[bb[2]] / (r * r * r);
+            double y[3];
+            for (int d = 0; d < 3; ++d) y[d] = (q[d] + xi[bb[d]]) / r - kc[d];
+            *vol += wt;
+            for (int a = 0; a < N3; ++a) {
+                double phi = lagrange(N, xi, a % N, y[0]) * lagrange(N, xi, (a / N) % N, y[1]) *
+                             lagrange(N, xi, a / (N * N), y[2]);
+                for (int v = 0; v < NV; ++v)
+                    acc[v * N3 + a] += wt * phi * u[((long)v * from->nc + f) * N3 + b];
+            }
+        }
+        return;
+    }
+    if (l >= from->max_level) return;
+    for (int c2 = 0; c2 < 3; ++c2)
+        for (int c1 = 0; c1 < 3; ++c1)
+            for (int c0 = 0; c0 < 3; ++c0) {
+                int q2[3] = { 3 * q[0] + c0, 3 * q[1] + c1, 3 * q[2] + c2 };
+                project_region(from, u, lc, kc, l + 1, q2, xi, w, acc, vol);
+            }
+}
+
+/* Volumetric data of a new mesh from an old one of the same box and order,
+ * u [5][nc][N^3] on both (Sec. 2.3: refinement interpolates volumetric data,
+ * coarsening merges cells).  For every cell C of `to`:
+ *   - C is a leaf of `from`: copied;
+ *   - C lies in a coarser leaf P of `from`: P's polynomial evaluated at C's
+ *     nodes (exact: the space of C contains P's polynomial restricted to C);
+ *   - C is covered by finer leaves of `from`: the L2 projection onto C's
+ *     polynomials, u_C(a) = (1 / (|C| w_a0 w_a1 w_a2)) * int_C u phi_a.
+ * Returns 1 if a cell of `to` is only partly covered by `from`. */
+int orc_volume_transfer(const orc_mesh *from, const double *u_from, const orc_mesh *to, double *u_to)
+{
+    int N = to->N, N3 = N * N * N;
+    if (from->N != N) return 1;
+    double xi[MAXN], w[MAXN];
+    orc_gauss_legendre(N, xi, w);
+    int rc = 0;
+    double *acc = (double *)malloc(sizeof(double) * NV * N3);
+    for (long c = 0; c < to->nc; ++c) {
+        int l = to->lev[c];
+        const int *k = &to->ijk[3 * c];
+        long s = find_cell(from, l, k);
+        if (s >= 0) {
+            for (int v = 0; v < NV; ++v)
+                for (int a = 0; a < N3; ++a)
+                    u_to[((long)v * to->nc + c) * N3 + a] = u_from[((long)v * from->nc + s) * N3 + a];
+            continue;
+        }
+        long p = -1;
+        int lp = -1, kp[3];
+        for (int l2 = l - 1; l2 >= 0 && p < 0; --l2) {
+            long r = ipow3(l - l2);
+            for (int d = 0; d < 3; ++d) kp[d] = (int)(k[d] / r);
+            p = find_cell(from, l2, kp);
+            lp = l2;
+        }
+        if (p >= 0) {
+            double r = (double)ipow3(l - lp);
+            for (int a = 0; a < N3; ++a) {
+                int aa[3] = { a % N, (a / N) % N, a / (N * N) };
+                double y[3], val[NV];
+                for (int d = 0; d < 3; ++d) y[d] = (k[d] + xi[aa[d]]) / r - kp[d];
+                eval_cell(from, u_from, p, xi, y, val);
+                for (int v = 0; v < NV; ++v) u_to[((long)v * to->nc + c) * N3 + a] = val[v];
+            }
+            continue;
+        }
+        memset(acc, 0, sizeof(double) * NV * N3);
+        double vol = 0.0;
+        project_region(from, u_from, l, k, l, k, xi, w, acc, &vol);
+        if (fabs(vol - 1.0) > 1e-12) rc = 1;
+        for (int a = 0; a < N3; ++a) {
+            double wa = w[a % N] * w[(a / N) % N] * w[a / (N * N)];
+            for (int v = 0; v < NV; ++v) u_to[((long)v * to->nc + c) * N3 + a] = acc[v * N3 + a] / wa;
+        }
+    }
+    free(acc);
+    return rc;
+}
+
+/* Integral of every variable over the box: sum over cells of |cell| times
+ * the Gauss rule of the cell. */
+void orc_integral(const orc_mesh *m, const double *u, double *out)
+{
+    int N = m->N, N3 = N * N * N;
+    double xi[MAXN], w[MAXN];
+    orc_gauss_legendre(N, xi, w);
+    for (int v = 0; v < NV; ++v) out[v] = 0.0;
+    for (long c = 0; c < m->nc; ++c) {
+        double dx[3];
+        cell_dx(m, c, dx);
+        double vol = dx[0] * dx[1] * dx[2];
+        for (int a = 0; a < N3; ++a) {
+            double wa = w[a % N] * w[(a / N) % N] * w[a / (N * N)];
+            for (int v = 0; v < NV; ++v) out[v] += vol * wa * u[((long)v * m->nc + c) * N3 + a];
+        }
+    }
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP
