@@ -167,11 +167,36 @@ def run_amr(A, steps=50):
     out = {"value": info["n_dofs"] * steps / el, "unit": "DoF-updates/s", "ms_per_step": el * 1e3 / steps,
            "steps": steps, "cells": info["n_cells"], "dofs": info["n_dofs"],
            "hanging_faces": info["n_hanging_faces"], "skeleton_cells": info["n_skeleton_cells"],
-           "path": "fp32, skeleton/enclave streams"}
+           "path": "fp32, skeleton/enclave streams",
+           "adaptation": adapt_once(A, mesh, u, 0.05, 0.005)}
     mesh.close()
     del u, ws
     torch.cuda.empty_cache()
     return out
+
+
+def adapt_once(A, mesh, u, theta_refine, theta_coarsen):
+    """One adaptation step of the state after the timed steps: indicator
+    (device), plan (host), the new handle (host mesh build and uploads) and
+    the volumetric transfer (host table, device kernel), timed each."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    eta = mesh.indicator(u).cpu().numpy()
+    t1 = time.perf_counter()
+    rows = A.adapt_plan(mesh.descs[0], eta, theta_refine, theta_coarsen)
+    t2 = time.perf_counter()
+    new = A.Mesh(dict(mesh.descs[0], refine=rows), mesh.precision)
+    t3 = time.perf_counter()
+    u_new = mesh.transfer_to(u, new)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    res = {"theta_refine": theta_refine, "theta_coarsen": theta_coarsen, "cells_before": mesh.info["n_cells"],
+           "cells_after": new.info["n_cells"], "indicator_ms": (t1 - t0) * 1e3, "plan_ms": (t2 - t1) * 1e3,
+           "new_mesh_ms": (t3 - t2) * 1e3, "transfer_ms": (t4 - t3) * 1e3, "total_ms": (t4 - t0) * 1e3}
+    new.close()
+    del u_new
+    return res
 
 
 def run_batch(A, steps=10, seed=0):

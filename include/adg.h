@@ -255,6 +255,43 @@ adg_status adg_sample(adg_mesh *mesh, const double *u_dev, const double *pts_dev
 adg_status adg_sample_adjoint(adg_mesh *mesh, const double *pts_dev, const double *wbar_dev, int64_t n_pts,
                               double *ubar_dev, hipStream_t stream);
 
+/* Dynamic adaptivity (Sec. 2.3, dynamic-adaptivity paragraph: a cell-wise,
+ * feature-based criterion reads the new solution in the corrector's
+ * epilogue; refinement interpolates volumetric data onto new cells and
+ * coarsening merges a cluster of 27 cells; both complete before the next
+ * predictor).  A step of adaptation is: adg_indicator on the state,
+ * adg_adapt_plan on the host, adg_init_mesh with the new refine rows,
+ * adg_transfer of the state, adg_free_mesh of the old handle.
+ *
+ * adg_indicator: eta_dev[c] (FP64, one per cell of the handle, cells in the
+ * handle's order) = max over nodes a and axes d of |d rho_h / d xi_d (x_a)|,
+ * the density derivative in the cell's reference coordinate xi_d in [0, 1],
+ * i.e. the largest change of density across the cell.  Reads u_dev. */
+adg_status adg_indicator(adg_mesh *mesh, const double *u_dev, double *eta_dev, hipStream_t stream);
+
+/* adg_adapt_plan (host only, no device work): the refine rows of the next
+ * mesh from the instance `desc` (whose refine rows describe the current
+ * mesh) and eta_host (one value per cell, cells in the handle's order).  A
+ * leaf with eta > theta_refine below desc->max_level is split; a refined
+ * cell whose 27 children are all leaves, none of them split now, all with
+ * eta < theta_coarsen, is merged.  Rows (level, i, j, k) sorted by (level,
+ * k, j, i) go to refine_out (host, 4 * capacity int32); *n_refine_out gets
+ * their number in any case, and ADG_ERR_WORKSPACE is returned when capacity
+ * is smaller (call again with a larger buffer). */
+adg_status adg_adapt_plan(const adg_instance_desc *desc, const double *eta_host, double theta_refine,
+                          double theta_coarsen, int32_t *refine_out, int64_t capacity, int64_t *n_refine_out);
+
+/* adg_transfer: the state u_to_dev of handle `to` from u_from_dev of handle
+ * `from` (one instance each, same order and base box; refinement levels may
+ * differ).  For every cell of `to`: a copy if `from` has the same cell; the
+ * polynomial of the coarser `from` cell that contains it, evaluated at its
+ * nodes; or the L2 projection of the finer `from` cells that cover it
+ * (exact Gauss rules, so mass is conserved to rounding either way).
+ * ADG_ERR_INVALID_ARG if the meshes differ or a cell is only partly covered.
+ * Allocates and frees a small device table and synchronises `stream`. */
+adg_status adg_transfer(const adg_mesh *from, const double *u_from_dev, adg_mesh *to, double *u_to_dev,
+                        hipStream_t stream);
+
 /* Synchronises the handle's device work and returns ADG_ERR_NONPHYSICAL if a
  * non-physical state was met since the last call (then clears the latch). */
 adg_status adg_get_status(adg_mesh *mesh);

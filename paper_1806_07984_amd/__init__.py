@@ -23,7 +23,7 @@ EXPORTS = ["adg_init_mesh", "adg_free_mesh", "adg_mesh_info", "adg_instance_info
            "adg_node_coords", "adg_cfl", "adg_predictor", "adg_riemann", "adg_corrector", "adg_step",
            "adg_profile", "adg_profile_read", "adg_get_status", "adg_last_error", "adg_autotune",
            "adg_tuning", "adg_set_options", "adg_step_adjoint", "adg_sample", "adg_sample_adjoint",
-           "adg_set_switch_tape", "adg_set_pipeline"]
+           "adg_set_switch_tape", "adg_set_pipeline", "adg_indicator", "adg_adapt_plan", "adg_transfer"]
 PHASES = ["cfl", "predictor", "hanging", "riemann", "corrector"]
 
 
@@ -88,6 +88,9 @@ def load():
         "adg_set_switch_tape": [P, P, I32],
         "adg_sample": [P, P, P, I64, P, P],
         "adg_sample_adjoint": [P, P, P, I64, P, P],
+        "adg_indicator": [P, P, P, P],
+        "adg_adapt_plan": [P, P, ctypes.c_double, ctypes.c_double, P, I64, P],
+        "adg_transfer": [P, P, P, P, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -131,6 +134,56 @@ def instance(order, n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), max_level=0, refi
                 gamma=gamma, cfl=cfl, picard_iters=picard_iters)
 
 
+def _fill_desc(a, d):
+    """Fills the InstanceDesc a from the dict d; returns the refine array that
+    must stay alive while a is used."""
+    ref = np.zeros((0, 4), dtype=np.int32) if d.get("refine") is None else \
+        np.ascontiguousarray(d["refine"], dtype=np.int32).reshape(-1, 4)
+    a.order = d["order"]
+    a.n[:] = list(d["n"])
+    a.lo[:] = list(d.get("lo", (0.0, 0.0, 0.0)))
+    a.hi[:] = list(d.get("hi", (1.0, 1.0, 1.0)))
+    a.periodic_mask = 7
+    a.max_level = d.get("max_level", 0)
+    a.n_refine = ref.shape[0]
+    a.refine = ref.ctypes.data if ref.shape[0] else None
+    a.gamma = d.get("gamma", 1.4)
+    a.cfl = d.get("cfl", 0.4)
+    a.picard_iters = d.get("picard_iters", 0)
+    return ref
+
+
+def adapt_plan(desc, eta, theta_refine, theta_coarsen):
+    """Refine rows [n, 4] (int32) of the next mesh (adg_adapt_plan; host only).
+    desc: the instance dict of the current mesh; eta: indicator per cell."""
+    L = load()
+    a = InstanceDesc()
+    keep = _fill_desc(a, desc)
+    eta = np.ascontiguousarray(eta, dtype=np.float64)
+    n = ctypes.c_int64(0)
+    # at most the current rows plus one per cell above the refinement threshold
+    cap = keep.shape[0] + int(np.count_nonzero(eta > theta_refine))
+    out = np.zeros((max(cap, 1), 4), dtype=np.int32)
+    _check(L.adg_adapt_plan(ctypes.byref(a), eta.ctypes.data, float(theta_refine), float(theta_coarsen),
+                            out.ctypes.data, out.shape[0], ctypes.byref(n)))
+    del keep
+    return out[: n.value]
+
+
+def adapt(mesh, u, theta_refine, theta_coarsen, stream=None):
+    """One adaptation step of a single-instance handle: indicator, plan, new
+    handle, transfer of the state.  Returns (new_mesh, new_u); the old handle
+    is left open (close it when done)."""
+    import torch
+    eta = mesh.indicator(u, stream=stream)
+    rows = adapt_plan(mesh.descs[0], eta.cpu().numpy(), theta_refine, theta_coarsen)
+    desc = dict(mesh.descs[0], refine=rows)
+    new = Mesh(desc, mesh.precision)
+    u_new = torch.empty(new.info["u_elems"], dtype=torch.float64, device=u.device)
+    mesh.transfer_to(u, new, u_new, stream=stream)
+    return new, u_new
+
+
 class Mesh:
     """Handle over one or more instances (adg_init_mesh).
 
@@ -143,23 +196,8 @@ class Mesh:
         self.precision = precision
         prec = {"fp64": FP64, "fp32": FP32_MFMA}[precision]
         arr = (InstanceDesc * len(descs))()
-        self._keep = []
-        for i, d in enumerate(descs):
-            ref = np.zeros((0, 4), dtype=np.int32) if d.get("refine") is None else \
-                np.ascontiguousarray(d["refine"], dtype=np.int32)
-            self._keep.append(ref)
-            a = arr[i]
-            a.order = d["order"]
-            a.n[:] = list(d["n"])
-            a.lo[:] = list(d.get("lo", (0.0, 0.0, 0.0)))
-            a.hi[:] = list(d.get("hi", (1.0, 1.0, 1.0)))
-            a.periodic_mask = 7
-            a.max_level = d.get("max_level", 0)
-            a.n_refine = ref.shape[0]
-            a.refine = ref.ctypes.data if ref.shape[0] else None
-            a.gamma = d.get("gamma", 1.4)
-            a.cfl = d.get("cfl", 0.4)
-            a.picard_iters = d.get("picard_iters", 0)
+        self._keep = [_fill_desc(arr[i], d) for i, d in enumerate(descs)]
+        self.descs = [dict(d) for d in descs]
         h = ctypes.c_void_p()
         _check(L.adg_init_mesh(arr, len(descs), prec, ctypes.byref(h)))
         self._h = h
@@ -329,6 +367,25 @@ class Mesh:
                                          _ptr(wbar, torch.float64, pts.shape[0], "wbar"), pts.shape[0],
                                          _ptr(ubar, torch.float64, self.info["u_elems"], "ubar"),
                                          _stream(stream)))
+
+    def indicator(self, u, eta=None, stream=None):
+        """Refinement indicator per cell (adg_indicator); returns eta (FP64)."""
+        import torch
+        if eta is None:
+            eta = torch.empty(self.info["n_cells"], dtype=torch.float64, device=u.device)
+        _check(load().adg_indicator(self._h, _ptr(u, torch.float64, self.info["u_elems"], "u"),
+                                    _ptr(eta, torch.float64, self.info["n_cells"], "eta"), _stream(stream)))
+        return eta
+
+    def transfer_to(self, u, other, u_other=None, stream=None):
+        """State of handle `other` from this handle's u (adg_transfer)."""
+        import torch
+        if u_other is None:
+            u_other = torch.empty(other.info["u_elems"], dtype=torch.float64, device=u.device)
+        _check(load().adg_transfer(self._h, _ptr(u, torch.float64, self.info["u_elems"], "u"), other._h,
+                                   _ptr(u_other, torch.float64, other.info["u_elems"], "u_other"),
+                                   _stream(stream)))
+        return u_other
 
     def status(self):
         """Synchronises; raises AdgError(NONPHYSICAL) if a bad state was met."""

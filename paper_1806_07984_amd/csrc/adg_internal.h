@@ -73,7 +73,8 @@ struct HostMesh {
 };
 
 // Returns an empty string on success, otherwise the error text.
-std::string build_host_mesh(const adg_instance_desc &d, HostMesh &m);
+// leaves_only: stop after the sorted cell table (level, ijk)
+std::string build_host_mesh(const adg_instance_desc &d, HostMesh &m, bool leaves_only = false);
 
 void set_error(const std::string &msg);
 

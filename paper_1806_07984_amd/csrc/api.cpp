@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <unordered_map>
 #include <new>
 
 #include "adg_internal.h"
@@ -1293,6 +1294,202 @@ adg_status adg_get_status(adg_mesh *mesh)
         ADG_HIP(hipMemcpy(mesh->status_dev, &zero, sizeof(int), hipMemcpyHostToDevice), "status reset");
         set_error("non-physical state (rho <= 0, p <= 0 or non-finite) met on the device");
         return ADG_ERR_NONPHYSICAL;
+    }
+    return ADG_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Dynamic adaptivity (Sec. 2.3, dynamic-adaptivity paragraph)
+// ---------------------------------------------------------------------------
+
+namespace {
+
+inline uint64_t cell_key(int l, int64_t i, int64_t j, int64_t k)
+{
+    return (uint64_t(l) << 60) | (uint64_t(k) << 40) | (uint64_t(j) << 20) | uint64_t(i);
+}
+
+int64_t pow3i(int e)
+{
+    int64_t r = 1;
+    while (e-- > 0) r *= 3;
+    return r;
+}
+
+// Leaves of `from` inside region (l, q) of target cell (lc, kc), in the order
+// z, y, x of the sub-cells at every level; adds 27^(depth - dl) per leaf to
+// *cover (depth = max_level - lc), which sums to 27^depth when covered.
+void collect_kids(const std::unordered_map<uint64_t, int32_t> &index, int max_level, int lc, const int64_t *kc,
+                  int l, const int64_t *q, std::vector<adg::VKid> &kids, int64_t &cover)
+{
+    auto it = index.find(cell_key(l, q[0], q[1], q[2]));
+    if (it != index.end()) {
+        const int dl = l - lc;
+        const int64_t r = pow3i(dl);
+        adg::VKid k{it->second, int8_t(dl), {int8_t(q[0] - r * kc[0]), int8_t(q[1] - r * kc[1]),
+                                             int8_t(q[2] - r * kc[2])}};
+        kids.push_back(k);
+        cover += pow3i(3 * (max_level - lc - dl));
+        return;
+    }
+    if (l >= max_level) return;
+    for (int c2 = 0; c2 < 3; ++c2)
+        for (int c1 = 0; c1 < 3; ++c1)
+            for (int c0 = 0; c0 < 3; ++c0) {
+                const int64_t q2[3] = {3 * q[0] + c0, 3 * q[1] + c1, 3 * q[2] + c2};
+                collect_kids(index, max_level, lc, kc, l + 1, q2, kids, cover);
+            }
+}
+
+}  // namespace
+
+extern "C" {
+
+adg_status adg_indicator(adg_mesh *mesh, const double *u, double *eta, hipStream_t stream)
+{
+    if (!valid_mesh(mesh) || !u || !eta) {
+        set_error("adg_indicator: null argument");
+        return ADG_ERR_INVALID_ARG;
+    }
+    for (auto &I : mesh->inst)
+        ADG_HIP(launch_indicator(I.N, u + I.u_off, I.nc, eta + I.cell_off, stream), "indicator");
+    return ADG_OK;
+}
+
+adg_status adg_transfer(const adg_mesh *from, const double *u_from, adg_mesh *to, double *u_to, hipStream_t stream)
+{
+    if (!valid_mesh(from) || !valid_mesh(to) || !u_from || !u_to) {
+        set_error("adg_transfer: null argument");
+        return ADG_ERR_INVALID_ARG;
+    }
+    if (from->inst.size() != 1 || to->inst.size() != 1) {
+        set_error("adg_transfer: handles must hold one instance each");
+        return ADG_ERR_UNSUPPORTED;
+    }
+    const Instance &F = from->inst[0];
+    Instance &T = to->inst[0];
+    bool same = F.N == T.N;
+    for (int a = 0; a < 3; ++a)
+        same = same && F.hm.n[a] == T.hm.n[a] && F.hm.lo[a] == T.hm.lo[a] && F.hm.hi[a] == T.hm.hi[a];
+    if (!same) {
+        set_error("adg_transfer: the meshes differ in order or base grid");
+        return ADG_ERR_INVALID_ARG;
+    }
+    std::unordered_map<uint64_t, int32_t> index;
+    index.reserve(size_t(F.nc) * 2);
+    for (int64_t c = 0; c < F.nc; ++c)
+        index.emplace(cell_key(F.hm.level[c], F.hm.ijk[3 * c], F.hm.ijk[3 * c + 1], F.hm.ijk[3 * c + 2]), int32_t(c));
+    std::vector<VOp> ops(size_t(T.nc));
+    std::vector<VKid> kids;
+    for (int64_t c = 0; c < T.nc; ++c) {
+        const int l = T.hm.level[c];
+        const int64_t k[3] = {T.hm.ijk[3 * c], T.hm.ijk[3 * c + 1], T.hm.ijk[3 * c + 2]};
+        VOp op{};
+        auto it = index.find(cell_key(l, k[0], k[1], k[2]));
+        if (it != index.end()) {
+            op.kind = 0;
+            op.src = it->second;
+            ops[size_t(c)] = op;
+            continue;
+        }
+        bool found = false;
+        for (int lp = l - 1; lp >= 0 && !found; --lp) {
+            const int64_t r = pow3i(l - lp);
+            auto jt = index.find(cell_key(lp, k[0] / r, k[1] / r, k[2] / r));
+            if (jt == index.end()) continue;
+            op.kind = 1;
+            op.src = jt->second;
+            op.dl = int8_t(l - lp);
+            for (int d = 0; d < 3; ++d) op.s[d] = int8_t(k[d] % r);
+            found = true;
+        }
+        if (!found) {
+            int64_t cover = 0;
+            op.kind = 2;
+            op.kid0 = int32_t(kids.size());
+            collect_kids(index, F.hm.max_level, l, k, l, k, kids, cover);
+            op.nkid = int32_t(kids.size()) - op.kid0;
+            if (op.nkid == 0 || cover != pow3i(3 * (F.hm.max_level - l))) {
+                set_error("adg_transfer: a cell of the target mesh is only partly covered by the source mesh");
+                return ADG_ERR_INVALID_ARG;
+            }
+        }
+        ops[size_t(c)] = op;
+    }
+    VOp *ops_dev = nullptr;
+    VKid *kids_dev = nullptr;
+    ADG_HIP(hipSetDevice(to->device), "set device");
+    ADG_HIP(hipMalloc(&ops_dev, sizeof(VOp) * ops.size()), "transfer table");
+    hipError_t e = hipMalloc(&kids_dev, sizeof(VKid) * std::max<size_t>(1, kids.size()));
+    if (e == hipSuccess) e = hipMemcpyAsync(ops_dev, ops.data(), sizeof(VOp) * ops.size(), hipMemcpyHostToDevice,
+                                            stream);
+    if (e == hipSuccess && !kids.empty())
+        e = hipMemcpyAsync(kids_dev, kids.data(), sizeof(VKid) * kids.size(), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = launch_vtransfer(T.N, u_from, F.nc, u_to, T.nc, ops_dev, kids_dev, T.ptab, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    (void)hipFree(ops_dev);
+    if (kids_dev) (void)hipFree(kids_dev);
+    if (e != hipSuccess) return hip_fail(e, "volumetric transfer");
+    return ADG_OK;
+}
+
+adg_status adg_adapt_plan(const adg_instance_desc *desc, const double *eta, double theta_refine, double theta_coarsen,
+                          int32_t *refine_out, int64_t capacity, int64_t *n_refine_out)
+{
+    if (!desc || !eta || !n_refine_out) {
+        set_error("adg_adapt_plan: null argument");
+        return ADG_ERR_INVALID_ARG;
+    }
+    HostMesh hm;
+    std::string err = build_host_mesh(*desc, hm, true);
+    if (!err.empty()) {
+        set_error("adg_adapt_plan: " + err);
+        return err.rfind("unsupported", 0) == 0 ? ADG_ERR_UNSUPPORTED : ADG_ERR_INVALID_ARG;
+    }
+    // cells come sorted by (level, k, j, i), which is the order of their keys
+    std::vector<uint64_t> keys(size_t(hm.nc));
+    for (int64_t c = 0; c < hm.nc; ++c)
+        keys[size_t(c)] = cell_key(hm.level[c], hm.ijk[3 * c], hm.ijk[3 * c + 1], hm.ijk[3 * c + 2]);
+    auto find_leaf = [&](uint64_t key) -> int64_t {
+        auto it = std::lower_bound(keys.begin(), keys.end(), key);
+        return (it != keys.end() && *it == key) ? int64_t(it - keys.begin()) : -1;
+    };
+    auto split = [&](int64_t c) { return eta[c] > theta_refine && hm.level[c] < desc->max_level; };
+    // current rows minus the merged parents, plus the split leaves
+    struct Row { int32_t l, i, j, k; };
+    std::vector<Row> rows;
+    for (int64_t r = 0; r < desc->n_refine; ++r) {
+        const int32_t *q = desc->refine + 4 * r;
+        bool merge = true;
+        for (int c2 = 0; c2 < 3 && merge; ++c2)
+            for (int c1 = 0; c1 < 3 && merge; ++c1)
+                for (int c0 = 0; c0 < 3 && merge; ++c0) {
+                    const int64_t f = find_leaf(cell_key(q[0] + 1, 3 * int64_t(q[1]) + c0, 3 * int64_t(q[2]) + c1,
+                                                         3 * int64_t(q[3]) + c2));
+                    merge = f >= 0 && !split(f) && eta[f] < theta_coarsen;
+                }
+        if (!merge) rows.push_back(Row{q[0], q[1], q[2], q[3]});
+    }
+    for (int64_t c = 0; c < hm.nc; ++c)
+        if (split(c)) rows.push_back(Row{hm.level[c], hm.ijk[3 * c], hm.ijk[3 * c + 1], hm.ijk[3 * c + 2]});
+    std::sort(rows.begin(), rows.end(), [](const Row &a, const Row &b) {
+        if (a.l != b.l) return a.l < b.l;
+        if (a.k != b.k) return a.k < b.k;
+        if (a.j != b.j) return a.j < b.j;
+        return a.i < b.i;
+    });
+    *n_refine_out = int64_t(rows.size());
+    if (!refine_out || capacity < int64_t(rows.size())) {
+        set_error("adg_adapt_plan: refine_out holds fewer rows than the plan (count returned in n_refine_out)");
+        return ADG_ERR_WORKSPACE;
+    }
+    for (size_t r = 0; r < rows.size(); ++r) {
+        refine_out[4 * r] = rows[r].l;
+        refine_out[4 * r + 1] = rows[r].i;
+        refine_out[4 * r + 2] = rows[r].j;
+        refine_out[4 * r + 3] = rows[r].k;
     }
     return ADG_OK;
 }

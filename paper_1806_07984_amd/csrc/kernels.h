@@ -90,6 +90,23 @@ hipError_t launch_cfl_prime(int N, const double *u, int64_t nc, const int8_t *le
 hipError_t launch_cfl_final(const double *partial, int nparts, double factor, double *dt_out, double *hist,
                             hipStream_t st);
 
+// Dynamic adaptivity.  One target cell's relation to the source mesh:
+// kind 0 copy of cell src; 1 evaluation of the coarser source cell src (dl
+// levels up, sub-position s per axis); 2 L2 projection of the finer source
+// cells kids[kid0 .. kid0+nkid) (each with its own dl and sub-position).
+struct VOp {
+    int32_t kind, src, kid0, nkid;
+    int8_t dl, s[3];
+};
+struct VKid {
+    int32_t cell;
+    int8_t dl, s[3];
+};
+// refinement indicator per cell: max over nodes and axes of |d rho/d xi_d|
+hipError_t launch_indicator(int N, const double *u, int64_t nc, double *eta, hipStream_t st);
+hipError_t launch_vtransfer(int N, const double *u_from, int64_t nc_from, double *u_to, int64_t nc_to,
+                            const VOp *ops, const VKid *kids, const double *ptab, hipStream_t st);
+
 int cfl_blocks(int N, int64_t nc);
 // factor = cfl / (2p + 1); writes dt_out[0] (and hist[0] if not null)
 hipError_t launch_cfl(int N, const double *u, int64_t nc, const int8_t *level, const Geo &geo, double gamma,

@@ -1692,6 +1692,91 @@ k_sample_adj(const double *__restrict__ pts, const double *__restrict__ wbar, in
 }
 
 // ---------------------------------------------------------------------------
+// Dynamic adaptivity: refinement indicator and volumetric transfer
+// ---------------------------------------------------------------------------
+
+// Indicator of one cell per block (lane = node): the largest change of the
+// density across the cell along any axis, max_{a,d} |d rho_h / d xi_d (x_a)|
+// (derivative in the cell's reference coordinate).
+template <int N>
+__global__ void __launch_bounds__(round64(N * N * N))
+k_indicator(const double *__restrict__ u, int64_t nc, double *__restrict__ eta)
+{
+    constexpr int N2 = N * N, N3 = N2 * N, W = round64(N3) / 64;
+    __shared__ double sh[W];
+    const DevBasis &B = c_basis[N];
+    const int64_t c = blockIdx.x;
+    const int a = threadIdx.x;
+    double m = 0.0;
+    if (a < N3) {
+        const double *rho = u + c * N3;  // variable 0
+        const int aa[3] = {a % N, (a / N) % N, a / N2};
+        const int stride[3] = {1, N, N2};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int base = a - aa[d] * stride[d];
+            double g = 0.0;
+#pragma unroll
+            for (int e = 0; e < N; ++e) g += B.D[aa[d] * N + e] * rho[base + e * stride[d]];
+            m = fmax(m, fabs(g));
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    if ((a & 63) == 0) sh[a >> 6] = m;
+    __syncthreads();
+    if (a == 0) {
+        double r = sh[0];
+        for (int w = 1; w < W; ++w) r = fmax(r, sh[w]);
+        eta[c] = r;
+    }
+}
+
+// Volumetric data of one target cell per block (lane = node): copy, the
+// coarser source cell's polynomial at the target nodes (tensor product of the
+// 1-D evaluation blocks P), or the L2 projection of the finer source cells
+// (tensor product of the 1-D projection blocks R, one term per source cell in
+// list order).
+template <int N>
+__global__ void __launch_bounds__(round64(N * N * N))
+k_vtransfer(const double *__restrict__ uf, int64_t ncf, double *__restrict__ ut, int64_t nct,
+            const VOp *__restrict__ ops, const VKid *__restrict__ kids, const double *__restrict__ ptab)
+{
+    constexpr int N2 = N * N, N3 = N2 * N;
+    const int64_t c = blockIdx.x;
+    const int a = threadIdx.x;
+    if (a >= N3) return;
+    const VOp op = ops[c];
+    const int aa[3] = {a % N, (a / N) % N, a / N2};
+    double acc[NV] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (op.kind == 0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] = uf[(int64_t(v) * ncf + op.src) * N3 + a];
+    } else {
+        const int n = op.kind == 1 ? 1 : op.nkid;
+        for (int t = 0; t < n; ++t) {
+            int64_t src;
+            int dl, sp[3], half;
+            if (op.kind == 1) {
+                src = op.src; dl = op.dl; sp[0] = op.s[0]; sp[1] = op.s[1]; sp[2] = op.s[2]; half = 0;
+            } else {
+                const VKid k = kids[op.kid0 + t];
+                src = k.cell; dl = k.dl; sp[0] = k.s[0]; sp[1] = k.s[1]; sp[2] = k.s[2]; half = N2;
+            }
+            const double *M[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) M[d] = ptab + int64_t(transfer_base(dl) + sp[d]) * 2 * N2 + half;
+            for (int b = 0; b < N3; ++b) {
+                const double wgt = M[0][aa[0] * N + b % N] * M[1][aa[1] * N + (b / N) % N] * M[2][aa[2] * N + b / N2];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) acc[v] += wgt * uf[(int64_t(v) * ncf + src) * N3 + b];
+            }
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ut[(int64_t(v) * nct + c) * N3 + a] = acc[v];
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 
@@ -2058,6 +2143,26 @@ hipError_t launch_sample_adjoint(int N, const double *pts, const double *wbar, i
     ADG_DISPATCH_N(N, {
         hipLaunchKernelGGL((k_sample_adj<NN>), dim3(1), dim3(round64(NN * NN * NN)), 0, st, pts, wbar, npts, sg,
                            ubar);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_indicator(int N, const double *u, int64_t nc, double *eta, hipStream_t st)
+{
+    if (nc <= 0) return hipSuccess;
+    ADG_DISPATCH_N(N, {
+        hipLaunchKernelGGL((k_indicator<NN>), dim3(unsigned(nc)), dim3(round64(NN * NN * NN)), 0, st, u, nc, eta);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_vtransfer(int N, const double *u_from, int64_t nc_from, double *u_to, int64_t nc_to,
+                            const VOp *ops, const VKid *kids, const double *ptab, hipStream_t st)
+{
+    if (nc_to <= 0) return hipSuccess;
+    ADG_DISPATCH_N(N, {
+        hipLaunchKernelGGL((k_vtransfer<NN>), dim3(unsigned(nc_to)), dim3(round64(NN * NN * NN)), 0, st, u_from,
+                           nc_from, u_to, nc_to, ops, kids, ptab);
     });
     return hipGetLastError();
 }

@@ -48,7 +48,7 @@ inline int64_t pow3(int e)
 
 }  // namespace
 
-std::string build_host_mesh(const adg_instance_desc &d, HostMesh &m)
+std::string build_host_mesh(const adg_instance_desc &d, HostMesh &m, bool leaves_only)
 {
     char buf[256];
     if (d.order < 0 || d.order > NMAX - 1) return "unsupported: order must be in [0, 7]";
@@ -110,15 +110,16 @@ std::string build_host_mesh(const adg_instance_desc &d, HostMesh &m)
     m.nc = int64_t(cells.size());
     m.level.resize(m.nc);
     m.ijk.resize(3 * m.nc);
-    std::unordered_map<uint64_t, int32_t> index;
-    index.reserve(cells.size() * 2);
     for (int64_t c = 0; c < m.nc; ++c) {
         m.level[c] = int8_t(cells[c].l);
         m.ijk[3 * c] = cells[c].i;
         m.ijk[3 * c + 1] = cells[c].j;
         m.ijk[3 * c + 2] = cells[c].k;
-        index.emplace(pack(cells[c].l, cells[c].i, cells[c].j, cells[c].k), int32_t(c));
     }
+    if (leaves_only) return "";
+    std::unordered_map<uint64_t, int32_t> index;
+    index.reserve(cells.size() * 2);
+    for (int64_t c = 0; c < m.nc; ++c) index.emplace(pack(cells[c].l, cells[c].i, cells[c].j, cells[c].k), int32_t(c));
 
     // side classification
     std::vector<int8_t> kind(6 * m.nc);
