@@ -69,6 +69,16 @@ def lib():
         L.orc_volume_transfer.restype = ctypes.c_int
         L.orc_volume_transfer.argtypes = [P, P, P, P]
         L.orc_integral.argtypes = [P, P, P]
+        L.orc_subcell_ops.restype = ctypes.c_int
+        L.orc_subcell_ops.argtypes = [ctypes.c_int, P, P, P]
+        L.orc_limiter_detect.restype = ctypes.c_int
+        L.orc_limiter_detect.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, P, P, P]
+        L.orc_limited_step.restype = ctypes.c_int
+        L.orc_limited_step.argtypes = [P, ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_int, P, P]
+        L.orc_run_limited.restype = ctypes.c_int
+        L.orc_run_limited.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_int, P, ctypes.c_int, P, P, P]
         _lib = L
     return _lib
 
@@ -220,6 +230,41 @@ def _integral(self, u):
     return out
 
 
+def _run_limited(self, u, nsteps, gamma=1.4, cfl=0.4, npic=None, dt_fixed=0.0, delta0=1e-4, eps=1e-3,
+                 force=False):
+    """Steps with the a-posteriori subcell limiter.  Returns (u_final,
+    dt_history, troubled cells per step, flags of the last step, status);
+    flags: 1 limited, 2 corrector re-run next to a limited cell, 0 else."""
+    u = np.array(u, dtype=np.float64, copy=True, order="C")
+    npic = self.N if npic is None else npic
+    hist = np.zeros(max(nsteps, 1))
+    nt = np.zeros(max(nsteps, 1), dtype=np.int64)
+    flags = np.zeros(self.nc, dtype=np.int32)
+    rc = lib().orc_run_limited(self._h, gamma, cfl, int(npic), float(dt_fixed), float(delta0), float(eps),
+                               int(bool(force)), _p(u), int(nsteps), _p(hist), _p(nt), _p(flags))
+    return u, hist[:nsteps], nt[:nsteps], flags, int(rc)
+
+
+def _limiter_detect(self, u_old, u_cand, gamma=1.4, delta0=1e-4, eps=1e-3):
+    """Troubled flags (1/0) of a candidate given the old solution."""
+    u_old, u_cand = _f64(u_old), _f64(u_cand)
+    flags = np.zeros(self.nc, dtype=np.int32)
+    rc = lib().orc_limiter_detect(self._h, gamma, float(delta0), float(eps), _p(u_old), _p(u_cand), _p(flags))
+    assert rc == 0, rc
+    return flags
+
+
+def subcell_ops(N):
+    """(A [ns, N], least-squares inverse [N, ns], face projection B [N, ns])
+    of the subcell limiter, ns = 2N - 1."""
+    ns = 2 * N - 1
+    A, Ap, B = np.zeros((ns, N)), np.zeros((N, ns)), np.zeros((N, ns))
+    assert lib().orc_subcell_ops(N, _p(A), _p(Ap), _p(B)) == 0
+    return A, Ap, B
+
+
+Mesh.run_limited = _run_limited
+Mesh.limiter_detect = _limiter_detect
 Mesh.run_sched = _run_sched
 Mesh.sample = _sample
 Mesh.indicator = _indicator

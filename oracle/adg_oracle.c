@@ -1071,6 +1071,441 @@ void orc_integral(const orc_mesh *m, const double *u, double *out)
     }
 }
 
+/* ------------------------------------------------------------------------- */
+/* A-posteriori finite-volume subcell limiter                                */
+/* ------------------------------------------------------------------------- */
+
+/* The limiter of Sec. 3 (block-structured methods; Sec. 5, Euler with
+ * shocks): after the ADER-DG update, a cell whose new solution is physically
+ * wrong or oscillates is rolled back and advanced over the same dt by a
+ * finite-volume scheme on (2p+1)^3 equal subcells.  Readings (the paper
+ * leaves the details to the limiter's own literature):
+ *   - the old subcell data of a cell are the subcell averages of its
+ *     polynomial; if one of them is unphysical, every subcell takes the cell
+ *     mean instead (a convex combination of the physical nodal states);
+ *   - the FV scheme is first order (piecewise constant data, Sec. 3: FV is
+ *     ADER-DG with a degenerate predictor) with the Rusanov flux on every
+ *     subcell face, the speed being the larger |u_d| + c of its two states;
+ *   - a cell is troubled if its candidate has a non-finite value, rho <= 0
+ *     or p <= 0 at a node or in a subcell average, or if a subcell average
+ *     of a variable leaves [m - delta, M + delta], where m and M are the
+ *     smallest and largest old subcell averages of that variable in the cell
+ *     and its face neighbours, delta = max(delta0, eps (M - m));
+ *   - the limited cell's new polynomial is the least-squares fit to its new
+ *     subcell averages (it keeps the cell mean); if that polynomial is
+ *     unphysical at a node or in a subcell average, the cell takes the
+ *     constant state of the mean;
+ *   - on a face between a limited cell and an unlimited one, the unlimited
+ *     cell's face flux is replaced by the L2 projection of the subcell face
+ *     fluxes onto the face polynomials and its corrector is run again, so
+ *     that both sides see the same flux (conservation).
+ * Single-level meshes only (no hanging faces). */
+
+/* 1-D subcell operators for N = p+1 nodes and ns = 2p+1 subintervals:
+ *   A[s][k]    average of phi_k over subinterval s
+ *              = sum_q w_q phi_k((s + xi_q)/ns)  (N-point Gauss, exact);
+ *   Ap[k][s]   least-squares inverse (A^T A)^{-1} A^T;
+ *   B[k][s]    L2 projection of piecewise constants onto the polynomials:
+ *              (B F)_k = (1/w_k) int phi_k F = sum_s F_s A[s][k] / (ns w_k).
+ * Any pointer may be NULL.  Returns nonzero on bad N. */
+int orc_subcell_ops(int N, double *A, double *Ap, double *B)
+{
+    if (N < 1 || N > MAXN) return 1;
+    int ns = 2 * N - 1;
+    double xi[MAXN], w[MAXN];
+    orc_gauss_legendre(N, xi, w);
+    double Aloc[(2 * MAXN - 1) * MAXN];
+    for (int s = 0; s < ns; ++s)
+        for (int k = 0; k < N; ++k) {
+            double acc = 0.0;
+            for (int q = 0; q < N; ++q) acc += w[q] * lagrange(N, xi, k, (s + xi[q]) / ns);
+            Aloc[s * N + k] = acc;
+        }
+    if (A) memcpy(A, Aloc, sizeof(double) * ns * N);
+    if (B)
+        for (int k = 0; k < N; ++k)
+            for (int s = 0; s < ns; ++s) B[k * ns + s] = Aloc[s * N + k] / (ns * w[k]);
+    if (Ap) {
+        double AtA[MAXN * MAXN], inv[MAXN * MAXN];
+        for (int i = 0; i < N; ++i)
+            for (int j = 0; j < N; ++j) {
+                double acc = 0.0;
+                for (int s = 0; s < ns; ++s) acc += Aloc[s * N + i] * Aloc[s * N + j];
+                AtA[i * N + j] = acc;
+            }
+        if (invert(N, AtA, inv)) return 1;
+        for (int k = 0; k < N; ++k)
+            for (int s = 0; s < ns; ++s) {
+                double acc = 0.0;
+                for (int j = 0; j < N; ++j) acc += inv[k * N + j] * Aloc[s * N + j];
+                Ap[k * ns + s] = acc;
+            }
+    }
+    return 0;
+}
+
+/* Subcell averages v[5][ns^3] (subcell index s0 + ns s1 + ns^2 s2) of cell c:
+ * v_s = sum_a A[s0][a0] A[s1][a1] A[s2][a2] u_a. */
+static void subcell_averages(int N, long nc, const double *A, const double *u, long c, double *v)
+{
+    int ns = 2 * N - 1, N3 = N * N * N, S3 = ns * ns * ns;
+    for (int vv = 0; vv < NV; ++vv)
+        for (int s = 0; s < S3; ++s) {
+            int ss[3] = { s % ns, (s / ns) % ns, s / (ns * ns) };
+            double acc = 0.0;
+            for (int a = 0; a < N3; ++a)
+                acc += A[ss[0] * N + a % N] * A[ss[1] * N + (a / N) % N] * A[ss[2] * N + a / (N * N)] *
+                       u[((long)vv * nc + c) * N3 + a];
+            v[vv * S3 + s] = acc;
+        }
+}
+
+/* Old subcell data of cell c: the subcell averages, or the cell mean in
+ * every subcell if an average is unphysical. */
+static void subcell_data(int N, long nc, double g, const double *A, const double *u, long c, double *v)
+{
+    int ns = 2 * N - 1, N3 = N * N * N, S3 = ns * ns * ns;
+    subcell_averages(N, nc, A, u, c, v);
+    int bad = 0;
+    for (int s = 0; s < S3 && !bad; ++s) {
+        double q[NV];
+        for (int vv = 0; vv < NV; ++vv) q[vv] = v[vv * S3 + s];
+        bad = unphysical(g, q);
+    }
+    if (!bad) return;
+    double xi[MAXN], w[MAXN];
+    orc_gauss_legendre(N, xi, w);
+    for (int vv = 0; vv < NV; ++vv) {
+        double mean = 0.0;
+        for (int a = 0; a < N3; ++a)
+            mean += w[a % N] * w[(a / N) % N] * w[a / (N * N)] * u[((long)vv * nc + c) * N3 + a];
+        for (int s = 0; s < S3; ++s) v[vv * S3 + s] = mean;
+    }
+}
+
+/* Rusanov flux along d between subcell states ql (minus side) and qr. */
+static void rusanov_point(double g, int d, const double ql[NV], const double qr[NV], double f[NV])
+{
+    double fl[NV], fr[NV];
+    euler_flux(g, ql, d, fl);
+    euler_flux(g, qr, d, fr);
+    double sl = euler_speed(g, ql, d), sr = euler_speed(g, qr, d);
+    double smax = sl > sr ? sl : sr;
+    for (int v = 0; v < NV; ++v) f[v] = 0.5 * (fl[v] + fr[v]) - 0.5 * smax * (qr[v] - ql[v]);
+}
+
+/* Troubled-cell test of one cell (see the readings above).  ucand: candidate
+ * polynomial of the whole mesh; vcand: the cell's candidate subcell averages;
+ * lo, hi: [5] neighbourhood bounds of the old averages. */
+static int is_troubled(int N, long nc, double g, const double *ucand, long c, const double *vcand,
+                       const double *lo, const double *hi, double delta0, double eps)
+{
+    int ns = 2 * N - 1, N3 = N * N * N, S3 = ns * ns * ns;
+    for (int a = 0; a < N3; ++a) {
+        double q[NV];
+        for (int v = 0; v < NV; ++v) q[v] = ucand[((long)v * nc + c) * N3 + a];
+        if (unphysical(g, q)) return 1;
+    }
+    for (int s = 0; s < S3; ++s) {
+        double q[NV];
+        for (int v = 0; v < NV; ++v) q[v] = vcand[v * S3 + s];
+        if (unphysical(g, q)) return 1;
+    }
+    for (int v = 0; v < NV; ++v) {
+        double delta = eps * (hi[v] - lo[v]);
+        if (delta < delta0) delta = delta0;
+        for (int s = 0; s < S3; ++s) {
+            double x = vcand[v * S3 + s];
+            if (!(x >= lo[v] - delta && x <= hi[v] + delta)) return 1;
+        }
+    }
+    return 0;
+}
+
+/* Troubled-cell flags (1 troubled, 0 not) of candidate ucand given the old
+ * solution uold, both [5][nc][N^3].  Returns 3 if the mesh has a hanging
+ * face, 2 on allocation failure, else 0. */
+int orc_limiter_detect(const orc_mesh *m, double g, double delta0, double eps, const double *uold,
+                       const double *ucand, int *flags)
+{
+    int N = m->N, ns = 2 * N - 1, S3 = ns * ns * ns;
+    long nc = m->nc;
+    for (long k = 0; k < 6 * nc; ++k)
+        if (m->kind[k] != SIDE_CONFORMING) return 3;
+    double A[(2 * MAXN - 1) * MAXN];
+    if (orc_subcell_ops(N, A, NULL, NULL)) return 2;
+    double *bnd = (double *)malloc(sizeof(double) * nc * 2 * NV);
+    if (!bnd) return 2;
+    /* per-cell extremes of the old subcell averages */
+#pragma omp parallel
+    {
+        double *tmp = (double *)malloc(sizeof(double) * NV * S3);
+#pragma omp for schedule(static)
+        for (long c = 0; c < nc; ++c) {
+            subcell_data(N, nc, g, A, uold, c, tmp);
+            for (int v = 0; v < NV; ++v) {
+                double lo = tmp[v * S3], hi = tmp[v * S3];
+                for (int s = 0; s < S3; ++s) {
+                    if (tmp[v * S3 + s] < lo) lo = tmp[v * S3 + s];
+                    if (tmp[v * S3 + s] > hi) hi = tmp[v * S3 + s];
+                }
+                bnd[(c * 2 + 0) * NV + v] = lo;
+                bnd[(c * 2 + 1) * NV + v] = hi;
+            }
+        }
+        free(tmp);
+    }
+    /* bounds over the cell and its face neighbours; test the candidate */
+#pragma omp parallel
+    {
+        double *tmp = (double *)malloc(sizeof(double) * NV * S3);
+#pragma omp for schedule(static)
+        for (long c = 0; c < nc; ++c) {
+            double lo[NV], hi[NV];
+            for (int v = 0; v < NV; ++v) {
+                lo[v] = bnd[(c * 2 + 0) * NV + v];
+                hi[v] = bnd[(c * 2 + 1) * NV + v];
+            }
+            for (int s = 0; s < 6; ++s) {
+                long o = m->nbr[6 * c + s];
+                for (int v = 0; v < NV; ++v) {
+                    if (bnd[(o * 2 + 0) * NV + v] < lo[v]) lo[v] = bnd[(o * 2 + 0) * NV + v];
+                    if (bnd[(o * 2 + 1) * NV + v] > hi[v]) hi[v] = bnd[(o * 2 + 1) * NV + v];
+                }
+            }
+            subcell_averages(N, nc, A, ucand, c, tmp);
+            flags[c] = is_troubled(N, nc, g, ucand, c, tmp, lo, hi, delta0, eps);
+        }
+        free(tmp);
+    }
+    free(bnd);
+    return 0;
+}
+
+/* Old subcell average of neighbour/own data at subcell (s0,s1,s2), variable v. */
+#define VOLD(cell, v, s) vold[((long)(cell) * NV + (v)) * S3 + (s)]
+
+/* One limited ADER-DG step of size dt in place on u.  flags[nc] receives 1
+ * for limited cells, 2 for unlimited cells whose corrector ran again, 0
+ * otherwise.  force != 0 limits every cell (test hook).  Returns 0, 1 if the
+ * final state is unphysical somewhere, 2 on allocation failure, 3 if the
+ * mesh has a hanging face. */
+int orc_limited_step(const orc_mesh *m, double g, int npic, double dt, double delta0, double eps, int force,
+                     double *u, int *flags)
+{
+    int N = m->N, N2 = N * N, N3 = N2 * N, ns = 2 * N - 1, S2 = ns * ns, S3 = S2 * ns;
+    long nc = m->nc;
+    for (long k = 0; k < 6 * nc; ++k)
+        if (m->kind[k] != SIDE_CONFORMING) return 3;
+    double A[(2 * MAXN - 1) * MAXN], Ap[MAXN * (2 * MAXN - 1)], B[MAXN * (2 * MAXN - 1)];
+    if (orc_subcell_ops(N, A, Ap, B)) return 2;
+    double xi[MAXN], w[MAXN], D[MAXN * MAXN], L[MAXN], R[MAXN], Kinv[MAXN * MAXN], Kw[MAXN * MAXN];
+    orc_basis(N, xi, w, D, L, R, Kinv, Kw);
+    double *vold = (double *)malloc(sizeof(double) * nc * NV * S3);
+    double *us = (double *)malloc(sizeof(double) * NV * nc * N3);
+    double *tr = (double *)malloc(sizeof(double) * 6 * 2 * NV * nc * N2);
+    double *fs = (double *)malloc(sizeof(double) * 6 * NV * nc * N2);
+    double *un = (double *)malloc(sizeof(double) * NV * nc * N3);
+    if (!vold || !us || !tr || !fs || !un) {
+        free(vold); free(us); free(tr); free(fs); free(un);
+        return 2;
+    }
+    /* old subcell data */
+#pragma omp parallel
+    {
+        double *tmp = (double *)malloc(sizeof(double) * NV * S3);
+#pragma omp for schedule(static)
+        for (long c = 0; c < nc; ++c) {
+            subcell_data(N, nc, g, A, u, c, tmp);
+            for (int v = 0; v < NV; ++v)
+                for (int s = 0; s < S3; ++s) VOLD(c, v, s) = tmp[v * S3 + s];
+        }
+        free(tmp);
+    }
+    /* the unlimited candidate (unphysical states are what the limiter is for) */
+    orc_predictor(m, g, npic, dt, u, us, tr);
+    (void)orc_riemann(m, g, tr, fs);
+    orc_corrector(m, dt, us, fs, un);
+    /* detection (u still holds the old solution) */
+    if (force) {
+        for (long c = 0; c < nc; ++c) flags[c] = 1;
+    } else if (orc_limiter_detect(m, g, delta0, eps, u, un, flags)) {
+        free(vold); free(us); free(tr); free(fs); free(un);
+        return 2;
+    }
+    /* finite-volume update of the limited cells; projected face fluxes for
+     * their unlimited neighbours */
+#pragma omp parallel
+    {
+        double *vn = (double *)malloc(sizeof(double) * NV * S3);
+        double *vfit = (double *)malloc(sizeof(double) * NV * S3);
+        double *Fsub = (double *)malloc(sizeof(double) * NV * S2);
+#pragma omp for schedule(dynamic)
+        for (long c = 0; c < nc; ++c) {
+            if (flags[c] != 1) continue;
+            double dx[3];
+            cell_dx(m, c, dx);
+            for (int s = 0; s < S3; ++s) {
+                int ss[3] = { s % ns, (s / ns) % ns, s / S2 };
+                double q[NV], acc[NV] = { 0 };
+                for (int v = 0; v < NV; ++v) q[v] = VOLD(c, v, s);
+                for (int d = 0; d < 3; ++d) {
+                    double h = dx[d] / ns;
+                    for (int side = 0; side < 2; ++side) {
+                        /* state across the subcell face on this side */
+                        double qo[NV];
+                        int sn[3] = { ss[0], ss[1], ss[2] };
+                        long co = c;
+                        sn[d] += side ? 1 : -1;
+                        if (sn[d] < 0 || sn[d] >= ns) {
+                            co = m->nbr[6 * c + 2 * d + side];
+                            sn[d] = side ? 0 : ns - 1;
+                        }
+                        int so = sn[0] + ns * sn[1] + S2 * sn[2];
+                        for (int v = 0; v < NV; ++v) qo[v] = VOLD(co, v, so);
+                        double f[NV];
+                        if (side) rusanov_point(g, d, q, qo, f);
+                        else rusanov_point(g, d, qo, q, f);
+                        for (int v = 0; v < NV; ++v) acc[v] += (side ? 1.0 : -1.0) * f[v] / h;
+                    }
+                }
+                for (int v = 0; v < NV; ++v) vn[v * S3 + s] = q[v] - dt * acc[v];
+            }
+            /* least-squares polynomial of the new averages */
+            for (int v = 0; v < NV; ++v)
+                for (int a = 0; a < N3; ++a) {
+                    int aa[3] = { a % N, (a / N) % N, a / N2 };
+                    double acc = 0.0;
+                    for (int s = 0; s < S3; ++s)
+                        acc += Ap[aa[0] * ns + s % ns] * Ap[aa[1] * ns + (s / ns) % ns] * Ap[aa[2] * ns + s / S2] *
+                               vn[v * S3 + s];
+                    un[((long)v * nc + c) * N3 + a] = acc;
+                }
+            /* an unphysical fit falls back to the constant mean state */
+            int bad = 0;
+            for (int a = 0; a < N3 && !bad; ++a) {
+                double q[NV];
+                for (int v = 0; v < NV; ++v) q[v] = un[((long)v * nc + c) * N3 + a];
+                bad = unphysical(g, q);
+            }
+            if (!bad) {
+                subcell_averages(N, nc, A, un, c, vfit);
+                for (int s = 0; s < S3 && !bad; ++s) {
+                    double q[NV];
+                    for (int v = 0; v < NV; ++v) q[v] = vfit[v * S3 + s];
+                    bad = unphysical(g, q);
+                }
+            }
+            if (bad)
+                for (int v = 0; v < NV; ++v) {
+                    double mean = 0.0;
+                    for (int s = 0; s < S3; ++s) mean += vn[v * S3 + s];
+                    mean /= S3;
+                    for (int a = 0; a < N3; ++a) un[((long)v * nc + c) * N3 + a] = mean;
+                }
+            /* subcell fluxes on the faces shared with unlimited cells */
+            for (int side6 = 0; side6 < 6; ++side6) {
+                int d = side6 / 2, plus = side6 % 2;
+                long o = m->nbr[6 * c + side6];
+                if (flags[o] == 1) continue;
+                int t1, t2;
+                tangential(d, &t1, &t2);
+                for (int j2 = 0; j2 < ns; ++j2)
+                    for (int j1 = 0; j1 < ns; ++j1) {
+                        int sc[3], so[3];
+                        sc[t1] = so[t1] = j1;
+                        sc[t2] = so[t2] = j2;
+                        sc[d] = plus ? ns - 1 : 0;
+                        so[d] = plus ? 0 : ns - 1;
+                        int ic = sc[0] + ns * sc[1] + S2 * sc[2], io = so[0] + ns * so[1] + S2 * so[2];
+                        double qc[NV], qo[NV], f[NV];
+                        for (int v = 0; v < NV; ++v) {
+                            qc[v] = VOLD(c, v, ic);
+                            qo[v] = VOLD(o, v, io);
+                        }
+                        if (plus) rusanov_point(g, d, qc, qo, f);
+                        else rusanov_point(g, d, qo, qc, f);
+                        for (int v = 0; v < NV; ++v) Fsub[v * S2 + j1 + ns * j2] = f[v];
+                    }
+                int sopp = 2 * d + (1 - plus);
+                for (int v = 0; v < NV; ++v)
+                    for (int b = 0; b < N2; ++b) {
+                        int b1 = b % N, b2 = b / N;
+                        double acc = 0.0;
+                        for (int j = 0; j < S2; ++j)
+                            acc += B[b1 * ns + j % ns] * B[b2 * ns + j / ns] * Fsub[v * S2 + j];
+                        fs[((long)(sopp * NV + v) * nc + o) * N2 + b] = acc;
+                    }
+            }
+        }
+        free(vn);
+        free(vfit);
+        free(Fsub);
+    }
+    /* unlimited cells next to a limited one: corrector again with the new
+     * face fluxes (written out as in orc_corrector) */
+    for (long c = 0; c < nc; ++c) {
+        if (flags[c] == 1) continue;
+        int near = 0;
+        for (int s = 0; s < 6; ++s)
+            if (flags[m->nbr[6 * c + s]] == 1) near = 1;
+        if (near) flags[c] = 2;
+    }
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < nc; ++c) {
+        if (flags[c] != 2) continue;
+        double dx[3];
+        cell_dx(m, c, dx);
+        for (int v = 0; v < NV; ++v)
+            for (int a = 0; a < N3; ++a) {
+                int aa[3] = { a % N, (a / N) % N, a / N2 };
+                double s = 0.0;
+                for (int d = 0; d < 3; ++d) {
+                    int b = face_index(N, a, d);
+                    double fm = fs[((long)((2 * d) * NV + v) * nc + c) * N2 + b];
+                    double fp = fs[((long)((2 * d + 1) * NV + v) * nc + c) * N2 + b];
+                    s += (dt / dx[d]) * (R[aa[d]] * fp - L[aa[d]] * fm) / w[aa[d]];
+                }
+                un[((long)v * nc + c) * N3 + a] = us[((long)v * nc + c) * N3 + a] - s;
+            }
+    }
+    memcpy(u, un, sizeof(double) * NV * nc * N3);
+    int rc = 0;
+    for (long c = 0; c < nc && !rc; ++c)
+        for (int a = 0; a < N3; ++a) {
+            double q[NV];
+            for (int v = 0; v < NV; ++v) q[v] = u[((long)v * nc + c) * N3 + a];
+            if (unphysical(g, q)) { rc = 1; break; }
+        }
+    free(vold); free(us); free(tr); free(fs); free(un);
+    return rc;
+}
+#undef VOLD
+
+/* nsteps limited steps in place on u, dt from orc_cfl (or dt_fixed > 0).
+ * dt_hist[n] and ntroubled[n] (may be NULL) receive each step's dt and its
+ * number of limited cells; flags holds the last step's flags.  Returns the
+ * first nonzero orc_limited_step code (u then holds that step's result), or
+ * 1 if a CFL evaluation meets an unphysical state. */
+int orc_run_limited(const orc_mesh *m, double g, double cfl, int npic, double dt_fixed, double delta0, double eps,
+                    int force, double *u, int nsteps, double *dt_hist, long *ntroubled, int *flags)
+{
+    for (int n = 0; n < nsteps; ++n) {
+        int st = 0;
+        double dt = dt_fixed > 0.0 ? dt_fixed : orc_cfl(m, g, cfl, u, &st);
+        if (st) return 1;
+        if (dt_hist) dt_hist[n] = dt;
+        int rc = orc_limited_step(m, g, npic, dt, delta0, eps, force, u, flags);
+        if (ntroubled) {
+            long k = 0;
+            for (long c = 0; c < m->nc; ++c) k += flags[c] == 1;
+            ntroubled[n] = k;
+        }
+        if (rc) return rc;
+    }
+    return 0;
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP
