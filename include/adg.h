@@ -205,6 +205,44 @@ adg_status adg_set_options(adg_mesh *mesh, int32_t use_graph, int32_t batched);
  * (locality only); it is slower (3.26 ms). */
 adg_status adg_set_pipeline(adg_mesh *mesh, int32_t enable);
 
+/* A-posteriori finite-volume subcell limiter (Sec. 3, block-structured
+ * methods; Sec. 5, Euler with shocks: a cell whose ADER-DG update is
+ * physically wrong or oscillates is rolled back and advanced over the same dt
+ * by FV on (2p+1)^3 subcells).  With the limiter on, every adg_step step:
+ *   1. takes the old subcell data of every cell: the averages of its
+ *      polynomial over (2p+1)^3 equal subcells, or the cell mean in every
+ *      subcell if one average is unphysical;
+ *   2. computes the unlimited ADER-DG candidate;
+ *   3. limits a cell if the candidate has a non-finite value, rho <= 0 or
+ *      p <= 0 at a node or in a subcell average, or a subcell average of a
+ *      variable outside [m - delta, M + delta], with m, M the extremes of the
+ *      old subcell data of that variable over the cell and its six face
+ *      neighbours and delta = max(delta0, eps (M - m));
+ *   4. advances a limited cell's old subcell data by one first-order
+ *      finite-volume step with the Rusanov flux (speed: the larger
+ *      |u_d| + c of the two subcell states), and takes the least-squares
+ *      polynomial of the result, or the constant state of its mean if that
+ *      polynomial is unphysical at a node or in a subcell average;
+ *   5. on each face between a limited and an unlimited cell, replaces the
+ *      unlimited cell's face flux by the L2 projection of the subcell fluxes
+ *      onto the face polynomials and runs its corrector again (the scheme
+ *      stays conservative).
+ * mode: 0 off, 1 on, 2 every cell limited (test hook).  delta0, eps >= 0
+ * (1e-4 and 1e-3 are usual).  The first enable allocates the limiter's
+ * device buffers (about one more state array); they live until
+ * adg_free_mesh.  ADG_ERR_UNSUPPORTED unless the handle has one instance,
+ * a uniform mesh (max_level 0) and p <= 6.  While on, adg_set_pipeline has no
+ * effect, the step runs on s_skel only, and the candidate's inadmissible
+ * states are not errors: only an unphysical final state sets the status
+ * adg_get_status reports.  Synchronises the device. */
+adg_status adg_set_limiter(adg_mesh *mesh, int32_t mode, double delta0, double eps);
+/* Of the last limited step: the number of limited cells and of cells whose
+ * corrector ran again; flags_dev (device, nc int32, may be NULL) receives per
+ * cell 1 limited, 2 corrector re-run, 0 otherwise.  Synchronises stream.
+ * ADG_ERR_INVALID_ARG if the limiter was never enabled on the handle. */
+adg_status adg_limiter_stats(adg_mesh *mesh, int64_t *n_limited, int64_t *n_recorrected, int32_t *flags_dev,
+                             hipStream_t stream);
+
 /* Phase timing for measurement.  While enabled, every launch made by the
  * handle's calls is bracketed by HIP events recorded on the stream the launch
  * goes to.  adg_profile(mesh, 1) enables (every phase) and clears the
@@ -215,7 +253,7 @@ adg_status adg_set_pipeline(adg_mesh *mesh, int32_t enable);
  * time in milliseconds and the number of launches (arrays of ADG_NPHASES).
  * Enabling adds an event pair per launch; results are unchanged. */
 enum { ADG_PHASE_CFL = 0, ADG_PHASE_PREDICTOR = 1, ADG_PHASE_HANGING = 2, ADG_PHASE_RIEMANN = 3,
-       ADG_PHASE_CORRECTOR = 4, ADG_NPHASES = 5 };
+       ADG_PHASE_CORRECTOR = 4, ADG_PHASE_LIMITER = 5, ADG_NPHASES = 6 };
 adg_status adg_profile(adg_mesh *mesh, int32_t enable);
 adg_status adg_profile_read(adg_mesh *mesh, double *ms, int64_t *launches);
 

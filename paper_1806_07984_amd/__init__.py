@@ -23,8 +23,9 @@ EXPORTS = ["adg_init_mesh", "adg_free_mesh", "adg_mesh_info", "adg_instance_info
            "adg_node_coords", "adg_cfl", "adg_predictor", "adg_riemann", "adg_corrector", "adg_step",
            "adg_profile", "adg_profile_read", "adg_get_status", "adg_last_error", "adg_autotune",
            "adg_tuning", "adg_set_options", "adg_step_adjoint", "adg_sample", "adg_sample_adjoint",
-           "adg_set_switch_tape", "adg_set_pipeline", "adg_indicator", "adg_adapt_plan", "adg_transfer"]
-PHASES = ["cfl", "predictor", "hanging", "riemann", "corrector"]
+           "adg_set_switch_tape", "adg_set_pipeline", "adg_indicator", "adg_adapt_plan", "adg_transfer",
+           "adg_set_limiter", "adg_limiter_stats"]
+PHASES = ["cfl", "predictor", "hanging", "riemann", "corrector", "limiter"]
 
 
 class AdgError(RuntimeError):
@@ -91,6 +92,8 @@ def load():
         "adg_indicator": [P, P, P, P],
         "adg_adapt_plan": [P, P, ctypes.c_double, ctypes.c_double, P, I64, P],
         "adg_transfer": [P, P, P, P, P],
+        "adg_set_limiter": [P, I32, ctypes.c_double, ctypes.c_double],
+        "adg_limiter_stats": [P, P, P, P, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -317,6 +320,23 @@ class Mesh:
         """Pipelined step over cell chunks (single instance, no hanging faces):
         0/False off, 1/True predictor and face/corrector streams, 2 one stream."""
         _check(load().adg_set_pipeline(self._h, int(mode)))
+
+    def set_limiter(self, mode, delta0=1e-4, eps=1e-3):
+        """A-posteriori subcell limiter: 0/False off, 1/True on, 2 every cell
+        limited (test hook); delta0, eps: relaxation of the bounds."""
+        _check(load().adg_set_limiter(self._h, int(mode), float(delta0), float(eps)))
+
+    def limiter_stats(self, flags=False, stream=None, device="cuda"):
+        """(limited cells, cells whose corrector ran again) of the last step,
+        plus the per-cell flags (int32 tensor: 1 limited, 2 re-run, 0 else)
+        if flags; synchronises the stream."""
+        import torch
+        nl = ctypes.c_int64(0)
+        nr = ctypes.c_int64(0)
+        f = torch.empty(self.info["n_cells"], dtype=torch.int32, device=device) if flags else None
+        _check(load().adg_limiter_stats(self._h, ctypes.byref(nl), ctypes.byref(nr),
+                                        ctypes.c_void_p(f.data_ptr()) if flags else None, _stream(stream)))
+        return (nl.value, nr.value, f) if flags else (nl.value, nr.value)
 
     def profile(self, enable, predictor_only=False):
         """Enable (and clear) or disable HIP-event timing of every phase (or of

@@ -41,6 +41,18 @@ struct DevBasis {
     double KWsum[NMAX];  // row sums sum_j KW[l][j] (time solve from a time-constant state)
 };
 
+// Subcell limiter operators of one order (ns = 2N - 1 equal subintervals):
+//   A[s][k]   average of phi_k over subinterval s
+//   Ap[k][s]  least-squares inverse (A^T A)^{-1} A^T
+//   Bf[k][s]  L2 projection of piecewise constants onto the polynomials,
+//             A[s][k] / (ns w_k)
+constexpr int LIM_NMAX = 7;                 // largest N of the limiter (LDS)
+constexpr int LIM_NS = 2 * LIM_NMAX - 1;
+struct DevSub {
+    double A[LIM_NS * LIM_NMAX], Ap[LIM_NMAX * LIM_NS], Bf[LIM_NMAX * LIM_NS];
+};
+bool make_subcell(const Basis &b, DevSub &out);
+
 // Per-mesh geometry passed to kernels by value.
 struct Geo {
     double inv_dx[LMAX + 1][3];  // 1/dx per level and axis

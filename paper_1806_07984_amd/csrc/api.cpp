@@ -95,6 +95,11 @@ struct adg_mesh {
     int pipeline = 0;                 // 0 off, 1 two streams, 2 one stream (chunk by chunk)
     std::vector<hipEvent_t> ev_chunk;
     hipEvent_t ev_join = nullptr;
+    // a-posteriori subcell limiter (one instance, uniform mesh)
+    int lim_mode = 0;  // 0 off, 1 on, 2 every cell limited
+    double lim_delta0 = 1e-4, lim_eps = 1e-3;
+    adg::LimDev lim{};
+    int *lim_status = nullptr;  // sink of the candidate's admissibility flags
 };
 
 namespace adg {
@@ -155,6 +160,19 @@ adg_status ensure_basis(int device)
             for (int j = 0; j < N && e < N; ++j) rs += b.KW[e * N + j];
             tab[N].KWsum[e] = rs;
         }
+    }
+    static DevSub sub[LIM_NMAX + 1];
+    std::memset(sub, 0, sizeof(sub));
+    for (int N = 1; N <= LIM_NMAX; ++N) {
+        Basis b;
+        if (!make_basis(N, b) || !make_subcell(b, sub[N])) {
+            set_error("subcell operator construction failed");
+            return ADG_ERR_INVALID_ARG;
+        }
+    }
+    if (upload_subcell(sub) != hipSuccess) {
+        set_error("uploading subcell constants failed");
+        return ADG_ERR_HIP;
     }
     if (upload_basis(tab) != hipSuccess) {
         set_error("uploading basis constants failed");
@@ -412,7 +430,7 @@ adg_status do_corrector(adg_mesh *m, const double *ustar, const T *fside, const 
 // number of CFL block maxima the corrector leaves for the next step
 int nparts(const adg_mesh *m, const Instance &I)
 {
-    return m->pipeline && I.ps > 0 ? int(I.ppoff[I.ps]) : corrector_blocks(I.N, I.nc);
+    return m->pipeline && !m->lim_mode && I.ps > 0 ? int(I.ppoff[I.ps]) : corrector_blocks(I.N, I.nc);
 }
 
 adg_status do_cfl(adg_mesh *m, const double *u, double *dt, double *hist, hipStream_t st)
@@ -499,9 +517,69 @@ void build_chunks(Instance &I)
 // Enqueues one whole step (CFL, predictor, faces, corrector) on the streams.
 // The block maxima of the CFL rate must be current (do_cfl_prime, or the
 // previous step's corrector); the corrector leaves them for the next step.
+// While alive, the launches of the handle report inadmissible states to a
+// scratch flag instead of the handle's status (the limited step's candidate
+// may be unphysical; its final state is checked by the CFL reduction).
+struct StatusSink {
+    adg_mesh *m;
+    int *keep;
+    explicit StatusSink(adg_mesh *mm) : m(mm), keep(mm->status_dev) { m->status_dev = m->lim_status; }
+    ~StatusSink() { m->status_dev = keep; }
+};
+
+// One step with the a-posteriori subcell limiter (one instance, uniform
+// mesh, one stream): CFL, the old subcell bounds and a copy of u, the
+// unlimited candidate (predictor, faces, corrector), detection, the FV step
+// of the limited cells with the flux replacement on their faces, the
+// corrector again for their unlimited neighbours, then the CFL block maxima
+// of the final state (which also flags an unphysical result).
+template <typename T>
+adg_status enqueue_step_limited(adg_mesh *m, double *u, double *hist, void *ws, hipStream_t st)
+{
+    char *w = static_cast<char *>(ws);
+    double *ustar = reinterpret_cast<double *>(w);
+    w += align_up(sizeof(double) * m->info.u_elems);
+    T *traces = reinterpret_cast<T *>(w);
+    w += align_up(sizeof(T) * m->info.trace_elems);
+    T *fside = reinterpret_cast<T *>(w);
+    Instance &I = m->inst[0];
+    adg_status s = do_cfl_fused(m, m->dt_dev, hist, st);
+    if (s != ADG_OK) return s;
+    {
+        PhaseTimer tm(m, ADG_PHASE_LIMITER, st);
+        ADG_HIP(launch_lim_prep(I.N, u, I.nc, I.gamma, m->lim, st), "limiter bounds");
+    }
+    {
+        StatusSink sink(m);
+        s = do_predictor<T>(m, u, m->dt_dev, ustar, traces, st, st, false);
+        if (s != ADG_OK) return s;
+        s = do_conforming<T>(m, traces, fside, st);
+        if (s != ADG_OK) return s;
+        s = do_corrector<T>(m, ustar, fside, m->dt_dev, u, st, false);
+        if (s != ADG_OK) return s;
+    }
+    {
+        PhaseTimer tm(m, ADG_PHASE_LIMITER, st);
+        ADG_HIP(launch_lim_detect(I.N, u, I.nc, I.gamma, m->lim_delta0, m->lim_eps, m->lim_mode == 2 ? 1 : 0, m->lim,
+                                  st),
+                "limiter detection");
+    }
+    {
+        PhaseTimer tm(m, ADG_PHASE_LIMITER, st);
+        ADG_HIP(launch_lim_fv<T>(I.N, u, fside, I.nc, I.geo, m->dt_dev, I.gamma, m->lim, st), "limiter FV step");
+    }
+    {
+        PhaseTimer tm(m, ADG_PHASE_LIMITER, st);
+        ADG_HIP(launch_lim_recorrect<T>(I.N, ustar, fside, u, I.nc, I.geo, m->dt_dev, m->lim, st),
+                "limiter corrector re-run");
+    }
+    return do_cfl_prime(m, u, st);
+}
+
 template <typename T>
 adg_status enqueue_step(adg_mesh *m, double *u, double *hist, void *ws, hipStream_t s_skel, hipStream_t s_encl)
 {
+    if (m->lim_mode) return enqueue_step_limited<T>(m, u, hist, ws, s_skel);
     char *w = static_cast<char *>(ws);
     double *ustar = reinterpret_cast<double *>(w);
     w += align_up(sizeof(double) * m->info.u_elems);
@@ -591,7 +669,7 @@ template <typename T>
 adg_status step_eager(adg_mesh *m, double *u, int32_t n_steps, double *hist, void *ws, hipStream_t s_skel,
                       hipStream_t s_encl)
 {
-    if (m->pipeline) {
+    if (m->pipeline && !m->lim_mode) {
         // the handle's two streams, joined with the caller's before and after
         hipStream_t A = m->gs_a, B = m->pipeline == 2 ? m->gs_a : m->gs_b;
         ADG_HIP(hipEventRecord(m->ev_in, s_skel), "event record");
@@ -650,8 +728,8 @@ adg_status step_graph(adg_mesh *m, double *u, int32_t n_steps, double *hist, voi
     if (!m->gexec || m->gkey_u != u || m->gkey_ws != ws || m->gkey_two != two) {
         drop_graph(m);
         ADG_HIP(hipStreamBeginCapture(A, hipStreamCaptureModeThreadLocal), "begin capture");
-        adg_status st = m->pipeline ? enqueue_step_pipe<T>(m, u, nullptr, ws, A, B)
-                                    : enqueue_step<T>(m, u, nullptr, ws, A, B);
+        adg_status st = m->pipeline && !m->lim_mode ? enqueue_step_pipe<T>(m, u, nullptr, ws, A, B)
+                                                    : enqueue_step<T>(m, u, nullptr, ws, A, B);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(A, &g);
         if (st != ADG_OK) {
@@ -1144,6 +1222,70 @@ adg_status adg_set_pipeline(adg_mesh *mesh, int32_t enable)
     ADG_HIP(hipDeviceSynchronize(), "synchronize");
     mesh->pipeline = enable;
     drop_graph(mesh);
+    return ADG_OK;
+}
+
+adg_status adg_set_limiter(adg_mesh *mesh, int32_t mode, double delta0, double eps)
+{
+    if (!valid_mesh(mesh)) return ADG_ERR_INVALID_ARG;
+    if (mode < 0 || mode > 2 || !(delta0 >= 0.0) || !(eps >= 0.0)) {
+        set_error("adg_set_limiter: mode must be 0, 1 or 2 and delta0, eps non-negative");
+        return ADG_ERR_INVALID_ARG;
+    }
+    // one face per cell side on every axis (periodic uniform mesh): the
+    // neighbour table is then complete
+    if (mode && (mesh->inst.size() != 1 || mesh->inst[0].level != nullptr || mesh->inst[0].N > LIM_NMAX ||
+                 mesh->inst[0].nf[0] != mesh->inst[0].nc || mesh->inst[0].nf[1] != mesh->inst[0].nc ||
+                 mesh->inst[0].nf[2] != mesh->inst[0].nc)) {
+        set_error("adg_set_limiter: the limiter needs a single instance on a uniform mesh with p <= 6");
+        return ADG_ERR_UNSUPPORTED;
+    }
+    ADG_HIP(hipSetDevice(mesh->device), "set device");
+    ADG_HIP(hipDeviceSynchronize(), "synchronize");
+    if (mode && !mesh->lim.uold) {
+        Instance &I = mesh->inst[0];
+        const size_t nc = size_t(I.nc);
+        LimDev L{};
+        bool ok = dev_alloc(mesh, L.uold, size_t(mesh->info.u_elems)) && dev_alloc(mesh, L.mm, nc * 2 * NV) &&
+                  dev_alloc(mesh, L.fb, nc) && dev_alloc(mesh, L.nbr, 6 * nc) && dev_alloc(mesh, L.flag, nc) &&
+                  dev_alloc(mesh, L.list, nc) && dev_alloc(mesh, L.rlist, nc) && dev_alloc(mesh, L.cnt, 2) &&
+                  dev_alloc(mesh, mesh->lim_status, 1);
+        if (!ok) {
+            set_error("adg_set_limiter: device allocation failed");
+            return ADG_ERR_OOM;
+        }
+        ADG_HIP(hipMemset(L.flag, 0, nc * sizeof(int32_t)), "limiter flags");
+        ADG_HIP(hipMemset(L.cnt, 0, 2 * sizeof(int32_t)), "limiter counters");
+        ADG_HIP(hipMemset(mesh->lim_status, 0, sizeof(int)), "limiter status sink");
+        for (int d = 0; d < 3; ++d)
+            ADG_HIP(launch_lim_nbr(I.face_m[d], I.face_p[d], I.nf[d], d, I.nc, L.nbr, nullptr), "neighbour table");
+        ADG_HIP(hipDeviceSynchronize(), "synchronize");
+        mesh->lim = L;
+    }
+    mesh->lim_mode = mode;
+    mesh->lim_delta0 = delta0;
+    mesh->lim_eps = eps;
+    drop_graph(mesh);
+    return ADG_OK;
+}
+
+adg_status adg_limiter_stats(adg_mesh *mesh, int64_t *n_limited, int64_t *n_recorrected, int32_t *flags_dev,
+                             hipStream_t stream)
+{
+    if (!valid_mesh(mesh)) return ADG_ERR_INVALID_ARG;
+    if (!mesh->lim.uold) {
+        set_error("adg_limiter_stats: the limiter was never enabled on this handle");
+        return ADG_ERR_INVALID_ARG;
+    }
+    int32_t cnt[2] = {0, 0};
+    ADG_HIP(hipMemcpyAsync(cnt, mesh->lim.cnt, sizeof(cnt), hipMemcpyDeviceToHost, stream), "counter read");
+    if (flags_dev)
+        ADG_HIP(hipMemcpyAsync(flags_dev, mesh->lim.flag, size_t(mesh->inst[0].nc) * sizeof(int32_t),
+                               hipMemcpyDeviceToDevice, stream),
+                "flag copy");
+    ADG_HIP(hipStreamSynchronize(stream), "synchronize");
+    if (n_limited) *n_limited = cnt[0];
+    if (n_recorrected) *n_recorrected = cnt[1];
     return ADG_OK;
 }
 

@@ -184,6 +184,40 @@ bool make_basis(int N, Basis &b)
     return true;
 }
 
+bool make_subcell(const Basis &b, DevSub &out)
+{
+    const int N = b.N, ns = 2 * N - 1;
+    if (N < 1 || N > LIM_NMAX) return false;
+    std::memset(&out, 0, sizeof(out));
+    double lam[NMAX], row[NMAX];
+    bary_weights(N, b.xi, lam);
+    // subinterval averages by the N-point Gauss rule on each subinterval
+    for (int s = 0; s < ns; ++s)
+        for (int q = 0; q < N; ++q) {
+            lagrange_all(N, b.xi, lam, (s + b.xi[q]) / ns, row);
+            for (int k = 0; k < N; ++k) out.A[s * N + k] += b.w[q] * row[k];
+        }
+    // (A^T A)^{-1} by LU, then times A^T
+    double G[NMAX * NMAX], I[NMAX * NMAX] = {0}, Gi[NMAX * NMAX];
+    for (int i = 0; i < N; ++i) {
+        I[i * N + i] = 1.0;
+        for (int j = 0; j < N; ++j) {
+            double acc = 0.0;
+            for (int s = 0; s < ns; ++s) acc += out.A[s * N + i] * out.A[s * N + j];
+            G[i * N + j] = acc;
+        }
+    }
+    if (!lu_solve(N, G, I, Gi)) return false;
+    for (int k = 0; k < N; ++k)
+        for (int s = 0; s < ns; ++s) {
+            double acc = 0.0;
+            for (int j = 0; j < N; ++j) acc += Gi[k * N + j] * out.A[s * N + j];
+            out.Ap[k * ns + s] = acc;
+            out.Bf[k * ns + s] = out.A[s * N + k] / (ns * b.w[k]);
+        }
+    return true;
+}
+
 void make_transfer(const Basis &b, int r, int s, double *P, double *Rm)
 {
     int N = b.N;

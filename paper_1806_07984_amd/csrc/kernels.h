@@ -107,6 +107,36 @@ hipError_t launch_indicator(int N, const double *u, int64_t nc, double *eta, hip
 hipError_t launch_vtransfer(int N, const double *u_from, int64_t nc_from, double *u_to, int64_t nc_to,
                             const VOp *ops, const VKid *kids, const double *ptab, hipStream_t st);
 
+// A-posteriori subcell limiter (single-level meshes, N <= LIM_NMAX).
+hipError_t upload_subcell(const DevSub *tab);
+// Device buffers of the limiter of one mesh.
+struct LimDev {
+    double *uold;     // [5][nc][N^3] copy of the step's input
+    double *mm;       // [nc][2][5] smallest / largest old subcell datum per variable
+    int32_t *fb;      // [nc] 1: old subcell data replaced by the cell mean
+    int32_t *nbr;     // [6][nc] face neighbour of every cell side
+    int32_t *flag;    // [nc] 1 limited, 2 corrector re-run, 0 else
+    int32_t *list;    // [nc] limited cells (first cnt[0] entries)
+    int32_t *rlist;   // [nc] cells whose corrector runs again (first cnt[1])
+    int32_t *cnt;     // [2]
+};
+constexpr int LIM_GRID = 2048;  // blocks of the persistent limiter kernels
+hipError_t launch_lim_nbr(const int32_t *fm, const int32_t *fp, int64_t nf, int d, int64_t nc, int32_t *nbr,
+                          hipStream_t st);
+// copy of u, old subcell bounds, fall-back flags; clears the counters
+hipError_t launch_lim_prep(int N, const double *u, int64_t nc, double gamma, const LimDev &L, hipStream_t st);
+// troubled-cell flags and list of the candidate u (force: every cell)
+hipError_t launch_lim_detect(int N, const double *u, int64_t nc, double gamma, double delta0, double eps, int force,
+                             const LimDev &L, hipStream_t st);
+// FV update of the listed cells into u; projected face fluxes for their
+// unlimited neighbours into fside, which are listed for the corrector re-run
+template <typename T>
+hipError_t launch_lim_fv(int N, double *u, T *fside, int64_t nc, const Geo &geo, const double *dt, double gamma,
+                         const LimDev &L, hipStream_t st);
+template <typename T>
+hipError_t launch_lim_recorrect(int N, const double *ustar, const T *fside, double *u, int64_t nc, const Geo &geo,
+                                const double *dt, const LimDev &L, hipStream_t st);
+
 int cfl_blocks(int N, int64_t nc);
 // factor = cfl / (2p + 1); writes dt_out[0] (and hist[0] if not null)
 hipError_t launch_cfl(int N, const double *u, int64_t nc, const int8_t *level, const Geo &geo, double gamma,

@@ -1777,6 +1777,509 @@ k_vtransfer(const double *__restrict__ uf, int64_t ncf, double *__restrict__ ut,
 }
 
 // ---------------------------------------------------------------------------
+// A-posteriori finite-volume subcell limiter
+// ---------------------------------------------------------------------------
+// A cell whose ADER-DG update is unphysical or leaves the relaxed bounds of
+// its neighbourhood is advanced instead by first-order finite volumes on
+// (2p+1)^3 subcells of the old solution, then fitted back to a polynomial;
+// its unlimited face neighbours take the projected subcell fluxes on the
+// shared face and run their corrector again (conservation).  The subcell
+// averages are tensor-product contractions staged through LDS; every average
+// is one fixed chain of fused multiply-adds, so a face layer computed for a
+// neighbour's halo equals the same layer of the full computation bit for
+// bit, and two limited cells see identical fluxes on their common face.
+
+__constant__ DevSub c_sub[LIM_NMAX + 1];
+
+template <int N> struct LimCfg {
+    static constexpr int NS = 2 * N - 1, N2 = N * N, N3 = N2 * N, S2 = NS * NS, S3 = S2 * NS;
+    static constexpr int T1 = NS * N2, T2 = S2 * N;  // per-variable contraction temporaries
+    static constexpr int TMP = (T1 + T2 > NV * S2) ? T1 + T2 : NV * S2;
+    // threads of the FV kernel; each keeps PT subcells' new data in registers
+    static constexpr int THREADS = N >= 6 ? 512 : 256;
+    static constexpr int PT = (S3 + THREADS - 1) / THREADS;
+};
+
+// non-finite, rho <= 0 or p <= 0
+__device__ __forceinline__ bool lim_bad(double gm1, const double q[NV])
+{
+    bool fin = true;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) fin = fin && isfinite(q[v]);
+    const double p = gm1 * (q[4] - 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0]);
+    return !fin || !(q[0] > 0.0) || !(p > 0.0);
+}
+
+// Subcell averages of one variable x[N^3] (node a0 + N a1 + N^2 a2).  axis <
+// 0: all subcells, out[s0 + NS s1 + NS^2 s2]; axis = d: only the layer s_d =
+// layer, out[j1 + NS j2] over the other two axes in increasing order.  t1, t2:
+// LimCfg<N>::T1, ::T2 doubles.  Block-wide (contains barriers).
+template <int N>
+__device__ void sub_avg(const double *__restrict__ A, const double *x, double *t1, double *t2, double *out, int axis,
+                        int layer)
+{
+    constexpr int NS = LimCfg<N>::NS, N2 = N * N;
+    const int lo0 = axis == 0 ? layer : 0, n0 = axis == 0 ? 1 : NS;
+    const int lo1 = axis == 1 ? layer : 0, n1 = axis == 1 ? 1 : NS;
+    const int lo2 = axis == 2 ? layer : 0, n2 = axis == 2 ? 1 : NS;
+    for (int i = threadIdx.x; i < n0 * N2; i += blockDim.x) {
+        const int s0 = lo0 + i % n0, a12 = i / n0;
+        double acc = 0.0;
+#pragma unroll
+        for (int a0 = 0; a0 < N; ++a0) acc = fma(A[s0 * N + a0], x[a0 + N * a12], acc);
+        t1[s0 + NS * a12] = acc;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n0 * n1 * N; i += blockDim.x) {
+        const int s0 = lo0 + i % n0, s1 = lo1 + (i / n0) % n1, a2 = i / (n0 * n1);
+        double acc = 0.0;
+#pragma unroll
+        for (int a1 = 0; a1 < N; ++a1) acc = fma(A[s1 * N + a1], t1[s0 + NS * (a1 + N * a2)], acc);
+        t2[s0 + NS * (s1 + NS * a2)] = acc;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n0 * n1 * n2; i += blockDim.x) {
+        const int j0 = i % n0, j1 = (i / n0) % n1, j2 = i / (n0 * n1);
+        const int s0 = lo0 + j0, s1 = lo1 + j1, s2 = lo2 + j2;
+        double acc = 0.0;
+#pragma unroll
+        for (int a2 = 0; a2 < N; ++a2) acc = fma(A[s2 * N + a2], t2[s0 + NS * (s1 + NS * a2)], acc);
+        out[i] = acc;
+    }
+    __syncthreads();
+}
+
+// Least-squares polynomial x[N^3] of one variable's subcell data v[NS^3]
+// (r1: T2 doubles, r2: T1 doubles).  Block-wide.
+template <int N>
+__device__ void sub_fit(const double *__restrict__ Ap, const double *v, double *r1, double *r2, double *x)
+{
+    constexpr int NS = LimCfg<N>::NS, S2 = NS * NS, N2 = N * N;
+    for (int i = threadIdx.x; i < N * S2; i += blockDim.x) {
+        const int k0 = i % N, s12 = i / N;
+        double acc = 0.0;
+        for (int s0 = 0; s0 < NS; ++s0) acc = fma(Ap[k0 * NS + s0], v[s0 + NS * s12], acc);
+        r1[i] = acc;  // k0 + N (s1 + NS s2)
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < N2 * NS; i += blockDim.x) {
+        const int k0 = i % N, k1 = (i / N) % N, s2 = i / N2;
+        double acc = 0.0;
+        for (int s1 = 0; s1 < NS; ++s1) acc = fma(Ap[k1 * NS + s1], r1[k0 + N * (s1 + NS * s2)], acc);
+        r2[i] = acc;  // k0 + N (k1 + N s2)
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < N2 * N; i += blockDim.x) {
+        const int k01 = i % N2, k2 = i / N2;
+        double acc = 0.0;
+        for (int s2 = 0; s2 < NS; ++s2) acc = fma(Ap[k2 * NS + s2], r2[k01 + N2 * s2], acc);
+        x[i] = acc;
+    }
+    __syncthreads();
+}
+
+// Cell mean of one variable (Gauss rule), one fixed sequential order.
+template <int N>
+__device__ double lim_mean(const double *x)
+{
+    const DevBasis &B = c_basis[N];
+    double acc = 0.0;
+    for (int a = 0; a < N * N * N; ++a) acc = fma(B.w[a % N] * B.w[(a / N) % N] * B.w[a / (N * N)], x[a], acc);
+    return acc;
+}
+
+// Rusanov flux along d between subcell states ql (minus side) and qr.
+__device__ __forceinline__ void lim_rusanov(double gamma, int d, const double ql[NV], const double qr[NV],
+                                            double f[NV])
+{
+    const double gm1 = gamma - 1.0;
+    const double pl = gm1 * (ql[4] - 0.5 * (ql[1] * ql[1] + ql[2] * ql[2] + ql[3] * ql[3]) / ql[0]);
+    const double pr = gm1 * (qr[4] - 0.5 * (qr[1] * qr[1] + qr[2] * qr[2] + qr[3] * qr[3]) / qr[0]);
+    const double vl = ql[1 + d] / ql[0], vr = qr[1 + d] / qr[0];
+    const double sl = fabs(vl) + sqrt(gamma * pl / ql[0]), sr = fabs(vr) + sqrt(gamma * pr / qr[0]);
+    const double smax = fmax(sl, sr);
+    double fl[NV], fr[NV];
+    fl[0] = ql[1 + d];
+    fr[0] = qr[1 + d];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        fl[1 + k] = vl * ql[1 + k];
+        fr[1 + k] = vr * qr[1 + k];
+    }
+    fl[1 + d] += pl;
+    fr[1 + d] += pr;
+    fl[4] = vl * (ql[4] + pl);
+    fr[4] = vr * (qr[4] + pr);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) f[v] = 0.5 * (fl[v] + fr[v]) - 0.5 * smax * (qr[v] - ql[v]);
+}
+
+// block-wide min / max of NV values per thread (red: 2 NV (THREADS/64) doubles)
+template <int THREADS>
+__device__ void lim_minmax(double lo[NV], double hi[NV], double *red)
+{
+    constexpr int W = THREADS / 64;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+        for (int off = 32; off > 0; off >>= 1) {
+            lo[v] = fmin(lo[v], __shfl_xor(lo[v], off));
+            hi[v] = fmax(hi[v], __shfl_xor(hi[v], off));
+        }
+    if (lane == 0)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            red[(0 * NV + v) * W + wv] = lo[v];
+            red[(1 * NV + v) * W + wv] = hi[v];
+        }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        lo[v] = red[(0 * NV + v) * W];
+        hi[v] = red[(1 * NV + v) * W];
+        for (int k = 1; k < W; ++k) {
+            lo[v] = fmin(lo[v], red[(0 * NV + v) * W + k]);
+            hi[v] = fmax(hi[v], red[(1 * NV + v) * W + k]);
+        }
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(256)
+k_lim_nbr(const int32_t *__restrict__ fm, const int32_t *__restrict__ fp, int64_t nf, int d, int64_t nc,
+          int32_t *__restrict__ nbr)
+{
+    const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    nbr[(2 * d + 1) * nc + fm[f]] = fp[f];
+    nbr[(2 * d) * nc + fp[f]] = fm[f];
+}
+
+// One block per cell: copy of u, bounds of the old subcell data (the subcell
+// averages, or the cell mean if one of them is unphysical).
+template <int N>
+__global__ void __launch_bounds__(256)
+k_lim_prep(const double *__restrict__ u, int64_t nc, double gamma, double *__restrict__ uold,
+           double *__restrict__ mm, int32_t *__restrict__ fb, int32_t *__restrict__ cnt)
+{
+    using C = LimCfg<N>;
+    constexpr int N3 = C::N3, S3 = C::S3;
+    __shared__ double x[NV * N3], tmp[C::TMP], v[NV * S3], red[2 * NV * 4], mean[NV];
+    const int64_t c = blockIdx.x;
+    if (c == 0 && threadIdx.x == 0) {
+        cnt[0] = 0;
+        cnt[1] = 0;
+    }
+    for (int i = threadIdx.x; i < NV * N3; i += blockDim.x) {
+        const int64_t o = (int64_t(i / N3) * nc + c) * N3 + i % N3;
+        const double val = u[o];
+        x[i] = val;
+        uold[o] = val;
+    }
+    __syncthreads();
+    for (int var = 0; var < NV; ++var) sub_avg<N>(c_sub[N].A, x + var * N3, tmp, tmp + C::T1, v + var * S3, -1, 0);
+    const double gm1 = gamma - 1.0;
+    bool bad = false;
+    double lo[NV], hi[NV];
+#pragma unroll
+    for (int var = 0; var < NV; ++var) {
+        lo[var] = INFINITY;
+        hi[var] = -INFINITY;
+    }
+    for (int s = threadIdx.x; s < S3; s += blockDim.x) {
+        double q[NV];
+#pragma unroll
+        for (int var = 0; var < NV; ++var) {
+            q[var] = v[var * S3 + s];
+            lo[var] = fmin(lo[var], q[var]);
+            hi[var] = fmax(hi[var], q[var]);
+        }
+        bad = bad || lim_bad(gm1, q);
+    }
+    bad = __syncthreads_or(bad);
+    if (bad) {
+        if (threadIdx.x < NV) mean[threadIdx.x] = lim_mean<N>(x + threadIdx.x * N3);
+        __syncthreads();
+        if (threadIdx.x < 2 * NV) mm[c * 2 * NV + threadIdx.x] = mean[threadIdx.x % NV];
+    } else {
+        lim_minmax<256>(lo, hi, red);
+        if (threadIdx.x < NV) {
+            mm[c * 2 * NV + threadIdx.x] = lo[threadIdx.x];
+            mm[c * 2 * NV + NV + threadIdx.x] = hi[threadIdx.x];
+        }
+    }
+    if (threadIdx.x == 0) fb[c] = bad ? 1 : 0;
+}
+
+// One block per cell: troubled-cell test of the candidate u.
+template <int N>
+__global__ void __launch_bounds__(256)
+k_lim_detect(const double *__restrict__ u, int64_t nc, double gamma, double delta0, double eps, int force,
+             const double *__restrict__ mm, const int32_t *__restrict__ nbr, int32_t *__restrict__ flag,
+             int32_t *__restrict__ list, int32_t *__restrict__ cnt)
+{
+    using C = LimCfg<N>;
+    constexpr int N3 = C::N3, S3 = C::S3;
+    __shared__ double x[NV * N3], tmp[C::TMP], v[NV * S3], bl[NV], bh[NV];
+    const int64_t c = blockIdx.x;
+    const double gm1 = gamma - 1.0;
+    for (int i = threadIdx.x; i < NV * N3; i += blockDim.x) x[i] = u[(int64_t(i / N3) * nc + c) * N3 + i % N3];
+    if (threadIdx.x < NV) {
+        const int var = threadIdx.x;
+        double lo = mm[c * 2 * NV + var], hi = mm[c * 2 * NV + NV + var];
+        for (int s = 0; s < 6; ++s) {
+            const int64_t o = nbr[s * nc + c];
+            lo = fmin(lo, mm[o * 2 * NV + var]);
+            hi = fmax(hi, mm[o * 2 * NV + NV + var]);
+        }
+        double delta = eps * (hi - lo);
+        if (delta < delta0) delta = delta0;
+        bl[var] = lo - delta;
+        bh[var] = hi + delta;
+    }
+    __syncthreads();
+    bool bad = false;
+    for (int a = threadIdx.x; a < N3; a += blockDim.x) {
+        double q[NV];
+#pragma unroll
+        for (int var = 0; var < NV; ++var) q[var] = x[var * N3 + a];
+        bad = bad || lim_bad(gm1, q);
+    }
+    for (int var = 0; var < NV; ++var) sub_avg<N>(c_sub[N].A, x + var * N3, tmp, tmp + C::T1, v + var * S3, -1, 0);
+    for (int s = threadIdx.x; s < S3; s += blockDim.x) {
+        double q[NV];
+        bool out = false;
+#pragma unroll
+        for (int var = 0; var < NV; ++var) {
+            q[var] = v[var * S3 + s];
+            out = out || !(q[var] >= bl[var] && q[var] <= bh[var]);
+        }
+        bad = bad || out || lim_bad(gm1, q);
+    }
+    const bool troubled = __syncthreads_or(bad) || force;
+    if (threadIdx.x == 0) {
+        flag[c] = troubled ? 1 : 0;
+        if (troubled) list[atomicAdd(cnt, 1)] = int32_t(c);
+    }
+}
+
+// Persistent over the limited cells: FV step on the subcells, least-squares
+// fit (or the constant mean), projected subcell fluxes for the unlimited face
+// neighbours.
+template <typename T, int N>
+__global__ void __launch_bounds__(LimCfg<N>::THREADS)
+k_lim_fv(double *__restrict__ u, T *__restrict__ fside, int64_t nc, Geo geo, const double *__restrict__ dt_dev,
+         double gamma, const double *__restrict__ uold, const int32_t *__restrict__ fb,
+         const int32_t *__restrict__ nbr, int32_t *__restrict__ flag, const int32_t *__restrict__ list,
+         int32_t *__restrict__ rlist, int32_t *__restrict__ cnt)
+{
+    using C = LimCfg<N>;
+    constexpr int NS = C::NS, N2 = C::N2, N3 = C::N3, S2 = C::S2, S3 = C::S3, PT = C::PT, TH = C::THREADS;
+    __shared__ double v[NV * S3], halo[6 * NV * S2], x[NV * N3], tmp[C::TMP], mean[NV], red[NV * (TH / 64)];
+    __shared__ double err[NV * N2], dlt[6 * NV];
+    const DevSub &S = c_sub[N];
+    const double dt = dt_dev[0], gm1 = gamma - 1.0;
+    const int n_lim = cnt[0];
+    double *t1 = tmp, *t2 = tmp + C::T1;
+    for (int it = blockIdx.x; it < n_lim; it += gridDim.x) {
+        const int64_t c = list[it];
+        // old subcell data of the cell and the face layers of its neighbours
+        for (int k = -1; k < 6; ++k) {
+            const int64_t o = k < 0 ? c : nbr[k * nc + c];
+            for (int i = threadIdx.x; i < NV * N3; i += blockDim.x)
+                x[i] = uold[(int64_t(i / N3) * nc + o) * N3 + i % N3];
+            __syncthreads();
+            const int cnt_out = k < 0 ? S3 : S2;
+            double *dst = k < 0 ? v : halo + k * NV * S2;
+            if (fb[o]) {
+                if (threadIdx.x < NV) mean[threadIdx.x] = lim_mean<N>(x + threadIdx.x * N3);
+                __syncthreads();
+                for (int i = threadIdx.x; i < NV * cnt_out; i += blockDim.x) dst[i] = mean[i / cnt_out];
+            } else {
+                const int axis = k < 0 ? -1 : k / 2, layer = (k & 1) ? 0 : NS - 1;
+                for (int var = 0; var < NV; ++var) sub_avg<N>(S.A, x + var * N3, t1, t2, dst + var * cnt_out, axis, layer);
+            }
+            __syncthreads();
+        }
+        // subcell fluxes on faces shared with unlimited cells, projected onto
+        // the face nodes of the neighbour's side.  The FP32 form stores face
+        // fluxes in FP32: dlt[k] = sum_b W_b (stored - exact) is added to this
+        // cell's subcell fluxes on face k, so that both sides exchange the
+        // same total (conservation to FP64 rounding).
+        if (threadIdx.x < 6 * NV) dlt[threadIdx.x] = 0.0;
+        __syncthreads();
+        for (int k = 0; k < 6; ++k) {
+            const int64_t o = nbr[k * nc + c];
+            if (flag[o] == 1) continue;  // 0 or 2 for every reader: uniform
+            const int d = k / 2, plus = k & 1;
+            const int t1a = d == 0 ? 1 : 0, t2a = d == 2 ? 1 : 2;
+            for (int j = threadIdx.x; j < S2; j += blockDim.x) {
+                int sc[3];
+                sc[t1a] = j % NS;
+                sc[t2a] = j / NS;
+                sc[d] = plus ? NS - 1 : 0;
+                const int is = sc[0] + NS * sc[1] + S2 * sc[2];
+                double qc[NV], qo[NV], f[NV];
+#pragma unroll
+                for (int var = 0; var < NV; ++var) {
+                    qc[var] = v[var * S3 + is];
+                    qo[var] = halo[(k * NV + var) * S2 + j];
+                }
+                if (plus) lim_rusanov(gamma, d, qc, qo, f);
+                else lim_rusanov(gamma, d, qo, qc, f);
+#pragma unroll
+                for (int var = 0; var < NV; ++var) tmp[var * S2 + j] = f[var];
+            }
+            __syncthreads();
+            const int sopp = 2 * d + (1 - plus);
+            for (int i = threadIdx.x; i < NV * N2; i += blockDim.x) {
+                const int var = i / N2, b = i % N2, b1 = b % N, b2 = b / N;
+                double acc = 0.0;
+                for (int j2 = 0; j2 < NS; ++j2) {
+                    double r = 0.0;
+                    for (int j1 = 0; j1 < NS; ++j1) r = fma(S.Bf[b1 * NS + j1], tmp[var * S2 + j1 + NS * j2], r);
+                    acc = fma(S.Bf[b2 * NS + j2], r, acc);
+                }
+                const T stored = T(acc);
+                fside[(int64_t(sopp * NV + var) * nc + o) * N2 + b] = stored;
+                err[i] = c_basis[N].w[b1] * c_basis[N].w[b2] * (double(stored) - acc);
+            }
+            __syncthreads();
+            if (!std::is_same<T, double>::value && threadIdx.x < NV) {
+                double sum = 0.0;
+                for (int b = 0; b < N2; ++b) sum += err[threadIdx.x * N2 + b];
+                dlt[k * NV + threadIdx.x] = sum;
+            }
+            if (threadIdx.x == 0 && atomicCAS(&flag[o], 0, 2) == 0) rlist[atomicAdd(&cnt[1], 1)] = int32_t(o);
+            __syncthreads();
+        }
+        // first-order update of every subcell (kept in registers)
+        double vn[PT][NV];
+#pragma unroll
+        for (int k = 0; k < PT; ++k) {
+            const int s = threadIdx.x + k * TH;
+            if (s >= S3) break;
+            const int ss[3] = {s % NS, (s / NS) % NS, s / S2};
+            double q[NV], acc[NV] = {0, 0, 0, 0, 0};
+#pragma unroll
+            for (int var = 0; var < NV; ++var) q[var] = v[var * S3 + s];
+#pragma unroll 1
+            for (int d = 0; d < 3; ++d) {
+                const double inv_h = geo.inv_dx[0][d] * NS;
+                const int t1a = d == 0 ? 1 : 0, t2a = d == 2 ? 1 : 2;
+#pragma unroll 1
+                for (int side = 0; side < 2; ++side) {
+                    double qo[NV], f[NV];
+                    const int sn = ss[d] + (side ? 1 : -1);
+                    if (sn >= 0 && sn < NS) {
+                        const int idx = s + (side ? 1 : -1) * (d == 0 ? 1 : (d == 1 ? NS : S2));
+#pragma unroll
+                        for (int var = 0; var < NV; ++var) qo[var] = v[var * S3 + idx];
+                    } else {
+                        const int j = ss[t1a] + NS * ss[t2a];
+#pragma unroll
+                        for (int var = 0; var < NV; ++var) qo[var] = halo[((2 * d + side) * NV + var) * S2 + j];
+                    }
+                    if (side) lim_rusanov(gamma, d, q, qo, f);
+                    else lim_rusanov(gamma, d, qo, q, f);
+                    if (sn < 0 || sn >= NS)
+#pragma unroll
+                        for (int var = 0; var < NV; ++var) f[var] += dlt[(2 * d + side) * NV + var];
+#pragma unroll
+                    for (int var = 0; var < NV; ++var) acc[var] += (side ? 1.0 : -1.0) * f[var] * inv_h;
+                }
+            }
+#pragma unroll
+            for (int var = 0; var < NV; ++var) vn[k][var] = q[var] - dt * acc[var];
+        }
+        // new subcell data (every read of the old data is done), their means
+        __syncthreads();
+        double part[NV] = {0, 0, 0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < PT; ++k) {
+            const int s = threadIdx.x + k * TH;
+            if (s >= S3) break;
+#pragma unroll
+            for (int var = 0; var < NV; ++var) {
+                v[var * S3 + s] = vn[k][var];
+                part[var] += vn[k][var];
+            }
+        }
+        {
+            const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+            for (int var = 0; var < NV; ++var) {
+                for (int off = 32; off > 0; off >>= 1) part[var] += __shfl_xor(part[var], off);
+                if (lane == 0) red[var * (TH / 64) + wv] = part[var];
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < NV) {
+            double sum = 0.0;
+            for (int w = 0; w < TH / 64; ++w) sum += red[threadIdx.x * (TH / 64) + w];
+            mean[threadIdx.x] = sum / S3;
+        }
+        // least-squares fit into x, its subcell averages back into v
+        for (int var = 0; var < NV; ++var) sub_fit<N>(S.Ap, v + var * S3, t2, t1, x + var * N3);
+        bool bad = false;
+        for (int a = threadIdx.x; a < N3; a += blockDim.x) {
+            double q[NV];
+#pragma unroll
+            for (int var = 0; var < NV; ++var) q[var] = x[var * N3 + a];
+            bad = bad || lim_bad(gm1, q);
+        }
+        for (int var = 0; var < NV; ++var) sub_avg<N>(S.A, x + var * N3, t1, t2, v + var * S3, -1, 0);
+        for (int s = threadIdx.x; s < S3; s += blockDim.x) {
+            double q[NV];
+#pragma unroll
+            for (int var = 0; var < NV; ++var) q[var] = v[var * S3 + s];
+            bad = bad || lim_bad(gm1, q);
+        }
+        bad = __syncthreads_or(bad);
+        for (int i = threadIdx.x; i < NV * N3; i += blockDim.x)
+            u[(int64_t(i / N3) * nc + c) * N3 + i % N3] = bad ? mean[i / N3] : x[i];
+        __syncthreads();
+    }
+}
+
+// Persistent over the listed cells: the corrector again with the face fluxes
+// the limited neighbours left in fside.
+template <typename T, int N>
+__global__ void __launch_bounds__(round64(N * N * N))
+k_lim_recorrect(const double *__restrict__ ustar, const T *__restrict__ fside, const double *__restrict__ dt_dev,
+                double *__restrict__ u, int64_t nc, Geo geo, const int32_t *__restrict__ rlist,
+                const int32_t *__restrict__ cnt)
+{
+    constexpr int N2 = N * N, N3 = N2 * N;
+    const DevBasis &B = c_basis[N];
+    const int a = threadIdx.x;
+    if (a >= N3) return;
+    const int a0 = a % N, a1 = (a / N) % N, a2 = a / N2;
+    const int bx = a1 + N * a2, by = a0 + N * a2, bz = a0 + N * a1;
+    const double dt = dt_dev[0];
+    const double sx = dt * geo.inv_dx[0][0] * B.winv[a0];
+    const double sy = dt * geo.inv_dx[0][1] * B.winv[a1];
+    const double sz = dt * geo.inv_dx[0][2] * B.winv[a2];
+    const int n = cnt[1];
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const int64_t c = rlist[it];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double fxm = fside[(int64_t(0 * NV + v) * nc + c) * N2 + bx];
+            const double fxp = fside[(int64_t(1 * NV + v) * nc + c) * N2 + bx];
+            const double fym = fside[(int64_t(2 * NV + v) * nc + c) * N2 + by];
+            const double fyp = fside[(int64_t(3 * NV + v) * nc + c) * N2 + by];
+            const double fzm = fside[(int64_t(4 * NV + v) * nc + c) * N2 + bz];
+            const double fzp = fside[(int64_t(5 * NV + v) * nc + c) * N2 + bz];
+            const double s = sx * (B.R[a0] * fxp - B.L[a0] * fxm) + sy * (B.R[a1] * fyp - B.L[a1] * fym) +
+                             sz * (B.R[a2] * fzp - B.L[a2] * fzm);
+            const int64_t o = (int64_t(v) * nc + c) * N3 + a;
+            u[o] = ustar[o] - s;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 
@@ -2167,6 +2670,64 @@ hipError_t launch_vtransfer(int N, const double *u_from, int64_t nc_from, double
     return hipGetLastError();
 }
 
+hipError_t upload_subcell(const DevSub *tab)
+{
+    return hipMemcpyToSymbol(HIP_SYMBOL(c_sub), tab, sizeof(DevSub) * (LIM_NMAX + 1));
+}
+
+hipError_t launch_lim_nbr(const int32_t *fm, const int32_t *fp, int64_t nf, int d, int64_t nc, int32_t *nbr,
+                          hipStream_t st)
+{
+    if (nf <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lim_nbr, dim3(unsigned((nf + 255) / 256)), dim3(256), 0, st, fm, fp, nf, d, nc, nbr);
+    return hipGetLastError();
+}
+
+hipError_t launch_lim_prep(int N, const double *u, int64_t nc, double gamma, const LimDev &L, hipStream_t st)
+{
+    if (nc <= 0) return hipSuccess;
+    ADG_DISPATCH_N(N, {
+        hipLaunchKernelGGL((k_lim_prep<NN>), dim3(unsigned(nc)), dim3(256), 0, st, u, nc, gamma, L.uold, L.mm, L.fb,
+                           L.cnt);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_lim_detect(int N, const double *u, int64_t nc, double gamma, double delta0, double eps, int force,
+                             const LimDev &L, hipStream_t st)
+{
+    if (nc <= 0) return hipSuccess;
+    ADG_DISPATCH_N(N, {
+        hipLaunchKernelGGL((k_lim_detect<NN>), dim3(unsigned(nc)), dim3(256), 0, st, u, nc, gamma, delta0, eps, force,
+                           L.mm, L.nbr, L.flag, L.list, L.cnt);
+    });
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_lim_fv(int N, double *u, T *fside, int64_t nc, const Geo &geo, const double *dt, double gamma,
+                         const LimDev &L, hipStream_t st)
+{
+    if (nc <= 0) return hipSuccess;
+    ADG_DISPATCH_N(N, {
+        hipLaunchKernelGGL((k_lim_fv<T, NN>), dim3(LIM_GRID), dim3(LimCfg<NN>::THREADS), 0, st, u, fside, nc, geo, dt,
+                           gamma, L.uold, L.fb, L.nbr, L.flag, L.list, L.rlist, L.cnt);
+    });
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_lim_recorrect(int N, const double *ustar, const T *fside, double *u, int64_t nc, const Geo &geo,
+                                const double *dt, const LimDev &L, hipStream_t st)
+{
+    if (nc <= 0) return hipSuccess;
+    ADG_DISPATCH_N(N, {
+        hipLaunchKernelGGL((k_lim_recorrect<T, NN>), dim3(LIM_GRID), dim3(round64(NN * NN * NN)), 0, st, ustar, fside,
+                           dt, u, nc, geo, L.rlist, L.cnt);
+    });
+    return hipGetLastError();
+}
+
 #define ADG_INSTANTIATE(T)                                                                              \
     template hipError_t launch_predictor<T>(int, const double *, double *, T *, const int32_t *, int64_t,  \
                                             int64_t, const int8_t *, const Geo &, const double *, double, \
@@ -2184,6 +2745,14 @@ hipError_t launch_vtransfer(int N, const double *u_from, int64_t nc_from, double
 
 ADG_INSTANTIATE(double)
 ADG_INSTANTIATE(float)
+template hipError_t launch_lim_fv<double>(int, double *, double *, int64_t, const Geo &, const double *, double,
+                                          const LimDev &, hipStream_t);
+template hipError_t launch_lim_fv<float>(int, double *, float *, int64_t, const Geo &, const double *, double,
+                                         const LimDev &, hipStream_t);
+template hipError_t launch_lim_recorrect<double>(int, const double *, const double *, double *, int64_t,
+                                                 const Geo &, const double *, const LimDev &, hipStream_t);
+template hipError_t launch_lim_recorrect<float>(int, const double *, const float *, double *, int64_t, const Geo &,
+                                                const double *, const LimDev &, hipStream_t);
 template hipError_t launch_predictor_batch<double>(const PredItem *, int64_t, const PredInst *, const double *,
                                                   double *, double *, const double *, int, int, hipStream_t);
 template hipError_t launch_predictor_batch<float>(const PredItem *, int64_t, const PredInst *, const double *,
