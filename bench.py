@@ -244,6 +244,51 @@ def run_batch(A, steps=10, seed=0):
     return out
 
 
+def run_limiter(A, steps=20, warmup=2):
+    """A-posteriori subcell limiter: uniform periodic 81^3 mesh, p = 3, the
+    discontinuous spherical blast wave (rho, p = 1, 1 inside radius 0.25,
+    0.125, 0.1 outside, at rest), delta0 = 1e-4, eps = 1e-3; both precisions.
+    Timed: `steps` limited steps (plain launches, one stream); then the same
+    again with every phase timed for the breakdown."""
+    import torch
+    from paper_1806_07984_amd import inputs
+    n = (N_BASE,) * 3
+    probe = A.Mesh(A.instance(ORDER, n), "fp64")
+    xyz = probe.node_coords().cpu().numpy().reshape(3, -1)
+    probe.close()
+    u0 = torch.from_numpy(inputs.blast(xyz).reshape(-1)).cuda()
+    del xyz
+    out = {"workload": "blast_p3_81cubed_limited", "unit": "DoF-updates/s", "steps": steps}
+    for precision in ("fp32", "fp64"):
+        mesh = A.Mesh(A.instance(ORDER, n), precision)
+        mesh.set_options(use_graph=False, batched=0)
+        mesh.set_limiter(1, 1e-4, 1e-3)
+        u = u0.clone()
+        ws = mesh.empty_workspace()
+        s = torch.cuda.current_stream()
+        mesh.step(u, warmup, ws, stream_skeleton=s, stream_enclave=s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mesh.step(u, steps, ws, stream_skeleton=s, stream_enclave=s)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        nl, nr = mesh.limiter_stats()
+        mesh.profile(True)
+        mesh.step(u, steps, ws, stream_skeleton=s, stream_enclave=s)
+        phases = mesh.profile_read()
+        mesh.profile(False)
+        mesh.status()
+        out[precision] = {"value": mesh.info["n_dofs"] * steps / el, "ms_per_step": el * 1e3 / steps,
+                          "limited_cells_last_step": nl, "rerun_cells_last_step": nr,
+                          "cells": mesh.info["n_cells"],
+                          "phases_ms_per_step": {k: v[0] / steps for k, v in phases.items()}}
+        mesh.close()
+        del u, ws
+        torch.cuda.empty_cache()
+    out["value"] = out["fp32"]["value"]
+    return out
+
+
 def run_adjoint(A, n=27, steps=20, k=5, n_pts=512):
     """Differentiation workload: 27^3 cells, p = 3, FP64, 20 steps; loss =
     sampled density misfit at 512 seeded points; gradient with respect to
@@ -290,7 +335,7 @@ def main():
     ap.add_argument("--only", choices=["fp64", "fp32"], default=None,
                     help="run one path only (for profiling runs)")
     ap.add_argument("--no-extra", action="store_true", help="skip the AMR and batch workloads")
-    ap.add_argument("--extra-only", choices=["amr", "batch", "adjoint"], default=None,
+    ap.add_argument("--extra-only", choices=["amr", "batch", "adjoint", "limiter"], default=None,
                     help="run only one of the other workloads and print its JSON (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB buffer 3 times (calibrates HBM byte counters) and exit")
@@ -314,7 +359,8 @@ def main():
 
     A.load()
     if args.extra_only:
-        res = {"amr": run_amr, "batch": run_batch, "adjoint": run_adjoint}[args.extra_only](A)
+        res = {"amr": run_amr, "batch": run_batch, "adjoint": run_adjoint,
+               "limiter": run_limiter}[args.extra_only](A)
         print(json.dumps({"workload": args.extra_only, **res}))
         return
     # initial state: node coordinates from the library, analytic state + seeded noise on the host
@@ -362,7 +408,8 @@ def main():
     if not args.no_extra:
         out["other_workloads"] = {"amr_blast_p4_27cubed_2levels": run_amr(A),
                                   "batch64_p2to6_seed0": run_batch(A),
-                                  "adjoint_p3_27cubed_20steps": run_adjoint(A)}
+                                  "adjoint_p3_27cubed_20steps": run_adjoint(A),
+                                  "limiter_blast_p3_81cubed": run_limiter(A)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

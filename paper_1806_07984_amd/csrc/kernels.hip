@@ -1914,37 +1914,6 @@ __device__ __forceinline__ void lim_rusanov(double gamma, int d, const double ql
     for (int v = 0; v < NV; ++v) f[v] = 0.5 * (fl[v] + fr[v]) - 0.5 * smax * (qr[v] - ql[v]);
 }
 
-// block-wide min / max of NV values per thread (red: 2 NV (THREADS/64) doubles)
-template <int THREADS>
-__device__ void lim_minmax(double lo[NV], double hi[NV], double *red)
-{
-    constexpr int W = THREADS / 64;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int v = 0; v < NV; ++v)
-        for (int off = 32; off > 0; off >>= 1) {
-            lo[v] = fmin(lo[v], __shfl_xor(lo[v], off));
-            hi[v] = fmax(hi[v], __shfl_xor(hi[v], off));
-        }
-    if (lane == 0)
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            red[(0 * NV + v) * W + wv] = lo[v];
-            red[(1 * NV + v) * W + wv] = hi[v];
-        }
-    __syncthreads();
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        lo[v] = red[(0 * NV + v) * W];
-        hi[v] = red[(1 * NV + v) * W];
-        for (int k = 1; k < W; ++k) {
-            lo[v] = fmin(lo[v], red[(0 * NV + v) * W + k]);
-            hi[v] = fmax(hi[v], red[(1 * NV + v) * W + k]);
-        }
-    }
-    __syncthreads();
-}
-
 __global__ void __launch_bounds__(256)
 k_lim_nbr(const int32_t *__restrict__ fm, const int32_t *__restrict__ fp, int64_t nf, int d, int64_t nc,
           int32_t *__restrict__ nbr)
@@ -1955,109 +1924,178 @@ k_lim_nbr(const int32_t *__restrict__ fm, const int32_t *__restrict__ fp, int64_
     nbr[(2 * d) * nc + fp[f]] = fm[f];
 }
 
-// One block per cell: copy of u, bounds of the old subcell data (the subcell
-// averages, or the cell mean if one of them is unphysical).
+// One wavefront per cell: loads the cell's u (NV N^3 doubles, coalesced)
+// into LDS x, copying it to ucopy (if not BND), and scans its subcell
+// averages: per variable min / max, whether an average is unphysical,
+// whether one leaves the relaxed bounds and whether a node is unphysical (if
+// BND; ext[k NV + var] and ext[7 NV + k NV + var] hold the old extremes of
+// the cell (k = 0) and its face neighbours, written by the caller before the
+// first barrier).  Stage 1 contracts x-pencils into t1 (NV NS N^2 doubles);
+// stages 2 and 3 are fused per
+// (s0, s1) column: the NV x N stage-2 values of a column stay in registers
+// and the column's subcells are produced one at a time.  Each average is the
+// same chain of fused multiply-adds as in sub_avg.  Results are valid in
+// every lane.
+template <int N, bool BND>
+__device__ void lim_cell_scan(const double *__restrict__ u, int64_t nc, int64_t c, double *__restrict__ ucopy,
+                              double gm1, double *x, double *t1, const double *ext, double delta0, double eps,
+                              double lo[NV], double hi[NV], bool &bad_avg, bool &bad_node, bool &outside)
+{
+    using C = LimCfg<N>;
+    constexpr int NS = C::NS, N2 = C::N2, N3 = C::N3, S2 = C::S2;
+    const double *__restrict__ A = c_sub[N].A;
+    const int lane = threadIdx.x;
+    for (int i = lane; i < NV * N3; i += 64) {
+        const int64_t o = (int64_t(i / N3) * nc + c) * N3 + i % N3;
+        const double val = u[o];
+        x[i] = val;
+        if (!BND) ucopy[o] = val;
+    }
+    __syncthreads();
+    for (int t = lane; t < NV * N2; t += 64) {
+        const int var = t / N2, a12 = t % N2;
+        double xv[N];
+#pragma unroll
+        for (int a0 = 0; a0 < N; ++a0) xv[a0] = x[var * N3 + N * a12 + a0];
+#pragma unroll
+        for (int s0 = 0; s0 < NS; ++s0) {
+            double acc = 0.0;
+#pragma unroll
+            for (int a0 = 0; a0 < N; ++a0) acc = fma(A[s0 * N + a0], xv[a0], acc);
+            t1[var * C::T1 + s0 + NS * a12] = acc;
+        }
+    }
+    __syncthreads();
+    bool bn = false;
+    if (BND)
+        for (int a = lane; a < N3; a += 64) {
+            double q[NV];
+#pragma unroll
+            for (int var = 0; var < NV; ++var) q[var] = x[var * N3 + a];
+            bn = bn || lim_bad(gm1, q);
+        }
+    double bl[NV], bh[NV];
+#pragma unroll
+    for (int var = 0; var < NV; ++var) {
+        lo[var] = INFINITY;
+        hi[var] = -INFINITY;
+        bl[var] = 0.0;
+        bh[var] = 0.0;
+        if (BND) {
+            double l = ext[var], h = ext[7 * NV + var];
+            for (int k = 1; k < 7; ++k) {
+                l = fmin(l, ext[k * NV + var]);
+                h = fmax(h, ext[7 * NV + k * NV + var]);
+            }
+            double delta = eps * (h - l);
+            if (delta < delta0) delta = delta0;
+            bl[var] = l - delta;
+            bh[var] = h + delta;
+        }
+    }
+    bool ba = false, bo = false;
+    for (int t = lane; t < S2; t += 64) {
+        const int s0 = t % NS, s1 = t / NS;
+        double t2[NV][N];
+#pragma unroll
+        for (int var = 0; var < NV; ++var)
+#pragma unroll
+            for (int a2 = 0; a2 < N; ++a2) {
+                double acc = 0.0;
+#pragma unroll
+                for (int a1 = 0; a1 < N; ++a1)
+                    acc = fma(A[s1 * N + a1], t1[var * C::T1 + s0 + NS * (a1 + N * a2)], acc);
+                t2[var][a2] = acc;
+            }
+#pragma unroll 1
+        for (int s2 = 0; s2 < NS; ++s2) {
+            double q[NV];
+#pragma unroll
+            for (int var = 0; var < NV; ++var) {
+                double acc = 0.0;
+#pragma unroll
+                for (int a2 = 0; a2 < N; ++a2) acc = fma(A[s2 * N + a2], t2[var][a2], acc);
+                q[var] = acc;
+                lo[var] = fmin(lo[var], acc);
+                hi[var] = fmax(hi[var], acc);
+                if (BND) bo = bo || !(acc >= bl[var] && acc <= bh[var]);
+            }
+            ba = ba || lim_bad(gm1, q);
+        }
+    }
+#pragma unroll
+    for (int var = 0; var < NV; ++var)
+        for (int off = 32; off > 0; off >>= 1) {
+            lo[var] = fmin(lo[var], __shfl_xor(lo[var], off));
+            hi[var] = fmax(hi[var], __shfl_xor(hi[var], off));
+        }
+    bad_avg = __any(ba);
+    bad_node = __any(bn);
+    outside = __any(bo);
+}
+
+// One wavefront per cell: copy of u, bounds of the old subcell data (the
+// subcell averages, or the cell mean if one of them is unphysical).
 template <int N>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64)
 k_lim_prep(const double *__restrict__ u, int64_t nc, double gamma, double *__restrict__ uold,
            double *__restrict__ mm, int32_t *__restrict__ fb, int32_t *__restrict__ cnt)
 {
     using C = LimCfg<N>;
-    constexpr int N3 = C::N3, S3 = C::S3;
-    __shared__ double x[NV * N3], tmp[C::TMP], v[NV * S3], red[2 * NV * 4], mean[NV];
+    __shared__ double x[NV * C::N3], t1[NV * C::T1];
     const int64_t c = blockIdx.x;
     if (c == 0 && threadIdx.x == 0) {
         cnt[0] = 0;
         cnt[1] = 0;
     }
-    for (int i = threadIdx.x; i < NV * N3; i += blockDim.x) {
-        const int64_t o = (int64_t(i / N3) * nc + c) * N3 + i % N3;
-        const double val = u[o];
-        x[i] = val;
-        uold[o] = val;
-    }
-    __syncthreads();
-    for (int var = 0; var < NV; ++var) sub_avg<N>(c_sub[N].A, x + var * N3, tmp, tmp + C::T1, v + var * S3, -1, 0);
-    const double gm1 = gamma - 1.0;
-    bool bad = false;
     double lo[NV], hi[NV];
-#pragma unroll
-    for (int var = 0; var < NV; ++var) {
-        lo[var] = INFINITY;
-        hi[var] = -INFINITY;
-    }
-    for (int s = threadIdx.x; s < S3; s += blockDim.x) {
-        double q[NV];
-#pragma unroll
-        for (int var = 0; var < NV; ++var) {
-            q[var] = v[var * S3 + s];
-            lo[var] = fmin(lo[var], q[var]);
-            hi[var] = fmax(hi[var], q[var]);
-        }
-        bad = bad || lim_bad(gm1, q);
-    }
-    bad = __syncthreads_or(bad);
+    bool bad, bn, bo;
+    lim_cell_scan<N, false>(u, nc, c, uold, gamma - 1.0, x, t1, nullptr, 0.0, 0.0, lo, hi, bad, bn, bo);
+    const int lane = threadIdx.x;
     if (bad) {
-        if (threadIdx.x < NV) mean[threadIdx.x] = lim_mean<N>(x + threadIdx.x * N3);
-        __syncthreads();
-        if (threadIdx.x < 2 * NV) mm[c * 2 * NV + threadIdx.x] = mean[threadIdx.x % NV];
-    } else {
-        lim_minmax<256>(lo, hi, red);
-        if (threadIdx.x < NV) {
-            mm[c * 2 * NV + threadIdx.x] = lo[threadIdx.x];
-            mm[c * 2 * NV + NV + threadIdx.x] = hi[threadIdx.x];
+        const double m = lane < NV ? lim_mean<N>(x + lane * C::N3) : 0.0;
+        if (lane < NV) {
+            mm[c * 2 * NV + lane] = m;
+            mm[c * 2 * NV + NV + lane] = m;
         }
+    } else if (lane < NV) {
+        double l = lo[0], h = hi[0];
+#pragma unroll
+        for (int var = 1; var < NV; ++var)
+            if (lane == var) {
+                l = lo[var];
+                h = hi[var];
+            }
+        mm[c * 2 * NV + lane] = l;
+        mm[c * 2 * NV + NV + lane] = h;
     }
-    if (threadIdx.x == 0) fb[c] = bad ? 1 : 0;
+    if (lane == 0) fb[c] = bad ? 1 : 0;
 }
 
-// One block per cell: troubled-cell test of the candidate u.
+// One wavefront per cell: troubled-cell test of the candidate u.  Lanes
+// 0..34 fetch the old extremes of (cell or face neighbour k, variable) while
+// the cell's data loads; every lane combines them after the first barrier.
 template <int N>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64)
 k_lim_detect(const double *__restrict__ u, int64_t nc, double gamma, double delta0, double eps, int force,
              const double *__restrict__ mm, const int32_t *__restrict__ nbr, int32_t *__restrict__ flag,
              int32_t *__restrict__ list, int32_t *__restrict__ cnt)
 {
     using C = LimCfg<N>;
-    constexpr int N3 = C::N3, S3 = C::S3;
-    __shared__ double x[NV * N3], tmp[C::TMP], v[NV * S3], bl[NV], bh[NV];
+    __shared__ double x[NV * C::N3], t1[NV * C::T1], ext[2 * 7 * NV];
     const int64_t c = blockIdx.x;
-    const double gm1 = gamma - 1.0;
-    for (int i = threadIdx.x; i < NV * N3; i += blockDim.x) x[i] = u[(int64_t(i / N3) * nc + c) * N3 + i % N3];
-    if (threadIdx.x < NV) {
-        const int var = threadIdx.x;
-        double lo = mm[c * 2 * NV + var], hi = mm[c * 2 * NV + NV + var];
-        for (int s = 0; s < 6; ++s) {
-            const int64_t o = nbr[s * nc + c];
-            lo = fmin(lo, mm[o * 2 * NV + var]);
-            hi = fmax(hi, mm[o * 2 * NV + NV + var]);
-        }
-        double delta = eps * (hi - lo);
-        if (delta < delta0) delta = delta0;
-        bl[var] = lo - delta;
-        bh[var] = hi + delta;
+    const int lane = threadIdx.x;
+    if (lane < 7 * NV) {
+        const int k = lane / NV, var = lane % NV;
+        const int64_t o = k == 0 ? c : nbr[(k - 1) * nc + c];
+        ext[lane] = mm[o * 2 * NV + var];
+        ext[7 * NV + lane] = mm[o * 2 * NV + NV + var];
     }
-    __syncthreads();
-    bool bad = false;
-    for (int a = threadIdx.x; a < N3; a += blockDim.x) {
-        double q[NV];
-#pragma unroll
-        for (int var = 0; var < NV; ++var) q[var] = x[var * N3 + a];
-        bad = bad || lim_bad(gm1, q);
-    }
-    for (int var = 0; var < NV; ++var) sub_avg<N>(c_sub[N].A, x + var * N3, tmp, tmp + C::T1, v + var * S3, -1, 0);
-    for (int s = threadIdx.x; s < S3; s += blockDim.x) {
-        double q[NV];
-        bool out = false;
-#pragma unroll
-        for (int var = 0; var < NV; ++var) {
-            q[var] = v[var * S3 + s];
-            out = out || !(q[var] >= bl[var] && q[var] <= bh[var]);
-        }
-        bad = bad || out || lim_bad(gm1, q);
-    }
-    const bool troubled = __syncthreads_or(bad) || force;
-    if (threadIdx.x == 0) {
+    double lo[NV], hi[NV];
+    bool ba, bn, bo;
+    lim_cell_scan<N, true>(u, nc, c, nullptr, gamma - 1.0, x, t1, ext, delta0, eps, lo, hi, ba, bn, bo);
+    const bool troubled = ba || bn || bo || force;
+    if (lane == 0) {
         flag[c] = troubled ? 1 : 0;
         if (troubled) list[atomicAdd(cnt, 1)] = int32_t(c);
     }
@@ -2687,7 +2725,7 @@ hipError_t launch_lim_prep(int N, const double *u, int64_t nc, double gamma, con
 {
     if (nc <= 0) return hipSuccess;
     ADG_DISPATCH_N(N, {
-        hipLaunchKernelGGL((k_lim_prep<NN>), dim3(unsigned(nc)), dim3(256), 0, st, u, nc, gamma, L.uold, L.mm, L.fb,
+        hipLaunchKernelGGL((k_lim_prep<NN>), dim3(unsigned(nc)), dim3(64), 0, st, u, nc, gamma, L.uold, L.mm, L.fb,
                            L.cnt);
     });
     return hipGetLastError();
@@ -2698,7 +2736,7 @@ hipError_t launch_lim_detect(int N, const double *u, int64_t nc, double gamma, d
 {
     if (nc <= 0) return hipSuccess;
     ADG_DISPATCH_N(N, {
-        hipLaunchKernelGGL((k_lim_detect<NN>), dim3(unsigned(nc)), dim3(256), 0, st, u, nc, gamma, delta0, eps, force,
+        hipLaunchKernelGGL((k_lim_detect<NN>), dim3(unsigned(nc)), dim3(64), 0, st, u, nc, gamma, delta0, eps, force,
                            L.mm, L.nbr, L.flag, L.list, L.cnt);
     });
     return hipGetLastError();
