@@ -527,8 +527,19 @@ struct StatusSink {
     ~StatusSink() { m->status_dev = keep; }
 };
 
+// Subcell bounds of u for the first limited step of a call (later steps
+// carry them from the previous step's kernels).
+adg_status do_lim_prime(adg_mesh *m, const double *u, hipStream_t st)
+{
+    if (!m->lim_mode) return ADG_OK;
+    PhaseTimer tm(m, ADG_PHASE_LIMITER, st);
+    const Instance &I = m->inst[0];
+    ADG_HIP(launch_lim_scan(I.N, u, I.nc, I.gamma, m->lim, false, st), "limiter bounds");
+    return ADG_OK;
+}
+
 // One step with the a-posteriori subcell limiter (one instance, uniform
-// mesh, one stream): CFL, the old subcell bounds and a copy of u, the
+// mesh, one stream): CFL, a copy of u and of the carried bounds, the
 // unlimited candidate (predictor, faces, corrector), detection, the FV step
 // of the limited cells with the flux replacement on their faces, the
 // corrector again for their unlimited neighbours, then the CFL block maxima
@@ -547,7 +558,7 @@ adg_status enqueue_step_limited(adg_mesh *m, double *u, double *hist, void *ws, 
     if (s != ADG_OK) return s;
     {
         PhaseTimer tm(m, ADG_PHASE_LIMITER, st);
-        ADG_HIP(launch_lim_prep(I.N, u, I.nc, I.gamma, m->lim, st), "limiter bounds");
+        ADG_HIP(launch_lim_copy(u, int64_t(m->info.u_elems), I.nc, m->lim, st), "limiter copy");
     }
     {
         StatusSink sink(m);
@@ -572,6 +583,7 @@ adg_status enqueue_step_limited(adg_mesh *m, double *u, double *hist, void *ws, 
         PhaseTimer tm(m, ADG_PHASE_LIMITER, st);
         ADG_HIP(launch_lim_recorrect<T>(I.N, ustar, fside, u, I.nc, I.geo, m->dt_dev, m->lim, st),
                 "limiter corrector re-run");
+        ADG_HIP(launch_lim_scan(I.N, u, I.nc, I.gamma, m->lim, true, st), "limiter bounds (re-run cells)");
     }
     return do_cfl_prime(m, u, st);
 }
@@ -693,6 +705,8 @@ adg_status step_eager(adg_mesh *m, double *u, int32_t n_steps, double *hist, voi
     const int ni = int(m->inst.size());
     adg_status st0 = do_cfl_prime(m, u, s_skel);
     if (st0 != ADG_OK) return st0;
+    st0 = do_lim_prime(m, u, s_skel);
+    if (st0 != ADG_OK) return st0;
     for (int n = 0; n < n_steps; ++n) {
         adg_status st = enqueue_step<T>(m, u, hist ? hist + int64_t(n) * ni : nullptr, ws, s_skel, s_encl);
         if (st != ADG_OK) return st;
@@ -723,6 +737,8 @@ adg_status step_graph(adg_mesh *m, double *u, int32_t n_steps, double *hist, voi
     }
     {
         adg_status st0 = do_cfl_prime(m, u, A);
+        if (st0 != ADG_OK) return st0;
+        st0 = do_lim_prime(m, u, A);
         if (st0 != ADG_OK) return st0;
     }
     if (!m->gexec || m->gkey_u != u || m->gkey_ws != ws || m->gkey_two != two) {
@@ -1247,7 +1263,7 @@ adg_status adg_set_limiter(adg_mesh *mesh, int32_t mode, double delta0, double e
         const size_t nc = size_t(I.nc);
         LimDev L{};
         bool ok = dev_alloc(mesh, L.uold, size_t(mesh->info.u_elems)) && dev_alloc(mesh, L.mm, nc * 2 * NV) &&
-                  dev_alloc(mesh, L.fb, nc) && dev_alloc(mesh, L.nbr, 6 * nc) && dev_alloc(mesh, L.flag, nc) &&
+                  dev_alloc(mesh, L.fb, nc) && dev_alloc(mesh, L.mm2, nc * 2 * NV) && dev_alloc(mesh, L.fb2, nc) && dev_alloc(mesh, L.nbr, 6 * nc) && dev_alloc(mesh, L.flag, nc) &&
                   dev_alloc(mesh, L.list, nc) && dev_alloc(mesh, L.rlist, nc) && dev_alloc(mesh, L.cnt, 2) &&
                   dev_alloc(mesh, mesh->lim_status, 1);
         if (!ok) {

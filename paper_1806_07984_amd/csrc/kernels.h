@@ -114,6 +114,8 @@ struct LimDev {
     double *uold;     // [5][nc][N^3] copy of the step's input
     double *mm;       // [nc][2][5] smallest / largest old subcell datum per variable
     int32_t *fb;      // [nc] 1: old subcell data replaced by the cell mean
+    double *mm2;      // the same of the step's result (carried to the next step)
+    int32_t *fb2;
     int32_t *nbr;     // [6][nc] face neighbour of every cell side
     int32_t *flag;    // [nc] 1 limited, 2 corrector re-run, 0 else
     int32_t *list;    // [nc] limited cells (first cnt[0] entries)
@@ -123,13 +125,19 @@ struct LimDev {
 constexpr int LIM_GRID = 2048;  // blocks of the persistent limiter kernels
 hipError_t launch_lim_nbr(const int32_t *fm, const int32_t *fp, int64_t nf, int d, int64_t nc, int32_t *nbr,
                           hipStream_t st);
-// copy of u, old subcell bounds, fall-back flags; clears the counters
-hipError_t launch_lim_prep(int N, const double *u, int64_t nc, double gamma, const LimDev &L, hipStream_t st);
-// troubled-cell flags and list of the candidate u (force: every cell)
+// subcell bounds and fall-back flags of u into mm2 / fb2: every cell, or
+// (listed) the cells whose corrector ran again
+hipError_t launch_lim_scan(int N, const double *u, int64_t nc, double gamma, const LimDev &L, bool listed,
+                           hipStream_t st);
+// start of a step: u -> uold, mm2 -> mm, fb2 -> fb; clears the counters
+hipError_t launch_lim_copy(const double *u, int64_t n_u, int64_t nc, const LimDev &L, hipStream_t st);
+// troubled-cell flags and list of the candidate u (force: every cell); the
+// candidate's subcell bounds into mm2 / fb2
 hipError_t launch_lim_detect(int N, const double *u, int64_t nc, double gamma, double delta0, double eps, int force,
                              const LimDev &L, hipStream_t st);
-// FV update of the listed cells into u; projected face fluxes for their
-// unlimited neighbours into fside, which are listed for the corrector re-run
+// FV update of the listed cells into u (and their new bounds into mm2 / fb2);
+// projected face fluxes for their unlimited neighbours into fside, which are
+// listed for the corrector re-run
 template <typename T>
 hipError_t launch_lim_fv(int N, double *u, T *fside, int64_t nc, const Geo &geo, const double *dt, double gamma,
                          const LimDev &L, hipStream_t st);

@@ -1800,14 +1800,20 @@ template <int N> struct LimCfg {
     static constexpr int PT = (S3 + THREADS - 1) / THREADS;
 };
 
+// rho <= 0 or p <= 0, the pressure test written without a division: for
+// rho > 0, p > 0 exactly when 2 rho E > |m|^2 (also false for NaN)
+__device__ __forceinline__ bool lim_nonpositive(const double q[NV])
+{
+    return !(q[0] > 0.0) || !(2.0 * q[0] * q[4] - (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) > 0.0);
+}
+
 // non-finite, rho <= 0 or p <= 0
-__device__ __forceinline__ bool lim_bad(double gm1, const double q[NV])
+__device__ __forceinline__ bool lim_bad(double, const double q[NV])
 {
     bool fin = true;
 #pragma unroll
     for (int v = 0; v < NV; ++v) fin = fin && isfinite(q[v]);
-    const double p = gm1 * (q[4] - 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0]);
-    return !fin || !(q[0] > 0.0) || !(p > 0.0);
+    return !fin || lim_nonpositive(q);
 }
 
 // Subcell averages of one variable x[N^3] (node a0 + N a1 + N^2 a2).  axis <
@@ -1925,7 +1931,7 @@ k_lim_nbr(const int32_t *__restrict__ fm, const int32_t *__restrict__ fp, int64_
 }
 
 // One wavefront per cell: loads the cell's u (NV N^3 doubles, coalesced)
-// into LDS x, copying it to ucopy (if not BND), and scans its subcell
+// into LDS x and scans its subcell
 // averages: per variable min / max, whether an average is unphysical,
 // whether one leaves the relaxed bounds and whether a node is unphysical (if
 // BND; ext[k NV + var] and ext[7 NV + k NV + var] hold the old extremes of
@@ -1937,8 +1943,8 @@ k_lim_nbr(const int32_t *__restrict__ fm, const int32_t *__restrict__ fp, int64_
 // same chain of fused multiply-adds as in sub_avg.  Results are valid in
 // every lane.
 template <int N, bool BND>
-__device__ void lim_cell_scan(const double *__restrict__ u, int64_t nc, int64_t c, double *__restrict__ ucopy,
-                              double gm1, double *x, double *t1, const double *ext, double delta0, double eps,
+__device__ void lim_cell_scan(const double *__restrict__ u, int64_t nc, int64_t c, double gm1, double *x,
+                              double *t1, const double *ext, double delta0, double eps,
                               double lo[NV], double hi[NV], bool &bad_avg, bool &bad_node, bool &outside)
 {
     using C = LimCfg<N>;
@@ -1947,9 +1953,7 @@ __device__ void lim_cell_scan(const double *__restrict__ u, int64_t nc, int64_t 
     const int lane = threadIdx.x;
     for (int i = lane; i < NV * N3; i += 64) {
         const int64_t o = (int64_t(i / N3) * nc + c) * N3 + i % N3;
-        const double val = u[o];
-        x[i] = val;
-        if (!BND) ucopy[o] = val;
+        x[i] = u[o];
     }
     __syncthreads();
     for (int t = lane; t < NV * N2; t += 64) {
@@ -2020,7 +2024,8 @@ __device__ void lim_cell_scan(const double *__restrict__ u, int64_t nc, int64_t 
                 hi[var] = fmax(hi[var], acc);
                 if (BND) bo = bo || !(acc >= bl[var] && acc <= bh[var]);
             }
-            ba = ba || lim_bad(gm1, q);
+            // with bounds, a non-finite average already fails them
+            ba = ba || (BND ? lim_nonpositive(q) : lim_bad(gm1, q));
         }
     }
 #pragma unroll
@@ -2034,29 +2039,21 @@ __device__ void lim_cell_scan(const double *__restrict__ u, int64_t nc, int64_t 
     outside = __any(bo);
 }
 
-// One wavefront per cell: copy of u, bounds of the old subcell data (the
-// subcell averages, or the cell mean if one of them is unphysical).
+// Subcell bounds of one cell's u (the subcell averages' extremes, or the
+// cell mean if an average is unphysical) into mm2 / fb2 (one wavefront).
 template <int N>
-__global__ void __launch_bounds__(64)
-k_lim_prep(const double *__restrict__ u, int64_t nc, double gamma, double *__restrict__ uold,
-           double *__restrict__ mm, int32_t *__restrict__ fb, int32_t *__restrict__ cnt)
+__device__ void lim_scan_cell(const double *__restrict__ u, int64_t nc, int64_t c, double gm1, double *x, double *t1,
+                              double *__restrict__ mm2, int32_t *__restrict__ fb2)
 {
-    using C = LimCfg<N>;
-    __shared__ double x[NV * C::N3], t1[NV * C::T1];
-    const int64_t c = blockIdx.x;
-    if (c == 0 && threadIdx.x == 0) {
-        cnt[0] = 0;
-        cnt[1] = 0;
-    }
     double lo[NV], hi[NV];
     bool bad, bn, bo;
-    lim_cell_scan<N, false>(u, nc, c, uold, gamma - 1.0, x, t1, nullptr, 0.0, 0.0, lo, hi, bad, bn, bo);
+    lim_cell_scan<N, false>(u, nc, c, gm1, x, t1, nullptr, 0.0, 0.0, lo, hi, bad, bn, bo);
     const int lane = threadIdx.x;
     if (bad) {
-        const double m = lane < NV ? lim_mean<N>(x + lane * C::N3) : 0.0;
+        const double m = lane < NV ? lim_mean<N>(x + lane * N * N * N) : 0.0;
         if (lane < NV) {
-            mm[c * 2 * NV + lane] = m;
-            mm[c * 2 * NV + NV + lane] = m;
+            mm2[c * 2 * NV + lane] = m;
+            mm2[c * 2 * NV + NV + lane] = m;
         }
     } else if (lane < NV) {
         double l = lo[0], h = hi[0];
@@ -2066,10 +2063,45 @@ k_lim_prep(const double *__restrict__ u, int64_t nc, double gamma, double *__res
                 l = lo[var];
                 h = hi[var];
             }
-        mm[c * 2 * NV + lane] = l;
-        mm[c * 2 * NV + NV + lane] = h;
+        mm2[c * 2 * NV + lane] = l;
+        mm2[c * 2 * NV + NV + lane] = h;
     }
-    if (lane == 0) fb[c] = bad ? 1 : 0;
+    if (lane == 0) fb2[c] = bad ? 1 : 0;
+    __syncthreads();
+}
+
+// LISTED = false: one wavefront per cell; true: persistent over the cells
+// whose corrector ran again.
+template <int N, bool LISTED>
+__global__ void __launch_bounds__(64)
+k_lim_scan(const double *__restrict__ u, int64_t nc, double gamma, double *__restrict__ mm2,
+           int32_t *__restrict__ fb2, const int32_t *__restrict__ rlist, const int32_t *__restrict__ cnt)
+{
+    using C = LimCfg<N>;
+    __shared__ double x[NV * C::N3], t1[NV * C::T1];
+    if (!LISTED) {
+        lim_scan_cell<N>(u, nc, blockIdx.x, gamma - 1.0, x, t1, mm2, fb2);
+        return;
+    }
+    const int n = cnt[1];
+    for (int it = blockIdx.x; it < n; it += gridDim.x) lim_scan_cell<N>(u, nc, rlist[it], gamma - 1.0, x, t1, mm2, fb2);
+}
+
+// Start of a limited step: copy of u, the carried bounds become the old ones,
+// counters cleared.
+__global__ void __launch_bounds__(256)
+k_lim_copy(const double *__restrict__ u, int64_t n_u, int64_t nc, double *__restrict__ uold,
+           const double *__restrict__ mm2, double *__restrict__ mm, const int32_t *__restrict__ fb2,
+           int32_t *__restrict__ fb, int32_t *__restrict__ cnt)
+{
+    const int64_t i0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x, stride = int64_t(gridDim.x) * blockDim.x;
+    if (i0 == 0) {
+        cnt[0] = 0;
+        cnt[1] = 0;
+    }
+    for (int64_t i = i0; i < n_u; i += stride) uold[i] = u[i];
+    for (int64_t i = i0; i < 2 * NV * nc; i += stride) mm[i] = mm2[i];
+    for (int64_t i = i0; i < nc; i += stride) fb[i] = fb2[i];
 }
 
 // One wavefront per cell: troubled-cell test of the candidate u.  Lanes
@@ -2079,7 +2111,8 @@ template <int N>
 __global__ void __launch_bounds__(64)
 k_lim_detect(const double *__restrict__ u, int64_t nc, double gamma, double delta0, double eps, int force,
              const double *__restrict__ mm, const int32_t *__restrict__ nbr, int32_t *__restrict__ flag,
-             int32_t *__restrict__ list, int32_t *__restrict__ cnt)
+             int32_t *__restrict__ list, int32_t *__restrict__ cnt, double *__restrict__ mm2,
+             int32_t *__restrict__ fb2)
 {
     using C = LimCfg<N>;
     __shared__ double x[NV * C::N3], t1[NV * C::T1], ext[2 * 7 * NV];
@@ -2093,11 +2126,24 @@ k_lim_detect(const double *__restrict__ u, int64_t nc, double gamma, double delt
     }
     double lo[NV], hi[NV];
     bool ba, bn, bo;
-    lim_cell_scan<N, true>(u, nc, c, nullptr, gamma - 1.0, x, t1, ext, delta0, eps, lo, hi, ba, bn, bo);
+    lim_cell_scan<N, true>(u, nc, c, gamma - 1.0, x, t1, ext, delta0, eps, lo, hi, ba, bn, bo);
     const bool troubled = ba || bn || bo || force;
     if (lane == 0) {
         flag[c] = troubled ? 1 : 0;
         if (troubled) list[atomicAdd(cnt, 1)] = int32_t(c);
+        fb2[c] = 0;  // an unlimited cell's averages are physical; limited cells are rewritten
+    }
+    // the bounds an unlimited cell carries into the next step (as lim_scan_cell)
+    if (lane < NV) {
+        double l = lo[0], h = hi[0];
+#pragma unroll
+        for (int var = 1; var < NV; ++var)
+            if (lane == var) {
+                l = lo[var];
+                h = hi[var];
+            }
+        mm2[c * 2 * NV + lane] = l;
+        mm2[c * 2 * NV + NV + lane] = h;
     }
 }
 
@@ -2109,11 +2155,11 @@ __global__ void __launch_bounds__(LimCfg<N>::THREADS)
 k_lim_fv(double *__restrict__ u, T *__restrict__ fside, int64_t nc, Geo geo, const double *__restrict__ dt_dev,
          double gamma, const double *__restrict__ uold, const int32_t *__restrict__ fb,
          const int32_t *__restrict__ nbr, int32_t *__restrict__ flag, const int32_t *__restrict__ list,
-         int32_t *__restrict__ rlist, int32_t *__restrict__ cnt)
+         int32_t *__restrict__ rlist, int32_t *__restrict__ cnt, double *__restrict__ mm2, int32_t *__restrict__ fb2)
 {
     using C = LimCfg<N>;
     constexpr int NS = C::NS, N2 = C::N2, N3 = C::N3, S2 = C::S2, S3 = C::S3, PT = C::PT, TH = C::THREADS;
-    __shared__ double v[NV * S3], halo[6 * NV * S2], x[NV * N3], tmp[C::TMP], mean[NV], red[NV * (TH / 64)];
+    __shared__ double v[NV * S3], halo[6 * NV * S2], x[NV * N3], tmp[C::TMP], mean[NV], red[2 * NV * (TH / 64)];
     __shared__ double err[NV * N2], dlt[6 * NV];
     const DevSub &S = c_sub[N];
     const double dt = dt_dev[0], gm1 = gamma - 1.0;
@@ -2274,8 +2320,59 @@ k_lim_fv(double *__restrict__ u, T *__restrict__ fside, int64_t nc, Geo geo, con
             bad = bad || lim_bad(gm1, q);
         }
         bad = __syncthreads_or(bad);
-        for (int i = threadIdx.x; i < NV * N3; i += blockDim.x)
-            u[(int64_t(i / N3) * nc + c) * N3 + i % N3] = bad ? mean[i / N3] : x[i];
+        for (int i = threadIdx.x; i < NV * N3; i += blockDim.x) {
+            if (bad) x[i] = mean[i / N3];
+            u[(int64_t(i / N3) * nc + c) * N3 + i % N3] = x[i];
+        }
+        __syncthreads();
+        // bounds of the new state for the next step, as lim_scan_cell gives
+        // them (same averages, exact extremes, the same mean)
+        if (bad)
+            for (int var = 0; var < NV; ++var) sub_avg<N>(S.A, x + var * N3, t1, t2, v + var * S3, -1, 0);
+        double lo[NV], hi[NV];
+        bool badv = false;
+#pragma unroll
+        for (int var = 0; var < NV; ++var) {
+            lo[var] = INFINITY;
+            hi[var] = -INFINITY;
+        }
+        for (int s = threadIdx.x; s < S3; s += blockDim.x) {
+            double q[NV];
+#pragma unroll
+            for (int var = 0; var < NV; ++var) {
+                q[var] = v[var * S3 + s];
+                lo[var] = fmin(lo[var], q[var]);
+                hi[var] = fmax(hi[var], q[var]);
+            }
+            badv = badv || lim_bad(gm1, q);
+        }
+        {
+            const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+            for (int var = 0; var < NV; ++var) {
+                for (int off = 32; off > 0; off >>= 1) {
+                    lo[var] = fmin(lo[var], __shfl_xor(lo[var], off));
+                    hi[var] = fmax(hi[var], __shfl_xor(hi[var], off));
+                }
+                if (lane == 0) {
+                    red[var * (TH / 64) + wv] = lo[var];
+                    red[(NV + var) * (TH / 64) + wv] = hi[var];
+                }
+            }
+        }
+        badv = __syncthreads_or(badv);
+        if (threadIdx.x < NV) {
+            const int var = threadIdx.x;
+            double l = red[var * (TH / 64)], h = red[(NV + var) * (TH / 64)];
+            for (int w = 1; w < TH / 64; ++w) {
+                l = fmin(l, red[var * (TH / 64) + w]);
+                h = fmax(h, red[(NV + var) * (TH / 64) + w]);
+            }
+            if (badv) l = h = lim_mean<N>(x + var * N3);
+            mm2[c * 2 * NV + var] = l;
+            mm2[c * 2 * NV + NV + var] = h;
+        }
+        if (threadIdx.x == 0) fb2[c] = badv ? 1 : 0;
         __syncthreads();
     }
 }
@@ -2721,13 +2818,24 @@ hipError_t launch_lim_nbr(const int32_t *fm, const int32_t *fp, int64_t nf, int 
     return hipGetLastError();
 }
 
-hipError_t launch_lim_prep(int N, const double *u, int64_t nc, double gamma, const LimDev &L, hipStream_t st)
+hipError_t launch_lim_scan(int N, const double *u, int64_t nc, double gamma, const LimDev &L, bool listed,
+                           hipStream_t st)
 {
     if (nc <= 0) return hipSuccess;
     ADG_DISPATCH_N(N, {
-        hipLaunchKernelGGL((k_lim_prep<NN>), dim3(unsigned(nc)), dim3(64), 0, st, u, nc, gamma, L.uold, L.mm, L.fb,
-                           L.cnt);
+        if (listed)
+            hipLaunchKernelGGL((k_lim_scan<NN, true>), dim3(LIM_GRID), dim3(64), 0, st, u, nc, gamma, L.mm2, L.fb2,
+                               L.rlist, L.cnt);
+        else
+            hipLaunchKernelGGL((k_lim_scan<NN, false>), dim3(unsigned(nc)), dim3(64), 0, st, u, nc, gamma, L.mm2,
+                               L.fb2, L.rlist, L.cnt);
     });
+    return hipGetLastError();
+}
+
+hipError_t launch_lim_copy(const double *u, int64_t n_u, int64_t nc, const LimDev &L, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_lim_copy, dim3(4096), dim3(256), 0, st, u, n_u, nc, L.uold, L.mm2, L.mm, L.fb2, L.fb, L.cnt);
     return hipGetLastError();
 }
 
@@ -2737,7 +2845,7 @@ hipError_t launch_lim_detect(int N, const double *u, int64_t nc, double gamma, d
     if (nc <= 0) return hipSuccess;
     ADG_DISPATCH_N(N, {
         hipLaunchKernelGGL((k_lim_detect<NN>), dim3(unsigned(nc)), dim3(64), 0, st, u, nc, gamma, delta0, eps, force,
-                           L.mm, L.nbr, L.flag, L.list, L.cnt);
+                           L.mm, L.nbr, L.flag, L.list, L.cnt, L.mm2, L.fb2);
     });
     return hipGetLastError();
 }
@@ -2749,7 +2857,7 @@ hipError_t launch_lim_fv(int N, double *u, T *fside, int64_t nc, const Geo &geo,
     if (nc <= 0) return hipSuccess;
     ADG_DISPATCH_N(N, {
         hipLaunchKernelGGL((k_lim_fv<T, NN>), dim3(LIM_GRID), dim3(LimCfg<NN>::THREADS), 0, st, u, fside, nc, geo, dt,
-                           gamma, L.uold, L.fb, L.nbr, L.flag, L.list, L.rlist, L.cnt);
+                           gamma, L.uold, L.fb, L.nbr, L.flag, L.list, L.rlist, L.cnt, L.mm2, L.fb2);
     });
     return hipGetLastError();
 }

@@ -165,3 +165,26 @@ def test_refusals():
         one.limiter_stats()  # never enabled
     for m in (amr, p7, two, one):
         m.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_carried_bounds_equal_recomputed(precision):
+    """Steps inside one call carry the subcell bounds from the previous
+    step's kernels; a new call recomputes them from u.  Both give the same
+    bits."""
+    p, n = 3, (6, 6, 6)
+    u0 = inputs.blast(oracle.Mesh(p, n).node_coords())
+    one_call, nl, _, _ = run_gpu(p, n, u0, 4, precision, 1)
+    gm = A.Mesh(A.instance(p, n), precision)
+    gm.set_options(use_graph=False, batched=0)
+    gm.set_limiter(1)
+    u = dev(u0)
+    ws = gm.empty_workspace()
+    for _ in range(4):
+        gm.step(u, 1, ws)
+    torch.cuda.synchronize()
+    gm.status()
+    nl2, _ = gm.limiter_stats()
+    gm.close()
+    assert nl == nl2 and nl > 0
+    assert np.array_equal(one_call, u.cpu().numpy().reshape(u0.shape))
