@@ -65,6 +65,16 @@ def lib():
         L.orc_sample.restype = ctypes.c_int
         L.orc_sample.argtypes = [P, P, P, ctypes.c_long, P]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_lin_flux_matrix.argtypes = [P, ctypes.c_int, P]
+        L.orc_lin_predictor.argtypes = [P, P, ctypes.c_double, ctypes.c_int, ctypes.c_int, P, P, P]
+        L.orc_lin_riemann.argtypes = [P, P, P, P]
+        L.orc_lin_corrector.argtypes = [P, ctypes.c_double, P, P, P]
+        L.orc_lin_cfl.restype = ctypes.c_double
+        L.orc_lin_cfl.argtypes = [P, P, ctypes.c_double]
+        L.orc_lin_run.restype = ctypes.c_int
+        L.orc_lin_run.argtypes = [P, P, ctypes.c_double, ctypes.c_double, P, ctypes.c_int, P]
+        L.orc_lin_energy.restype = ctypes.c_double
+        L.orc_lin_energy.argtypes = [P, P, P]
         L.orc_indicator.argtypes = [P, P, P]
         L.orc_volume_transfer.restype = ctypes.c_int
         L.orc_volume_transfer.argtypes = [P, P, P, P]
@@ -263,6 +273,61 @@ def subcell_ops(N):
     return A, Ap, B
 
 
+NL = 9  # elastic unknowns: s_xx, s_yy, s_zz, s_xy, s_yz, s_xz, v_x, v_y, v_z
+
+
+def lin_flux_matrix(mat, d):
+    """A_d (9 x 9) of the elastic system for material (rho, lambda, mu)."""
+    A = np.zeros((NL, NL))
+    lib().orc_lin_flux_matrix(_p(_f64(mat)), int(d), _p(A))
+    return A
+
+
+def _lin_predictor(self, mat, u, dt, ck=True, npic=None):
+    """(ustar [9, nc, N^3], traces [6, 2, 9, nc, N^2]); material [3, nc]."""
+    mat, u = _f64(mat), _f64(u)
+    us = np.zeros((NL, self.nc, self.N ** 3))
+    tr = np.zeros((6, 2, NL, self.nc, self.N ** 2))
+    lib().orc_lin_predictor(self._h, _p(mat), float(dt), int(bool(ck)), int(self.N if npic is None else npic),
+                            _p(u), _p(us), _p(tr))
+    return us, tr
+
+
+def _lin_riemann(self, mat, traces):
+    fs = np.zeros((6, NL, self.nc, self.N ** 2))
+    lib().orc_lin_riemann(self._h, _p(_f64(mat)), _p(_f64(traces)), _p(fs))
+    return fs
+
+
+def _lin_corrector(self, ustar, fside, dt):
+    un = np.zeros_like(_f64(ustar))
+    lib().orc_lin_corrector(self._h, float(dt), _p(_f64(ustar)), _p(_f64(fside)), _p(un))
+    return un
+
+
+def _lin_run(self, mat, u, nsteps, cfl=0.4, dt_fixed=0.0):
+    """Elastic steps (Cauchy-Kowalevski predictor); returns (u, dt)."""
+    u = np.array(u, dtype=np.float64, copy=True, order="C")
+    dt = np.zeros(1)
+    rc = lib().orc_lin_run(self._h, _p(_f64(mat)), float(cfl), float(dt_fixed), _p(u), int(nsteps), _p(dt))
+    assert rc == 0, rc
+    return u, float(dt[0])
+
+
+def _lin_cfl(self, mat, cfl=0.4):
+    return lib().orc_lin_cfl(self._h, _p(_f64(mat)), float(cfl))
+
+
+def _lin_energy(self, mat, u):
+    return lib().orc_lin_energy(self._h, _p(_f64(mat)), _p(_f64(u)))
+
+
+Mesh.lin_predictor = _lin_predictor
+Mesh.lin_riemann = _lin_riemann
+Mesh.lin_corrector = _lin_corrector
+Mesh.lin_run = _lin_run
+Mesh.lin_cfl = _lin_cfl
+Mesh.lin_energy = _lin_energy
 Mesh.run_limited = _run_limited
 Mesh.limiter_detect = _limiter_detect
 Mesh.run_sched = _run_sched

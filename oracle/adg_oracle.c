@@ -1506,6 +1506,352 @@ int orc_run_limited(const orc_mesh *m, double g, double cfl, int npic, double dt
     return 0;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Linear PDE: elastic waves, space-time predictor by Cauchy-Kowalevski      */
+/* ------------------------------------------------------------------------- */
+
+/* The seismic variant (Sec. 2.1: a linear PDE is integrated in time by the
+ * Cauchy-Kowalevski procedure instead of an iterative predictor; Sec. 5: the
+ * seismic benchmark is elastic wave propagation with the material carried
+ * along as time-constant unknowns).  Readings:
+ *   - 3-D linear elasticity in velocity-stress form, 9 unknowns
+ *     q = (s_xx, s_yy, s_zz, s_xy, s_yz, s_xz, v_x, v_y, v_z):
+ *       d_t s_ij = lambda delta_ij div v + mu (d_i v_j + d_j v_i),
+ *       rho d_t v_i = sum_j d_j s_ij,
+ *     written as d_t q + sum_d d_d (A_d q) = 0;
+ *   - the material (rho, lambda, mu) is constant inside each cell (the
+ *     paper's time-constant material unknowns, stored once per cell);
+ *   - Cauchy-Kowalevski: d_t^k q = L^k q with L q = -sum_d (1/dx_d) A_d D_d q
+ *     on the nodal polynomial; L lowers the degree, so the series ends after
+ *     p+1 terms and the time average is exact:
+ *       qbar = sum_{k=0}^{p} dt^k / (k+1)! L^k u;
+ *   - the rest of the step is the one of the Euler path with the flux A_d q:
+ *     volume term, face projections, one Rusanov solve per face with the
+ *     larger P-wave speed of its two cells, corrector;
+ *   - dt = cfl / ((2p+1) max_c c_p(c) sum_d 1/dx_d), c_p = sqrt((lambda+2mu)/rho).
+ * Layouts: u [9][nc][N^3], traces [6][2][9][nc][N^2], fside [6][9][nc][N^2],
+ * material [3][nc] (rho, lambda, mu).  Uniform meshes. */
+#define NL 9
+enum { SXX = 0, SYY, SZZ, SXY, SYZ, SXZ, VX, VY, VZ };
+
+/* f = A_d q for material (rho, lambda, mu) */
+static void elastic_flux(const double mat[3], const double q[NL], int d, double f[NL])
+{
+    double rho = mat[0], lam = mat[1], mu = mat[2];
+    for (int v = 0; v < NL; ++v) f[v] = 0.0;
+    if (d == 0) {
+        f[SXX] = -(lam + 2 * mu) * q[VX];
+        f[SYY] = -lam * q[VX];
+        f[SZZ] = -lam * q[VX];
+        f[SXY] = -mu * q[VY];
+        f[SXZ] = -mu * q[VZ];
+        f[VX] = -q[SXX] / rho;
+        f[VY] = -q[SXY] / rho;
+        f[VZ] = -q[SXZ] / rho;
+    } else if (d == 1) {
+        f[SXX] = -lam * q[VY];
+        f[SYY] = -(lam + 2 * mu) * q[VY];
+        f[SZZ] = -lam * q[VY];
+        f[SXY] = -mu * q[VX];
+        f[SYZ] = -mu * q[VZ];
+        f[VX] = -q[SXY] / rho;
+        f[VY] = -q[SYY] / rho;
+        f[VZ] = -q[SYZ] / rho;
+    } else {
+        f[SXX] = -lam * q[VZ];
+        f[SYY] = -lam * q[VZ];
+        f[SZZ] = -(lam + 2 * mu) * q[VZ];
+        f[SYZ] = -mu * q[VY];
+        f[SXZ] = -mu * q[VX];
+        f[VX] = -q[SXZ] / rho;
+        f[VY] = -q[SYZ] / rho;
+        f[VZ] = -q[SZZ] / rho;
+    }
+}
+
+static double p_speed(const double mat[3]) { return sqrt((mat[1] + 2 * mat[2]) / mat[0]); }
+
+static void cell_mat(const orc_mesh *m, const double *mat, long c, double out[3])
+{
+    for (int k = 0; k < 3; ++k) out[k] = mat[(long)k * m->nc + c];
+}
+
+/* A_d as a 9 x 9 matrix (row-major), column k = A_d e_k */
+void orc_lin_flux_matrix(const double mat[3], int d, double *A)
+{
+    for (int k = 0; k < NL; ++k) {
+        double e[NL] = { 0 }, f[NL];
+        e[k] = 1.0;
+        elastic_flux(mat, e, d, f);
+        for (int r = 0; r < NL; ++r) A[r * NL + k] = f[r];
+    }
+}
+
+/* Shared epilogue: from qbar (one cell, [9][N^3]) the volume term into ustar
+ * and the face projections of qbar and of the normal flux into traces. */
+static void lin_epilogue(const orc_mesh *m, long c, const double *cm, double dt, const double *uc,
+                         const double *qbar, const double *D, const double *L, const double *R,
+                         const double *w, const double *Kw, double *ustar, double *traces)
+{
+    int N = m->N, N2 = N * N, N3 = N2 * N;
+    long nc = m->nc;
+    double dx[3];
+    cell_dx(m, c, dx);
+    double *Fbar = (double *)malloc(sizeof(double) * 3 * NL * N3);
+    for (int a = 0; a < N3; ++a) {
+        double qq[NL], f[NL];
+        for (int v = 0; v < NL; ++v) qq[v] = qbar[v * N3 + a];
+        for (int d = 0; d < 3; ++d) {
+            elastic_flux(cm, qq, d, f);
+            for (int v = 0; v < NL; ++v) Fbar[(d * NL + v) * N3 + a] = f[v];
+        }
+    }
+    (void)D;
+    for (int v = 0; v < NL; ++v)
+        for (int a = 0; a < N3; ++a) {
+            int aa[3] = { a % N, (a / N) % N, a / N2 };
+            double s = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                double sd = 0.0;
+                for (int e = 0; e < N; ++e) sd += Kw[aa[d] * N + e] * Fbar[(d * NL + v) * N3 + node_with(N, a, d, e)];
+                s += (dt / dx[d]) * sd / w[aa[d]];
+            }
+            ustar[((long)v * nc + c) * N3 + a] = uc[v * N3 + a] + s;
+        }
+    for (int s = 0; s < 6; ++s) {
+        int d = s / 2;
+        const double *E = (s % 2) ? R : L;
+        for (int v = 0; v < NL; ++v)
+            for (int b = 0; b < N2; ++b) {
+                double sq = 0.0, sf = 0.0;
+                for (int e = 0; e < N; ++e) {
+                    int a = node_from_face(N, d, e, b);
+                    sq += E[e] * qbar[v * N3 + a];
+                    sf += E[e] * Fbar[(d * NL + v) * N3 + a];
+                }
+                traces[(((long)(s * 2 + 0) * NL + v) * nc + c) * N2 + b] = sq;
+                traces[(((long)(s * 2 + 1) * NL + v) * nc + c) * N2 + b] = sf;
+            }
+    }
+    free(Fbar);
+}
+
+/* Predictor of the elastic system.  ck != 0: Cauchy-Kowalevski as above;
+ * ck == 0: the Picard iteration of orc_predictor with the flux A_d q and
+ * npic iterations (test reference: for a linear PDE, p+1 iterations reach
+ * the same space-time polynomial). */
+void orc_lin_predictor(const orc_mesh *m, const double *mat, double dt, int ck, int npic, const double *u,
+                       double *ustar, double *traces)
+{
+    int N = m->N, N2 = N * N, N3 = N2 * N;
+    long nc = m->nc;
+    double xi[MAXN], w[MAXN], D[MAXN * MAXN], L[MAXN], R[MAXN], Kinv[MAXN * MAXN], Kw[MAXN * MAXN];
+    orc_basis(N, xi, w, D, L, R, Kinv, Kw);
+#pragma omp parallel
+    {
+        double *uc = (double *)malloc(sizeof(double) * NL * N3);
+        double *qbar = (double *)malloc(sizeof(double) * NL * N3);
+        double *dk = (double *)malloc(sizeof(double) * NL * N3);
+        double *dn = (double *)malloc(sizeof(double) * NL * N3);
+        double *q = (double *)malloc(sizeof(double) * N * NL * N3);
+        double *qn = (double *)malloc(sizeof(double) * N * NL * N3);
+        double *F = (double *)malloc(sizeof(double) * N * 3 * NL * N3);
+#pragma omp for schedule(static)
+        for (long c = 0; c < nc; ++c) {
+            double cm[3], dx[3];
+            cell_mat(m, mat, c, cm);
+            cell_dx(m, c, dx);
+            for (int v = 0; v < NL; ++v)
+                for (int a = 0; a < N3; ++a) uc[v * N3 + a] = u[((long)v * nc + c) * N3 + a];
+            if (ck) {
+                memcpy(dk, uc, sizeof(double) * NL * N3);
+                memcpy(qbar, uc, sizeof(double) * NL * N3);
+                double fac = 1.0;
+                for (int k = 1; k < N; ++k) {
+                    /* dn = L dk = -sum_d (1/dx_d) D_d (A_d dk) */
+                    for (int v = 0; v < NL; ++v)
+                        for (int a = 0; a < N3; ++a) {
+                            int aa[3] = { a % N, (a / N) % N, a / N2 };
+                            double s = 0.0;
+                            for (int d = 0; d < 3; ++d) {
+                                double sd = 0.0;
+                                for (int e = 0; e < N; ++e) {
+                                    int b = node_with(N, a, d, e);
+                                    double qq[NL], f[NL];
+                                    for (int vv = 0; vv < NL; ++vv) qq[vv] = dk[vv * N3 + b];
+                                    elastic_flux(cm, qq, d, f);
+                                    sd += D[aa[d] * N + e] * f[v];
+                                }
+                                s += sd / dx[d];
+                            }
+                            dn[v * N3 + a] = -s;
+                        }
+                    memcpy(dk, dn, sizeof(double) * NL * N3);
+                    fac *= dt / (k + 1);
+                    for (int i = 0; i < NL * N3; ++i) qbar[i] += fac * dk[i];
+                }
+            } else {
+                for (int l = 0; l < N; ++l) memcpy(q + l * NL * N3, uc, sizeof(double) * NL * N3);
+                for (int it = 0; it < npic; ++it) {
+                    for (int j = 0; j < N; ++j)
+                        for (int a = 0; a < N3; ++a) {
+                            double qq[NL], f[NL];
+                            for (int v = 0; v < NL; ++v) qq[v] = q[(j * NL + v) * N3 + a];
+                            for (int d = 0; d < 3; ++d) {
+                                elastic_flux(cm, qq, d, f);
+                                for (int v = 0; v < NL; ++v) F[((j * 3 + d) * NL + v) * N3 + a] = f[v];
+                            }
+                        }
+                    for (int l = 0; l < N; ++l)
+                        for (int v = 0; v < NL; ++v)
+                            for (int a = 0; a < N3; ++a) {
+                                int aa[3] = { a % N, (a / N) % N, a / N2 };
+                                double s = 0.0;
+                                for (int j = 0; j < N; ++j) {
+                                    double g = 0.0;
+                                    for (int d = 0; d < 3; ++d) {
+                                        double sd = 0.0;
+                                        for (int e = 0; e < N; ++e)
+                                            sd += D[aa[d] * N + e] * F[((j * 3 + d) * NL + v) * N3 + node_with(N, a, d, e)];
+                                        g += (dt / dx[d]) * sd;
+                                    }
+                                    s += Kinv[l * N + j] * w[j] * g;
+                                }
+                                qn[(l * NL + v) * N3 + a] = uc[v * N3 + a] - s;
+                            }
+                    double *t = q; q = qn; qn = t;
+                }
+                for (int v = 0; v < NL; ++v)
+                    for (int a = 0; a < N3; ++a) {
+                        double s = 0.0;
+                        for (int j = 0; j < N; ++j) s += w[j] * q[(j * NL + v) * N3 + a];
+                        qbar[v * N3 + a] = s;
+                    }
+            }
+            lin_epilogue(m, c, cm, dt, uc, qbar, D, L, R, w, Kw, ustar, traces);
+        }
+        free(uc); free(qbar); free(dk); free(dn); free(q); free(qn); free(F);
+    }
+}
+
+/* Rusanov on every face (uniform mesh): F = (F_L + F_R)/2 - s (Q_R - Q_L)/2
+ * with s the larger P-wave speed of the two cells; both sides get F. */
+void orc_lin_riemann(const orc_mesh *m, const double *mat, const double *traces, double *fside)
+{
+    int N = m->N, N2 = N * N;
+    long nc = m->nc;
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < nc; ++c)
+        for (int s = 0; s < 6; ++s) {
+            int d = s / 2, plus = s % 2;
+            long o = m->nbr[6 * c + s];
+            int so = 2 * d + (1 - plus);
+            long cl = plus ? c : o, cr = plus ? o : c;
+            int sl = plus ? s : so, sr = plus ? so : s;
+            double ml[3], mr[3];
+            cell_mat(m, mat, cl, ml);
+            cell_mat(m, mat, cr, mr);
+            double sp = p_speed(ml) > p_speed(mr) ? p_speed(ml) : p_speed(mr);
+            for (int v = 0; v < NL; ++v)
+                for (int b = 0; b < N2; ++b) {
+                    double QL = traces[(((long)(sl * 2 + 0) * NL + v) * nc + cl) * N2 + b];
+                    double FL = traces[(((long)(sl * 2 + 1) * NL + v) * nc + cl) * N2 + b];
+                    double QR = traces[(((long)(sr * 2 + 0) * NL + v) * nc + cr) * N2 + b];
+                    double FR = traces[(((long)(sr * 2 + 1) * NL + v) * nc + cr) * N2 + b];
+                    fside[((long)(s * NL + v) * nc + c) * N2 + b] = 0.5 * (FL + FR) - 0.5 * sp * (QR - QL);
+                }
+        }
+}
+
+void orc_lin_corrector(const orc_mesh *m, double dt, const double *ustar, const double *fside, double *unew)
+{
+    int N = m->N, N2 = N * N, N3 = N2 * N;
+    long nc = m->nc;
+    double xi[MAXN], w[MAXN], D[MAXN * MAXN], L[MAXN], R[MAXN], Kinv[MAXN * MAXN], Kw[MAXN * MAXN];
+    orc_basis(N, xi, w, D, L, R, Kinv, Kw);
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < nc; ++c) {
+        double dx[3];
+        cell_dx(m, c, dx);
+        for (int v = 0; v < NL; ++v)
+            for (int a = 0; a < N3; ++a) {
+                int aa[3] = { a % N, (a / N) % N, a / N2 };
+                double s = 0.0;
+                for (int d = 0; d < 3; ++d) {
+                    int b = face_index(N, a, d);
+                    double fm = fside[((long)((2 * d) * NL + v) * nc + c) * N2 + b];
+                    double fp = fside[((long)((2 * d + 1) * NL + v) * nc + c) * N2 + b];
+                    s += (dt / dx[d]) * (R[aa[d]] * fp - L[aa[d]] * fm) / w[aa[d]];
+                }
+                unew[((long)v * nc + c) * N3 + a] = ustar[((long)v * nc + c) * N3 + a] - s;
+            }
+    }
+}
+
+double orc_lin_cfl(const orc_mesh *m, const double *mat, double cfl)
+{
+    double best = 0.0;
+    for (long c = 0; c < m->nc; ++c) {
+        double cm[3], dx[3];
+        cell_mat(m, mat, c, cm);
+        cell_dx(m, c, dx);
+        double r = p_speed(cm) * (1.0 / dx[0] + 1.0 / dx[1] + 1.0 / dx[2]);
+        if (r > best) best = r;
+    }
+    return cfl / ((2.0 * (m->N - 1) + 1.0) * best);
+}
+
+/* Steps in place; dt from orc_lin_cfl (or dt_fixed > 0).  Returns 0, 2 on
+ * allocation failure, 3 on a mesh with hanging faces. */
+int orc_lin_run(const orc_mesh *m, const double *mat, double cfl, double dt_fixed, double *u, int nsteps,
+                double *dt_out)
+{
+    int N = m->N, N2 = N * N, N3 = N2 * N;
+    long nc = m->nc;
+    for (long k = 0; k < 6 * nc; ++k)
+        if (m->kind[k] != SIDE_CONFORMING) return 3;
+    double *us = (double *)malloc(sizeof(double) * NL * nc * N3);
+    double *tr = (double *)malloc(sizeof(double) * 6 * 2 * NL * nc * N2);
+    double *fs = (double *)malloc(sizeof(double) * 6 * NL * nc * N2);
+    if (!us || !tr || !fs) { free(us); free(tr); free(fs); return 2; }
+    double dt = dt_fixed > 0.0 ? dt_fixed : orc_lin_cfl(m, mat, cfl);
+    if (dt_out) *dt_out = dt;
+    for (int n = 0; n < nsteps; ++n) {
+        orc_lin_predictor(m, mat, dt, 1, 0, u, us, tr);
+        orc_lin_riemann(m, mat, tr, fs);
+        orc_lin_corrector(m, dt, us, fs, u);
+    }
+    free(us); free(tr); free(fs);
+    return 0;
+}
+
+/* Elastic energy: sum over cells of |cell| sum_a W_a e(q_a),
+ * e = rho |v|^2 / 2 + (s:s)/(4 mu) - lambda (tr s)^2 / (4 mu (3 lambda + 2 mu)). */
+double orc_lin_energy(const orc_mesh *m, const double *mat, const double *u)
+{
+    int N = m->N, N3 = N * N * N;
+    double xi[MAXN], w[MAXN];
+    orc_gauss_legendre(N, xi, w);
+    double total = 0.0;
+    for (long c = 0; c < m->nc; ++c) {
+        double cm[3], dx[3];
+        cell_mat(m, mat, c, cm);
+        cell_dx(m, c, dx);
+        double rho = cm[0], lam = cm[1], mu = cm[2];
+        for (int a = 0; a < N3; ++a) {
+            double q[NL];
+            for (int v = 0; v < NL; ++v) q[v] = u[((long)v * m->nc + c) * N3 + a];
+            double ss = q[SXX] * q[SXX] + q[SYY] * q[SYY] + q[SZZ] * q[SZZ] +
+                        2 * (q[SXY] * q[SXY] + q[SYZ] * q[SYZ] + q[SXZ] * q[SXZ]);
+            double tr = q[SXX] + q[SYY] + q[SZZ];
+            double e = 0.5 * rho * (q[VX] * q[VX] + q[VY] * q[VY] + q[VZ] * q[VZ]) + ss / (4 * mu) -
+                       lam * tr * tr / (4 * mu * (3 * lam + 2 * mu));
+            total += dx[0] * dx[1] * dx[2] * w[a % N] * w[(a / N) % N] * w[a / (N * N)] * e;
+        }
+    }
+    return total;
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP
