@@ -334,6 +334,55 @@ adg_status adg_transfer(const adg_mesh *from, const double *u_from_dev, adg_mesh
  * non-physical state was met since the last call (then clears the latch). */
 adg_status adg_get_status(adg_mesh *mesh);
 
+/* ------------------------------------------------------------------------ */
+/* Linear variant: elastic waves, Cauchy-Kowalevski predictor                */
+/* ------------------------------------------------------------------------ */
+/* The seismic variant of the method (Sec. 2.1: for a linear PDE the
+ * space-time predictor is the Cauchy-Kowalevski procedure instead of an
+ * iteration; Sec. 5: elastic wave propagation with the material carried as
+ * time-constant unknowns).  3-D linear elasticity in velocity-stress form,
+ * 9 unknowns q = (s_xx, s_yy, s_zz, s_xy, s_yz, s_xz, v_x, v_y, v_z),
+ *   d_t s_ij = lambda delta_ij div v + mu (d_i v_j + d_j v_i),
+ *   rho d_t v_i = sum_j d_j s_ij,
+ * i.e. d_t q + sum_d d_d (A_d q) = 0 with the material constant per cell.
+ * One step: qbar = sum_{k=0}^{p} dt^k / (k+1)! L^k u with
+ * L q = -sum_d (1/dx_d) A_d D_d q (the Taylor series in time of degree p;
+ * it equals p Picard iterations from the time-constant start); then the
+ * Euler path's volume term, face projections, one Rusanov solve per face
+ * with the larger P-wave speed c_p = sqrt((lambda + 2 mu)/rho) of its two
+ * cells, and the corrector.  dt = cfl / ((2p+1) max_c c_p sum_d 1/dx_d),
+ * fixed by the material.  Uniform fully periodic boxes, p <= 6, FP64.
+ * Layouts (device, caller-owned): u, ustar [9][n_cells][N^3]; traces
+ * [6][2][9][n_cells][N^2]; face fluxes [6][9][n_cells][N^2]; material
+ * [3][n_cells] (rho, lambda, mu), cells ordered i + n0 (j + n1 k). */
+typedef struct adg_lin adg_lin;
+typedef struct {
+    int32_t order;    /* p, 0..6 */
+    int32_t n[3];     /* cells per axis */
+    double lo[3], hi[3];
+    double cfl;       /* e.g. 0.4 */
+} adg_lin_desc;
+/* Handle of one uniform periodic mesh on the current device.
+ * ADG_ERR_UNSUPPORTED for p > 6 or too many cells; ADG_ERR_INVALID_ARG for
+ * bad sizes. */
+adg_status adg_lin_init(const adg_lin_desc *desc, adg_lin **out);
+adg_status adg_lin_free(adg_lin *lin);
+/* Element counts of the arrays above and the adg_lin_step workspace size
+ * (any pointer may be NULL). */
+adg_status adg_lin_info(adg_lin *lin, int64_t *n_cells, int64_t *u_elems, int64_t *trace_elems,
+                        int64_t *fside_elems, int64_t *workspace_bytes);
+/* dt of the material into dt_dev (device, one double). */
+adg_status adg_lin_dt(adg_lin *lin, const double *material, double *dt_dev, hipStream_t stream);
+/* Cauchy-Kowalevski predictor with the dt in dt_dev: ustar (u plus the
+ * volume term) and the face projections of the time-averaged state and of
+ * its normal flux. */
+adg_status adg_lin_predictor(adg_lin *lin, const double *material, const double *u, const double *dt_dev,
+                             double *ustar, double *traces, hipStream_t stream);
+/* n_steps whole steps in place on u; dt_out (device, may be NULL) receives
+ * dt.  ws holds workspace_bytes.  Enqueued on stream, no synchronisation. */
+adg_status adg_lin_step(adg_lin *lin, const double *material, double *u, int32_t n_steps, double *dt_out,
+                        void *ws, hipStream_t stream);
+
 const char *adg_last_error(void);
 
 #ifdef __cplusplus

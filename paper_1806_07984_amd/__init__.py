@@ -24,7 +24,8 @@ EXPORTS = ["adg_init_mesh", "adg_free_mesh", "adg_mesh_info", "adg_instance_info
            "adg_profile", "adg_profile_read", "adg_get_status", "adg_last_error", "adg_autotune",
            "adg_tuning", "adg_set_options", "adg_step_adjoint", "adg_sample", "adg_sample_adjoint",
            "adg_set_switch_tape", "adg_set_pipeline", "adg_indicator", "adg_adapt_plan", "adg_transfer",
-           "adg_set_limiter", "adg_limiter_stats"]
+           "adg_set_limiter", "adg_limiter_stats", "adg_lin_init", "adg_lin_free", "adg_lin_info", "adg_lin_dt",
+           "adg_lin_predictor", "adg_lin_step"]
 PHASES = ["cfl", "predictor", "hanging", "riemann", "corrector", "limiter"]
 
 
@@ -52,6 +53,11 @@ class Info(ctypes.Structure):
 class InstanceGeom(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("n_cells", ctypes.c_int64), ("cell_offset", ctypes.c_int64),
                 ("u_offset", ctypes.c_int64), ("trace_offset", ctypes.c_int64), ("fside_offset", ctypes.c_int64)]
+
+
+class LinDesc(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int32), ("n", ctypes.c_int32 * 3), ("lo", ctypes.c_double * 3),
+                ("hi", ctypes.c_double * 3), ("cfl", ctypes.c_double)]
 
 
 _lib = None
@@ -94,6 +100,12 @@ def load():
         "adg_transfer": [P, P, P, P, P],
         "adg_set_limiter": [P, I32, ctypes.c_double, ctypes.c_double],
         "adg_limiter_stats": [P, P, P, P, P],
+        "adg_lin_init": [ctypes.POINTER(LinDesc), ctypes.POINTER(P)],
+        "adg_lin_free": [P],
+        "adg_lin_info": [P, P, P, P, P, P],
+        "adg_lin_dt": [P, P, P, P],
+        "adg_lin_predictor": [P, P, P, P, P, P, P],
+        "adg_lin_step": [P, P, P, I32, P, P, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -410,3 +422,66 @@ class Mesh:
     def status(self):
         """Synchronises; raises AdgError(NONPHYSICAL) if a bad state was met."""
         _check(load().adg_get_status(self._h))
+
+
+class LinMesh:
+    """Linear variant: elastic waves (9 unknowns) on a uniform periodic box
+    with the Cauchy-Kowalevski predictor (adg_lin_*).  material: float64
+    tensor [3, n_cells] (rho, lambda, mu); u: float64 [9, n_cells, N^3]."""
+
+    def __init__(self, order, n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), cfl=0.4):
+        L = load()
+        d = LinDesc()
+        d.order = int(order)
+        for a in range(3):
+            d.n[a], d.lo[a], d.hi[a] = int(n[a]), float(lo[a]), float(hi[a])
+        d.cfl = float(cfl)
+        h = ctypes.c_void_p()
+        _check(L.adg_lin_init(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        self.N = int(order) + 1
+        vals = [ctypes.c_int64(0) for _ in range(5)]
+        _check(L.adg_lin_info(self._h, *[ctypes.byref(v) for v in vals]))
+        self.info = dict(zip(["n_cells", "u_elems", "trace_elems", "fside_elems", "workspace_bytes"],
+                             [v.value for v in vals]))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().adg_lin_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def empty_workspace(self, device="cuda"):
+        import torch
+        return torch.empty(self.info["workspace_bytes"], dtype=torch.uint8, device=device)
+
+    def dt(self, material, stream=None):
+        import torch
+        out = torch.empty(1, dtype=torch.float64, device=material.device)
+        _check(load().adg_lin_dt(self._h, _ptr(material, torch.float64, 3 * self.info["n_cells"], "material"),
+                                 _ptr(out, torch.float64, 1, "dt"), _stream(stream)))
+        return out
+
+    def predictor(self, material, u, dt, stream=None):
+        """(ustar, traces) of the Cauchy-Kowalevski predictor at the dt in the
+        one-element device tensor dt."""
+        import torch
+        ustar = torch.empty(self.info["u_elems"], dtype=torch.float64, device=u.device)
+        traces = torch.empty(self.info["trace_elems"], dtype=torch.float64, device=u.device)
+        _check(load().adg_lin_predictor(self._h, _ptr(material, torch.float64, 3 * self.info["n_cells"], "material"),
+                                        _ptr(u, torch.float64, self.info["u_elems"], "u"),
+                                        _ptr(dt, torch.float64, 1, "dt"), ctypes.c_void_p(ustar.data_ptr()),
+                                        ctypes.c_void_p(traces.data_ptr()), _stream(stream)))
+        return ustar, traces
+
+    def step(self, material, u, n_steps, ws, dt_out=None, stream=None):
+        import torch
+        _check(load().adg_lin_step(self._h, _ptr(material, torch.float64, 3 * self.info["n_cells"], "material"),
+                                   _ptr(u, torch.float64, self.info["u_elems"], "u"), int(n_steps),
+                                   ctypes.c_void_p(0) if dt_out is None else _ptr(dt_out, torch.float64, 1, "dt_out"),
+                                   ctypes.c_void_p(ws.data_ptr()), _stream(stream)))

@@ -1653,3 +1653,159 @@ adg_status adg_adapt_plan(const adg_instance_desc *desc, const double *eta, doub
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Linear variant: elastic waves with the Cauchy-Kowalevski predictor
+// ---------------------------------------------------------------------------
+
+struct adg_lin {
+    int device = 0;
+    int N = 0;
+    int n[3] = {0, 0, 0};
+    double inv_dx[3] = {0, 0, 0};
+    double cfl = 0.0;
+    int64_t nc = 0;
+    double *dt_dev = nullptr;
+};
+
+namespace {
+
+bool valid_lin(const adg_lin *l) { return l && l->nc > 0 && l->dt_dev; }
+
+size_t lin_u_elems(const adg_lin *l) { return size_t(9) * size_t(l->nc) * size_t(l->N * l->N * l->N); }
+size_t lin_trace_elems(const adg_lin *l) { return size_t(6 * 2 * 9) * size_t(l->nc) * size_t(l->N * l->N); }
+size_t lin_fside_elems(const adg_lin *l) { return size_t(6 * 9) * size_t(l->nc) * size_t(l->N * l->N); }
+
+adg_status lin_dt(adg_lin *l, const double *material, hipStream_t st)
+{
+    const double sum_inv = l->inv_dx[0] + l->inv_dx[1] + l->inv_dx[2];
+    const double factor = l->cfl / ((2.0 * (l->N - 1) + 1.0) * sum_inv);
+    ADG_HIP(launch_lin_cfl(material, l->nc, factor, l->dt_dev, st), "linear time step");
+    return ADG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+adg_status adg_lin_init(const adg_lin_desc *desc, adg_lin **out)
+{
+    if (!desc || !out) {
+        set_error("adg_lin_init: null argument");
+        return ADG_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    if (desc->order < 0 || desc->order > 6) {
+        set_error("adg_lin_init: order must be in [0, 6]");
+        return ADG_ERR_UNSUPPORTED;
+    }
+    for (int a = 0; a < 3; ++a)
+        if (desc->n[a] < 1 || !(desc->hi[a] > desc->lo[a])) {
+            set_error("adg_lin_init: need n >= 1 and hi > lo on every axis");
+            return ADG_ERR_INVALID_ARG;
+        }
+    if (!(desc->cfl > 0.0)) {
+        set_error("adg_lin_init: cfl must be > 0");
+        return ADG_ERR_INVALID_ARG;
+    }
+    const int64_t nc = int64_t(desc->n[0]) * desc->n[1] * desc->n[2];
+    if (nc * (desc->order + 1) * (desc->order + 1) >= (int64_t(1) << 31) / 2) {
+        set_error("adg_lin_init: mesh too large for one launch");
+        return ADG_ERR_UNSUPPORTED;
+    }
+    int dev = 0;
+    ADG_HIP(hipGetDevice(&dev), "get device");
+    adg_status bs = ensure_basis(dev);
+    if (bs != ADG_OK) return bs;
+    auto *l = new adg_lin;
+    l->device = dev;
+    l->N = desc->order + 1;
+    l->nc = nc;
+    l->cfl = desc->cfl;
+    for (int a = 0; a < 3; ++a) {
+        l->n[a] = desc->n[a];
+        l->inv_dx[a] = desc->n[a] / (desc->hi[a] - desc->lo[a]);
+    }
+    if (hipMalloc(&l->dt_dev, sizeof(double)) != hipSuccess) {
+        delete l;
+        set_error("adg_lin_init: device allocation failed");
+        return ADG_ERR_OOM;
+    }
+    *out = l;
+    return ADG_OK;
+}
+
+adg_status adg_lin_free(adg_lin *lin)
+{
+    if (!lin) return ADG_OK;
+    if (lin->dt_dev) (void)hipFree(lin->dt_dev);
+    delete lin;
+    return ADG_OK;
+}
+
+adg_status adg_lin_info(adg_lin *lin, int64_t *n_cells, int64_t *u_elems, int64_t *trace_elems, int64_t *fside_elems,
+                        int64_t *workspace_bytes)
+{
+    if (!valid_lin(lin)) return ADG_ERR_INVALID_ARG;
+    if (n_cells) *n_cells = lin->nc;
+    if (u_elems) *u_elems = int64_t(lin_u_elems(lin));
+    if (trace_elems) *trace_elems = int64_t(lin_trace_elems(lin));
+    if (fside_elems) *fside_elems = int64_t(lin_fside_elems(lin));
+    if (workspace_bytes)
+        *workspace_bytes = int64_t(align_up(sizeof(double) * lin_u_elems(lin)) +
+                                   align_up(sizeof(double) * lin_trace_elems(lin)) +
+                                   align_up(sizeof(double) * lin_fside_elems(lin)));
+    return ADG_OK;
+}
+
+adg_status adg_lin_dt(adg_lin *lin, const double *material, double *dt_dev, hipStream_t stream)
+{
+    if (!valid_lin(lin) || !material || !dt_dev) {
+        set_error("adg_lin_dt: null argument");
+        return ADG_ERR_INVALID_ARG;
+    }
+    adg_status s = lin_dt(lin, material, stream);
+    if (s != ADG_OK) return s;
+    ADG_HIP(hipMemcpyAsync(dt_dev, lin->dt_dev, sizeof(double), hipMemcpyDeviceToDevice, stream), "dt copy");
+    return ADG_OK;
+}
+
+adg_status adg_lin_predictor(adg_lin *lin, const double *material, const double *u, const double *dt_dev,
+                             double *ustar, double *traces, hipStream_t stream)
+{
+    if (!valid_lin(lin) || !material || !u || !dt_dev || !ustar || !traces) {
+        set_error("adg_lin_predictor: null argument");
+        return ADG_ERR_INVALID_ARG;
+    }
+    ADG_HIP(launch_lin_predictor(lin->N, u, material, dt_dev, ustar, traces, lin->nc, lin->inv_dx, stream),
+            "linear predictor");
+    return ADG_OK;
+}
+
+adg_status adg_lin_step(adg_lin *lin, const double *material, double *u, int32_t n_steps, double *dt_out, void *ws,
+                        hipStream_t stream)
+{
+    if (!valid_lin(lin) || !material || !u || !ws || n_steps < 0) {
+        set_error("adg_lin_step: null argument or n_steps < 0");
+        return ADG_ERR_INVALID_ARG;
+    }
+    char *w = static_cast<char *>(ws);
+    double *ustar = reinterpret_cast<double *>(w);
+    w += align_up(sizeof(double) * lin_u_elems(lin));
+    double *traces = reinterpret_cast<double *>(w);
+    w += align_up(sizeof(double) * lin_trace_elems(lin));
+    double *fside = reinterpret_cast<double *>(w);
+    adg_status s = lin_dt(lin, material, stream);
+    if (s != ADG_OK) return s;
+    for (int32_t k = 0; k < n_steps; ++k) {
+        ADG_HIP(launch_lin_predictor(lin->N, u, material, lin->dt_dev, ustar, traces, lin->nc, lin->inv_dx, stream),
+                "linear predictor");
+        ADG_HIP(launch_lin_riemann(lin->N, traces, material, fside, lin->nc, lin->n, stream), "linear riemann");
+        ADG_HIP(launch_lin_corrector(lin->N, ustar, fside, lin->dt_dev, u, lin->nc, lin->inv_dx, stream),
+                "linear corrector");
+    }
+    if (dt_out) ADG_HIP(hipMemcpyAsync(dt_out, lin->dt_dev, sizeof(double), hipMemcpyDeviceToDevice, stream), "dt copy");
+    return ADG_OK;
+}
+
+}  // extern "C"

@@ -145,6 +145,16 @@ template <typename T>
 hipError_t launch_lim_recorrect(int N, const double *ustar, const T *fside, double *u, int64_t nc, const Geo &geo,
                                 const double *dt, const LimDev &L, hipStream_t st);
 
+// Linear variant (elastic waves, 9 unknowns, uniform periodic mesh, FP64).
+// mat: [3][nc] (rho, lambda, mu); factor = cfl / ((2p+1) sum_d 1/dx_d).
+hipError_t launch_lin_cfl(const double *mat, int64_t nc, double factor, double *dt, hipStream_t st);
+hipError_t launch_lin_predictor(int N, const double *u, const double *mat, const double *dt, double *ustar,
+                                double *traces, int64_t nc, const double inv_dx[3], hipStream_t st);
+hipError_t launch_lin_riemann(int N, const double *traces, const double *mat, double *fside, int64_t nc,
+                              const int n[3], hipStream_t st);
+hipError_t launch_lin_corrector(int N, const double *ustar, const double *fside, const double *dt, double *u,
+                                int64_t nc, const double inv_dx[3], hipStream_t st);
+
 int cfl_blocks(int N, int64_t nc);
 // factor = cfl / (2p + 1); writes dt_out[0] (and hist[0] if not null)
 hipError_t launch_cfl(int N, const double *u, int64_t nc, const int8_t *level, const Geo &geo, double gamma,

@@ -2415,6 +2415,237 @@ k_lim_recorrect(const double *__restrict__ ustar, const T *__restrict__ fside, c
 }
 
 // ---------------------------------------------------------------------------
+// Linear variant: elastic waves with the Cauchy-Kowalevski predictor
+// ---------------------------------------------------------------------------
+// 9 unknowns (s_xx, s_yy, s_zz, s_xy, s_yz, s_xz, v_x, v_y, v_z), material
+// (rho, lambda, mu) constant per cell, flux A_d q.  Uniform periodic meshes
+// (neighbours by index arithmetic), FP64.  The predictor keeps the k-th time
+// derivative L^k u of every node in LDS for the derivative contractions and
+// accumulates qbar = sum_k dt^k/(k+1)! L^k u in registers; L lowers the
+// polynomial degree and is applied p times.
+
+constexpr int NLV = 9;
+enum { LSXX = 0, LSYY, LSZZ, LSXY, LSYZ, LSXZ, LVX, LVY, LVZ };
+
+// f = A_d q (lam2 = lambda + 2 mu, irho = 1/rho)
+__device__ __forceinline__ void lin_flux(int d, double lam, double mu, double lam2, double irho, const double q[NLV],
+                                         double f[NLV])
+{
+    if (d == 0) {
+        f[LSXX] = -lam2 * q[LVX];
+        f[LSYY] = -lam * q[LVX];
+        f[LSZZ] = -lam * q[LVX];
+        f[LSXY] = -mu * q[LVY];
+        f[LSYZ] = 0.0;
+        f[LSXZ] = -mu * q[LVZ];
+        f[LVX] = -q[LSXX] * irho;
+        f[LVY] = -q[LSXY] * irho;
+        f[LVZ] = -q[LSXZ] * irho;
+    } else if (d == 1) {
+        f[LSXX] = -lam * q[LVY];
+        f[LSYY] = -lam2 * q[LVY];
+        f[LSZZ] = -lam * q[LVY];
+        f[LSXY] = -mu * q[LVX];
+        f[LSYZ] = -mu * q[LVZ];
+        f[LSXZ] = 0.0;
+        f[LVX] = -q[LSXY] * irho;
+        f[LVY] = -q[LSYY] * irho;
+        f[LVZ] = -q[LSYZ] * irho;
+    } else {
+        f[LSXX] = -lam * q[LVZ];
+        f[LSYY] = -lam * q[LVZ];
+        f[LSZZ] = -lam2 * q[LVZ];
+        f[LSXY] = 0.0;
+        f[LSYZ] = -mu * q[LVY];
+        f[LSXZ] = -mu * q[LVX];
+        f[LVX] = -q[LSXZ] * irho;
+        f[LVY] = -q[LSYZ] * irho;
+        f[LVZ] = -q[LSZZ] * irho;
+    }
+}
+
+// One block per cell, one thread per node.
+template <int N>
+__global__ void __launch_bounds__(round64(N * N * N))
+k_lin_predictor(const double *__restrict__ u, const double *__restrict__ mat, const double *__restrict__ dt_dev,
+                double *__restrict__ ustar, double *__restrict__ traces, int64_t nc, double idx0, double idx1,
+                double idx2)
+{
+    constexpr int N2 = N * N, N3 = N2 * N;
+    __shared__ double dk[NLV * N3];
+    const DevBasis &B = c_basis[N];
+    const int64_t c = blockIdx.x;
+    const int a = threadIdx.x;
+    const bool node = a < N3;
+    const int aa[3] = {a % N, (a / N) % N, a / N2};
+    const double rho = mat[c], lam = mat[nc + c], mu = mat[2 * nc + c];
+    const double lam2 = lam + 2.0 * mu, irho = 1.0 / rho;
+    const double idx[3] = {idx0, idx1, idx2};
+    const double dt = dt_dev[0];
+    double uc[NLV], qbar[NLV];
+#pragma unroll
+    for (int v = 0; v < NLV; ++v) {
+        uc[v] = node ? u[(int64_t(v) * nc + c) * N3 + a] : 0.0;
+        qbar[v] = uc[v];
+        if (node) dk[v * N3 + a] = uc[v];
+    }
+    __syncthreads();
+    double fac = 1.0;
+    for (int k = 1; k < N; ++k) {
+        // L dk at this node: -sum_d (1/dx_d) A_d (D_d dk)
+        double nd[NLV] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        if (node)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const int stride = d == 0 ? 1 : (d == 1 ? N : N2);
+                const int base = a - aa[d] * stride;
+                double g[NLV];
+#pragma unroll
+                for (int v = 0; v < NLV; ++v) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int e = 0; e < N; ++e) s = fma(B.D[aa[d] * N + e], dk[v * N3 + base + e * stride], s);
+                    g[v] = s;
+                }
+                double f[NLV];
+                lin_flux(d, lam, mu, lam2, irho, g, f);
+#pragma unroll
+                for (int v = 0; v < NLV; ++v) nd[v] = fma(-idx[d], f[v], nd[v]);
+            }
+        __syncthreads();
+        fac *= dt / (k + 1);
+#pragma unroll
+        for (int v = 0; v < NLV; ++v) {
+            if (node) dk[v * N3 + a] = nd[v];
+            qbar[v] = fma(fac, nd[v], qbar[v]);
+        }
+        __syncthreads();
+    }
+    // qbar into LDS for the volume term and the face projections
+#pragma unroll
+    for (int v = 0; v < NLV; ++v)
+        if (node) dk[v * N3 + a] = qbar[v];
+    __syncthreads();
+    if (!node) return;
+    // volume term: u + sum_d (dt/dx_d) (1/w) A_d (Kw_d qbar)
+    double us[NLV];
+#pragma unroll
+    for (int v = 0; v < NLV; ++v) us[v] = uc[v];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int stride = d == 0 ? 1 : (d == 1 ? N : N2);
+        const int base = a - aa[d] * stride;
+        double g[NLV], f[NLV];
+#pragma unroll
+        for (int v = 0; v < NLV; ++v) {
+            double s = 0.0;
+#pragma unroll
+            for (int e = 0; e < N; ++e) s = fma(B.Kw[aa[d] * N + e], dk[v * N3 + base + e * stride], s);
+            g[v] = s;
+        }
+        lin_flux(d, lam, mu, lam2, irho, g, f);
+        const double sc = dt * idx[d] * B.winv[aa[d]];
+#pragma unroll
+        for (int v = 0; v < NLV; ++v) us[v] = fma(sc, f[v], us[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < NLV; ++v) ustar[(int64_t(v) * nc + c) * N3 + a] = us[v];
+    // face projections: threads with a_d = 0 write side 2d, a_d = N-1 side 2d+1
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int stride = d == 0 ? 1 : (d == 1 ? N : N2);
+        const int base = a - aa[d] * stride;
+        const int b = d == 0 ? aa[1] + N * aa[2] : (d == 1 ? aa[0] + N * aa[2] : aa[0] + N * aa[1]);
+        for (int plus = 0; plus < 2; ++plus) {
+            if (aa[d] != (plus ? N - 1 : 0)) continue;
+            const double *E = plus ? B.R : B.L;
+            double qf[NLV], f[NLV];
+#pragma unroll
+            for (int v = 0; v < NLV; ++v) {
+                double s = 0.0;
+#pragma unroll
+                for (int e = 0; e < N; ++e) s = fma(E[e], dk[v * N3 + base + e * stride], s);
+                qf[v] = s;
+            }
+            lin_flux(d, lam, mu, lam2, irho, qf, f);
+            const int side = 2 * d + plus;
+#pragma unroll
+            for (int v = 0; v < NLV; ++v) {
+                traces[((int64_t(side * 2 + 0) * NLV + v) * nc + c) * N2 + b] = qf[v];
+                traces[((int64_t(side * 2 + 1) * NLV + v) * nc + c) * N2 + b] = f[v];
+            }
+        }
+    }
+}
+
+// Rusanov on the +d faces: thread per (cell, face node); both sides written.
+template <int N>
+__global__ void __launch_bounds__(256)
+k_lin_riemann(const double *__restrict__ traces, const double *__restrict__ mat, double *__restrict__ fside, int64_t nc,
+              int d, int n0, int n1, int n2)
+{
+    constexpr int N2 = N * N;
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= nc * N2) return;
+    const int64_t c = t / N2;
+    const int b = int(t % N2);
+    const int64_t i = c % n0, j = (c / n0) % n1, k = c / (int64_t(n0) * n1);
+    const int64_t cp = d == 0 ? ((i + 1) % n0) + n0 * (j + int64_t(n1) * k)
+                              : (d == 1 ? i + n0 * (((j + 1) % n1) + int64_t(n1) * k)
+                                        : i + n0 * (j + int64_t(n1) * ((k + 1) % n2)));
+    const double sl = sqrt((mat[nc + c] + 2.0 * mat[2 * nc + c]) / mat[c]);
+    const double sr = sqrt((mat[nc + cp] + 2.0 * mat[2 * nc + cp]) / mat[cp]);
+    const double s = fmax(sl, sr);
+    const int side_l = 2 * d + 1, side_r = 2 * d;
+#pragma unroll
+    for (int v = 0; v < NLV; ++v) {
+        const double QL = traces[((int64_t(side_l * 2 + 0) * NLV + v) * nc + c) * N2 + b];
+        const double FL = traces[((int64_t(side_l * 2 + 1) * NLV + v) * nc + c) * N2 + b];
+        const double QR = traces[((int64_t(side_r * 2 + 0) * NLV + v) * nc + cp) * N2 + b];
+        const double FR = traces[((int64_t(side_r * 2 + 1) * NLV + v) * nc + cp) * N2 + b];
+        const double F = 0.5 * (FL + FR) - 0.5 * s * (QR - QL);
+        fside[(int64_t(side_l * NLV + v) * nc + c) * N2 + b] = F;
+        fside[(int64_t(side_r * NLV + v) * nc + cp) * N2 + b] = F;
+    }
+}
+
+template <int N>
+__global__ void __launch_bounds__(256)
+k_lin_corrector(const double *__restrict__ ustar, const double *__restrict__ fside, const double *__restrict__ dt_dev,
+                double *__restrict__ u, int64_t nc, double idx0, double idx1, double idx2)
+{
+    constexpr int N2 = N * N, N3 = N2 * N;
+    const DevBasis &B = c_basis[N];
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= nc * N3) return;
+    const int64_t c = t / N3;
+    const int a = int(t % N3), a0 = a % N, a1 = (a / N) % N, a2 = a / N2;
+    const double dt = dt_dev[0];
+    const double sx = dt * idx0 * B.winv[a0], sy = dt * idx1 * B.winv[a1], sz = dt * idx2 * B.winv[a2];
+    const int bx = a1 + N * a2, by = a0 + N * a2, bz = a0 + N * a1;
+#pragma unroll
+    for (int v = 0; v < NLV; ++v) {
+        auto F = [&](int side, int b) { return fside[(int64_t(side * NLV + v) * nc + c) * N2 + b]; };
+        const double s = sx * (B.R[a0] * F(1, bx) - B.L[a0] * F(0, bx)) + sy * (B.R[a1] * F(3, by) - B.L[a1] * F(2, by)) +
+                         sz * (B.R[a2] * F(5, bz) - B.L[a2] * F(4, bz));
+        const int64_t o = (int64_t(v) * nc + c) * N3 + a;
+        u[o] = ustar[o] - s;
+    }
+}
+
+// dt = factor / max_c c_p(c) (one block); factor = cfl / ((2p+1) sum_d 1/dx_d)
+__global__ void __launch_bounds__(1024)
+k_lin_cfl(const double *__restrict__ mat, int64_t nc, double factor, double *__restrict__ dt_out)
+{
+    __shared__ double sh[16];
+    double m = 0.0;
+    for (int64_t c = threadIdx.x; c < nc; c += blockDim.x)
+        m = fmax(m, sqrt((mat[nc + c] + 2.0 * mat[2 * nc + c]) / mat[c]));
+    m = block_max(m, sh);
+    if (threadIdx.x == 0) dt_out[0] = (m > 0.0 && m < INFINITY) ? factor / m : 0.0;
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 
@@ -2870,6 +3101,48 @@ hipError_t launch_lim_recorrect(int N, const double *ustar, const T *fside, doub
     ADG_DISPATCH_N(N, {
         hipLaunchKernelGGL((k_lim_recorrect<T, NN>), dim3(LIM_GRID), dim3(round64(NN * NN * NN)), 0, st, ustar, fside,
                            dt, u, nc, geo, L.rlist, L.cnt);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_lin_cfl(const double *mat, int64_t nc, double factor, double *dt, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_lin_cfl, dim3(1), dim3(1024), 0, st, mat, nc, factor, dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_lin_predictor(int N, const double *u, const double *mat, const double *dt, double *ustar,
+                                double *traces, int64_t nc, const double inv_dx[3], hipStream_t st)
+{
+    if (nc <= 0) return hipSuccess;
+    ADG_DISPATCH_N(N, {
+        hipLaunchKernelGGL((k_lin_predictor<NN>), dim3(unsigned(nc)), dim3(round64(NN * NN * NN)), 0, st, u, mat, dt,
+                           ustar, traces, nc, inv_dx[0], inv_dx[1], inv_dx[2]);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_lin_riemann(int N, const double *traces, const double *mat, double *fside, int64_t nc,
+                              const int n[3], hipStream_t st)
+{
+    if (nc <= 0) return hipSuccess;
+    ADG_DISPATCH_N(N, {
+        const int64_t work = nc * NN * NN;
+        for (int d = 0; d < 3; ++d)
+            hipLaunchKernelGGL((k_lin_riemann<NN>), dim3(unsigned((work + 255) / 256)), dim3(256), 0, st, traces, mat,
+                               fside, nc, d, n[0], n[1], n[2]);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_lin_corrector(int N, const double *ustar, const double *fside, const double *dt, double *u,
+                                int64_t nc, const double inv_dx[3], hipStream_t st)
+{
+    if (nc <= 0) return hipSuccess;
+    ADG_DISPATCH_N(N, {
+        const int64_t work = nc * NN * NN * NN;
+        hipLaunchKernelGGL((k_lin_corrector<NN>), dim3(unsigned((work + 255) / 256)), dim3(256), 0, st, ustar, fside,
+                           dt, u, nc, inv_dx[0], inv_dx[1], inv_dx[2]);
     });
     return hipGetLastError();
 }
