@@ -289,6 +289,66 @@ def run_limiter(A, steps=20, warmup=2):
     return out
 
 
+def run_linear(A, steps=20, warmup=2):
+    """Linear variant: elastic waves, uniform periodic 81^3 mesh, p = 3,
+    Cauchy-Kowalevski predictor, FP64.  Synthetic layered medium (a softer
+    layer, rho, lambda, mu = 2.0, 2.0, 1.0, for z > 0.75 over rho, lambda,
+    mu = 2.7, 4.0, 2.0) and a Gaussian velocity pulse of width 0.05 at the
+    centre (stands in for the point-source benchmark, whose data are not
+    here).  Timed with events around `steps` steps."""
+    import torch
+    n = (N_BASE,) * 3
+    p = ORDER
+    N = p + 1
+    lm = A.LinMesh(p, n)
+    nc = lm.info["n_cells"]
+    c = torch.arange(nc, device="cuda")
+    k = c // (n[0] * n[1])
+    soft = (k + 0.5) / n[2] > 0.75
+    def layered(top, below):
+        return torch.where(soft, torch.tensor(top, dtype=torch.float64, device="cuda"),
+                           torch.tensor(below, dtype=torch.float64, device="cuda"))
+    mat = torch.stack([layered(2.0, 2.7), layered(2.0, 4.0), layered(1.0, 2.0)]).contiguous()
+    xi = torch.tensor(_gl_nodes(N), device="cuda")
+    i, j = c % n[0], (c // n[0]) % n[1]
+
+    def coord(idx, m):
+        return (idx[:, None] + xi[None, :]) / m
+    x = coord(i, n[0])[:, None, None, :].expand(nc, N, N, N).reshape(nc, -1)
+    y = coord(j, n[1])[:, None, :, None].expand(nc, N, N, N).reshape(nc, -1)
+    z = coord(k, n[2])[:, :, None, None].expand(nc, N, N, N).reshape(nc, -1)
+    r2 = (x - 0.5) ** 2 + (y - 0.5) ** 2 + (z - 0.5) ** 2
+    u = torch.zeros(9, nc, N ** 3, dtype=torch.float64, device="cuda")
+    pulse = torch.exp(-r2 / 0.05 ** 2)
+    u[6], u[7], u[8] = pulse, 0.5 * pulse, -0.25 * pulse
+    del x, y, z, r2, pulse
+    ws = lm.empty_workspace()
+    lm.step(mat, u, warmup, ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    lm.step(mat, u, steps, ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    assert torch.isfinite(u).all().item()
+    dofs = 9 * nc * N ** 3
+    out = {"workload": "elastic_p3_81cubed_layered", "value": dofs * 1e3 / ms, "unit": "DoF-updates/s",
+           "ms_per_step": ms, "steps": steps, "cells": nc, "dofs": dofs, "path": "fp64, Cauchy-Kowalevski",
+           "predictor_bytes_per_cell": 9 * N ** 3 * 8 * 2 + 24 + 6 * 2 * 9 * N * N * 8}
+    lm.close()
+    del u, ws, mat
+    torch.cuda.empty_cache()
+    return out
+
+
+def _gl_nodes(N):
+    """Gauss-Legendre nodes on [0, 1] (numpy), for placing the pulse."""
+    import numpy as np
+    x, _ = np.polynomial.legendre.leggauss(N)
+    return (x + 1.0) / 2.0
+
+
 def run_adjoint(A, n=27, steps=20, k=5, n_pts=512):
     """Differentiation workload: 27^3 cells, p = 3, FP64, 20 steps; loss =
     sampled density misfit at 512 seeded points; gradient with respect to
@@ -335,7 +395,7 @@ def main():
     ap.add_argument("--only", choices=["fp64", "fp32"], default=None,
                     help="run one path only (for profiling runs)")
     ap.add_argument("--no-extra", action="store_true", help="skip the AMR and batch workloads")
-    ap.add_argument("--extra-only", choices=["amr", "batch", "adjoint", "limiter"], default=None,
+    ap.add_argument("--extra-only", choices=["amr", "batch", "adjoint", "limiter", "linear"], default=None,
                     help="run only one of the other workloads and print its JSON (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB buffer 3 times (calibrates HBM byte counters) and exit")
@@ -360,7 +420,7 @@ def main():
     A.load()
     if args.extra_only:
         res = {"amr": run_amr, "batch": run_batch, "adjoint": run_adjoint,
-               "limiter": run_limiter}[args.extra_only](A)
+               "limiter": run_limiter, "linear": run_linear}[args.extra_only](A)
         print(json.dumps({"workload": args.extra_only, **res}))
         return
     # initial state: node coordinates from the library, analytic state + seeded noise on the host
@@ -409,7 +469,8 @@ def main():
         out["other_workloads"] = {"amr_blast_p4_27cubed_2levels": run_amr(A),
                                   "batch64_p2to6_seed0": run_batch(A),
                                   "adjoint_p3_27cubed_20steps": run_adjoint(A),
-                                  "limiter_blast_p3_81cubed": run_limiter(A)}
+                                  "limiter_blast_p3_81cubed": run_limiter(A),
+                                  "elastic_p3_81cubed_layered": run_linear(A)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))
