@@ -2464,21 +2464,30 @@ __device__ __forceinline__ void lin_flux(int d, double lam, double mu, double la
     }
 }
 
-// One block per cell, one thread per node.
+// Cells per block of the elastic predictor: CPB cells of N^3 threads each.
+template <int N> struct LinCfg {
+    static constexpr int N3 = N * N * N;
+    static constexpr int CPB = N3 >= 256 ? 1 : 256 / N3;
+    static constexpr int THREADS = round64(CPB * N3);
+};
+
+// CPB cells per block, one thread per node.
 template <int N>
-__global__ void __launch_bounds__(round64(N * N * N))
+__global__ void __launch_bounds__(LinCfg<N>::THREADS)
 k_lin_predictor(const double *__restrict__ u, const double *__restrict__ mat, const double *__restrict__ dt_dev,
                 double *__restrict__ ustar, double *__restrict__ traces, int64_t nc, double idx0, double idx1,
                 double idx2)
 {
-    constexpr int N2 = N * N, N3 = N2 * N;
-    __shared__ double dk[NLV * N3];
+    constexpr int N2 = N * N, N3 = N2 * N, CPB = LinCfg<N>::CPB;
+    __shared__ double lds[CPB * NLV * N3];
     const DevBasis &B = c_basis[N];
-    const int64_t c = blockIdx.x;
-    const int a = threadIdx.x;
-    const bool node = a < N3;
+    const int lc = threadIdx.x / N3, a = threadIdx.x % N3;
+    const int64_t c = int64_t(blockIdx.x) * CPB + lc;
+    const bool node = lc < CPB && c < nc;
+    double *dk = lds + (lc < CPB ? lc : 0) * NLV * N3;
     const int aa[3] = {a % N, (a / N) % N, a / N2};
-    const double rho = mat[c], lam = mat[nc + c], mu = mat[2 * nc + c];
+    const int64_t cm = node ? c : 0;
+    const double rho = mat[cm], lam = mat[nc + cm], mu = mat[2 * nc + cm];
     const double lam2 = lam + 2.0 * mu, irho = 1.0 / rho;
     const double idx[3] = {idx0, idx1, idx2};
     const double dt = dt_dev[0];
@@ -3116,8 +3125,9 @@ hipError_t launch_lin_predictor(int N, const double *u, const double *mat, const
 {
     if (nc <= 0) return hipSuccess;
     ADG_DISPATCH_N(N, {
-        hipLaunchKernelGGL((k_lin_predictor<NN>), dim3(unsigned(nc)), dim3(round64(NN * NN * NN)), 0, st, u, mat, dt,
-                           ustar, traces, nc, inv_dx[0], inv_dx[1], inv_dx[2]);
+        constexpr int CPB = LinCfg<NN>::CPB;
+        hipLaunchKernelGGL((k_lin_predictor<NN>), dim3(unsigned((nc + CPB - 1) / CPB)), dim3(LinCfg<NN>::THREADS), 0,
+                           st, u, mat, dt, ustar, traces, nc, inv_dx[0], inv_dx[1], inv_dx[2]);
     });
     return hipGetLastError();
 }
