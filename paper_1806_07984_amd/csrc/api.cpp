@@ -855,6 +855,23 @@ adg_status autotune_impl(adg_mesh *m, const double *u, void *ws, hipStream_t st)
 
 using namespace adg;
 
+namespace {
+// Makes `device` current for the lifetime of the guard and then restores the
+// caller's current device.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int device)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != device) (void)hipSetDevice(device);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+}  // namespace
+
 extern "C" {
 
 const char *adg_last_error(void) { return g_last_error.c_str(); }
@@ -1256,7 +1273,7 @@ adg_status adg_set_limiter(adg_mesh *mesh, int32_t mode, double delta0, double e
         set_error("adg_set_limiter: the limiter needs a single instance on a uniform mesh with p <= 6");
         return ADG_ERR_UNSUPPORTED;
     }
-    ADG_HIP(hipSetDevice(mesh->device), "set device");
+    DeviceGuard dg(mesh->device);
     ADG_HIP(hipDeviceSynchronize(), "synchronize");
     if (mode && !mesh->lim.uold) {
         Instance &I = mesh->inst[0];
@@ -1578,7 +1595,7 @@ adg_status adg_transfer(const adg_mesh *from, const double *u_from, adg_mesh *to
     }
     VOp *ops_dev = nullptr;
     VKid *kids_dev = nullptr;
-    ADG_HIP(hipSetDevice(to->device), "set device");
+    DeviceGuard dg(to->device);
     ADG_HIP(hipMalloc(&ops_dev, sizeof(VOp) * ops.size()), "transfer table");
     hipError_t e = hipMalloc(&kids_dev, sizeof(VKid) * std::max<size_t>(1, kids.size()));
     if (e == hipSuccess) e = hipMemcpyAsync(ops_dev, ops.data(), sizeof(VOp) * ops.size(), hipMemcpyHostToDevice,
