@@ -265,8 +265,8 @@ adg_status adg_profile_read(adg_mesh *mesh, double *ms, int64_t *launches);
  * maximiser in (node, minus side first) order; |x|' = 0 at 0), then the
  * predictor (time averages, volume term and face projections, then the
  * Picard iterations in reverse, with the forward iterates recomputed and
- * stored in ws_dev).  FP64 handles with uniform meshes only
- * (ADG_ERR_UNSUPPORTED otherwise).  ws_dev holds adjoint_workspace_bytes;
+ * stored in ws_dev).  FP64 handles with uniform meshes and the limiter off
+ * only (ADG_ERR_UNSUPPORTED otherwise).  ws_dev holds adjoint_workspace_bytes;
  * ubar_n_dev must not alias ubar_np1_dev. */
 adg_status adg_step_adjoint(adg_mesh *mesh, const double *u_n_dev, const double *dt_dev,
                             const double *ubar_np1_dev, double *ubar_n_dev, void *ws_dev,

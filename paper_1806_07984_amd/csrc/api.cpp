@@ -1385,6 +1385,10 @@ adg_status adg_step_adjoint(adg_mesh *mesh, const double *u, const double *dt, c
         set_error("adg_step_adjoint: needs an FP64 handle");
         return ADG_ERR_UNSUPPORTED;
     }
+    if (mesh->lim_mode) {
+        set_error("adg_step_adjoint: the adjoint is that of the unlimited step; switch the limiter off");
+        return ADG_ERR_UNSUPPORTED;
+    }
     for (const auto &I : mesh->inst)
         if (I.hm.max_level > 0) {
             set_error("adg_step_adjoint: adaptive meshes are not supported");

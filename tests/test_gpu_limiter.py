@@ -163,6 +163,14 @@ def test_refusals():
         assert e.value.code == 1  # INVALID_ARG
     with pytest.raises(A.AdgError):
         one.limiter_stats()  # never enabled
+    # the adjoint is that of the unlimited step: refused while the limiter is on
+    one.set_limiter(1)
+    u = torch.ones(one.info["u_elems"], dtype=torch.float64, device="cuda")
+    dt = torch.full((1,), 1e-3, dtype=torch.float64, device="cuda")
+    ws = torch.empty(one.info["adjoint_workspace_bytes"], dtype=torch.uint8, device="cuda")
+    with pytest.raises(A.AdgError) as e:
+        one.step_adjoint(u, dt, u.clone(), torch.empty_like(u), ws)
+    assert e.value.code == 2  # UNSUPPORTED
     for m in (amr, p7, two, one):
         m.close()
 
