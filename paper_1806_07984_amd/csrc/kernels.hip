@@ -1742,38 +1742,65 @@ k_vtransfer(const double *__restrict__ uf, int64_t ncf, double *__restrict__ ut,
             const VOp *__restrict__ ops, const VKid *__restrict__ kids, const double *__restrict__ ptab)
 {
     constexpr int N2 = N * N, N3 = N2 * N;
+    __shared__ double src[NV * N3], t1[NV * N3], t2[NV * N3];
     const int64_t c = blockIdx.x;
     const int a = threadIdx.x;
-    if (a >= N3) return;
+    const bool node = a < N3;
     const VOp op = ops[c];
     const int aa[3] = {a % N, (a / N) % N, a / N2};
     double acc[NV] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (op.kind == 0) {
+        if (node)
 #pragma unroll
-        for (int v = 0; v < NV; ++v) acc[v] = uf[(int64_t(v) * ncf + op.src) * N3 + a];
+            for (int v = 0; v < NV; ++v) acc[v] = uf[(int64_t(v) * ncf + op.src) * N3 + a];
     } else {
+        // the tensor product M0 x M1 x M2 of one source cell applied axis by
+        // axis (x, then y, then z), accumulated over the source cells
         const int n = op.kind == 1 ? 1 : op.nkid;
         for (int t = 0; t < n; ++t) {
-            int64_t src;
+            int64_t sc;
             int dl, sp[3], half;
             if (op.kind == 1) {
-                src = op.src; dl = op.dl; sp[0] = op.s[0]; sp[1] = op.s[1]; sp[2] = op.s[2]; half = 0;
+                sc = op.src; dl = op.dl; sp[0] = op.s[0]; sp[1] = op.s[1]; sp[2] = op.s[2]; half = 0;
             } else {
                 const VKid k = kids[op.kid0 + t];
-                src = k.cell; dl = k.dl; sp[0] = k.s[0]; sp[1] = k.s[1]; sp[2] = k.s[2]; half = N2;
+                sc = k.cell; dl = k.dl; sp[0] = k.s[0]; sp[1] = k.s[1]; sp[2] = k.s[2]; half = N2;
             }
             const double *M[3];
 #pragma unroll
             for (int d = 0; d < 3; ++d) M[d] = ptab + int64_t(transfer_base(dl) + sp[d]) * 2 * N2 + half;
-            for (int b = 0; b < N3; ++b) {
-                const double wgt = M[0][aa[0] * N + b % N] * M[1][aa[1] * N + (b / N) % N] * M[2][aa[2] * N + b / N2];
+            for (int i = a; i < NV * N3; i += blockDim.x) src[i] = uf[(int64_t(i / N3) * ncf + sc) * N3 + i % N3];
+            __syncthreads();
+            for (int i = a; i < NV * N3; i += blockDim.x) {
+                const int v = i / N3, r = i % N3, o0 = r % N, b12 = r / N;
+                double s = 0.0;
 #pragma unroll
-                for (int v = 0; v < NV; ++v) acc[v] += wgt * uf[(int64_t(v) * ncf + src) * N3 + b];
+                for (int b0 = 0; b0 < N; ++b0) s += M[0][o0 * N + b0] * src[v * N3 + b0 + N * b12];
+                t1[i] = s;  // (o0, b1, b2)
             }
+            __syncthreads();
+            for (int i = a; i < NV * N3; i += blockDim.x) {
+                const int v = i / N3, r = i % N3, o0 = r % N, o1 = (r / N) % N, b2 = r / N2;
+                double s = 0.0;
+#pragma unroll
+                for (int b1 = 0; b1 < N; ++b1) s += M[1][o1 * N + b1] * t1[v * N3 + o0 + N * b1 + N2 * b2];
+                t2[i] = s;  // (o0, o1, b2)
+            }
+            __syncthreads();
+            if (node)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int b2 = 0; b2 < N; ++b2)
+                        s += M[2][aa[2] * N + b2] * t2[v * N3 + aa[0] + N * aa[1] + N2 * b2];
+                    acc[v] += s;
+                }
         }
     }
+    if (node)
 #pragma unroll
-    for (int v = 0; v < NV; ++v) ut[(int64_t(v) * nct + c) * N3 + a] = acc[v];
+        for (int v = 0; v < NV; ++v) ut[(int64_t(v) * nct + c) * N3 + a] = acc[v];
 }
 
 // ---------------------------------------------------------------------------
