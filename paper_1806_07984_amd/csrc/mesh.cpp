@@ -12,6 +12,7 @@
 //   * skeleton: cells on either side of a resolution transition (Sec. 3);
 //     enclave: the rest.
 #include <algorithm>
+#include <iterator>
 #include <cstdio>
 #include <unordered_map>
 
@@ -79,33 +80,65 @@ std::string build_host_mesh(const adg_instance_desc &d, HostMesh &m, bool leaves
         ref[k.l].push_back(k);
     }
 
-    // leaves as a hash set, level by level
-    std::unordered_map<uint64_t, char> leaves;
-    leaves.reserve(size_t(d.n[0]) * d.n[1] * d.n[2] * 2);
-    for (int k = 0; k < d.n[2]; ++k)
-        for (int j = 0; j < d.n[1]; ++j)
-            for (int i = 0; i < d.n[0]; ++i) leaves.emplace(pack(0, i, j, k), 1);
+    // Leaves level by level: level 0 is the base grid, level l+1 the children
+    // of the cells refined at level l, and each level loses its refined
+    // cells.  Every list is kept sorted by packed key, i.e. by (level, k, j, i),
+    // so the checks are binary searches, the removal is a merge, and the
+    // children are emitted in order (no hashing, no global sort).
+    auto ki = [](uint64_t p) { return int(p & 0xFFFFF); };
+    auto kj = [](uint64_t p) { return int((p >> 20) & 0xFFFFF); };
+    auto kk = [](uint64_t p) { return int((p >> 40) & 0xFFFFF); };
+    std::vector<std::vector<uint64_t>> rk(LMAX + 1);
     for (int l = 0; l < d.max_level; ++l) {
+        const int64_t ext[3] = {d.n[0] * pow3(l), d.n[1] * pow3(l), d.n[2] * pow3(l)};
+        rk[l].reserve(ref[l].size());
         for (const Key &k : ref[l]) {
-            int64_t ext[3] = {d.n[0] * pow3(l), d.n[1] * pow3(l), d.n[2] * pow3(l)};
             if (k.i < 0 || k.j < 0 || k.k < 0 || k.i >= ext[0] || k.j >= ext[1] || k.k >= ext[2])
                 return "refine row outside the grid";
-            auto it = leaves.find(pack(l, k.i, k.j, k.k));
-            if (it == leaves.end()) return "refine row names a cell that is not a leaf (or a duplicate)";
-            leaves.erase(it);
-            for (int c = 0; c < 3; ++c)
-                for (int b = 0; b < 3; ++b)
-                    for (int a = 0; a < 3; ++a)
-                        leaves.emplace(pack(l + 1, 3 * k.i + a, 3 * k.j + b, 3 * k.k + c), 1);
+            rk[l].push_back(pack(l, k.i, k.j, k.k));
         }
+        std::sort(rk[l].begin(), rk[l].end());
+        if (std::adjacent_find(rk[l].begin(), rk[l].end()) != rk[l].end())
+            return "refine row names a cell that is not a leaf (or a duplicate)";
+        if (l > 0)
+            for (uint64_t key : rk[l])
+                if (!std::binary_search(rk[l - 1].begin(), rk[l - 1].end(),
+                                        pack(l - 1, ki(key) / 3, kj(key) / 3, kk(key) / 3)))
+                    return "refine row names a cell that is not a leaf (or a duplicate)";
+    }
+    std::vector<uint64_t> all, lev, next;
+    lev.reserve(size_t(d.n[0]) * d.n[1] * d.n[2]);
+    for (int k = 0; k < d.n[2]; ++k)
+        for (int j = 0; j < d.n[1]; ++j)
+            for (int i = 0; i < d.n[0]; ++i) lev.push_back(pack(0, i, j, k));
+    for (int l = 0;; ++l) {
+        const std::vector<uint64_t> &r = rk[l];  // empty at max_level
+        std::set_difference(lev.begin(), lev.end(), r.begin(), r.end(), std::back_inserter(all));
+        if (l >= d.max_level) break;
+        // children of the refined cells, in (k, j, i) order: parents grouped by
+        // their k, then j; child rows 3 kp + c, 3 jp + b, then 3 ip + a
+        next.clear();
+        next.reserve(27 * r.size());
+        for (size_t p = 0; p < r.size();) {
+            size_t q = p;
+            while (q < r.size() && kk(r[q]) == kk(r[p])) ++q;
+            for (int c = 0; c < 3; ++c)
+                for (size_t s0 = p; s0 < q;) {
+                    size_t e = s0;
+                    while (e < q && kj(r[e]) == kj(r[s0])) ++e;
+                    for (int b = 0; b < 3; ++b)
+                        for (size_t t = s0; t < e; ++t)
+                            for (int a = 0; a < 3; ++a)
+                                next.push_back(pack(l + 1, 3 * ki(r[t]) + a, 3 * kj(r[t]) + b, 3 * kk(r[t]) + c));
+                    s0 = e;
+                }
+            p = q;
+        }
+        lev.swap(next);
     }
     std::vector<Key> cells;
-    cells.reserve(leaves.size());
-    for (auto &kv : leaves) {
-        uint64_t p = kv.first;
-        cells.push_back(Key{int(p >> 60), int(p & 0xFFFFF), int((p >> 20) & 0xFFFFF), int((p >> 40) & 0xFFFFF)});
-    }
-    std::sort(cells.begin(), cells.end(), key_less);
+    cells.reserve(all.size());
+    for (uint64_t p : all) cells.push_back(Key{int(p >> 60), ki(p), kj(p), kk(p)});
     if (cells.size() > size_t(INT32_MAX) / 8) return "too many cells";
     m.nc = int64_t(cells.size());
     m.level.resize(m.nc);
@@ -119,7 +152,7 @@ std::string build_host_mesh(const adg_instance_desc &d, HostMesh &m, bool leaves
     if (leaves_only) return "";
     std::unordered_map<uint64_t, int32_t> index;
     index.reserve(cells.size() * 2);
-    for (int64_t c = 0; c < m.nc; ++c) index.emplace(pack(cells[c].l, cells[c].i, cells[c].j, cells[c].k), int32_t(c));
+    for (int64_t c = 0; c < m.nc; ++c) index.emplace(all[size_t(c)], int32_t(c));
 
     // side classification
     std::vector<int8_t> kind(6 * m.nc);
