@@ -105,7 +105,9 @@ template <> struct PredCfg<5> { static constexpr int CPB = 2; };
 template <> struct PredCfg<6> { static constexpr int CPB = 1; };
 template <> struct PredCfg<7> { static constexpr int CPB = 1; };
 
-// wavefront-per-cell FP32 predictor for N = 4 (defined below)
+// wavefront-per-cell FP32 predictor for N = 4 (defined below); KEEP_U holds
+// the FP64 state in registers for u* = u + V instead of reading it again
+template <bool KEEP_U = false>
 __device__ __forceinline__ void pred4_wave(const double *__restrict__ u, double *__restrict__ ustar,
                                            float *__restrict__ traces, int64_t c, int64_t nc, int lev,
                                            const Geo &geo, double dt, double gamma, int npic);
@@ -381,7 +383,8 @@ __device__ __forceinline__ void predictor_item(T *lds, const double *u, double *
         if (g_pred4_mfma_dev) {
             for (int k = int(threadIdx.x >> 6); k < CPB; k += int(blockDim.x >> 6)) {
                 if (first + k >= nc) break;
-                pred4_wave(u, ustar, traces, first + k, nc, level ? level[first + k] : 0, *geo, dt, gamma, npic);
+                pred4_wave<true>(u, ustar, traces, first + k, nc, level ? level[first + k] : 0, *geo, dt, gamma,
+                                 npic);
             }
             return;
         }
@@ -602,6 +605,7 @@ template <typename T> __device__ __forceinline__ const T *lane_at(const T *base,
 }
 
 // One cell per wavefront; work item w covers cells first + w.
+template <bool KEEP_U>
 __device__ __forceinline__ void pred4_wave(const double *__restrict__ u, double *__restrict__ ustar,
                                            float *__restrict__ traces, int64_t c, int64_t nc, int lev,
                                            const Geo &geo, double dt, double gamma, int npic)
@@ -618,8 +622,12 @@ __device__ __forceinline__ void pred4_wave(const double *__restrict__ u, double 
     // wave-uniform bases plus a 32-bit lane byte offset (scalar-base addressing)
     const unsigned lu = unsigned(l) * unsigned(sizeof(double));
     float uu[NV];
+    double ud[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) uu[v] = float(*lane_at(u + (int64_t(v) * nc + c) * N3, lu));
+    for (int v = 0; v < NV; ++v) {
+        ud[v] = *lane_at(u + (int64_t(v) * nc + c) * N3, lu);
+        uu[v] = float(ud[v]);
+    }
 
     // per-lane coefficients (one scalar base, one lane offset)
     const float *Tl = lane_at(static_cast<const float *>(c_lane4), unsigned(l) * unsigned(LANE4 * sizeof(float)));
@@ -731,7 +739,7 @@ __device__ __forceinline__ void pred4_wave(const double *__restrict__ u, double 
             V = quad_sum(Vx, Fb[0][v], V);
             V = row_sum(Vy, Fb[1][v], V);
             const int64_t o = (int64_t(v) * nc + c) * N3;
-            *lane_at(ustar + o, lu) = *lane_at(u + o, lu) + double(V);
+            *lane_at(ustar + o, lu) = (KEEP_U ? ud[v] : *lane_at(u + o, lu)) + double(V);
         }
     }
 
@@ -793,7 +801,7 @@ k_predictor4_mfma(const double *__restrict__ u, double *__restrict__ ustar, floa
     const int64_t idx = int64_t(blockIdx.x) * (blockDim.x >> 6) + wave;
     if (idx >= nlist) return;  // whole wavefront leaves together
     const int64_t c = list ? int64_t(list[idx]) : idx;
-    pred4_wave(u, ustar, traces, c, nc, level ? level[c] : 0, geo, dt_dev[0], gamma, npic);
+    pred4_wave<true>(u, ustar, traces, c, nc, level ? level[c] : 0, geo, dt_dev[0], gamma, npic);
 }
 
 // persistent form over batched work items of order 4 (items of CPB cells)
@@ -809,8 +817,8 @@ k_predictor4_mfma_order(const PredItem *__restrict__ items, int64_t nitems, cons
         for (int k = wave; k < cpb; k += nwaves) {
             const int64_t c = w.first + k;
             if (c >= I.nc) break;
-            pred4_wave(u + I.u_off, ustar + I.u_off, traces + I.tr_off, c, I.nc, I.level ? I.level[c] : 0, I.geo,
-                       dt[w.inst], I.gamma, I.npic);
+            pred4_wave<true>(u + I.u_off, ustar + I.u_off, traces + I.tr_off, c, I.nc, I.level ? I.level[c] : 0,
+                             I.geo, dt[w.inst], I.gamma, I.npic);
         }
     }
 }
@@ -1821,7 +1829,9 @@ __constant__ DevSub c_sub[LIM_NMAX + 1];
 template <int N> struct LimCfg {
     static constexpr int NS = 2 * N - 1, N2 = N * N, N3 = N2 * N, S2 = NS * NS, S3 = S2 * NS;
     static constexpr int T1 = NS * N2, T2 = S2 * N;  // per-variable contraction temporaries
-    static constexpr int TMP = (T1 + T2 > NV * S2) ? T1 + T2 : NV * S2;
+    // variables contracted together in the FV kernel (all five while they fit in LDS)
+    static constexpr int NVB = N <= 6 ? NV : 1;
+    static constexpr int TMP = (NVB * (T1 + T2) > NV * S2) ? NVB * (T1 + T2) : NV * S2;
     // threads of the FV kernel; each keeps PT subcells' new data in registers
     static constexpr int THREADS = N >= 6 ? 512 : 256;
     static constexpr int PT = (S3 + THREADS - 1) / THREADS;
@@ -1843,70 +1853,83 @@ __device__ __forceinline__ bool lim_bad(double, const double q[NV])
     return !fin || lim_nonpositive(q);
 }
 
-// Subcell averages of one variable x[N^3] (node a0 + N a1 + N^2 a2).  axis <
-// 0: all subcells, out[s0 + NS s1 + NS^2 s2]; axis = d: only the layer s_d =
-// layer, out[j1 + NS j2] over the other two axes in increasing order.  t1, t2:
-// LimCfg<N>::T1, ::T2 doubles.  Block-wide (contains barriers).
-template <int N>
-__device__ void sub_avg(const double *__restrict__ A, const double *x, double *t1, double *t2, double *out, int axis,
-                        int layer)
+// Subcell averages of NVAR variables x[var N^3 + a] (node a0 + N a1 + N^2 a2).
+// axis < 0: all subcells, out[var ostride + s0 + NS s1 + NS^2 s2]; axis = d:
+// only the layer s_d = layer, out[var ostride + j1 + NS j2] over the other two
+// axes in increasing order.  t1, t2: NVAR LimCfg<N>::T1 and ::T2 doubles.
+// Every value is the same chain of fused multiply-adds whatever NVAR and
+// whichever outputs are asked for, so a layer matches the full result bit for
+// bit.  Block-wide (contains barriers).
+template <int N, int NVAR = 1>
+__device__ void sub_avg(const double *__restrict__ A, const double *x, double *t1, double *t2, double *out, int ostride,
+                        int axis, int layer)
 {
-    constexpr int NS = LimCfg<N>::NS, N2 = N * N;
+    using C = LimCfg<N>;
+    constexpr int NS = C::NS, N2 = N * N, N3 = N2 * N;
     const int lo0 = axis == 0 ? layer : 0, n0 = axis == 0 ? 1 : NS;
     const int lo1 = axis == 1 ? layer : 0, n1 = axis == 1 ? 1 : NS;
     const int lo2 = axis == 2 ? layer : 0, n2 = axis == 2 ? 1 : NS;
-    for (int i = threadIdx.x; i < n0 * N2; i += blockDim.x) {
-        const int s0 = lo0 + i % n0, a12 = i / n0;
+    const int m1 = n0 * N2, m2 = n0 * n1 * N, m3 = n0 * n1 * n2;
+    for (int i = threadIdx.x; i < NVAR * m1; i += blockDim.x) {
+        const int var = i / m1, r = i % m1;
+        const int s0 = lo0 + r % n0, a12 = r / n0;
         double acc = 0.0;
 #pragma unroll
-        for (int a0 = 0; a0 < N; ++a0) acc = fma(A[s0 * N + a0], x[a0 + N * a12], acc);
-        t1[s0 + NS * a12] = acc;
+        for (int a0 = 0; a0 < N; ++a0) acc = fma(A[s0 * N + a0], x[var * N3 + a0 + N * a12], acc);
+        t1[var * C::T1 + s0 + NS * a12] = acc;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < n0 * n1 * N; i += blockDim.x) {
-        const int s0 = lo0 + i % n0, s1 = lo1 + (i / n0) % n1, a2 = i / (n0 * n1);
+    for (int i = threadIdx.x; i < NVAR * m2; i += blockDim.x) {
+        const int var = i / m2, r = i % m2;
+        const int s0 = lo0 + r % n0, s1 = lo1 + (r / n0) % n1, a2 = r / (n0 * n1);
         double acc = 0.0;
 #pragma unroll
-        for (int a1 = 0; a1 < N; ++a1) acc = fma(A[s1 * N + a1], t1[s0 + NS * (a1 + N * a2)], acc);
-        t2[s0 + NS * (s1 + NS * a2)] = acc;
+        for (int a1 = 0; a1 < N; ++a1)
+            acc = fma(A[s1 * N + a1], t1[var * C::T1 + s0 + NS * (a1 + N * a2)], acc);
+        t2[var * C::T2 + s0 + NS * (s1 + NS * a2)] = acc;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < n0 * n1 * n2; i += blockDim.x) {
-        const int j0 = i % n0, j1 = (i / n0) % n1, j2 = i / (n0 * n1);
+    for (int i = threadIdx.x; i < NVAR * m3; i += blockDim.x) {
+        const int var = i / m3, r = i % m3;
+        const int j0 = r % n0, j1 = (r / n0) % n1, j2 = r / (n0 * n1);
         const int s0 = lo0 + j0, s1 = lo1 + j1, s2 = lo2 + j2;
         double acc = 0.0;
 #pragma unroll
-        for (int a2 = 0; a2 < N; ++a2) acc = fma(A[s2 * N + a2], t2[s0 + NS * (s1 + NS * a2)], acc);
-        out[i] = acc;
+        for (int a2 = 0; a2 < N; ++a2) acc = fma(A[s2 * N + a2], t2[var * C::T2 + s0 + NS * (s1 + NS * a2)], acc);
+        out[var * ostride + r] = acc;
     }
     __syncthreads();
 }
 
-// Least-squares polynomial x[N^3] of one variable's subcell data v[NS^3]
-// (r1: T2 doubles, r2: T1 doubles).  Block-wide.
-template <int N>
+// Least-squares polynomials x[var N^3 + a] of NVAR variables' subcell data
+// v[var NS^3 + s] (r1: NVAR T2 doubles, r2: NVAR T1 doubles).  Block-wide.
+template <int N, int NVAR = 1>
 __device__ void sub_fit(const double *__restrict__ Ap, const double *v, double *r1, double *r2, double *x)
 {
-    constexpr int NS = LimCfg<N>::NS, S2 = NS * NS, N2 = N * N;
-    for (int i = threadIdx.x; i < N * S2; i += blockDim.x) {
-        const int k0 = i % N, s12 = i / N;
+    using C = LimCfg<N>;
+    constexpr int NS = C::NS, S2 = NS * NS, S3 = S2 * NS, N2 = N * N, N3 = N2 * N;
+    for (int i = threadIdx.x; i < NVAR * N * S2; i += blockDim.x) {
+        const int var = i / (N * S2), r = i % (N * S2);
+        const int k0 = r % N, s12 = r / N;
         double acc = 0.0;
-        for (int s0 = 0; s0 < NS; ++s0) acc = fma(Ap[k0 * NS + s0], v[s0 + NS * s12], acc);
-        r1[i] = acc;  // k0 + N (s1 + NS s2)
+        for (int s0 = 0; s0 < NS; ++s0) acc = fma(Ap[k0 * NS + s0], v[var * S3 + s0 + NS * s12], acc);
+        r1[var * C::T2 + r] = acc;  // k0 + N (s1 + NS s2)
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < N2 * NS; i += blockDim.x) {
-        const int k0 = i % N, k1 = (i / N) % N, s2 = i / N2;
+    for (int i = threadIdx.x; i < NVAR * N2 * NS; i += blockDim.x) {
+        const int var = i / (N2 * NS), r = i % (N2 * NS);
+        const int k0 = r % N, k1 = (r / N) % N, s2 = r / N2;
         double acc = 0.0;
-        for (int s1 = 0; s1 < NS; ++s1) acc = fma(Ap[k1 * NS + s1], r1[k0 + N * (s1 + NS * s2)], acc);
-        r2[i] = acc;  // k0 + N (k1 + N s2)
+        for (int s1 = 0; s1 < NS; ++s1) acc = fma(Ap[k1 * NS + s1], r1[var * C::T2 + k0 + N * (s1 + NS * s2)], acc);
+        r2[var * C::T1 + r] = acc;  // k0 + N (k1 + N s2)
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < N2 * N; i += blockDim.x) {
-        const int k01 = i % N2, k2 = i / N2;
+    for (int i = threadIdx.x; i < NVAR * N3; i += blockDim.x) {
+        const int var = i / N3, r = i % N3;
+        const int k01 = r % N2, k2 = r / N2;
         double acc = 0.0;
-        for (int s2 = 0; s2 < NS; ++s2) acc = fma(Ap[k2 * NS + s2], r2[k01 + N2 * s2], acc);
-        x[i] = acc;
+        for (int s2 = 0; s2 < NS; ++s2) acc = fma(Ap[k2 * NS + s2], r2[var * C::T1 + k01 + N2 * s2], acc);
+        x[var * N3 + r] = acc;
     }
     __syncthreads();
 }
@@ -2191,7 +2214,8 @@ k_lim_fv(double *__restrict__ u, T *__restrict__ fside, int64_t nc, Geo geo, con
     const DevSub &S = c_sub[N];
     const double dt = dt_dev[0], gm1 = gamma - 1.0;
     const int n_lim = cnt[0];
-    double *t1 = tmp, *t2 = tmp + C::T1;
+    constexpr int NVB = C::NVB;
+    double *t1 = tmp, *t2 = tmp + NVB * C::T1;
     for (int it = blockIdx.x; it < n_lim; it += gridDim.x) {
         const int64_t c = list[it];
         // old subcell data of the cell and the face layers of its neighbours
@@ -2208,7 +2232,8 @@ k_lim_fv(double *__restrict__ u, T *__restrict__ fside, int64_t nc, Geo geo, con
                 for (int i = threadIdx.x; i < NV * cnt_out; i += blockDim.x) dst[i] = mean[i / cnt_out];
             } else {
                 const int axis = k < 0 ? -1 : k / 2, layer = (k & 1) ? 0 : NS - 1;
-                for (int var = 0; var < NV; ++var) sub_avg<N>(S.A, x + var * N3, t1, t2, dst + var * cnt_out, axis, layer);
+                for (int var = 0; var < NV; var += NVB)
+                    sub_avg<N, NVB>(S.A, x + var * N3, t1, t2, dst + var * cnt_out, cnt_out, axis, layer);
             }
             __syncthreads();
         }
@@ -2331,7 +2356,7 @@ k_lim_fv(double *__restrict__ u, T *__restrict__ fside, int64_t nc, Geo geo, con
             mean[threadIdx.x] = sum / S3;
         }
         // least-squares fit into x, its subcell averages back into v
-        for (int var = 0; var < NV; ++var) sub_fit<N>(S.Ap, v + var * S3, t2, t1, x + var * N3);
+        for (int var = 0; var < NV; var += NVB) sub_fit<N, NVB>(S.Ap, v + var * S3, t2, t1, x + var * N3);
         bool bad = false;
         for (int a = threadIdx.x; a < N3; a += blockDim.x) {
             double q[NV];
@@ -2339,7 +2364,7 @@ k_lim_fv(double *__restrict__ u, T *__restrict__ fside, int64_t nc, Geo geo, con
             for (int var = 0; var < NV; ++var) q[var] = x[var * N3 + a];
             bad = bad || lim_bad(gm1, q);
         }
-        for (int var = 0; var < NV; ++var) sub_avg<N>(S.A, x + var * N3, t1, t2, v + var * S3, -1, 0);
+        for (int var = 0; var < NV; var += NVB) sub_avg<N, NVB>(S.A, x + var * N3, t1, t2, v + var * S3, S3, -1, 0);
         for (int s = threadIdx.x; s < S3; s += blockDim.x) {
             double q[NV];
 #pragma unroll
@@ -2355,7 +2380,7 @@ k_lim_fv(double *__restrict__ u, T *__restrict__ fside, int64_t nc, Geo geo, con
         // bounds of the new state for the next step, as lim_scan_cell gives
         // them (same averages, exact extremes, the same mean)
         if (bad)
-            for (int var = 0; var < NV; ++var) sub_avg<N>(S.A, x + var * N3, t1, t2, v + var * S3, -1, 0);
+            for (int var = 0; var < NV; var += NVB) sub_avg<N, NVB>(S.A, x + var * N3, t1, t2, v + var * S3, S3, -1, 0);
         double lo[NV], hi[NV];
         bool badv = false;
 #pragma unroll
