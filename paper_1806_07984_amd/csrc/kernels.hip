@@ -2521,11 +2521,13 @@ template <int N> struct LinCfg {
     static constexpr int N3 = N * N * N;
     static constexpr int CPB = N3 >= 256 ? 1 : 256 / N3;
     static constexpr int THREADS = round64(CPB * N3);
+    // waves per SIMD asked of the register allocator (fits without spills for N <= 4)
+    static constexpr int MIN_WAVES = N <= 4 ? 4 : 1;
 };
 
 // CPB cells per block, one thread per node.
 template <int N>
-__global__ void __launch_bounds__(LinCfg<N>::THREADS)
+__global__ void __launch_bounds__(LinCfg<N>::THREADS) __attribute__((amdgpu_waves_per_eu(LinCfg<N>::MIN_WAVES, 8)))
 k_lin_predictor(const double *__restrict__ u, const double *__restrict__ mat, const double *__restrict__ dt_dev,
                 double *__restrict__ ustar, double *__restrict__ traces, int64_t nc, double idx0, double idx1,
                 double idx2)
