@@ -359,8 +359,14 @@ __device__ __forceinline__ void predictor_body(T *__restrict__ lds, const double
     }
 }
 
+// waves per SIMD asked of the register allocator for the per-launch predictor
+template <typename T, int N, bool STORE> struct PredWaves {
+    static constexpr int MIN = (std::is_same<T, float>::value && N == 5 && !STORE) ? 4 : 1;
+};
+
 template <typename T, int N, int CPB, bool STORE>
 __global__ void __launch_bounds__(round64(CPB * N * N * N))
+__attribute__((amdgpu_waves_per_eu(PredWaves<T, N, STORE>::MIN, 8)))
 k_predictor(const double *__restrict__ u, double *__restrict__ ustar, T *__restrict__ traces,
             const int32_t *__restrict__ list, int64_t nlist, int64_t nc,
             const int8_t *__restrict__ level, Geo geo, const double *__restrict__ dt_dev,
