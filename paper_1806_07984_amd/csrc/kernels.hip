@@ -398,10 +398,18 @@ __device__ __forceinline__ void predictor_item(T *lds, const double *u, double *
     predictor_body<T, N, CPB>(lds, u, ustar, traces, nullptr, nc, nc, level, *geo, dt, gamma, npic, first);
 }
 
+// waves per SIMD asked of the register allocator for the per-order
+// persistent predictor (FP32 N = 5 and 6 run faster with a few spills at the
+// higher occupancy; N = 7 does not)
+template <typename T, int N> struct PredOrderWaves {
+    static constexpr int MIN = !std::is_same<T, float>::value ? 1 : N == 5 ? 4 : N == 6 ? 3 : 1;
+};
+
 // Persistent predictor over the work items of ONE order (all instances of
 // that order): block b processes items b, b + gridDim, ...
 template <typename T, int N, int CPB>
 __global__ void __launch_bounds__(round64(CPB * N * N * N))
+__attribute__((amdgpu_waves_per_eu(PredOrderWaves<T, N>::MIN, 8)))
 k_predictor_order(const PredItem *__restrict__ items, int64_t nitems, const PredInst *__restrict__ insts,
                   const double *__restrict__ u, double *__restrict__ ustar, T *__restrict__ traces,
                   const double *__restrict__ dt)
