@@ -65,6 +65,12 @@ def lib():
         L.orc_sample.restype = ctypes.c_int
         L.orc_sample.argtypes = [P, P, P, ctypes.c_long, P]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_step_tlm.restype = ctypes.c_int
+        L.orc_step_tlm.argtypes = [P, ctypes.c_double, ctypes.c_int, ctypes.c_double, P, ctypes.c_int, P]
+        L.orc_step_adj.restype = ctypes.c_int
+        L.orc_step_adj.argtypes = [P, ctypes.c_double, ctypes.c_int, ctypes.c_double, P, P, P]
+        L.orc_sample_adj.restype = ctypes.c_int
+        L.orc_sample_adj.argtypes = [P, P, ctypes.c_long, P, P]
         L.orc_lin_flux_matrix.argtypes = [P, ctypes.c_int, P]
         L.orc_lin_predictor.argtypes = [P, P, ctypes.c_double, ctypes.c_int, ctypes.c_int, P, P, P]
         L.orc_lin_riemann.argtypes = [P, P, P, P]
@@ -213,6 +219,43 @@ def _sample(self, u, pts):
     return out
 
 
+def _sample_adj(self, pts, wbar, ubar=None):
+    """Transpose of sample(): adds wbar_s phi_a(x_s) into the density part of
+    ubar (a new zero array if None) and returns it."""
+    pts = np.ascontiguousarray(pts, dtype=np.float64)
+    wbar = _f64(wbar)
+    ubar = np.zeros((NV, self.nc, self.N ** 3)) if ubar is None else np.ascontiguousarray(ubar, dtype=np.float64)
+    assert lib().orc_sample_adj(self._h, _p(pts), pts.shape[0], _p(wbar), _p(ubar)) == 0
+    return ubar
+
+
+def _step_tlm(self, u, dt, du, gamma=1.4, npic=None):
+    """One step at the fixed dt together with its tangent-linear model.
+
+    du: one direction [5, nc, N^3] or K directions [K, 5, nc, N^3].
+    Returns (u_next, du_next of the same shape as du, status); du_next is the
+    derivative of the step at u applied to du (face speed differentiated at
+    its first maximiser)."""
+    u = np.array(u, dtype=np.float64, copy=True, order="C")
+    du = np.asarray(du, dtype=np.float64)
+    single = du.ndim == 3
+    d = np.array(du[None] if single else du, dtype=np.float64, copy=True, order="C")
+    npic = self.N if npic is None else npic
+    rc = lib().orc_step_tlm(self._h, gamma, int(npic), float(dt), _p(u), int(d.shape[0]), _p(d))
+    return u, (d[0] if single else d), int(rc)
+
+
+def _step_adj(self, u, dt, ubar, gamma=1.4, npic=None):
+    """Adjoint of one step at the fixed dt: (d u_next / d u)^T ubar at u.
+    Returns (ubar_n, status)."""
+    u = _f64(u)
+    ubar = _f64(ubar)
+    out = np.zeros_like(ubar)
+    npic = self.N if npic is None else npic
+    rc = lib().orc_step_adj(self._h, gamma, int(npic), float(dt), _p(u), _p(ubar), _p(out))
+    return out, int(rc)
+
+
 def _indicator(self, u):
     """Refinement indicator per cell: max over nodes and axes of the density
     derivative in the cell's reference coordinate (change across the cell)."""
@@ -332,6 +375,9 @@ Mesh.run_limited = _run_limited
 Mesh.limiter_detect = _limiter_detect
 Mesh.run_sched = _run_sched
 Mesh.sample = _sample
+Mesh.sample_adj = _sample_adj
+Mesh.step_tlm = _step_tlm
+Mesh.step_adj = _step_adj
 Mesh.indicator = _indicator
 Mesh.transfer_to = _transfer_to
 Mesh.integral = _integral

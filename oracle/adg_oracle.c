@@ -1860,3 +1860,674 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------------- */
+/* Tangent-linear model and adjoint of one step at a fixed dt                */
+/* ------------------------------------------------------------------------- */
+/* At a fixed time step size the step u^n -> u^{n+1} (Eq. 3-4, Alg. 1) is a
+ * piecewise-smooth map.  Its derivative goes through the same phases:
+ *   - predictor: every Picard iterate, the time averages, the volume term and
+ *     the face projections differentiate term by term (chain rule through the
+ *     Euler flux);
+ *   - Rusanov: F* = (F_L + F_R)/2 - s (Q_R - Q_L)/2 with s a maximum; s is
+ *     differentiated at its FIRST maximiser in the order (face node, minus
+ *     side first), and d|x|/dx is taken as 0 at x = 0;
+ *   - virtual-cell interpolation, restriction and corrector are linear.
+ * dt is held fixed: the CFL reduction is not differentiated.
+ * The tangent (forward mode) carries K directions at once; the adjoint is the
+ * transpose of the same phases in reverse order.  Both exist to check the
+ * GPU adjoint; they are written plainly from the definitions above. */
+
+/* d f_d(q)[dq]: directional derivative of the flux along axis d. */
+static void euler_flux_tan(double g, const double q[NV], const double dq[NV], int d, double df[NV])
+{
+    double r = q[0], dr = dq[0];
+    double mm = q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+    double mdm = q[1] * dq[1] + q[2] * dq[2] + q[3] * dq[3];
+    double p = (g - 1.0) * (q[4] - 0.5 * mm / r);
+    double dp = (g - 1.0) * (dq[4] - mdm / r + 0.5 * mm * dr / (r * r));
+    double vd = q[1 + d] / r;
+    double dvd = (dq[1 + d] - vd * dr) / r;
+    df[0] = dq[1 + d];
+    for (int i = 1; i <= 3; ++i) df[i] = dvd * q[i] + vd * dq[i];
+    df[1 + d] += dp;
+    df[4] = dvd * (q[4] + p) + vd * (dq[4] + dp);
+}
+
+/* d lambda_d(q)[dq] for lambda_d = |u_d| + c, with d|x|/dx = 0 at 0. */
+static double euler_speed_tan(double g, const double q[NV], const double dq[NV], int d)
+{
+    double r = q[0], dr = dq[0];
+    double mm = q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+    double mdm = q[1] * dq[1] + q[2] * dq[2] + q[3] * dq[3];
+    double p = (g - 1.0) * (q[4] - 0.5 * mm / r);
+    double dp = (g - 1.0) * (dq[4] - mdm / r + 0.5 * mm * dr / (r * r));
+    double vd = q[1 + d] / r;
+    double dvd = (dq[1 + d] - vd * dr) / r;
+    double c = sqrt(g * p / r);
+    double dc = g * (dp * r - p * dr) / (r * r) / (2.0 * c);
+    double sg = vd > 0.0 ? 1.0 : (vd < 0.0 ? -1.0 : 0.0);
+    return sg * dvd + dc;
+}
+
+/* f_d'(q)^T y, built column by column from the directional derivative. */
+static void euler_flux_vjp(double g, const double q[NV], int d, const double y[NV], double out[NV])
+{
+    for (int k = 0; k < NV; ++k) {
+        double e[NV] = { 0, 0, 0, 0, 0 }, df[NV];
+        e[k] = 1.0;
+        euler_flux_tan(g, q, e, d, df);
+        double s = 0.0;
+        for (int v = 0; v < NV; ++v) s += y[v] * df[v];
+        out[k] = s;
+    }
+}
+
+/* Face speed of the Rusanov flux and where it is attained: the first
+ * maximiser in (node b, minus side first) order. */
+static double rusanov_speed(double g, int d, int N2, const double *QL, const double *QR, int *bstar, int *side)
+{
+    double smax = 0.0;
+    *bstar = -1;
+    *side = 0;
+    for (int b = 0; b < N2; ++b) {
+        double ql[NV], qr[NV];
+        for (int v = 0; v < NV; ++v) { ql[v] = QL[v * N2 + b]; qr[v] = QR[v * N2 + b]; }
+        double sl = euler_speed(g, ql, d), sr = euler_speed(g, qr, d);
+        if (sl > smax) { smax = sl; *bstar = b; *side = 0; }
+        if (sr > smax) { smax = sr; *bstar = b; *side = 1; }
+    }
+    return smax;
+}
+
+/* Predictor with K tangent directions: the forward results (ustar, traces)
+ * and their directional derivatives (dus, dtr: [K][...] of the same layout)
+ * along du ([K][5][nc][N^3]). */
+static void predictor_tlm(const orc_mesh *m, double g, int npic, double dt, const double *u, int K,
+                          const double *du, double *ustar, double *traces, double *dus, double *dtr)
+{
+    int N = m->N, N2 = N * N, N3 = N2 * N;
+    long nc = m->nc;
+    long usz = (long)NV * nc * N3, tsz = (long)6 * 2 * NV * nc * N2;
+    double xi[MAXN], w[MAXN], D[MAXN * MAXN], L[MAXN], R[MAXN], Kinv[MAXN * MAXN], Kw[MAXN * MAXN];
+    orc_basis(N, xi, w, D, L, R, Kinv, Kw);
+    int K1 = K + 1; /* slot 0: the forward state, slots 1..K: the tangents */
+#pragma omp parallel
+    {
+        double *q = (double *)malloc(sizeof(double) * K1 * N * NV * N3);      /* [k][l][v][a] */
+        double *qn = (double *)malloc(sizeof(double) * K1 * N * NV * N3);
+        double *F = (double *)malloc(sizeof(double) * K1 * N * 3 * NV * N3);  /* [k][j][d][v][a] */
+        double *G = (double *)malloc(sizeof(double) * N * NV * N3);
+        double *uc = (double *)malloc(sizeof(double) * K1 * NV * N3);
+        double *qbar = (double *)malloc(sizeof(double) * NV * N3);
+        double *Fbar = (double *)malloc(sizeof(double) * 3 * NV * N3);
+#pragma omp for schedule(static)
+        for (long c = 0; c < nc; ++c) {
+            double dx[3];
+            cell_dx(m, c, dx);
+            for (int k = 0; k < K1; ++k)
+                for (int v = 0; v < NV; ++v)
+                    for (int a = 0; a < N3; ++a)
+                        uc[((long)k * NV + v) * N3 + a] =
+                            k == 0 ? u[((long)v * nc + c) * N3 + a] : du[(k - 1) * usz + ((long)v * nc + c) * N3 + a];
+            for (int k = 0; k < K1; ++k)
+                for (int l = 0; l < N; ++l)
+                    for (int v = 0; v < NV; ++v)
+                        for (int a = 0; a < N3; ++a)
+                            q[(((long)k * N + l) * NV + v) * N3 + a] = uc[((long)k * NV + v) * N3 + a];
+            for (int it = 0; it <= npic; ++it) {
+                /* fluxes of the iterate and their derivatives */
+                for (int j = 0; j < N; ++j)
+                    for (int a = 0; a < N3; ++a) {
+                        double qq[NV], f[NV];
+                        for (int v = 0; v < NV; ++v) qq[v] = q[((long)j * NV + v) * N3 + a];
+                        for (int d = 0; d < 3; ++d) {
+                            euler_flux(g, qq, d, f);
+                            for (int v = 0; v < NV; ++v) F[((long)(j * 3 + d) * NV + v) * N3 + a] = f[v];
+                            for (int k = 1; k < K1; ++k) {
+                                double dq[NV], df[NV];
+                                for (int v = 0; v < NV; ++v) dq[v] = q[(((long)k * N + j) * NV + v) * N3 + a];
+                                euler_flux_tan(g, qq, dq, d, df);
+                                for (int v = 0; v < NV; ++v)
+                                    F[(((long)k * N + j) * 3 + d) * NV * N3 + (long)v * N3 + a] = df[v];
+                            }
+                        }
+                    }
+                if (it == npic) break;
+                /* the iteration is linear in (u, F): the same operators act on
+                 * the forward data and on every tangent */
+                for (int k = 0; k < K1; ++k) {
+                    const double *Fk = F + (long)k * N * 3 * NV * N3;
+                    for (int j = 0; j < N; ++j)
+                        for (int v = 0; v < NV; ++v)
+                            for (int a = 0; a < N3; ++a) {
+                                int aa[3] = { a % N, (a / N) % N, a / N2 };
+                                double s = 0.0;
+                                for (int d = 0; d < 3; ++d) {
+                                    double sd = 0.0;
+                                    for (int e = 0; e < N; ++e)
+                                        sd += D[aa[d] * N + e] * Fk[((j * 3 + d) * NV + v) * N3 + node_with(N, a, d, e)];
+                                    s += (dt / dx[d]) * sd;
+                                }
+                                G[(j * NV + v) * N3 + a] = s;
+                            }
+                    for (int l = 0; l < N; ++l)
+                        for (int v = 0; v < NV; ++v)
+                            for (int a = 0; a < N3; ++a) {
+                                double s = 0.0;
+                                for (int j = 0; j < N; ++j) s += Kinv[l * N + j] * w[j] * G[(j * NV + v) * N3 + a];
+                                qn[(((long)k * N + l) * NV + v) * N3 + a] = uc[((long)k * NV + v) * N3 + a] - s;
+                            }
+                }
+                double *t = q; q = qn; qn = t;
+            }
+            /* time averages, volume term and face projections (linear in q, F) */
+            for (int k = 0; k < K1; ++k) {
+                const double *qk = q + (long)k * N * NV * N3;
+                const double *Fk = F + (long)k * N * 3 * NV * N3;
+                for (int v = 0; v < NV; ++v)
+                    for (int a = 0; a < N3; ++a) {
+                        double s = 0.0;
+                        for (int j = 0; j < N; ++j) s += w[j] * qk[(j * NV + v) * N3 + a];
+                        qbar[v * N3 + a] = s;
+                        for (int d = 0; d < 3; ++d) {
+                            double sf = 0.0;
+                            for (int j = 0; j < N; ++j) sf += w[j] * Fk[((j * 3 + d) * NV + v) * N3 + a];
+                            Fbar[(d * NV + v) * N3 + a] = sf;
+                        }
+                    }
+                double *uo = k == 0 ? ustar : dus + (k - 1) * usz;
+                double *to = k == 0 ? traces : dtr + (k - 1) * tsz;
+                for (int v = 0; v < NV; ++v)
+                    for (int a = 0; a < N3; ++a) {
+                        int aa[3] = { a % N, (a / N) % N, a / N2 };
+                        double s = 0.0;
+                        for (int d = 0; d < 3; ++d) {
+                            double sd = 0.0;
+                            for (int e = 0; e < N; ++e)
+                                sd += Kw[aa[d] * N + e] * Fbar[(d * NV + v) * N3 + node_with(N, a, d, e)];
+                            s += (dt / dx[d]) * sd / w[aa[d]];
+                        }
+                        uo[((long)v * nc + c) * N3 + a] = uc[((long)k * NV + v) * N3 + a] + s;
+                    }
+                for (int s = 0; s < 6; ++s) {
+                    int d = s / 2;
+                    const double *E = (s % 2) ? R : L;
+                    for (int v = 0; v < NV; ++v)
+                        for (int b = 0; b < N2; ++b) {
+                            double sq = 0.0, sf = 0.0;
+                            for (int e = 0; e < N; ++e) {
+                                int a = node_from_face(N, d, e, b);
+                                sq += E[e] * qbar[v * N3 + a];
+                                sf += E[e] * Fbar[(d * NV + v) * N3 + a];
+                            }
+                            to[(((long)(s * 2 + 0) * NV + v) * nc + c) * N2 + b] = sq;
+                            to[(((long)(s * 2 + 1) * NV + v) * nc + c) * N2 + b] = sf;
+                        }
+                }
+            }
+        }
+        free(q); free(qn); free(F); free(G); free(uc); free(qbar); free(Fbar);
+    }
+}
+
+/* Riemann phase with K tangents: fside and dfs ([K] x fside layout) from the
+ * traces and their tangents dtr.  Returns 1 if a node is unphysical. */
+static int riemann_tlm(const orc_mesh *m, double g, const double *traces, int K, const double *dtr,
+                       double *fside, double *dfs)
+{
+    int N = m->N, N2 = N * N;
+    long nc = m->nc;
+    long tsz = (long)6 * 2 * NV * nc * N2, fsz = (long)6 * NV * nc * N2;
+    int bad = orc_riemann(m, g, traces, fside);
+#pragma omp parallel
+    {
+        double *QL = (double *)malloc(sizeof(double) * NV * N2 * 9);
+        double *QR = QL + NV * N2, *dQL = QR + NV * N2, *dFL = dQL + NV * N2, *dQR = dFL + NV * N2;
+        double *dFR = dQR + NV * N2, *tmp = dFR + NV * N2, *Fs = tmp + NV * N2, *Qtmp = Fs + NV * N2;
+#pragma omp for schedule(static)
+        for (long c = 0; c < nc; ++c) {
+            for (int s = 0; s < 6; ++s) {
+                int d = s / 2, plus = s % 2;
+                int kind = m->kind[6 * c + s];
+                long o = m->nbr[6 * c + s];
+                if (kind == SIDE_COARSE) continue;
+                int so = 2 * d + (1 - plus);
+                int r = 1, s1 = 0, s2 = 0;
+                if (kind == SIDE_FINE) {
+                    int t1, t2;
+                    tangential(d, &t1, &t2);
+                    r = (int)ipow3(m->lev[c] - m->lev[o]);
+                    s1 = sub_position(m, c, o, t1);
+                    s2 = sub_position(m, c, o, t2);
+                }
+                /* forward states of the face: this cell's trace and the
+                 * neighbour's (interpolated to the child face if coarser) */
+                double *Qc = plus ? QL : QR, *Qo = plus ? QR : QL;
+                get_trace(m, traces, c, s, 0, Qc);
+                if (kind == SIDE_CONFORMING) {
+                    get_trace(m, traces, o, so, 0, Qo);
+                } else {
+                    get_trace(m, traces, o, so, 0, Qtmp);
+                    prolong_face(N, r, s1, s2, Qtmp, Qo);
+                }
+                int bs, side;
+                double smax = rusanov_speed(g, d, N2, QL, QR, &bs, &side);
+                for (int k = 0; k < K; ++k) {
+                    const double *dt_k = dtr + k * tsz;
+                    double *dQc = plus ? dQL : dQR, *dFc = plus ? dFL : dFR;
+                    double *dQo = plus ? dQR : dQL, *dFo = plus ? dFR : dFL;
+                    get_trace(m, dt_k, c, s, 0, dQc);
+                    get_trace(m, dt_k, c, s, 1, dFc);
+                    if (kind == SIDE_CONFORMING) {
+                        get_trace(m, dt_k, o, so, 0, dQo);
+                        get_trace(m, dt_k, o, so, 1, dFo);
+                    } else {
+                        get_trace(m, dt_k, o, so, 0, tmp);
+                        prolong_face(N, r, s1, s2, tmp, dQo);
+                        get_trace(m, dt_k, o, so, 1, tmp);
+                        prolong_face(N, r, s1, s2, tmp, dFo);
+                    }
+                    double ds = 0.0;
+                    if (bs >= 0) {
+                        double q[NV], dq[NV];
+                        const double *Qa = side ? QR : QL, *dQa = side ? dQR : dQL;
+                        for (int v = 0; v < NV; ++v) { q[v] = Qa[v * N2 + bs]; dq[v] = dQa[v * N2 + bs]; }
+                        ds = euler_speed_tan(g, q, dq, d);
+                    }
+                    for (int v = 0; v < NV; ++v)
+                        for (int b = 0; b < N2; ++b)
+                            Fs[v * N2 + b] = 0.5 * (dFL[v * N2 + b] + dFR[v * N2 + b])
+                                             - 0.5 * ds * (QR[v * N2 + b] - QL[v * N2 + b])
+                                             - 0.5 * smax * (dQR[v * N2 + b] - dQL[v * N2 + b]);
+                    put_side(m, dfs + k * fsz, c, s, Fs);
+                }
+            }
+        }
+        free(QL);
+    }
+    /* restriction of the tangents into the coarse sides (linear) */
+    for (int k = 0; k < K; ++k) {
+        double *dk = dfs + k * fsz;
+        for (long c = 0; c < nc; ++c)
+            for (int s = 0; s < 6; ++s)
+                if (m->kind[6 * c + s] == SIDE_COARSE)
+                    for (int v = 0; v < NV; ++v)
+                        for (int b = 0; b < N2; ++b) dk[((long)(s * NV + v) * nc + c) * N2 + b] = 0.0;
+        for (long f = 0; f < nc; ++f)
+            for (int s = 0; s < 6; ++s) {
+                if (m->kind[6 * f + s] != SIDE_FINE) continue;
+                int d = s / 2, plus = s % 2;
+                long cc = m->nbr[6 * f + s];
+                int sc = 2 * d + (1 - plus);
+                int t1, t2;
+                tangential(d, &t1, &t2);
+                int r = (int)ipow3(m->lev[f] - m->lev[cc]);
+                int s1 = sub_position(m, f, cc, t1), s2 = sub_position(m, f, cc, t2);
+                double P[MAXN * MAXN], R1[MAXN * MAXN], R2[MAXN * MAXN];
+                orc_transfer(N, r, s1, P, R1);
+                orc_transfer(N, r, s2, P, R2);
+                for (int v = 0; v < NV; ++v)
+                    for (int k2 = 0; k2 < N; ++k2)
+                        for (int k1 = 0; k1 < N; ++k1) {
+                            double acc = 0.0;
+                            for (int e2 = 0; e2 < N; ++e2)
+                                for (int e1 = 0; e1 < N; ++e1)
+                                    acc += R1[k1 * N + e1] * R2[k2 * N + e2] *
+                                           dk[((long)(s * NV + v) * nc + f) * N2 + e1 + N * e2];
+                            dk[((long)(sc * NV + v) * nc + cc) * N2 + k1 + N * k2] += acc;
+                        }
+            }
+    }
+    return bad;
+}
+
+/* One step at the fixed dt with K tangent directions: u <- u^{n+1} and
+ * du[k] <- (d u^{n+1} / d u^n) du[k] (du is [K][5][nc][N^3]).  Returns 0,
+ * 1 if an unphysical state was met, 2 on allocation failure. */
+int orc_step_tlm(const orc_mesh *m, double g, int npic, double dt, double *u, int K, double *du)
+{
+    int N = m->N, N2 = N * N, N3 = N2 * N;
+    long nc = m->nc;
+    long usz = (long)NV * nc * N3, tsz = (long)6 * 2 * NV * nc * N2, fsz = (long)6 * NV * nc * N2;
+    double *us = (double *)malloc(sizeof(double) * usz);
+    double *tr = (double *)malloc(sizeof(double) * tsz);
+    double *fs = (double *)malloc(sizeof(double) * fsz);
+    double *dus = (double *)malloc(sizeof(double) * usz * (K > 0 ? K : 1));
+    double *dtr = (double *)malloc(sizeof(double) * tsz * (K > 0 ? K : 1));
+    double *dfs = (double *)malloc(sizeof(double) * fsz * (K > 0 ? K : 1));
+    int rc = 0;
+    if (!us || !tr || !fs || !dus || !dtr || !dfs) {
+        rc = 2;
+    } else {
+        predictor_tlm(m, g, npic, dt, u, K, du, us, tr, dus, dtr);
+        if (riemann_tlm(m, g, tr, K, dtr, fs, dfs)) {
+            rc = 1;
+        } else {
+            /* the corrector is linear in (ustar, fside) */
+            orc_corrector(m, dt, us, fs, u);
+            for (int k = 0; k < K; ++k) orc_corrector(m, dt, dus + k * usz, dfs + k * fsz, du + k * usz);
+        }
+    }
+    free(us); free(tr); free(fs); free(dus); free(dtr); free(dfs);
+    return rc;
+}
+
+/* Adjoint of one step at the fixed dt: ubar_n = (d u^{n+1} / d u^n)^T
+ * ubar_np1 at the state u (unchanged).  The phases are transposed in reverse
+ * order: corrector, restriction, Rusanov (with the virtual-cell
+ * interpolation), predictor (face projections, volume term, time averages,
+ * then the Picard iterations backwards with the forward iterates
+ * recomputed per cell).  Returns 0, 1 if an unphysical state was met, 2 on
+ * allocation failure. */
+int orc_step_adj(const orc_mesh *m, double g, int npic, double dt, const double *u, const double *ubar_np1,
+                 double *ubar_n)
+{
+    int N = m->N, N2 = N * N, N3 = N2 * N;
+    long nc = m->nc;
+    long usz = (long)NV * nc * N3, tsz = (long)6 * 2 * NV * nc * N2, fsz = (long)6 * NV * nc * N2;
+    double xi[MAXN], w[MAXN], D[MAXN * MAXN], L[MAXN], R[MAXN], Kinv[MAXN * MAXN], Kw[MAXN * MAXN];
+    orc_basis(N, xi, w, D, L, R, Kinv, Kw);
+    double *us = (double *)malloc(sizeof(double) * usz);
+    double *tr = (double *)malloc(sizeof(double) * tsz);
+    double *trb = (double *)calloc(tsz, sizeof(double));
+    double *fsb = (double *)calloc(fsz, sizeof(double));
+    if (!us || !tr || !trb || !fsb) { free(us); free(tr); free(trb); free(fsb); return 2; }
+    orc_predictor(m, g, npic, dt, u, us, tr);
+
+    /* corrector: u^{n+1} = ustar - sum_d (dt/dx_d)(1/w)(R F*_{d+} - L F*_{d-}) */
+    for (long c = 0; c < nc; ++c) {
+        double dx[3];
+        cell_dx(m, c, dx);
+        for (int v = 0; v < NV; ++v)
+            for (int a = 0; a < N3; ++a) {
+                int aa[3] = { a % N, (a / N) % N, a / N2 };
+                double y = ubar_np1[((long)v * nc + c) * N3 + a];
+                for (int d = 0; d < 3; ++d) {
+                    int b = face_index(N, a, d);
+                    double k = (dt / dx[d]) / w[aa[d]];
+                    fsb[((long)((2 * d + 1) * NV + v) * nc + c) * N2 + b] -= k * R[aa[d]] * y;
+                    fsb[((long)((2 * d) * NV + v) * nc + c) * N2 + b] += k * L[aa[d]] * y;
+                }
+            }
+    }
+    /* restriction: coarse side = sum over child faces of (R1 x R2) fine side */
+    for (long f = 0; f < nc; ++f)
+        for (int s = 0; s < 6; ++s) {
+            if (m->kind[6 * f + s] != SIDE_FINE) continue;
+            int d = s / 2, plus = s % 2;
+            long cc = m->nbr[6 * f + s];
+            int sc = 2 * d + (1 - plus);
+            int t1, t2;
+            tangential(d, &t1, &t2);
+            int r = (int)ipow3(m->lev[f] - m->lev[cc]);
+            int s1 = sub_position(m, f, cc, t1), s2 = sub_position(m, f, cc, t2);
+            double P[MAXN * MAXN], R1[MAXN * MAXN], R2[MAXN * MAXN];
+            orc_transfer(N, r, s1, P, R1);
+            orc_transfer(N, r, s2, P, R2);
+            for (int v = 0; v < NV; ++v)
+                for (int k2 = 0; k2 < N; ++k2)
+                    for (int k1 = 0; k1 < N; ++k1) {
+                        double y = fsb[((long)(sc * NV + v) * nc + cc) * N2 + k1 + N * k2];
+                        for (int e2 = 0; e2 < N; ++e2)
+                            for (int e1 = 0; e1 < N; ++e1)
+                                fsb[((long)(s * NV + v) * nc + f) * N2 + e1 + N * e2] +=
+                                    R1[k1 * N + e1] * R2[k2 * N + e2] * y;
+                    }
+        }
+    /* Rusanov per (cell, non-coarse side); the bars go to both traces (through
+     * the transposed interpolation on hanging faces) */
+    int bad = 0;
+    {
+        double *QL = (double *)malloc(sizeof(double) * NV * N2 * 8);
+        double *QR = QL + NV * N2, *bQL = QR + NV * N2, *bFL = bQL + NV * N2, *bQR = bFL + NV * N2;
+        double *bFR = bQR + NV * N2, *Qtmp = bFR + NV * N2;
+        for (long c = 0; c < nc; ++c)
+            for (int s = 0; s < 6; ++s) {
+                int d = s / 2, plus = s % 2;
+                int kind = m->kind[6 * c + s];
+                long o = m->nbr[6 * c + s];
+                if (kind == SIDE_COARSE) continue;
+                int so = 2 * d + (1 - plus);
+                int r = 1, s1 = 0, s2 = 0;
+                if (kind == SIDE_FINE) {
+                    int t1, t2;
+                    tangential(d, &t1, &t2);
+                    r = (int)ipow3(m->lev[c] - m->lev[o]);
+                    s1 = sub_position(m, c, o, t1);
+                    s2 = sub_position(m, c, o, t2);
+                }
+                double *Qc = plus ? QL : QR, *Qo = plus ? QR : QL;
+                get_trace(m, tr, c, s, 0, Qc);
+                if (kind == SIDE_CONFORMING) {
+                    get_trace(m, tr, o, so, 0, Qo);
+                } else {
+                    get_trace(m, tr, o, so, 0, Qtmp);
+                    prolong_face(N, r, s1, s2, Qtmp, Qo);
+                }
+                for (int b = 0; b < N2; ++b) {
+                    double ql[NV], qr[NV];
+                    for (int v = 0; v < NV; ++v) { ql[v] = QL[v * N2 + b]; qr[v] = QR[v * N2 + b]; }
+                    if (unphysical(g, ql) || unphysical(g, qr)) bad = 1;
+                }
+                int bs, side;
+                double smax = rusanov_speed(g, d, N2, QL, QR, &bs, &side);
+                double sbar = 0.0;
+                for (int v = 0; v < NV; ++v)
+                    for (int b = 0; b < N2; ++b) {
+                        double y = fsb[((long)(s * NV + v) * nc + c) * N2 + b];
+                        bFL[v * N2 + b] = 0.5 * y;
+                        bFR[v * N2 + b] = 0.5 * y;
+                        bQL[v * N2 + b] = 0.5 * smax * y;
+                        bQR[v * N2 + b] = -0.5 * smax * y;
+                        sbar += -0.5 * (QR[v * N2 + b] - QL[v * N2 + b]) * y;
+                    }
+                if (bs >= 0) {
+                    const double *Qa = side ? QR : QL;
+                    double *bQa = side ? bQR : bQL;
+                    double q[NV];
+                    for (int v = 0; v < NV; ++v) q[v] = Qa[v * N2 + bs];
+                    for (int kk = 0; kk < NV; ++kk) {
+                        double e[NV] = { 0, 0, 0, 0, 0 };
+                        e[kk] = 1.0;
+                        bQa[kk * N2 + bs] += sbar * euler_speed_tan(g, q, e, d);
+                    }
+                }
+                double *bQc = plus ? bQL : bQR, *bFc = plus ? bFL : bFR;
+                double *bQo = plus ? bQR : bQL, *bFo = plus ? bFR : bFL;
+                for (int v = 0; v < NV; ++v)
+                    for (int b = 0; b < N2; ++b) {
+                        trb[(((long)(s * 2 + 0) * NV + v) * nc + c) * N2 + b] += bQc[v * N2 + b];
+                        trb[(((long)(s * 2 + 1) * NV + v) * nc + c) * N2 + b] += bFc[v * N2 + b];
+                    }
+                if (kind == SIDE_CONFORMING) {
+                    for (int v = 0; v < NV; ++v)
+                        for (int b = 0; b < N2; ++b) {
+                            trb[(((long)(so * 2 + 0) * NV + v) * nc + o) * N2 + b] += bQo[v * N2 + b];
+                            trb[(((long)(so * 2 + 1) * NV + v) * nc + o) * N2 + b] += bFo[v * N2 + b];
+                        }
+                } else {
+                    /* fine[k1 + N k2] = sum_e P1[k1][e1] P2[k2][e2] coarse[e1 + N e2] */
+                    double P1[MAXN * MAXN], P2[MAXN * MAXN], Rm[MAXN * MAXN];
+                    orc_transfer(N, r, s1, P1, Rm);
+                    orc_transfer(N, r, s2, P2, Rm);
+                    for (int arr = 0; arr < 2; ++arr) {
+                        const double *bo = arr ? bFo : bQo;
+                        for (int v = 0; v < NV; ++v)
+                            for (int k2 = 0; k2 < N; ++k2)
+                                for (int k1 = 0; k1 < N; ++k1) {
+                                    double y = bo[v * N2 + k1 + N * k2];
+                                    for (int e2 = 0; e2 < N; ++e2)
+                                        for (int e1 = 0; e1 < N; ++e1)
+                                            trb[(((long)(so * 2 + arr) * NV + v) * nc + o) * N2 + e1 + N * e2] +=
+                                                P1[k1 * N + e1] * P2[k2 * N + e2] * y;
+                                }
+                    }
+                }
+            }
+        free(QL);
+    }
+    /* predictor, cell by cell: ustar = u + volume term, traces from the time
+     * averages, Picard iterations backwards */
+    const double *usb = ubar_np1; /* ustar enters the corrector with weight 1 */
+#pragma omp parallel
+    {
+        double *qs = (double *)malloc(sizeof(double) * (npic + 1) * N * NV * N3); /* [it][j][v][a] */
+        double *Fs = (double *)malloc(sizeof(double) * (npic + 1) * N * 3 * NV * N3);
+        double *qb = (double *)malloc(sizeof(double) * N * NV * N3);
+        double *Fb = (double *)malloc(sizeof(double) * N * 3 * NV * N3);
+        double *Gb = (double *)malloc(sizeof(double) * N * NV * N3);
+        double *qbarb = (double *)malloc(sizeof(double) * NV * N3);
+        double *Fbarb = (double *)malloc(sizeof(double) * 3 * NV * N3);
+        double *ub = (double *)malloc(sizeof(double) * NV * N3);
+#pragma omp for schedule(static)
+        for (long c = 0; c < nc; ++c) {
+            double dx[3];
+            cell_dx(m, c, dx);
+            /* forward iterates q^(0..npic) and their fluxes */
+            for (int j = 0; j < N; ++j)
+                for (int v = 0; v < NV; ++v)
+                    for (int a = 0; a < N3; ++a) qs[(j * NV + v) * N3 + a] = u[((long)v * nc + c) * N3 + a];
+            for (int it = 0; it <= npic; ++it) {
+                double *q = qs + (long)it * N * NV * N3;
+                double *F = Fs + (long)it * N * 3 * NV * N3;
+                for (int j = 0; j < N; ++j)
+                    for (int a = 0; a < N3; ++a) {
+                        double qq[NV], f[NV];
+                        for (int v = 0; v < NV; ++v) qq[v] = q[(j * NV + v) * N3 + a];
+                        for (int d = 0; d < 3; ++d) {
+                            euler_flux(g, qq, d, f);
+                            for (int v = 0; v < NV; ++v) F[((j * 3 + d) * NV + v) * N3 + a] = f[v];
+                        }
+                    }
+                if (it == npic) break;
+                double *qn = qs + (long)(it + 1) * N * NV * N3;
+                for (int l = 0; l < N; ++l)
+                    for (int v = 0; v < NV; ++v)
+                        for (int a = 0; a < N3; ++a) {
+                            int aa[3] = { a % N, (a / N) % N, a / N2 };
+                            double s = 0.0;
+                            for (int j = 0; j < N; ++j) {
+                                double Gj = 0.0;
+                                for (int d = 0; d < 3; ++d) {
+                                    double sd = 0.0;
+                                    for (int e = 0; e < N; ++e)
+                                        sd += D[aa[d] * N + e] * F[((j * 3 + d) * NV + v) * N3 + node_with(N, a, d, e)];
+                                    Gj += (dt / dx[d]) * sd;
+                                }
+                                s += Kinv[l * N + j] * w[j] * Gj;
+                            }
+                            qn[(l * NV + v) * N3 + a] = u[((long)v * nc + c) * N3 + a] - s;
+                        }
+            }
+            /* bars of the time averages from ustar and the traces */
+            for (int i = 0; i < NV * N3; ++i) qbarb[i] = 0.0;
+            for (int i = 0; i < 3 * NV * N3; ++i) Fbarb[i] = 0.0;
+            for (int v = 0; v < NV; ++v)
+                for (int a = 0; a < N3; ++a) {
+                    int aa[3] = { a % N, (a / N) % N, a / N2 };
+                    double y = usb[((long)v * nc + c) * N3 + a];
+                    ub[v * N3 + a] = y;
+                    for (int d = 0; d < 3; ++d)
+                        for (int e = 0; e < N; ++e)
+                            Fbarb[(d * NV + v) * N3 + node_with(N, a, d, e)] +=
+                                (dt / dx[d]) / w[aa[d]] * Kw[aa[d] * N + e] * y;
+                }
+            for (int s = 0; s < 6; ++s) {
+                int d = s / 2;
+                const double *E = (s % 2) ? R : L;
+                for (int v = 0; v < NV; ++v)
+                    for (int b = 0; b < N2; ++b) {
+                        double yq = trb[(((long)(s * 2 + 0) * NV + v) * nc + c) * N2 + b];
+                        double yf = trb[(((long)(s * 2 + 1) * NV + v) * nc + c) * N2 + b];
+                        for (int e = 0; e < N; ++e) {
+                            int a = node_from_face(N, d, e, b);
+                            qbarb[v * N3 + a] += E[e] * yq;
+                            Fbarb[(d * NV + v) * N3 + a] += E[e] * yf;
+                        }
+                    }
+            }
+            /* qbar = sum_j w_j q_j, Fbar_d = sum_j w_j f_d(q_j) of the final iterate */
+            for (int j = 0; j < N; ++j)
+                for (int i = 0; i < NV * N3; ++i) qb[j * NV * N3 + i] = w[j] * qbarb[i];
+            for (int j = 0; j < N; ++j)
+                for (int i = 0; i < 3 * NV * N3; ++i) Fb[(long)j * 3 * NV * N3 + i] = w[j] * Fbarb[i];
+            for (int it = npic; it >= 0; --it) {
+                /* q^(it) -> F^(it) */
+                const double *q = qs + (long)it * N * NV * N3;
+                for (int j = 0; j < N; ++j)
+                    for (int a = 0; a < N3; ++a) {
+                        double qq[NV], y[NV], o[NV];
+                        for (int v = 0; v < NV; ++v) qq[v] = q[(j * NV + v) * N3 + a];
+                        for (int d = 0; d < 3; ++d) {
+                            for (int v = 0; v < NV; ++v) y[v] = Fb[((j * 3 + d) * NV + v) * N3 + a];
+                            euler_flux_vjp(g, qq, d, y, o);
+                            for (int v = 0; v < NV; ++v) qb[(j * NV + v) * N3 + a] += o[v];
+                        }
+                    }
+                if (it == 0) {
+                    /* q^(0)_j = u for every time node */
+                    for (int j = 0; j < N; ++j)
+                        for (int i = 0; i < NV * N3; ++i) ub[i] += qb[j * NV * N3 + i];
+                    break;
+                }
+                /* q^(it)_l = u - sum_j Kinv[l][j] w_j G_j,
+                 * G_j = sum_d (dt/dx_d) D_d F^(it-1)[j][d] */
+                for (int l = 0; l < N; ++l)
+                    for (int i = 0; i < NV * N3; ++i) ub[i] += qb[l * NV * N3 + i];
+                for (int j = 0; j < N; ++j)
+                    for (int i = 0; i < NV * N3; ++i) {
+                        double s = 0.0;
+                        for (int l = 0; l < N; ++l) s += Kinv[l * N + j] * qb[l * NV * N3 + i];
+                        Gb[j * NV * N3 + i] = -w[j] * s;
+                    }
+                for (int i = 0; i < N * 3 * NV * N3; ++i) Fb[i] = 0.0;
+                for (int j = 0; j < N; ++j)
+                    for (int v = 0; v < NV; ++v)
+                        for (int a = 0; a < N3; ++a) {
+                            int aa[3] = { a % N, (a / N) % N, a / N2 };
+                            double y = Gb[(j * NV + v) * N3 + a];
+                            for (int d = 0; d < 3; ++d)
+                                for (int e = 0; e < N; ++e)
+                                    Fb[((j * 3 + d) * NV + v) * N3 + node_with(N, a, d, e)] +=
+                                        (dt / dx[d]) * D[aa[d] * N + e] * y;
+                        }
+                for (int i = 0; i < N * NV * N3; ++i) qb[i] = 0.0;
+            }
+            for (int v = 0; v < NV; ++v)
+                for (int a = 0; a < N3; ++a) ubar_n[((long)v * nc + c) * N3 + a] = ub[v * N3 + a];
+        }
+        free(qs); free(Fs); free(qb); free(Fb); free(Gb); free(qbarb); free(Fbarb); free(ub);
+    }
+    free(us); free(tr); free(trb); free(fsb);
+    return bad;
+}
+
+/* Transpose of orc_sample: ubar[rho][c_s][a] += wbar_s phi_a(x_s) for every
+ * point in order (base-level meshes only).  The sample is linear in u, so
+ * this is its adjoint. */
+int orc_sample_adj(const orc_mesh *m, const double *pts, long n, const double *wbar, double *ubar)
+{
+    if (m->max_level != 0) return 1;
+    int N = m->N, N3 = N * N * N;
+    double xi[MAXN], w[MAXN];
+    orc_gauss_legendre(N, xi, w);
+    for (long s = 0; s < n; ++s) {
+        int ijk[3];
+        double phi[3][MAXN];
+        for (int d = 0; d < 3; ++d) {
+            double y = (pts[3 * s + d] - m->lo[d]) / (m->hi[d] - m->lo[d]) * m->n[d];
+            int i = (int)floor(y);
+            if (i < 0) i = 0;
+            if (i >= m->n[d]) i = m->n[d] - 1;
+            ijk[d] = i;
+            for (int e = 0; e < N; ++e) phi[d][e] = lagrange(N, xi, e, y - i);
+        }
+        long c = ijk[0] + (long)m->n[0] * (ijk[1] + (long)m->n[1] * ijk[2]);
+        for (int a2 = 0; a2 < N; ++a2)
+            for (int a1 = 0; a1 < N; ++a1)
+                for (int a0 = 0; a0 < N; ++a0)
+                    ubar[c * N3 + a0 + N * a1 + N * N * a2] += wbar[s] * phi[0][a0] * phi[1][a1] * phi[2][a2];
+    }
+    return 0;
+}
