@@ -287,7 +287,8 @@ def _run_limited(self, u, nsteps, gamma=1.4, cfl=0.4, npic=None, dt_fixed=0.0, d
                  force=False):
     """Steps with the a-posteriori subcell limiter.  Returns (u_final,
     dt_history, troubled cells per step, flags of the last step, status);
-    flags: 1 limited, 2 corrector re-run next to a limited cell, 0 else."""
+    flags: 1 limited, 2 corrector re-run next to a limited cell, 3 troubled
+    but not limitable (a hanging side, adaptive meshes), 0 else."""
     u = np.array(u, dtype=np.float64, copy=True, order="C")
     npic = self.N if npic is None else npic
     hist = np.zeros(max(nsteps, 1))
@@ -299,7 +300,9 @@ def _run_limited(self, u, nsteps, gamma=1.4, cfl=0.4, npic=None, dt_fixed=0.0, d
 
 
 def _limiter_detect(self, u_old, u_cand, gamma=1.4, delta0=1e-4, eps=1e-3):
-    """Troubled flags (1/0) of a candidate given the old solution."""
+    """Troubled flags of a candidate given the old solution: 1 troubled,
+    3 troubled with a hanging side (adaptive meshes: cannot be limited), 0
+    else."""
     u_old, u_cand = _f64(u_old), _f64(u_cand)
     flags = np.zeros(self.nc, dtype=np.int32)
     rc = lib().orc_limiter_detect(self._h, gamma, float(delta0), float(eps), _p(u_old), _p(u_cand), _p(flags))

@@ -918,7 +918,7 @@ int orc_sample(const orc_mesh *m, const double *u, const double *pts, long n, do
 /* ------------------------------------------------------------------------- */
 
 /* Feature-based criterion read in the corrector's epilogue (Sec. 2.3,
- * dynamic-adaptivity paragraph; Sec. 2.5: criteria study first or second
+ * dynamic-adaptivity paragraph; Sec. 2.4: criteria study first or second
  * derivatives of the solution, cell by cell).  Reading: the indicator of a
  * cell is the largest change of the density across the cell along any axis,
  *   eta_c = max_{nodes a, axes d} | d rho_h / d xi_d (x_a) |,
@@ -1075,8 +1075,8 @@ void orc_integral(const orc_mesh *m, const double *u, double *out)
 /* A-posteriori finite-volume subcell limiter                                */
 /* ------------------------------------------------------------------------- */
 
-/* The limiter of Sec. 3 (block-structured methods; Sec. 5, Euler with
- * shocks): after the ADER-DG update, a cell whose new solution is physically
+/* The limiter of Sec. 5.3 (block-structured methods) and Sec. 6 (Euler
+ * with shocks): after the ADER-DG update, a cell whose new solution is physically
  * wrong or oscillates is rolled back and advanced over the same dt by a
  * finite-volume scheme on (2p+1)^3 equal subcells.  Readings (the paper
  * leaves the details to the limiter's own literature):
@@ -1099,7 +1099,20 @@ void orc_integral(const orc_mesh *m, const double *u, double *out)
  *     cell's face flux is replaced by the L2 projection of the subcell face
  *     fluxes onto the face polynomials and its corrector is run again, so
  *     that both sides see the same flux (conservation).
- * Single-level meshes only (no hanging faces). */
+ * On adaptive meshes (Sec. 6: the solution is refined down to the FV level
+ * near shocks, so no resolution transition cuts an FV region) only cells
+ * whose six sides are conforming can be limited.  A troubled cell with a
+ * hanging side keeps its unlimited candidate and is reported (flag 3); the
+ * bounds of the relaxed maximum principle run over the cell and its
+ * conforming face neighbours. */
+
+/* 1 if every side of cell c is conforming (a same-level face neighbour). */
+static int all_conforming(const orc_mesh *m, long c)
+{
+    for (int s = 0; s < 6; ++s)
+        if (m->kind[6 * c + s] != SIDE_CONFORMING) return 0;
+    return 1;
+}
 
 /* 1-D subcell operators for N = p+1 nodes and ns = 2p+1 subintervals:
  *   A[s][k]    average of phi_k over subinterval s
@@ -1230,8 +1243,6 @@ int orc_limiter_detect(const orc_mesh *m, double g, double delta0, double eps, c
 {
     int N = m->N, ns = 2 * N - 1, S3 = ns * ns * ns;
     long nc = m->nc;
-    for (long k = 0; k < 6 * nc; ++k)
-        if (m->kind[k] != SIDE_CONFORMING) return 3;
     double A[(2 * MAXN - 1) * MAXN];
     if (orc_subcell_ops(N, A, NULL, NULL)) return 2;
     double *bnd = (double *)malloc(sizeof(double) * nc * 2 * NV);
@@ -1267,6 +1278,7 @@ int orc_limiter_detect(const orc_mesh *m, double g, double delta0, double eps, c
                 hi[v] = bnd[(c * 2 + 1) * NV + v];
             }
             for (int s = 0; s < 6; ++s) {
+                if (m->kind[6 * c + s] != SIDE_CONFORMING) continue;
                 long o = m->nbr[6 * c + s];
                 for (int v = 0; v < NV; ++v) {
                     if (bnd[(o * 2 + 0) * NV + v] < lo[v]) lo[v] = bnd[(o * 2 + 0) * NV + v];
@@ -1275,6 +1287,7 @@ int orc_limiter_detect(const orc_mesh *m, double g, double delta0, double eps, c
             }
             subcell_averages(N, nc, A, ucand, c, tmp);
             flags[c] = is_troubled(N, nc, g, ucand, c, tmp, lo, hi, delta0, eps);
+            if (flags[c] && !all_conforming(m, c)) flags[c] = 3;
         }
         free(tmp);
     }
@@ -1286,17 +1299,15 @@ int orc_limiter_detect(const orc_mesh *m, double g, double delta0, double eps, c
 #define VOLD(cell, v, s) vold[((long)(cell) * NV + (v)) * S3 + (s)]
 
 /* One limited ADER-DG step of size dt in place on u.  flags[nc] receives 1
- * for limited cells, 2 for unlimited cells whose corrector ran again, 0
- * otherwise.  force != 0 limits every cell (test hook).  Returns 0, 1 if the
- * final state is unphysical somewhere, 2 on allocation failure, 3 if the
- * mesh has a hanging face. */
+ * for limited cells, 2 for unlimited cells whose corrector ran again, 3 for
+ * troubled cells that cannot be limited (a hanging side), 0 otherwise.
+ * force != 0 limits every cell that can be limited (test hook).  Returns 0,
+ * 1 if the final state is unphysical somewhere, 2 on allocation failure. */
 int orc_limited_step(const orc_mesh *m, double g, int npic, double dt, double delta0, double eps, int force,
                      double *u, int *flags)
 {
     int N = m->N, N2 = N * N, N3 = N2 * N, ns = 2 * N - 1, S2 = ns * ns, S3 = S2 * ns;
     long nc = m->nc;
-    for (long k = 0; k < 6 * nc; ++k)
-        if (m->kind[k] != SIDE_CONFORMING) return 3;
     double A[(2 * MAXN - 1) * MAXN], Ap[MAXN * (2 * MAXN - 1)], B[MAXN * (2 * MAXN - 1)];
     if (orc_subcell_ops(N, A, Ap, B)) return 2;
     double xi[MAXN], w[MAXN], D[MAXN * MAXN], L[MAXN], R[MAXN], Kinv[MAXN * MAXN], Kw[MAXN * MAXN];
@@ -1328,7 +1339,7 @@ int orc_limited_step(const orc_mesh *m, double g, int npic, double dt, double de
     orc_corrector(m, dt, us, fs, un);
     /* detection (u still holds the old solution) */
     if (force) {
-        for (long c = 0; c < nc; ++c) flags[c] = 1;
+        for (long c = 0; c < nc; ++c) flags[c] = all_conforming(m, c) ? 1 : 3;
     } else if (orc_limiter_detect(m, g, delta0, eps, u, un, flags)) {
         free(vold); free(us); free(tr); free(fs); free(un);
         return 2;
@@ -1442,18 +1453,27 @@ int orc_limited_step(const orc_mesh *m, double g, int npic, double dt, double de
         free(vfit);
         free(Fsub);
     }
-    /* unlimited cells next to a limited one: corrector again with the new
+    /* unlimited cells next to a limited one (flag 2, or 3 kept for a
+     * troubled cell that cannot be limited): corrector again with the new
      * face fluxes (written out as in orc_corrector) */
+    unsigned char *rerun = (unsigned char *)calloc(nc > 0 ? nc : 1, 1);
+    if (!rerun) {
+        free(vold); free(us); free(tr); free(fs); free(un);
+        return 2;
+    }
     for (long c = 0; c < nc; ++c) {
         if (flags[c] == 1) continue;
         int near = 0;
         for (int s = 0; s < 6; ++s)
-            if (flags[m->nbr[6 * c + s]] == 1) near = 1;
-        if (near) flags[c] = 2;
+            if (m->kind[6 * c + s] == SIDE_CONFORMING && flags[m->nbr[6 * c + s]] == 1) near = 1;
+        if (near) {
+            rerun[c] = 1;
+            if (flags[c] == 0) flags[c] = 2;
+        }
     }
 #pragma omp parallel for schedule(static)
     for (long c = 0; c < nc; ++c) {
-        if (flags[c] != 2) continue;
+        if (!rerun[c]) continue;
         double dx[3];
         cell_dx(m, c, dx);
         for (int v = 0; v < NV; ++v)
@@ -1469,6 +1489,7 @@ int orc_limited_step(const orc_mesh *m, double g, int npic, double dt, double de
                 un[((long)v * nc + c) * N3 + a] = us[((long)v * nc + c) * N3 + a] - s;
             }
     }
+    free(rerun);
     memcpy(u, un, sizeof(double) * NV * nc * N3);
     int rc = 0;
     for (long c = 0; c < nc && !rc; ++c)
@@ -1510,8 +1531,8 @@ int orc_run_limited(const orc_mesh *m, double g, double cfl, int npic, double dt
 /* Linear PDE: elastic waves, space-time predictor by Cauchy-Kowalevski      */
 /* ------------------------------------------------------------------------- */
 
-/* The seismic variant (Sec. 2.1: a linear PDE is integrated in time by the
- * Cauchy-Kowalevski procedure instead of an iterative predictor; Sec. 5: the
+/* The seismic variant (Sec. 2.4: a linear PDE is integrated in time by the
+ * Cauchy-Kowalevski procedure instead of an iterative predictor; Sec. 6: the
  * seismic benchmark is elastic wave propagation with the material carried
  * along as time-constant unknowns).  Readings:
  *   - 3-D linear elasticity in velocity-stress form, 9 unknowns
