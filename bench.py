@@ -8,10 +8,14 @@ U[-0.01, 0.01] noise on the nodal density; CFL 0.4, Rusanov faces.
 The timed region runs K whole steps through adg_step (CFL reduction,
 predictor, Riemann, corrector, all on the device; dt never leaves the GPU) for
 the FP32 form (predictor, face data and Riemann in FP32; u, u*, dt and the
-corrector accumulation in FP64) and for the plain FP64 path.  `value` is the
-FP32 form's DoF-updates/s; the FP64 path is reported beside it.  Per-kernel
+corrector accumulation in FP64) and for the plain FP64 path.  Per-kernel
 durations come from HIP events the library records around every launch on
 the launch's own stream during the timed region.
+
+`value` is the plain FP64 path's DoF-updates/s (the paper's precision); the
+FP32 form is reported beside it under `paths`, each path with the roofline
+of its predictor kernel and a whole-step figure (algorithmic HBM bytes of the
+three phases per step over the measured time per step, against 8 TB/s).
 
 Prints ONE JSON line.
 """
@@ -55,6 +59,19 @@ def predictor_bytes_per_cell(N, real_bytes):
     """HBM bytes of the predictor per cell: read u, write u* (FP64), write the
     face projections (12 arrays x 5 variables x N^2 reals)."""
     return 2 * 5 * N ** 3 * 8 + 12 * 5 * N ** 2 * real_bytes
+
+
+def step_bytes_per_cell(N, real_bytes):
+    """Algorithmic HBM bytes of one whole step per cell of a uniform periodic
+    mesh (3 faces per cell): the predictor (read u, write u* and the 12 face
+    projection arrays), the Riemann solves (read both sides' state and normal
+    flux projections, write the flux both sides see), the corrector (read u*
+    and the 6 face fluxes, write u; the next step's CFL maximum is fused into
+    it).  The CFL final reduction reads one value per corrector block."""
+    pred = predictor_bytes_per_cell(N, real_bytes)
+    riem = 3 * 6 * 5 * N ** 2 * real_bytes
+    corr = 2 * 5 * N ** 3 * 8 + 6 * 5 * N ** 2 * real_bytes
+    return pred + riem + corr
 
 
 def cpu_baseline(budget_s=12.0):
@@ -140,37 +157,57 @@ def run_path(A, precision, u0, steps, warmup):
     return res
 
 
-def run_amr(A, steps=50):
+def run_amr(A, steps=50, sharp=False):
     """Adaptive mesh: 27^3 base cells, two levels of 3:1 refinement in the
-    sphere |x - c| <= 0.25 (1,074,035 cells), p = 4, blast wave with its
-    interface smoothed over one finest cell, FP32 form; skeleton predictor on
-    one stream, enclave predictor on another (default priorities)."""
+    sphere |x - c| <= 0.25 (1,074,035 cells), p = 4, FP32 form.  The blast
+    wave with its interface smoothed over one finest cell (sharp=False), or
+    the sharp blast with the a-posteriori subcell limiter (sharp=True).
+    Timed both ways: the skeleton/enclave split on the handle's two streams
+    (two different caller streams passed), and every phase on one stream."""
     import torch
     from paper_1806_07984_amd import inputs
     n = (27, 27, 27)
     ref = inputs.sphere_refine_list(n, 2, radius=0.25)
     mesh = A.Mesh(A.instance(4, n, max_level=2, refine=ref), "fp32")
     xyz = mesh.node_coords().cpu().numpy().reshape(3, -1)
-    u = torch.from_numpy(inputs.blast_smooth(xyz, width=1.0 / (27 * 9)).reshape(-1)).cuda()
-    del xyz
+    state = inputs.blast(xyz) if sharp else inputs.blast_smooth(xyz, width=1.0 / (27 * 9))
+    u0 = torch.from_numpy(state.reshape(-1)).cuda()
+    del xyz, state
+    if sharp:
+        mesh.set_limiter(1, 1e-4, 1e-3)
     ws = mesh.empty_workspace()
     s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
-    s1.wait_stream(torch.cuda.current_stream())
-    mesh.step(u, 1, ws, stream_skeleton=s1, stream_enclave=s2)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    mesh.step(u, steps, ws, stream_skeleton=s1, stream_enclave=s2)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    mesh.status()
+    cur = torch.cuda.current_stream()
+    times = {}
+    for mode in ("two streams", "one stream"):
+        u = u0.clone()
+        a, b = (s1, s2) if mode == "two streams" else (cur, cur)
+        a.wait_stream(cur)
+        b.wait_stream(cur)
+        mesh.step(u, 1, ws, stream_skeleton=a, stream_enclave=b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mesh.step(u, steps, ws, stream_skeleton=a, stream_enclave=b)
+        torch.cuda.synchronize()
+        times[mode] = time.perf_counter() - t0
+        mesh.status()
+    el = times["two streams"]
     info = mesh.info
     out = {"value": info["n_dofs"] * steps / el, "unit": "DoF-updates/s", "ms_per_step": el * 1e3 / steps,
            "steps": steps, "cells": info["n_cells"], "dofs": info["n_dofs"],
            "hanging_faces": info["n_hanging_faces"], "skeleton_cells": info["n_skeleton_cells"],
-           "path": "fp32, skeleton/enclave streams",
-           "adaptation": adapt_once(A, mesh, u, 0.05, 0.005)}
+           "state": "sharp blast, subcell limiter" if sharp else "blast smoothed over one finest cell",
+           "path": "fp32, skeleton/enclave split on two streams",
+           "ms_per_step_by_streams": {k: v * 1e3 / steps for k, v in times.items()}}
+    if sharp:
+        nl, nr, fl = mesh.limiter_stats(flags=True)
+        out["limited_cells_last_step"] = nl
+        out["rerun_cells_last_step"] = nr
+        out["troubled_not_limitable_last_step"] = int(((fl == 3) | (fl == 4)).sum().item())
+    else:
+        out["adaptation"] = adapt_once(A, mesh, u, 0.05, 0.005)
     mesh.close()
-    del u, ws
+    del u, u0, ws
     torch.cuda.empty_cache()
     return out
 
@@ -395,7 +432,8 @@ def main():
     ap.add_argument("--only", choices=["fp64", "fp32"], default=None,
                     help="run one path only (for profiling runs)")
     ap.add_argument("--no-extra", action="store_true", help="skip the AMR and batch workloads")
-    ap.add_argument("--extra-only", choices=["amr", "batch", "adjoint", "limiter", "linear"], default=None,
+    ap.add_argument("--extra-only", choices=["amr", "amr_sharp", "batch", "adjoint", "limiter", "linear"],
+                    default=None,
                     help="run only one of the other workloads and print its JSON (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB buffer 3 times (calibrates HBM byte counters) and exit")
@@ -419,8 +457,8 @@ def main():
 
     A.load()
     if args.extra_only:
-        res = {"amr": run_amr, "batch": run_batch, "adjoint": run_adjoint,
-               "limiter": run_limiter, "linear": run_linear}[args.extra_only](A)
+        res = {"amr": run_amr, "amr_sharp": lambda A: run_amr(A, sharp=True), "batch": run_batch,
+               "adjoint": run_adjoint, "limiter": run_limiter, "linear": run_linear}[args.extra_only](A)
         print(json.dumps({"workload": args.extra_only, **res}))
         return
     # initial state: node coordinates from the library, analytic state + seeded noise on the host
@@ -430,16 +468,29 @@ def main():
     u0 = torch.from_numpy(inputs.density_wave_noisy(xyz, seed=SEED, noise=0.01).reshape(-1)).cuda()
     del xyz
 
-    paths = ["fp32", "fp64"] if args.only is None else [args.only]
+    paths = ["fp64", "fp32"] if args.only is None else [args.only]
     res = {p: run_path(A, p, u0, args.steps, args.warmup) for p in paths}
-    head = res.get("fp32", res.get("fp64"))
-    head_prec = "fp32" if "fp32" in res else "fp64"
-    pr = head["predictor"]
-    if head_prec == "fp32":
-        bound, peak = "alu", PEAK["fp32_TFs"]
-    else:
-        bound, peak = "alu", PEAK["fp64_TFs"]
-    traffic = load_traffic(f"predictor_{head_prec}")
+    head_prec = "fp64" if "fp64" in res else "fp32"
+    head = res[head_prec]
+    kernels = {"fp64": "adg::k_predictor4_f64", "fp32": "adg::k_predictor4_mfma"}
+    nc = N_BASE ** 3
+    N = ORDER + 1
+
+    def roofline(prec):
+        pr = res[prec]["predictor"]
+        peak = PEAK["fp64_TFs"] if prec == "fp64" else PEAK["fp32_TFs"]
+        return {"bound": "alu", "achieved": pr["tflops"], "peak": peak, "unit": "TFLOP/s",
+                "frac": pr["tflops"] / peak, "traffic": load_traffic(f"predictor_{prec}"),
+                "kernel": kernels[prec], "avg_launch_ms": pr["avg_ms"],
+                "flops_per_launch": pr["flops_per_launch"], "bytes_per_launch": pr["bytes_per_launch"],
+                "hbm_GBs_algorithmic": pr["bytes_per_launch"] / (pr["avg_ms"] * 1e-3) / 1e9}
+
+    def whole_step(prec):
+        b = step_bytes_per_cell(N, 8 if prec == "fp64" else 4) * nc
+        ms = res[prec]["ms_per_step"]
+        gbs = b / (ms * 1e-3) / 1e9
+        return {"bound": "hbm", "bytes_per_step": b, "achieved": gbs, "peak": PEAK["hbm_GBs"], "unit": "GB/s",
+                "frac": gbs / PEAK["hbm_GBs"]}
     out = {
         "metric": "DoF-updates/s, 3D Euler ADER-DG p=3-5: FP64 plain vs FP32-MFMA batched; % roofline",
         "value": head["value"],
@@ -451,19 +502,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if head_prec == "fp32" else "f64",
+        "dtype": "f64" if head_prec == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": "euler3d_aderdg_p3_periodic_81cubed_density_wave_noise", "order": ORDER,
                    "cells": N_BASE ** 3, "dofs": 5 * N_BASE ** 3 * (ORDER + 1) ** 3, "path": head_prec,
                    "parallelism": "single-gpu"},
-        "roofline": {"bound": bound, "achieved": pr["tflops"], "peak": peak, "unit": "TFLOP/s",
-                     "frac": pr["tflops"] / peak, "traffic": traffic,
-                     "kernel": "adg::k_predictor4_mfma" if head_prec == "fp32" else "adg::k_predictor<double, 4, 4, false>",
-                     "avg_launch_ms": pr["avg_ms"],
-                     "hbm_GBs_algorithmic": pr["bytes_per_launch"] / (pr["avg_ms"] * 1e-3) / 1e9},
+        "roofline": roofline(head_prec),
+        "whole_step_roofline": whole_step(head_prec),
         "paths": {k: {"value": v["value"], "ms_per_step": v["ms_per_step"],
+                      "dtype": "f64" if k == "fp64" else "f32+f64",
                       "phases_ms_per_step": v["phases_ms_per_step"],
-                      "predictor_tflops": v["predictor"]["tflops"]} for k, v in res.items()},
+                      "roofline": roofline(k), "whole_step_roofline": whole_step(k)} for k, v in res.items()},
     }
     if not args.no_extra:
         out["other_workloads"] = {"amr_blast_p4_27cubed_2levels": run_amr(A),

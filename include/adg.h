@@ -64,8 +64,10 @@ typedef enum {
 typedef enum {
     ADG_FP64 = 0,       /* every step in FP64                                    */
     ADG_FP32_MFMA = 1   /* predictor, traces, Riemann in FP32; for p = 3 the
-                           predictor's z contraction and time solve run on MFMA
-                           (other orders on the vector units); u, u*, dt and the
+                           predictor's time solve runs on MFMA (4x4x1 FP32
+                           blocks) and its spatial derivative contractions on
+                           the vector units (DPP and ds_bpermute); other orders
+                           run wholly on the vector units; u, u*, dt and the
                            corrector accumulation stay FP64                        */
 } adg_precision;
 
@@ -155,14 +157,23 @@ adg_status adg_corrector(adg_mesh *mesh, const double *ustar_dev, const void *fs
                          const double *dt_dev, double *u_out_dev, hipStream_t stream);
 
 /* n_steps whole steps in place on u_dev (cfl -> predictor -> riemann ->
- * corrector per step).  ws_dev must hold workspace_bytes.  dt_hist_dev, if not
- * NULL, receives n_steps * n_instances doubles (step-major).  Skeleton cells
- * (cells at a resolution transition) run their predictor on stream_skeleton
- * and the hanging-face work follows them there; enclave cells run on
- * stream_enclave; both streams are joined before the corrector.  Passing the
- * same stream twice serialises the phases.  Results do not depend on the
- * schedule. */
-adg_status adg_step(adg_mesh *mesh, double *u_dev, int32_t n_steps, double *dt_hist_dev,
+ * corrector per step).  t_end > 0 is an end time, measured from the state
+ * the call starts from: every step takes dt = min(dt_cfl, t_end - t), so the
+ * last step lands on t_end exactly and any further steps of the call have
+ * dt = 0 and leave u unchanged (per instance; the clock stays on the device).
+ * t_end <= 0: no end time.  ws_dev must hold workspace_bytes.  dt_hist_dev,
+ * if not NULL, receives n_steps * n_instances doubles (step-major).
+ * Passing two different streams splits each step (Sec. 3): the skeleton
+ * cells (cells at a resolution transition) run their predictor first and the
+ * hanging-face work follows them on one of the handle's two streams, the
+ * enclave cells' predictor runs on the other, and the two join before the
+ * conforming faces and the corrector.  The handle's streams are created one
+ * after the other at init, so the runtime gives them different hardware
+ * queues (a caller's streams may share one); they are ordered after both
+ * caller streams at the start and both caller streams after them at the
+ * end.  Passing the same stream twice runs every phase on that stream.
+ * Results do not depend on the schedule. */
+adg_status adg_step(adg_mesh *mesh, double *u_dev, int32_t n_steps, double t_end, double *dt_hist_dev,
                     void *ws_dev, hipStream_t stream_skeleton, hipStream_t stream_enclave);
 
 /* Batched handles (more than one instance, none with hanging faces) run the
@@ -205,8 +216,8 @@ adg_status adg_set_options(adg_mesh *mesh, int32_t use_graph, int32_t batched);
  * (locality only); it is slower (3.26 ms). */
 adg_status adg_set_pipeline(adg_mesh *mesh, int32_t enable);
 
-/* A-posteriori finite-volume subcell limiter (Sec. 3, block-structured
- * methods; Sec. 5, Euler with shocks: a cell whose ADER-DG update is
+/* A-posteriori finite-volume subcell limiter (Sec. 5.3, block-structured
+ * methods; Sec. 6, Euler with shocks: a cell whose ADER-DG update is
  * physically wrong or oscillates is rolled back and advanced over the same dt
  * by FV on (2p+1)^3 subcells).  With the limiter on, every adg_step step:
  *   1. takes the old subcell data of every cell: the averages of its
@@ -227,18 +238,25 @@ adg_status adg_set_pipeline(adg_mesh *mesh, int32_t enable);
  *      unlimited cell's face flux by the L2 projection of the subcell fluxes
  *      onto the face polynomials and runs its corrector again (the scheme
  *      stays conservative).
- * mode: 0 off, 1 on, 2 every cell limited (test hook).  delta0, eps >= 0
- * (1e-4 and 1e-3 are usual).  The first enable allocates the limiter's
- * device buffers (about one more state array); they live until
- * adg_free_mesh.  ADG_ERR_UNSUPPORTED unless the handle has one instance,
- * a uniform mesh (max_level 0) and p <= 6.  While on, adg_set_pipeline has no
- * effect, the step runs on s_skel only, and the candidate's inadmissible
- * states are not errors: only an unphysical final state sets the status
- * adg_get_status reports.  Synchronises the device. */
+ * On adaptive meshes only cells whose six sides are conforming (same-level
+ * face neighbours) can be limited: the paper refines down to the FV level
+ * near shocks, so no resolution transition cuts an FV region (Sec. 6).  A
+ * troubled cell with a hanging side keeps its unlimited candidate (flag 3,
+ * or 4 when its corrector ran again next to a limited cell); the relaxed
+ * bounds use the cell and its same-level face neighbours.
+ * mode: 0 off, 1 on, 2 every cell limited (test hook; every cell that can
+ * be).  delta0, eps >= 0 (1e-4 and 1e-3 are usual).  The first enable
+ * allocates the limiter's device buffers (about one more state array); they
+ * live until adg_free_mesh.  ADG_ERR_UNSUPPORTED unless the handle has one
+ * instance and p <= 6.  While on, adg_set_pipeline has no effect, the step
+ * runs on s_skel only, and the candidate's inadmissible states are not
+ * errors: only an unphysical final state sets the status adg_get_status
+ * reports.  Synchronises the device. */
 adg_status adg_set_limiter(adg_mesh *mesh, int32_t mode, double delta0, double eps);
 /* Of the last limited step: the number of limited cells and of cells whose
  * corrector ran again; flags_dev (device, nc int32, may be NULL) receives per
- * cell 1 limited, 2 corrector re-run, 0 otherwise.  Synchronises stream.
+ * cell 1 limited, 2 corrector re-run, 3 troubled but not limitable (a
+ * hanging side), 4 the same with its corrector re-run, 0 otherwise.  Synchronises stream.
  * ADG_ERR_INVALID_ARG if the limiter was never enabled on the handle. */
 adg_status adg_limiter_stats(adg_mesh *mesh, int64_t *n_limited, int64_t *n_recorrected, int32_t *flags_dev,
                              hipStream_t stream);
@@ -265,8 +283,12 @@ adg_status adg_profile_read(adg_mesh *mesh, double *ms, int64_t *launches);
  * maximiser in (node, minus side first) order; |x|' = 0 at 0), then the
  * predictor (time averages, volume term and face projections, then the
  * Picard iterations in reverse, with the forward iterates recomputed and
- * stored in ws_dev).  FP64 handles with uniform meshes and the limiter off
- * only (ADG_ERR_UNSUPPORTED otherwise).  ws_dev holds adjoint_workspace_bytes;
+ * stored in ws_dev).  On adaptive meshes (Sec. 2.3) the restriction's
+ * transpose sends each coarse side's adjoint to its child faces, and the
+ * transpose of the interpolation to virtual cells gathers the child faces'
+ * virtual-side adjoints into the coarse side in a fixed order.  FP64 handles
+ * with the limiter off only (ADG_ERR_UNSUPPORTED otherwise).  ws_dev holds
+ * adjoint_workspace_bytes;
  * ubar_n_dev must not alias ubar_np1_dev. */
 adg_status adg_step_adjoint(adg_mesh *mesh, const double *u_n_dev, const double *dt_dev,
                             const double *ubar_np1_dev, double *ubar_n_dev, void *ws_dev,
@@ -287,7 +309,9 @@ adg_status adg_set_switch_tape(adg_mesh *mesh, int16_t *tape_dev, int32_t mode);
  * is the cell containing pts_dev[3s..3s+2] (floor of the cell coordinate,
  * clamped into the grid, so a point on a face goes to the upper cell).
  * adg_sample_adjoint ADDS wbar_dev[s] phi_a(x_s) into the density part of
- * ubar_dev, point by point in order (deterministic). */
+ * ubar_dev: the points of one cell are summed in increasing s, then added
+ * (deterministic).  Its work grows with the square of n_pts (meant for up
+ * to about 10^4 points); n_pts below 2^31. */
 adg_status adg_sample(adg_mesh *mesh, const double *u_dev, const double *pts_dev, int64_t n_pts,
                       double *out_dev, hipStream_t stream);
 adg_status adg_sample_adjoint(adg_mesh *mesh, const double *pts_dev, const double *wbar_dev, int64_t n_pts,
@@ -337,9 +361,9 @@ adg_status adg_get_status(adg_mesh *mesh);
 /* ------------------------------------------------------------------------ */
 /* Linear variant: elastic waves, Cauchy-Kowalevski predictor                */
 /* ------------------------------------------------------------------------ */
-/* The seismic variant of the method (Sec. 2.1: for a linear PDE the
+/* The seismic variant of the method (Sec. 2.4: for a linear PDE the
  * space-time predictor is the Cauchy-Kowalevski procedure instead of an
- * iteration; Sec. 5: elastic wave propagation with the material carried as
+ * iteration; Sec. 6: elastic wave propagation with the material carried as
  * time-constant unknowns).  3-D linear elasticity in velocity-stress form,
  * 9 unknowns q = (s_xx, s_yy, s_zz, s_xy, s_yz, s_xz, v_x, v_y, v_z),
  *   d_t s_ij = lambda delta_ij div v + mu (d_i v_j + d_j v_i),

@@ -83,7 +83,7 @@ def load():
         "adg_predictor": [P, P, P, P, P, P],
         "adg_riemann": [P, P, P, P],
         "adg_corrector": [P, P, P, P, P, P],
-        "adg_step": [P, P, I32, P, P, P, P],
+        "adg_step": [P, P, I32, ctypes.c_double, P, P, P, P],
         "adg_get_status": [P],
         "adg_profile": [P, I32],
         "adg_profile_read": [P, P, P],
@@ -298,8 +298,9 @@ class Mesh:
                                     _ptr(dt, torch.float64, self.n_instances, "dt"),
                                     _ptr(uout, torch.float64, n, "uout"), _stream(stream)))
 
-    def step(self, u, n_steps, ws, dt_hist=None, stream_skeleton=None, stream_enclave=None):
-        """n_steps whole steps in place on u (adg_step)."""
+    def step(self, u, n_steps, ws, dt_hist=None, stream_skeleton=None, stream_enclave=None, t_end=0.0):
+        """n_steps whole steps in place on u (adg_step); t_end > 0 stops the
+        run at that time, measured from the state's time at the call."""
         import torch
         hist = ctypes.c_void_p(0) if dt_hist is None else \
             _ptr(dt_hist, torch.float64, n_steps * self.n_instances, "dt_hist")
@@ -307,8 +308,8 @@ class Mesh:
         s2 = _stream(stream_enclave) if stream_enclave is not None else s1
         if ws.numel() < self.info["workspace_bytes"]:
             raise ValueError("workspace too small")
-        _check(load().adg_step(self._h, _ptr(u, torch.float64, self.info["u_elems"], "u"), int(n_steps), hist,
-                               ctypes.c_void_p(ws.data_ptr()), s1, s2))
+        _check(load().adg_step(self._h, _ptr(u, torch.float64, self.info["u_elems"], "u"), int(n_steps),
+                               float(t_end), hist, ctypes.c_void_p(ws.data_ptr()), s1, s2))
 
     def autotune(self, u, ws, stream=None):
         """Pick the cells per work item of every order by timing (adg_autotune)."""

@@ -60,6 +60,10 @@ struct adg_mesh {
     std::vector<void *> allocs;
     int *status_dev = nullptr;
     double *dt_dev = nullptr;  // one per instance
+    // end time of the current adg_step call (0: none) and the time reached
+    // since the call started, per instance (device)
+    double t_end = 0.0;
+    double *clock_dev = nullptr;
     hipEvent_t ev_dt = nullptr, ev_skel = nullptr, ev_encl = nullptr;
     adg_info info{};
     // phase timing (adg_profile)
@@ -90,6 +94,7 @@ struct adg_mesh {
     hipGraphExec_t gexec = nullptr;
     const void *gkey_u = nullptr, *gkey_ws = nullptr;
     bool gkey_two = false;
+    double gkey_tend = 0.0;
     // pipelined step: predictors chunk by chunk on one stream, the faces and
     // correctors of finished chunks on another
     int pipeline = 0;                 // 0 off, 1 two streams, 2 one stream (chunk by chunk)
@@ -257,6 +262,14 @@ struct PhaseTimer {
         return m->ev_pool[m->ev_used++];
     }
 };
+
+// doubles of the Picard iterates the adjoint step stores (all instances)
+int64_t adjoint_iter_elems(const adg_mesh *m)
+{
+    int64_t n = 0;
+    for (const auto &I : m->inst) n += int64_t(I.npic) * I.N * NV * I.nc * I.N * I.N * I.N;
+    return n;
+}
 
 bool valid_mesh(const adg_mesh *m)
 {
@@ -464,7 +477,7 @@ adg_status do_cfl_fused(adg_mesh *m, double *dt, double *hist, hipStream_t st)
     for (size_t i = 0; i < m->inst.size(); ++i) {
         Instance &I = m->inst[i];
         ADG_HIP(launch_cfl_final(I.partial, nparts(m, I), I.cfl / (2.0 * I.order + 1.0), dt + i,
-                                 hist ? hist + i : nullptr, st),
+                                 hist ? hist + i : nullptr, st, m->t_end, m->t_end > 0.0 ? m->clock_dev + i : nullptr),
                 "cfl final");
     }
     return ADG_OK;
@@ -563,6 +576,8 @@ adg_status enqueue_step_limited(adg_mesh *m, double *u, double *hist, void *ws, 
     {
         StatusSink sink(m);
         s = do_predictor<T>(m, u, m->dt_dev, ustar, traces, st, st, false);
+        if (s != ADG_OK) return s;
+        s = do_hanging<T>(m, traces, fside, st);
         if (s != ADG_OK) return s;
         s = do_conforming<T>(m, traces, fside, st);
         if (s != ADG_OK) return s;
@@ -703,6 +718,27 @@ adg_status step_eager(adg_mesh *m, double *u, int32_t n_steps, double *hist, voi
         return ADG_OK;
     }
     const int ni = int(m->inst.size());
+    if (s_skel != s_encl && !m->lim_mode) {
+        // Skeleton/enclave split on the handle's two streams, created at
+        // init one after the other, so that the runtime gives them different
+        // hardware queues (a caller's streams may share one); joined with
+        // the caller's streams by events before and after.
+        hipStream_t A = m->gs_a, B = m->gs_b;
+        ADG_HIP(hipEventRecord(m->ev_in, s_skel), "event record");
+        ADG_HIP(hipStreamWaitEvent(A, m->ev_in, 0), "stream wait");
+        ADG_HIP(hipEventRecord(m->ev_in2, s_encl), "event record");
+        ADG_HIP(hipStreamWaitEvent(A, m->ev_in2, 0), "stream wait");
+        adg_status st0 = do_cfl_prime(m, u, A);
+        if (st0 != ADG_OK) return st0;
+        for (int n = 0; n < n_steps; ++n) {
+            adg_status st = enqueue_step<T>(m, u, hist ? hist + int64_t(n) * ni : nullptr, ws, A, B);
+            if (st != ADG_OK) return st;
+        }
+        ADG_HIP(hipEventRecord(m->ev_out, A), "event record");
+        ADG_HIP(hipStreamWaitEvent(s_skel, m->ev_out, 0), "stream wait");
+        ADG_HIP(hipStreamWaitEvent(s_encl, m->ev_out, 0), "stream wait");
+        return ADG_OK;
+    }
     adg_status st0 = do_cfl_prime(m, u, s_skel);
     if (st0 != ADG_OK) return st0;
     st0 = do_lim_prime(m, u, s_skel);
@@ -712,7 +748,7 @@ adg_status step_eager(adg_mesh *m, double *u, int32_t n_steps, double *hist, voi
         if (st != ADG_OK) return st;
     }
     if (s_skel != s_encl) {
-        // leave both streams ordered after the last corrector
+        // the limited step runs on s_skel only: leave s_encl ordered after it
         ADG_HIP(hipEventRecord(m->ev_skel, s_skel), "event record");
         ADG_HIP(hipStreamWaitEvent(s_encl, m->ev_skel, 0), "stream wait");
     }
@@ -741,7 +777,7 @@ adg_status step_graph(adg_mesh *m, double *u, int32_t n_steps, double *hist, voi
         st0 = do_lim_prime(m, u, A);
         if (st0 != ADG_OK) return st0;
     }
-    if (!m->gexec || m->gkey_u != u || m->gkey_ws != ws || m->gkey_two != two) {
+    if (!m->gexec || m->gkey_u != u || m->gkey_ws != ws || m->gkey_two != two || m->gkey_tend != m->t_end) {
         drop_graph(m);
         ADG_HIP(hipStreamBeginCapture(A, hipStreamCaptureModeThreadLocal), "begin capture");
         adg_status st = m->pipeline && !m->lim_mode ? enqueue_step_pipe<T>(m, u, nullptr, ws, A, B)
@@ -758,6 +794,7 @@ adg_status step_graph(adg_mesh *m, double *u, int32_t n_steps, double *hist, voi
         m->gkey_u = u;
         m->gkey_ws = ws;
         m->gkey_two = two;
+        m->gkey_tend = m->t_end;
     }
     const int ni = int(m->inst.size());
     for (int n = 0; n < n_steps; ++n) {
@@ -772,11 +809,23 @@ adg_status step_graph(adg_mesh *m, double *u, int32_t n_steps, double *hist, voi
     return ADG_OK;
 }
 
+// Starts the clock of a run to t_end (t_end <= 0: no end time) on s_skel,
+// ahead of everything the step sequence enqueues.
+adg_status start_clock(adg_mesh *m, double t_end, hipStream_t s_skel)
+{
+    m->t_end = t_end > 0.0 ? t_end : 0.0;
+    if (m->t_end > 0.0)
+        ADG_HIP(launch_fill(m->clock_dev, int64_t(m->inst.size()), 0.0, s_skel), "clock reset");
+    return ADG_OK;
+}
+
 template <typename T>
-adg_status step_impl(adg_mesh *m, double *u, int32_t n_steps, double *hist, void *ws, hipStream_t s_skel,
-                     hipStream_t s_encl)
+adg_status step_impl(adg_mesh *m, double *u, int32_t n_steps, double t_end, double *hist, void *ws,
+                     hipStream_t s_skel, hipStream_t s_encl)
 {
     if (n_steps == 0) return ADG_OK;
+    adg_status st = start_clock(m, t_end, s_skel);
+    if (st != ADG_OK) return st;
     if (m->use_graph && !m->prof && m->tape_mode == 0) return step_graph<T>(m, u, n_steps, hist, ws, s_skel, s_encl);
     return step_eager<T>(m, u, n_steps, hist, ws, s_skel, s_encl);
 }
@@ -995,7 +1044,8 @@ adg_status adg_init_mesh(const adg_instance_desc *desc, int32_t n_instances, adg
             std::vector<int32_t>().swap(h.face_p[a]);
         }
     }
-    ok = ok && dev_alloc(m, m->status_dev, 1) && dev_alloc(m, m->dt_dev, size_t(n_instances));
+    ok = ok && dev_alloc(m, m->status_dev, 1) && dev_alloc(m, m->dt_dev, size_t(n_instances)) &&
+         dev_alloc(m, m->clock_dev, size_t(n_instances));
     if (ok) {
         hipDeviceProp_t prop;
         ok = hipGetDeviceProperties(&prop, m->device) == hipSuccess;
@@ -1055,12 +1105,15 @@ adg_status adg_init_mesh(const adg_instance_desc *desc, int32_t n_instances, adg
     inf.n_skeleton_cells = nskel;
     inf.real_bytes = rb;
     {
-        // adjoint workspace: u*, traces, their adjoint, face-flux adjoint (FP64), Picard iterates
-        int64_t iters = 0;
-        for (auto &I : m->inst) iters += int64_t(I.npic) * I.N * NV * I.nc * I.N * I.N * I.N;
+        // adjoint workspace: u*, traces, their adjoint, face-flux adjoint (FP64), Picard iterates, the
+        // virtual-cell adjoints of the hanging faces
+        int64_t vb = 0;
+        for (auto &I : m->inst) vb += I.nh * 2 * NV * I.N * I.N;
         inf.adjoint_workspace_bytes =
             int64_t(align_up(sizeof(double) * u_off) + 2 * align_up(sizeof(double) * tr_off) +
-                    align_up(sizeof(double) * fs_off) + align_up(sizeof(double) * std::max<int64_t>(iters, 1)));
+                    align_up(sizeof(double) * fs_off) +
+                    align_up(sizeof(double) * std::max<int64_t>(adjoint_iter_elems(m), 1)) +
+                    align_up(sizeof(double) * std::max<int64_t>(vb, 1)));
     }
     *out = m;
     return ADG_OK;
@@ -1181,8 +1234,8 @@ adg_status adg_corrector(adg_mesh *mesh, const double *ustar, const void *fside,
     return do_corrector<float>(mesh, ustar, static_cast<const float *>(fside), dt, uout, stream);
 }
 
-adg_status adg_step(adg_mesh *mesh, double *u, int32_t n_steps, double *dt_hist, void *ws, hipStream_t s_skel,
-                    hipStream_t s_encl)
+adg_status adg_step(adg_mesh *mesh, double *u, int32_t n_steps, double t_end, double *dt_hist, void *ws,
+                    hipStream_t s_skel, hipStream_t s_encl)
 {
     if (!valid_mesh(mesh) || !u || !ws || n_steps < 0) {
         set_error("adg_step: null argument or negative step count");
@@ -1192,8 +1245,8 @@ adg_status adg_step(adg_mesh *mesh, double *u, int32_t n_steps, double *dt_hist,
         set_error("adg_step: workspace must be 256-byte aligned");
         return ADG_ERR_WORKSPACE;
     }
-    if (mesh->prec == ADG_FP64) return step_impl<double>(mesh, u, n_steps, dt_hist, ws, s_skel, s_encl);
-    return step_impl<float>(mesh, u, n_steps, dt_hist, ws, s_skel, s_encl);
+    if (mesh->prec == ADG_FP64) return step_impl<double>(mesh, u, n_steps, t_end, dt_hist, ws, s_skel, s_encl);
+    return step_impl<float>(mesh, u, n_steps, t_end, dt_hist, ws, s_skel, s_encl);
 }
 
 adg_status adg_autotune(adg_mesh *mesh, const double *u, void *ws, hipStream_t stream)
@@ -1265,12 +1318,8 @@ adg_status adg_set_limiter(adg_mesh *mesh, int32_t mode, double delta0, double e
         set_error("adg_set_limiter: mode must be 0, 1 or 2 and delta0, eps non-negative");
         return ADG_ERR_INVALID_ARG;
     }
-    // one face per cell side on every axis (periodic uniform mesh): the
-    // neighbour table is then complete
-    if (mode && (mesh->inst.size() != 1 || mesh->inst[0].level != nullptr || mesh->inst[0].N > LIM_NMAX ||
-                 mesh->inst[0].nf[0] != mesh->inst[0].nc || mesh->inst[0].nf[1] != mesh->inst[0].nc ||
-                 mesh->inst[0].nf[2] != mesh->inst[0].nc)) {
-        set_error("adg_set_limiter: the limiter needs a single instance on a uniform mesh with p <= 6");
+    if (mode && (mesh->inst.size() != 1 || mesh->inst[0].N > LIM_NMAX)) {
+        set_error("adg_set_limiter: the limiter needs a single instance with p <= 6");
         return ADG_ERR_UNSUPPORTED;
     }
     DeviceGuard dg(mesh->device);
@@ -1290,6 +1339,9 @@ adg_status adg_set_limiter(adg_mesh *mesh, int32_t mode, double delta0, double e
         ADG_HIP(hipMemset(L.flag, 0, nc * sizeof(int32_t)), "limiter flags");
         ADG_HIP(hipMemset(L.cnt, 0, 2 * sizeof(int32_t)), "limiter counters");
         ADG_HIP(hipMemset(mesh->lim_status, 0, sizeof(int)), "limiter status sink");
+        // same-level neighbours from the conforming faces; -1 marks a hanging side
+        ADG_HIP(hipMemset(L.nbr, 0xff, 6 * nc * sizeof(int32_t)), "neighbour table");
+        L.level = I.level;
         for (int d = 0; d < 3; ++d)
             ADG_HIP(launch_lim_nbr(I.face_m[d], I.face_p[d], I.nf[d], d, I.nc, L.nbr, nullptr), "neighbour table");
         ADG_HIP(hipDeviceSynchronize(), "synchronize");
@@ -1389,11 +1441,6 @@ adg_status adg_step_adjoint(adg_mesh *mesh, const double *u, const double *dt, c
         set_error("adg_step_adjoint: the adjoint is that of the unlimited step; switch the limiter off");
         return ADG_ERR_UNSUPPORTED;
     }
-    for (const auto &I : mesh->inst)
-        if (I.hm.max_level > 0) {
-            set_error("adg_step_adjoint: adaptive meshes are not supported");
-            return ADG_ERR_UNSUPPORTED;
-        }
     char *w = static_cast<char *>(ws);
     double *ustar = reinterpret_cast<double *>(w);
     w += align_up(sizeof(double) * mesh->info.u_elems);
@@ -1404,15 +1451,28 @@ adg_status adg_step_adjoint(adg_mesh *mesh, const double *u, const double *dt, c
     double *fbar = reinterpret_cast<double *>(w);
     w += align_up(sizeof(double) * mesh->info.fside_elems);
     double *iters = reinterpret_cast<double *>(w);
+    w += align_up(sizeof(double) * std::max<int64_t>(adjoint_iter_elems(mesh), 1));
+    double *vbar = reinterpret_cast<double *>(w);
     for (size_t i = 0; i < mesh->inst.size(); ++i) {
         Instance &I = mesh->inst[i];
         const int32_t *fm[3] = {I.face_m[0], I.face_m[1], I.face_m[2]};
         const int32_t *fp[3] = {I.face_p[0], I.face_p[1], I.face_p[2]};
+        AdjHang ah;
+        ah.hang = I.hang;
+        ah.nh = I.nh;
+        ah.ccell = I.ccell;
+        ah.cptr = I.cptr;
+        ah.cchild = I.cchild;
+        ah.cside = I.cside;
+        ah.ncs = I.ncs;
+        ah.ptab = I.ptab;
+        ah.vbar = vbar;
         ADG_HIP(launch_adjoint_step(I.N, u + I.u_off, dt + i, ubar_next + I.u_off, ubar + I.u_off, ustar + I.u_off,
                                     traces + I.tr_off, tbar + I.tr_off, fbar + I.fs_off, iters, fm, fp, I.nf, I.nc,
-                                    I.geo, I.gamma, I.npic, stream),
+                                    I.level, I.geo, I.gamma, I.npic, ah, stream),
                 "adjoint step");
         iters += int64_t(I.npic) * I.N * NV * I.nc * I.N * I.N * I.N;
+        vbar += I.nh * 2 * NV * I.N * I.N;
     }
     return ADG_OK;
 }
@@ -1450,7 +1510,7 @@ adg_status adg_sample(adg_mesh *mesh, const double *u, const double *pts, int64_
 adg_status adg_sample_adjoint(adg_mesh *mesh, const double *pts, const double *wbar, int64_t n_pts, double *ubar,
                               hipStream_t stream)
 {
-    if (!valid_mesh(mesh) || !ubar || (n_pts > 0 && (!pts || !wbar)) || n_pts < 0) {
+    if (!valid_mesh(mesh) || !ubar || (n_pts > 0 && (!pts || !wbar)) || n_pts < 0 || n_pts >= (int64_t(1) << 31)) {
         set_error("adg_sample_adjoint: bad argument");
         return ADG_ERR_INVALID_ARG;
     }

@@ -27,6 +27,7 @@ hipError_t upload_basis(const DevBasis *tab);
 
 // FP32, N = 4: use the LDS-free DPP/MFMA predictor (default) or the generic one
 extern bool g_pred4_mfma;
+extern bool g_pred4_f64;
 
 // Batched predictor: one work item = CPB cells of one instance.
 struct PredItem {
@@ -87,8 +88,12 @@ int corrector_blocks(int N, int64_t nc);
 // launch_cfl_final reads)
 hipError_t launch_cfl_prime(int N, const double *u, int64_t nc, const int8_t *level, const Geo &geo, double gamma,
                             double *partial, int nb, int *status, hipStream_t st);
+// clock != nullptr: dt = min(dt, t_end - clock), then clock += dt (the
+// last step of a run to t_end lands on it exactly)
 hipError_t launch_cfl_final(const double *partial, int nparts, double factor, double *dt_out, double *hist,
-                            hipStream_t st);
+                            hipStream_t st, double t_end = 0.0, double *clock = nullptr);
+// p[0 .. n-1] = x
+hipError_t launch_fill(double *p, int64_t n, double x, hipStream_t st);
 
 // Dynamic adaptivity.  One target cell's relation to the source mesh:
 // kind 0 copy of cell src; 1 evaluation of the coarser source cell src (dl
@@ -116,11 +121,13 @@ struct LimDev {
     int32_t *fb;      // [nc] 1: old subcell data replaced by the cell mean
     double *mm2;      // the same of the step's result (carried to the next step)
     int32_t *fb2;
-    int32_t *nbr;     // [6][nc] face neighbour of every cell side
-    int32_t *flag;    // [nc] 1 limited, 2 corrector re-run, 0 else
+    int32_t *nbr;     // [6][nc] same-level face neighbour of every cell side, -1 at a hanging side
+    int32_t *flag;    // [nc] 1 limited, 2 corrector re-run, 3 troubled with a hanging
+                      // side (not limited), 4 the same with its corrector re-run, 0 else
     int32_t *list;    // [nc] limited cells (first cnt[0] entries)
     int32_t *rlist;   // [nc] cells whose corrector runs again (first cnt[1])
     int32_t *cnt;     // [2]
+    const int8_t *level;  // [nc] cell levels (adaptive meshes), else nullptr
 };
 constexpr int LIM_GRID = 2048;  // blocks of the persistent limiter kernels
 hipError_t launch_lim_nbr(const int32_t *fm, const int32_t *fp, int64_t nf, int d, int64_t nc, int32_t *nbr,
@@ -166,12 +173,27 @@ struct SampleGeo {
     double lo[3], inv_h[3];
 };
 
-// One adjoint step (FP64, uniform mesh): recomputes the predictor storing its
-// iterates, then applies the transposed corrector, Riemann and predictor.
+// Hanging-face tables of an adaptive instance for the adjoint step (nh = 0
+// and ncs = 0 on uniform meshes); vbar is scratch of nh * 2 * 5 * N^2 doubles.
+struct AdjHang {
+    const HangDev *hang = nullptr;
+    int64_t nh = 0;
+    const int32_t *ccell = nullptr, *cptr = nullptr, *cchild = nullptr;
+    const int8_t *cside = nullptr;
+    int64_t ncs = 0;
+    const double *ptab = nullptr;
+    double *vbar = nullptr;
+};
+
+// One adjoint step (FP64): recomputes the predictor storing its iterates,
+// then applies the transposed corrector, restriction, Riemann solves
+// (conforming and hanging faces), interpolation to virtual cells and
+// predictor.
 hipError_t launch_adjoint_step(int N, const double *u, const double *dt, const double *ubar_next, double *ubar,
                                double *ustar, double *traces, double *tbar, double *fbar, double *iters,
                                const int32_t *const fm[3], const int32_t *const fp[3], const int64_t nf[3],
-                               int64_t nc, const Geo &geo, double gamma, int npic, hipStream_t st);
+                               int64_t nc, const int8_t *level, const Geo &geo, double gamma, int npic,
+                               const AdjHang &ah, hipStream_t st);
 hipError_t launch_sample(int N, const double *u, int64_t nc, const SampleGeo &sg, const double *pts, int64_t npts,
                          double *out, hipStream_t st);
 hipError_t launch_sample_adjoint(int N, const double *pts, const double *wbar, int64_t npts, const SampleGeo &sg,

@@ -838,6 +838,227 @@ k_predictor4_mfma_order(const PredItem *__restrict__ items, int64_t nitems, cons
 }
 
 // ---------------------------------------------------------------------------
+// Predictor for N = 4 in FP64 on one wavefront per cell, without LDS memory.
+// The same lane layout as the FP32 kernel above (lane l = node a = l, the
+// whole time history of the node in registers).  A double moves between
+// lanes as two 32-bit halves:
+//   x contraction: DPP quad permutations of both halves, then FMAs;
+//   y contraction: DPP row rotations by 4 k lanes;
+//   z contraction: ds_bpermute of both halves (the LDS crossbar);
+//   time solve:    q_l = u - sum_j KW[l][j] G_j with the KW entries
+//                  wave-uniform (scalar operands of the FMAs).
+// ---------------------------------------------------------------------------
+
+// x from the lane that the DPP control CTRL selects (two 32-bit DPP moves
+// into a register pair; every source lane exists for these controls)
+template <int CTRL> __device__ __forceinline__ double dpp64(double x)
+{
+    return __longlong_as_double(__builtin_amdgcn_mov_dpp(__double_as_longlong(x), CTRL, 0xf, 0xf, true));
+}
+// DPP controls: quad_perm [1,2,3,0], [2,3,0,1], [3,0,1,2]; row_ror by 4, 8, 12
+constexpr int DPP_QP1 = 0x39, DPP_QP2 = 0x4E, DPP_QP3 = 0x93;
+constexpr int DPP_ROR4 = 0x124, DPP_ROR8 = 0x128, DPP_ROR12 = 0x12C;
+
+// x of the lane whose byte address (4 x lane index) is addr
+__device__ __forceinline__ double from_lane64(int addr, double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_ds_bpermute(addr, int(b & 0xffffffff));
+    const int hi = __builtin_amdgcn_ds_bpermute(addr, int(b >> 32));
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+
+// sum_e c[e] x(lane of the e-th neighbour along the axis): x through quad
+// permutations (axis 0), row rotations (axis 1) or the crossbar (axis 2)
+template <int AXIS>
+__device__ __forceinline__ double fibre_sum64(const double c[4], double x, double acc, const int pz[4])
+{
+    acc = fma(c[0], x, acc);
+    if constexpr (AXIS == 0) {
+        acc = fma(c[1], dpp64<DPP_QP1>(x), acc);
+        acc = fma(c[2], dpp64<DPP_QP2>(x), acc);
+        acc = fma(c[3], dpp64<DPP_QP3>(x), acc);
+    } else if constexpr (AXIS == 1) {
+        acc = fma(c[1], dpp64<DPP_ROR4>(x), acc);
+        acc = fma(c[2], dpp64<DPP_ROR8>(x), acc);
+        acc = fma(c[3], dpp64<DPP_ROR12>(x), acc);
+    } else {
+#pragma unroll
+        for (int k = 1; k < 4; ++k) acc = fma(c[k], from_lane64(pz[k], x), acc);
+    }
+    return acc;
+}
+
+__device__ __forceinline__ void pred4_wave_f64(const double *__restrict__ u, double *__restrict__ ustar,
+                                               double *__restrict__ traces, int64_t c, int64_t nc, int lev,
+                                               const Geo &geo, double dt, double gamma, int npic)
+{
+    constexpr int N = 4, N2 = 16, N3 = 64;
+    const DevBasis &B = c_basis[N];
+    const int l = threadIdx.x & 63;
+    const int a0 = l & 3, a1 = (l >> 2) & 3, a2 = l >> 4;
+    const double cd[3] = {dt * geo.inv_dx[lev][0], dt * geo.inv_dx[lev][1], dt * geo.inv_dx[lev][2]};
+    const double gm1 = gamma - 1.0;
+    const unsigned lu = unsigned(l) * unsigned(sizeof(double));
+    double uu[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) uu[v] = *lane_at(u + (int64_t(v) * nc + c) * N3, lu);
+
+    // neighbour e of this lane along each axis: a0 + e (quad permutation),
+    // a1 - e (row rotation), a2 + e (crossbar), all mod 4
+    const int nx[4] = {a0, (a0 + 1) & 3, (a0 + 2) & 3, (a0 + 3) & 3};
+    const int ny[4] = {a1, (a1 + 3) & 3, (a1 + 2) & 3, (a1 + 1) & 3};
+    const int nz[4] = {a2, (a2 + 1) & 3, (a2 + 2) & 3, (a2 + 3) & 3};
+    int pz[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pz[k] = ((l + 16 * k) & 63) * 4;
+    double Cx[4], Cy[4], Cz[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        Cx[e] = cd[0] * B.D[a0 * N + nx[e]];
+        Cy[e] = cd[1] * B.D[a1 * N + ny[e]];
+        Cz[e] = cd[2] * B.D[a2 * N + nz[e]];
+    }
+
+    // scaled divergence sum_d (dt/dx_d) D_d F_d(qn) at this lane's node
+    auto spatial = [&](const double qn[NV], double g[NV]) {
+        double f[3][NV];
+        euler_flux3(gm1, qn, f);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double s = fibre_sum64<2>(Cz, f[2][v], 0.0, pz);
+            s = fibre_sum64<0>(Cx, f[0][v], s, pz);
+            g[v] = fibre_sum64<1>(Cy, f[1][v], s, pz);
+        }
+    };
+
+    double q[N][NV];
+    if (npic > 0) {
+        // first iteration from q = u at every time node: one flux and one
+        // divergence serve all time nodes; the row sums of KW finish it
+        double g[NV];
+        spatial(uu, g);
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) q[j][v] = fma(-B.KWsum[j], g[v], uu[v]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) q[j][v] = uu[v];
+    }
+    for (int it = 1; it < npic; ++it) {
+        double acc[N][NV];
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[i][v] = 0.0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            double g[NV];
+            spatial(q[j], g);
+#pragma unroll
+            for (int i = 0; i < N; ++i)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) acc[i][v] = fma(B.KW[i * N + j], g[v], acc[i][v]);
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) q[i][v] = uu[v] - acc[i][v];
+    }
+
+    // time averages of the final iterate
+    double qb[NV], Fb[3][NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        qb[v] = 0.0;
+        Fb[0][v] = Fb[1][v] = Fb[2][v] = 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        double f[3][NV];
+        euler_flux3(gm1, q[j], f);
+        const double wj = B.w[j];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            qb[v] = fma(wj, q[j][v], qb[v]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) Fb[d][v] = fma(wj, f[d][v], Fb[d][v]);
+        }
+    }
+
+    // volume term of the corrector with the weak stiffness Kw
+    {
+        double Vx[4], Vy[4], Vz[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            Vx[e] = cd[0] * B.winv[a0] * B.Kw[a0 * N + nx[e]];
+            Vy[e] = cd[1] * B.winv[a1] * B.Kw[a1 * N + ny[e]];
+            Vz[e] = cd[2] * B.winv[a2] * B.Kw[a2 * N + nz[e]];
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double V = fibre_sum64<2>(Vz, Fb[2][v], 0.0, pz);
+            V = fibre_sum64<0>(Vx, Fb[0][v], V, pz);
+            V = fibre_sum64<1>(Vy, Fb[1][v], V, pz);
+            *lane_at(ustar + (int64_t(v) * nc + c) * N3, lu) = uu[v] + V;
+        }
+    }
+
+    // face projections: along each axis the lanes at index 0 hold the minus
+    // face (L weights) and the lanes at index 3 the plus face (R weights) of
+    // one sum; the others' stores get an offset beyond the 128-byte plane
+    // view, which buffer range checking drops
+    {
+        double Px[4], Py[4], Pz[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            Px[e] = a0 == 0 ? B.L[nx[e]] : B.R[nx[e]];
+            Py[e] = a1 == 0 ? B.L[ny[e]] : B.R[ny[e]];
+            Pz[e] = a2 == 0 ? B.L[nz[e]] : B.R[nz[e]];
+        }
+        constexpr unsigned F = sizeof(double), OUT = 0x80000000u;
+        const unsigned bx = (a1 + 4 * a2) * F, by = (a0 + 4 * a2) * F, bz = (a0 + 4 * a1) * F;
+        const unsigned o0 = a0 == 0 ? bx : OUT, o1 = a0 == 3 ? bx : OUT;
+        const unsigned o2 = a1 == 0 ? by : OUT, o3 = a1 == 3 ? by : OUT;
+        const unsigned o4 = a2 == 0 ? bz : OUT, o5 = a2 == 3 ? bz : OUT;
+        auto put = [&](int s, int arr, int v, unsigned off, double x) {
+            double *plane = traces + ((int64_t(s * 2 + arr) * NV + v) * nc + c) * N2;
+            buf_st(buf_view(plane, N2 * F), off, x);
+        };
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+#pragma unroll
+            for (int arr = 0; arr < 2; ++arr) {
+                const double px = fibre_sum64<0>(Px, arr == 0 ? qb[v] : Fb[0][v], 0.0, pz);
+                put(0, arr, v, o0, px);
+                put(1, arr, v, o1, px);
+                const double py = fibre_sum64<1>(Py, arr == 0 ? qb[v] : Fb[1][v], 0.0, pz);
+                put(2, arr, v, o2, py);
+                put(3, arr, v, o3, py);
+                const double pzv = fibre_sum64<2>(Pz, arr == 0 ? qb[v] : Fb[2][v], 0.0, pz);
+                put(4, arr, v, o4, pzv);
+                put(5, arr, v, o5, pzv);
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
+k_predictor4_f64(const double *__restrict__ u, double *__restrict__ ustar, double *__restrict__ traces,
+                 const int32_t *__restrict__ list, int64_t nlist, int64_t nc, const int8_t *__restrict__ level,
+                 Geo geo, const double *__restrict__ dt_dev, double gamma, int npic)
+{
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const int64_t idx = int64_t(blockIdx.x) * (blockDim.x >> 6) + wave;
+    if (idx >= nlist) return;  // whole wavefront leaves together
+    const int64_t c = list ? int64_t(list[idx]) : idx;
+    pred4_wave_f64(u, ustar, traces, c, nc, level ? level[c] : 0, geo, dt_dev[0], gamma, npic);
+}
+
+// ---------------------------------------------------------------------------
 // Riemann solves on conforming faces of one axis
 // ---------------------------------------------------------------------------
 
@@ -1297,17 +1518,35 @@ k_cfl_partial(const double *__restrict__ u, int64_t nc, const int8_t *__restrict
 
 __global__ void __launch_bounds__(1024)
 k_cfl_final(const double *__restrict__ partial, int nparts, double factor, double *__restrict__ dt_out,
-            double *__restrict__ hist)
+            double *__restrict__ hist, double t_end, double *__restrict__ clock)
 {
     __shared__ double sh[16];
     double m = 0.0;
     for (int i = threadIdx.x; i < nparts; i += blockDim.x) m = fmax(m, partial[i]);
     m = block_max(m, sh);
     if (threadIdx.x == 0) {
-        const double dt = (m > 0.0 && m < INFINITY) ? factor / m : 0.0;
+        double dt = (m > 0.0 && m < INFINITY) ? factor / m : 0.0;
+        if (clock) {
+            // the last step ends at t_end exactly; later steps have dt = 0
+            const double rest = fmax(t_end - clock[0], 0.0);
+            if (dt >= rest) {
+                dt = rest;
+                clock[0] = t_end;
+            } else {
+                clock[0] += dt;
+            }
+        }
         dt_out[0] = dt;
         if (hist) hist[0] = dt;
     }
+}
+
+// p[0 .. n-1] = x (a kernel rather than a memset, so that graph captures
+// hold no memset node)
+__global__ void __launch_bounds__(256) k_fill(double *__restrict__ p, int64_t n, double x)
+{
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i < n) p[i] = x;
 }
 
 // ---------------------------------------------------------------------------
@@ -1402,7 +1641,7 @@ __device__ __forceinline__ void speed_vjp(double gamma, const double q[NV], int 
 template <int N>
 __global__ void __launch_bounds__(256)
 k_corrector_adj(const double *__restrict__ ubar, double *__restrict__ fbar, const double *__restrict__ dt_dev,
-                int64_t nc, Geo geo)
+                int64_t nc, const int8_t *__restrict__ level, Geo geo)
 {
     constexpr int N2 = N * N, N3 = N2 * N;
     const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -1412,7 +1651,7 @@ k_corrector_adj(const double *__restrict__ ubar, double *__restrict__ fbar, cons
     const int sv = int(t / (N2 * nc));
     const int s = sv / NV, v = sv % NV, d = s >> 1;
     const DevBasis &B = c_basis[N];
-    const double sc = dt_dev[0] * geo.inv_dx[0][d];
+    const double sc = dt_dev[0] * geo.inv_dx[level ? level[c] : 0][d];
     const double *E = (s & 1) ? B.R : B.L;
     const double sign = (s & 1) ? -1.0 : 1.0;
     double acc = 0.0;
@@ -1496,6 +1735,181 @@ k_riemann_adj(const double *__restrict__ traces, const double *__restrict__ fbar
     }
 }
 
+// Transpose of the restriction (coarse side = sum over its child faces of
+// (R1 x R2) applied to the fine side's flux): the fine side of every hanging
+// child face also receives (R1 x R2)^T of its coarse side's adjoint.  Every
+// fine side belongs to one hanging record, so each lane owns its output.
+template <int N>
+__global__ void __launch_bounds__(256)
+k_restrict_adj(double *__restrict__ fbar, const HangDev *__restrict__ hang, int64_t nh, int64_t nc,
+               const double *__restrict__ ptab)
+{
+    constexpr int N2 = N * N;
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= nh * N2) return;
+    const int64_t h = t / N2;
+    const int e = int(t % N2), e1 = e % N, e2 = e / N;
+    const HangDev H = hang[h];
+    const int sf = 2 * H.d + (H.fine_minus ? 1 : 0), sc = 2 * H.d + (H.fine_minus ? 0 : 1);
+    const double *R1 = ptab + (transfer_base(H.dl) + H.s1) * 2 * N2 + N2;
+    const double *R2 = ptab + (transfer_base(H.dl) + H.s2) * 2 * N2 + N2;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const double *cb = fbar + (int64_t(sc * NV + v) * nc + H.coarse) * N2;
+        double sum = 0.0;
+#pragma unroll
+        for (int k2 = 0; k2 < N; ++k2) {
+            double r = 0.0;
+#pragma unroll
+            for (int k1 = 0; k1 < N; ++k1) r += R1[k1 * N + e1] * cb[k1 + N * k2];
+            sum += R2[k2 * N + e2] * r;
+        }
+        fbar[(int64_t(sf * NV + v) * nc + H.fine) * N2 + e] += sum;
+    }
+}
+
+// Transpose of the Rusanov solve on hanging child faces between the fine
+// cell's projection and the coarse projection interpolated to the child face
+// (virtual cell).  The fine side's adjoint goes to tbar; the virtual side's
+// adjoint (state and normal flux) goes to vbar [nh][2][5][N^2], from which
+// k_prolong_adj gathers the coarse side.  The face speed takes the
+// subgradient at its first maximiser in (node, minus side first) order.
+template <int N>
+__global__ void __launch_bounds__(FaceCfg<N>::THREADS)
+k_hang_adj(const double *__restrict__ traces, const double *__restrict__ fbar, double *__restrict__ tbar,
+           double *__restrict__ vbar, const HangDev *__restrict__ hang, int64_t nh, int64_t nc,
+           const double *__restrict__ ptab, double gamma)
+{
+    constexpr int N2 = N * N, FPB = FaceCfg<N>::FPB;
+    __shared__ double lam[FPB * N2 * 2];
+    __shared__ double part[FPB * N2];
+    const int tid = threadIdx.x;
+    const int fl = tid / N2, b = tid % N2;
+    const int64_t h = int64_t(blockIdx.x) * FPB + fl;
+    const bool lane_ok = tid < FPB * N2;
+    const bool active = lane_ok && h < nh;
+    const double gm1 = gamma - 1.0;
+    double Qf[NV], Ff[NV], Qv[NV], Fv[NV], Fb[NV];
+    HangDev H{};
+    int sf = 0;
+    double lL = 0.0, lR = 0.0, sb = 0.0;
+    bool dummy;
+    if (active) {
+        H = hang[h];
+        sf = 2 * H.d + (H.fine_minus ? 1 : 0);
+        const int sc = 2 * H.d + (H.fine_minus ? 0 : 1);
+        const double *P1 = ptab + (transfer_base(H.dl) + H.s1) * 2 * N2;
+        const double *P2 = ptab + (transfer_base(H.dl) + H.s2) * 2 * N2;
+        const int k1 = b % N, k2 = b / N;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            Qf[v] = traces[((int64_t(sf * 2 + 0) * NV + v) * nc + H.fine) * N2 + b];
+            Ff[v] = traces[((int64_t(sf * 2 + 1) * NV + v) * nc + H.fine) * N2 + b];
+            const double *cq = traces + ((int64_t(sc * 2 + 0) * NV + v) * nc + H.coarse) * N2;
+            const double *cf = traces + ((int64_t(sc * 2 + 1) * NV + v) * nc + H.coarse) * N2;
+            double sq = 0.0, sfl = 0.0;
+#pragma unroll
+            for (int e2 = 0; e2 < N; ++e2) {
+                double rq = 0.0, rf = 0.0;
+#pragma unroll
+                for (int e1 = 0; e1 < N; ++e1) {
+                    rq += P1[k1 * N + e1] * cq[e1 + N * e2];
+                    rf += P1[k1 * N + e1] * cf[e1 + N * e2];
+                }
+                sq += P2[k2 * N + e2] * rq;
+                sfl += P2[k2 * N + e2] * rf;
+            }
+            Qv[v] = sq;
+            Fv[v] = sfl;
+            Fb[v] = fbar[(int64_t(sf * NV + v) * nc + H.fine) * N2 + b];
+        }
+        const double *QL = H.fine_minus ? Qf : Qv, *QR = H.fine_minus ? Qv : Qf;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sb += -0.5 * (QR[v] - QL[v]) * Fb[v];
+        lL = wave_speed(gamma, gm1, QL, H.d, dummy);
+        lR = wave_speed(gamma, gm1, QR, H.d, dummy);
+    }
+    if (lane_ok) {
+        lam[2 * tid] = lL;
+        lam[2 * tid + 1] = lR;
+        part[tid] = sb;
+    }
+    __syncthreads();
+    if (!active) return;
+    double s = -1.0, sbar = 0.0;
+    int arg = 0;
+    for (int k = 0; k < 2 * N2; ++k) {
+        const double x = lam[2 * fl * N2 + k];
+        if (x > s) {
+            s = x;
+            arg = k;
+        }
+    }
+    for (int k = 0; k < N2; ++k) sbar += part[fl * N2 + k];
+    double QLb[NV], QRb[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        QLb[v] = 0.5 * s * Fb[v];
+        QRb[v] = -0.5 * s * Fb[v];
+    }
+    if (arg / 2 == b) {
+        if (arg % 2 == 0) speed_vjp(gamma, H.fine_minus ? Qf : Qv, H.d, sbar, QLb);
+        else speed_vjp(gamma, H.fine_minus ? Qv : Qf, H.d, sbar, QRb);
+    }
+    const double *Qfb = H.fine_minus ? QLb : QRb, *Qvb = H.fine_minus ? QRb : QLb;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        tbar[((int64_t(sf * 2 + 0) * NV + v) * nc + H.fine) * N2 + b] = Qfb[v];
+        tbar[((int64_t(sf * 2 + 1) * NV + v) * nc + H.fine) * N2 + b] = 0.5 * Fb[v];
+        vbar[((h * 2 + 0) * NV + v) * N2 + b] = Qvb[v];
+        vbar[((h * 2 + 1) * NV + v) * N2 + b] = 0.5 * Fb[v];
+    }
+}
+
+// Transpose of the interpolation to virtual cells: every coarse side with
+// hanging children gets sum over its children of (P1 x P2)^T applied to the
+// virtual side's adjoint, children in the restriction lists' fixed order.
+template <int N>
+__global__ void __launch_bounds__(256)
+k_prolong_adj(double *__restrict__ tbar, const double *__restrict__ vbar, const HangDev *__restrict__ hang,
+              const int32_t *__restrict__ ccell, const int8_t *__restrict__ cside, const int32_t *__restrict__ cptr,
+              const int32_t *__restrict__ cchild, int64_t ncs, int64_t nc, const double *__restrict__ ptab)
+{
+    constexpr int N2 = N * N;
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= ncs * N2) return;
+    const int64_t i = t / N2;
+    const int e = int(t % N2), e1 = e % N, e2 = e / N;
+    const int64_t C = ccell[i];
+    const int sc = cside[i];
+    double acc[2][NV] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};
+    for (int q = cptr[i]; q < cptr[i + 1]; ++q) {
+        const int64_t h = cchild[q];
+        const HangDev H = hang[h];
+        const double *P1 = ptab + (transfer_base(H.dl) + H.s1) * 2 * N2;
+        const double *P2 = ptab + (transfer_base(H.dl) + H.s2) * 2 * N2;
+#pragma unroll
+        for (int arr = 0; arr < 2; ++arr)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const double *src = vbar + ((h * 2 + arr) * NV + v) * N2;
+                double sum = 0.0;
+#pragma unroll
+                for (int k2 = 0; k2 < N; ++k2) {
+                    double r = 0.0;
+#pragma unroll
+                    for (int k1 = 0; k1 < N; ++k1) r += P1[k1 * N + e1] * src[k1 + N * k2];
+                    sum += P2[k2 * N + e2] * r;
+                }
+                acc[arr][v] += sum;
+            }
+    }
+#pragma unroll
+    for (int arr = 0; arr < 2; ++arr)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) tbar[((int64_t(sc * 2 + arr) * NV + v) * nc + C) * N2 + e] = acc[arr][v];
+}
+
 // Transpose of the predictor (Picard iterations, time averages, volume term,
 // face projections).  One lane per node as in the forward kernel; iterates
 // come from the forward run (iters, slots 0..npic-1 = iterates 1..npic).
@@ -1503,7 +1917,7 @@ template <int N, int CPB>
 __global__ void __launch_bounds__(round64(CPB * N * N * N))
 k_predictor_adj(const double *__restrict__ u, const double *__restrict__ iters, const double *__restrict__ ubar_next,
                 const double *__restrict__ tbar, const double *__restrict__ dt_dev, double *__restrict__ ubar,
-                int64_t nc, Geo geo, double gamma, int npic)
+                int64_t nc, const int8_t *__restrict__ level, Geo geo, double gamma, int npic)
 {
     constexpr int N2 = N * N, N3 = N2 * N, NT = CPB * N3;
     // per cell: the adjoint divergence inputs Gb_j of all N time nodes
@@ -1517,7 +1931,8 @@ k_predictor_adj(const double *__restrict__ u, const double *__restrict__ iters, 
     const int aa[3] = {a % N, (a / N) % N, a / N2};
     const int bf[3] = {aa[1] + N * aa[2], aa[0] + N * aa[2], aa[0] + N * aa[1]};
     const double dt = dt_dev[0];
-    const double cd[3] = {dt * geo.inv_dx[0][0], dt * geo.inv_dx[0][1], dt * geo.inv_dx[0][2]};
+    const int lev = level && active ? level[c] : 0;
+    const double cd[3] = {dt * geo.inv_dx[lev][0], dt * geo.inv_dx[lev][1], dt * geo.inv_dx[lev][2]};
     const double gm1 = gamma - 1.0;
     double *my = lds + (lane_ok ? cl : 0) * N * NV * N3;
     auto node_with = [&](int d, int k) {
@@ -1696,21 +2111,46 @@ k_sample(const double *__restrict__ u, int64_t nc, SampleGeo sg, const double *_
     out[s] = acc;
 }
 
-// ubar_rho[cell(s)][a] += wbar[s] phi_a(x_s), points in order (deterministic)
+// cell index of a point (floor of the cell coordinate, clamped into the grid)
+__device__ __forceinline__ int64_t cell_of(const double *x, const int *n, const double *lo, const double *inv_h)
+{
+    int ijk[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        int i = int(floor((x[d] - lo[d]) * inv_h[d]));
+        ijk[d] = i < 0 ? 0 : (i >= n[d] ? n[d] - 1 : i);
+    }
+    return ijk[0] + int64_t(n[0]) * (ijk[1] + int64_t(n[1]) * ijk[2]);
+}
+
+// ubar_rho[c][a] += sum over the points s in cell c, in increasing s, of
+// wbar[s] phi_a(x_s).  One block per point; the block of the lowest-index
+// point of a cell forms that cell's sum (lane = node) and the others leave,
+// so every cell is written once and the order of the sum is fixed.  The
+// leader test scans the earlier points, so the work grows with the square
+// of the number of points (meant for up to about 10^4 points).
 template <int N>
 __global__ void __launch_bounds__(round64(N * N * N))
 k_sample_adj(const double *__restrict__ pts, const double *__restrict__ wbar, int64_t npts, SampleGeo sg,
              double *__restrict__ ubar)
 {
     constexpr int N3 = N * N * N;
+    const int64_t s = blockIdx.x;
     const int a = threadIdx.x;
+    const int64_t cs = cell_of(pts + 3 * s, sg.n, sg.lo, sg.inv_h);
+    int earlier = 0;
+    for (int64_t t = a; t < s; t += blockDim.x) earlier |= cell_of(pts + 3 * t, sg.n, sg.lo, sg.inv_h) == cs;
+    if (__syncthreads_or(earlier)) return;  // the same decision in every lane of the block
     if (a >= N3) return;
-    for (int64_t s = 0; s < npts; ++s) {
+    double acc = 0.0;
+    for (int64_t t = s; t < npts; ++t) {
+        if (cell_of(pts + 3 * t, sg.n, sg.lo, sg.inv_h) != cs) continue;
         int64_t cell;
         double phi[3][N];
-        locate<N>(pts + 3 * s, sg.n, sg.lo, sg.inv_h, cell, phi);
-        ubar[cell * N3 + a] += wbar[s] * phi[0][a % N] * phi[1][(a / N) % N] * phi[2][a / (N * N)];
+        locate<N>(pts + 3 * t, sg.n, sg.lo, sg.inv_h, cell, phi);
+        acc += wbar[t] * phi[0][a % N] * phi[1][(a / N) % N] * phi[2][a / (N * N)];
     }
+    ubar[cs * N3 + a] += acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -2182,9 +2622,12 @@ k_lim_detect(const double *__restrict__ u, int64_t nc, double gamma, double delt
     __shared__ double x[NV * C::N3], t1[NV * C::T1], ext[2 * 7 * NV];
     const int64_t c = blockIdx.x;
     const int lane = threadIdx.x;
+    // a hanging side (no same-level neighbour) adds no bounds; such a cell
+    // cannot be limited
     if (lane < 7 * NV) {
         const int k = lane / NV, var = lane % NV;
-        const int64_t o = k == 0 ? c : nbr[(k - 1) * nc + c];
+        const int64_t n = k == 0 ? c : nbr[(k - 1) * nc + c];
+        const int64_t o = n < 0 ? c : n;
         ext[lane] = mm[o * 2 * NV + var];
         ext[7 * NV + lane] = mm[o * 2 * NV + NV + var];
     }
@@ -2193,8 +2636,10 @@ k_lim_detect(const double *__restrict__ u, int64_t nc, double gamma, double delt
     lim_cell_scan<N, true>(u, nc, c, gamma - 1.0, x, t1, ext, delta0, eps, lo, hi, ba, bn, bo);
     const bool troubled = ba || bn || bo || force;
     if (lane == 0) {
-        flag[c] = troubled ? 1 : 0;
-        if (troubled) list[atomicAdd(cnt, 1)] = int32_t(c);
+        bool hang = false;
+        for (int k = 0; k < 6; ++k) hang = hang || nbr[k * nc + c] < 0;
+        flag[c] = troubled ? (hang ? 3 : 1) : 0;
+        if (troubled && !hang) list[atomicAdd(cnt, 1)] = int32_t(c);
         fb2[c] = 0;  // an unlimited cell's averages are physical; limited cells are rewritten
     }
     // the bounds an unlimited cell carries into the next step (as lim_scan_cell)
@@ -2219,7 +2664,8 @@ __global__ void __launch_bounds__(LimCfg<N>::THREADS)
 k_lim_fv(double *__restrict__ u, T *__restrict__ fside, int64_t nc, Geo geo, const double *__restrict__ dt_dev,
          double gamma, const double *__restrict__ uold, const int32_t *__restrict__ fb,
          const int32_t *__restrict__ nbr, int32_t *__restrict__ flag, const int32_t *__restrict__ list,
-         int32_t *__restrict__ rlist, int32_t *__restrict__ cnt, double *__restrict__ mm2, int32_t *__restrict__ fb2)
+         int32_t *__restrict__ rlist, int32_t *__restrict__ cnt, double *__restrict__ mm2, int32_t *__restrict__ fb2,
+         const int8_t *__restrict__ level)
 {
     using C = LimCfg<N>;
     constexpr int NS = C::NS, N2 = C::N2, N3 = C::N3, S2 = C::S2, S3 = C::S3, PT = C::PT, TH = C::THREADS;
@@ -2260,7 +2706,7 @@ k_lim_fv(double *__restrict__ u, T *__restrict__ fside, int64_t nc, Geo geo, con
         __syncthreads();
         for (int k = 0; k < 6; ++k) {
             const int64_t o = nbr[k * nc + c];
-            if (flag[o] == 1) continue;  // 0 or 2 for every reader: uniform
+            if (flag[o] == 1) continue;  // never 1 for every reader: uniform
             const int d = k / 2, plus = k & 1;
             const int t1a = d == 0 ? 1 : 0, t2a = d == 2 ? 1 : 2;
             for (int j = threadIdx.x; j < S2; j += blockDim.x) {
@@ -2300,7 +2746,8 @@ k_lim_fv(double *__restrict__ u, T *__restrict__ fside, int64_t nc, Geo geo, con
                 for (int b = 0; b < N2; ++b) sum += err[threadIdx.x * N2 + b];
                 dlt[k * NV + threadIdx.x] = sum;
             }
-            if (threadIdx.x == 0 && atomicCAS(&flag[o], 0, 2) == 0) rlist[atomicAdd(&cnt[1], 1)] = int32_t(o);
+            if (threadIdx.x == 0 && (atomicCAS(&flag[o], 0, 2) == 0 || atomicCAS(&flag[o], 3, 4) == 3))
+                rlist[atomicAdd(&cnt[1], 1)] = int32_t(o);
             __syncthreads();
         }
         // first-order update of every subcell (kept in registers)
@@ -2315,7 +2762,7 @@ k_lim_fv(double *__restrict__ u, T *__restrict__ fside, int64_t nc, Geo geo, con
             for (int var = 0; var < NV; ++var) q[var] = v[var * S3 + s];
 #pragma unroll 1
             for (int d = 0; d < 3; ++d) {
-                const double inv_h = geo.inv_dx[0][d] * NS;
+                const double inv_h = geo.inv_dx[level ? level[c] : 0][d] * NS;
                 const int t1a = d == 0 ? 1 : 0, t2a = d == 2 ? 1 : 2;
 #pragma unroll 1
                 for (int side = 0; side < 2; ++side) {
@@ -2449,7 +2896,7 @@ template <typename T, int N>
 __global__ void __launch_bounds__(round64(N * N * N))
 k_lim_recorrect(const double *__restrict__ ustar, const T *__restrict__ fside, const double *__restrict__ dt_dev,
                 double *__restrict__ u, int64_t nc, Geo geo, const int32_t *__restrict__ rlist,
-                const int32_t *__restrict__ cnt)
+                const int32_t *__restrict__ cnt, const int8_t *__restrict__ level)
 {
     constexpr int N2 = N * N, N3 = N2 * N;
     const DevBasis &B = c_basis[N];
@@ -2458,12 +2905,13 @@ k_lim_recorrect(const double *__restrict__ ustar, const T *__restrict__ fside, c
     const int a0 = a % N, a1 = (a / N) % N, a2 = a / N2;
     const int bx = a1 + N * a2, by = a0 + N * a2, bz = a0 + N * a1;
     const double dt = dt_dev[0];
-    const double sx = dt * geo.inv_dx[0][0] * B.winv[a0];
-    const double sy = dt * geo.inv_dx[0][1] * B.winv[a1];
-    const double sz = dt * geo.inv_dx[0][2] * B.winv[a2];
     const int n = cnt[1];
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const int64_t c = rlist[it];
+        const int lev = level ? level[c] : 0;
+        const double sx = dt * geo.inv_dx[lev][0] * B.winv[a0];
+        const double sy = dt * geo.inv_dx[lev][1] * B.winv[a1];
+        const double sz = dt * geo.inv_dx[lev][2] * B.winv[a2];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const double fxm = fside[(int64_t(0 * NV + v) * nc + c) * N2 + bx];
@@ -2739,6 +3187,7 @@ k_lin_cfl(const double *__restrict__ mat, int64_t nc, double factor, double *__r
     }
 
 bool g_pred4_mfma = true;
+bool g_pred4_f64 = true;
 
 hipError_t upload_basis(const DevBasis *tab)
 {
@@ -2793,6 +3242,13 @@ hipError_t launch_predictor(int N, const double *u, double *ustar, T *traces, co
         if (N == 4 && iters == nullptr && g_pred4_mfma) {
             const int64_t blocks = (nlist + 3) / 4;
             hipLaunchKernelGGL(k_predictor4_mfma, dim3(unsigned(blocks)), dim3(256), 0, st, u, ustar, traces, list,
+                               nlist, nc, level, geo, dt, gamma, npic);
+            return hipGetLastError();
+        }
+    } else {
+        if (N == 4 && iters == nullptr && g_pred4_f64) {
+            const int64_t blocks = (nlist + 3) / 4;
+            hipLaunchKernelGGL(k_predictor4_f64, dim3(unsigned(blocks)), dim3(256), 0, st, u, ustar, traces, list,
                                nlist, nc, level, geo, dt, gamma, npic);
             return hipGetLastError();
         }
@@ -3004,7 +3460,8 @@ hipError_t launch_cfl(int N, const double *u, int64_t nc, const int8_t *level, c
         hipLaunchKernelGGL((k_cfl_partial<NN>), dim3(nb), dim3(256), 0, st, u, nc, level, geo, gamma, partial,
                            status);
     });
-    hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(1024), 0, st, partial, nb, factor, dt_out, hist);
+    hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(1024), 0, st, partial, nb, factor, dt_out, hist, 0.0,
+                       static_cast<double *>(nullptr));
     return hipGetLastError();
 }
 
@@ -3025,9 +3482,16 @@ hipError_t launch_cfl_prime(int N, const double *u, int64_t nc, const int8_t *le
 }
 
 hipError_t launch_cfl_final(const double *partial, int nparts, double factor, double *dt_out, double *hist,
-                            hipStream_t st)
+                            hipStream_t st, double t_end, double *clock)
 {
-    hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(1024), 0, st, partial, nparts, factor, dt_out, hist);
+    hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(1024), 0, st, partial, nparts, factor, dt_out, hist, t_end, clock);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double *p, int64_t n, double x, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, p, n, x);
     return hipGetLastError();
 }
 
@@ -3047,26 +3511,36 @@ hipError_t launch_node_coords(int N, double *xyz, const int32_t *ijk, const int8
 hipError_t launch_adjoint_step(int N, const double *u, const double *dt, const double *ubar_next, double *ubar,
                                double *ustar, double *traces, double *tbar, double *fbar, double *iters,
                                const int32_t *const fm[3], const int32_t *const fp[3], const int64_t nf[3],
-                               int64_t nc, const Geo &geo, double gamma, int npic, hipStream_t st)
+                               int64_t nc, const int8_t *level, const Geo &geo, double gamma, int npic,
+                               const AdjHang &ah, hipStream_t st)
 {
-    hipError_t e = launch_predictor<double>(N, u, ustar, traces, nullptr, nc, nc, nullptr, geo, dt, gamma, npic, st,
+    hipError_t e = launch_predictor<double>(N, u, ustar, traces, nullptr, nc, nc, level, geo, dt, gamma, npic, st,
                                             iters);
     if (e != hipSuccess) return e;
     ADG_DISPATCH_N(N, {
         constexpr int N2 = NN * NN;
+        constexpr int FPB = FaceCfg<NN>::FPB;
         const int64_t items = 6 * int64_t(NV) * nc * N2;
         hipLaunchKernelGGL((k_corrector_adj<NN>), dim3(unsigned((items + 255) / 256)), dim3(256), 0, st, ubar_next,
-                           fbar, dt, nc, geo);
+                           fbar, dt, nc, level, geo);
+        if (ah.nh > 0)
+            hipLaunchKernelGGL((k_restrict_adj<NN>), dim3(unsigned((ah.nh * N2 + 255) / 256)), dim3(256), 0, st,
+                               fbar, ah.hang, ah.nh, nc, ah.ptab);
         for (int d = 0; d < 3; ++d) {
             if (nf[d] <= 0) continue;
-            constexpr int FPB = FaceCfg<NN>::FPB;
             hipLaunchKernelGGL((k_riemann_adj<NN>), dim3(unsigned((nf[d] + FPB - 1) / FPB)), dim3(FaceCfg<NN>::THREADS),
                                0, st, traces, fbar, tbar, fm[d], fp[d], nf[d], d, nc, gamma);
         }
+        if (ah.nh > 0)
+            hipLaunchKernelGGL((k_hang_adj<NN>), dim3(unsigned((ah.nh + FPB - 1) / FPB)), dim3(FaceCfg<NN>::THREADS),
+                               0, st, traces, fbar, tbar, ah.vbar, ah.hang, ah.nh, nc, ah.ptab, gamma);
+        if (ah.ncs > 0)
+            hipLaunchKernelGGL((k_prolong_adj<NN>), dim3(unsigned((ah.ncs * N2 + 255) / 256)), dim3(256), 0, st,
+                               tbar, ah.vbar, ah.hang, ah.ccell, ah.cside, ah.cptr, ah.cchild, ah.ncs, nc, ah.ptab);
         constexpr int CPB = PredCfg<NN>::CPB;
         hipLaunchKernelGGL((k_predictor_adj<NN, CPB>), dim3(unsigned((nc + CPB - 1) / CPB)),
-                           dim3(round64(CPB * NN * NN * NN)), 0, st, u, iters, ubar_next, tbar, dt, ubar, nc, geo,
-                           gamma, npic);
+                           dim3(round64(CPB * NN * NN * NN)), 0, st, u, iters, ubar_next, tbar, dt, ubar, nc, level,
+                           geo, gamma, npic);
     });
     return hipGetLastError();
 }
@@ -3087,8 +3561,8 @@ hipError_t launch_sample_adjoint(int N, const double *pts, const double *wbar, i
 {
     if (npts <= 0) return hipSuccess;
     ADG_DISPATCH_N(N, {
-        hipLaunchKernelGGL((k_sample_adj<NN>), dim3(1), dim3(round64(NN * NN * NN)), 0, st, pts, wbar, npts, sg,
-                           ubar);
+        hipLaunchKernelGGL((k_sample_adj<NN>), dim3(unsigned(npts)), dim3(round64(NN * NN * NN)), 0, st, pts, wbar,
+                           npts, sg, ubar);
     });
     return hipGetLastError();
 }
@@ -3165,7 +3639,7 @@ hipError_t launch_lim_fv(int N, double *u, T *fside, int64_t nc, const Geo &geo,
     if (nc <= 0) return hipSuccess;
     ADG_DISPATCH_N(N, {
         hipLaunchKernelGGL((k_lim_fv<T, NN>), dim3(LIM_GRID), dim3(LimCfg<NN>::THREADS), 0, st, u, fside, nc, geo, dt,
-                           gamma, L.uold, L.fb, L.nbr, L.flag, L.list, L.rlist, L.cnt, L.mm2, L.fb2);
+                           gamma, L.uold, L.fb, L.nbr, L.flag, L.list, L.rlist, L.cnt, L.mm2, L.fb2, L.level);
     });
     return hipGetLastError();
 }
@@ -3177,7 +3651,7 @@ hipError_t launch_lim_recorrect(int N, const double *ustar, const T *fside, doub
     if (nc <= 0) return hipSuccess;
     ADG_DISPATCH_N(N, {
         hipLaunchKernelGGL((k_lim_recorrect<T, NN>), dim3(LIM_GRID), dim3(round64(NN * NN * NN)), 0, st, ustar, fside,
-                           dt, u, nc, geo, L.rlist, L.cnt);
+                           dt, u, nc, geo, L.rlist, L.cnt, L.level);
     });
     return hipGetLastError();
 }

@@ -63,16 +63,16 @@ def blast(xyz, center=(0.5, 0.5, 0.5), radius=0.25, inside=(1.0, 1.0), outside=(
 
 
 def blast_smooth(xyz, width, center=(0.5, 0.5, 0.5), radius=0.25, inside=(1.0, 1.0),
-                 outside=(0.125, 0.1), gamma=GAMMA):
+                 outside=(0.125, 0.1), gamma=GAMMA, velocity=(0.0, 0.0, 0.0)):
     """Blast wave whose interface is smoothed by a tanh profile of the given
     width: s = (1 - tanh((r - R)/width))/2, value = outside + s (inside - outside)
-    for density and pressure, zero velocity."""
+    for density and pressure; a uniform velocity (zero by default)."""
     xyz = np.asarray(xyz, dtype=np.float64)
     r = np.sqrt(sum((xyz[d] - center[d]) ** 2 for d in range(3)))
     s = 0.5 * (1.0 - np.tanh((r - radius) / width))
     rho = outside[0] + s * (inside[0] - outside[0])
     p = outside[1] + s * (inside[1] - outside[1])
-    return conserved(rho, (0.0, 0.0, 0.0), p, gamma)
+    return conserved(rho, velocity, p, gamma)
 
 
 def sphere_refine_list(n, max_level, center=(0.5, 0.5, 0.5), radius=0.25, lo=(0.0, 0.0, 0.0),

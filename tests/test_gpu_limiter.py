@@ -5,7 +5,9 @@ the FV step and the fit for orders 0-6; the normal mode on blast waves adds
 detection (flags compared exactly in FP64), the interface flux replacement
 and the corrector re-run.  Whole runs conserve mass and energy; a constant
 state is never limited and then the step is bit-identical to the unlimited
-one; graph replays equal eager steps."""
+one; graph replays equal eager steps.  On adaptive meshes (hanging faces with
+level jumps of 1 and 2) the limited runs, flags included, match the oracle's,
+which limits only cells with six conforming sides."""
 import numpy as np
 import pytest
 
@@ -144,10 +146,6 @@ def test_graph_replays_equal_eager_steps(precision):
 
 
 def test_refusals():
-    amr = A.Mesh(A.instance(2, (3, 3, 3), max_level=1, refine=[[0, 1, 1, 1]]), "fp64")
-    with pytest.raises(A.AdgError) as e:
-        amr.set_limiter(1)
-    assert e.value.code == 2
     p7 = A.Mesh(A.instance(7, (2, 2, 2)), "fp64")
     with pytest.raises(A.AdgError) as e:
         p7.set_limiter(1)
@@ -171,7 +169,7 @@ def test_refusals():
     with pytest.raises(A.AdgError) as e:
         one.step_adjoint(u, dt, u.clone(), torch.empty_like(u), ws)
     assert e.value.code == 2  # UNSUPPORTED
-    for m in (amr, p7, two, one):
+    for m in (p7, two, one):
         m.close()
 
 
@@ -196,3 +194,85 @@ def test_carried_bounds_equal_recomputed(precision):
     gm.close()
     assert nl == nl2 and nl > 0
     assert np.array_equal(one_call, u.cpu().numpy().reshape(u0.shape))
+
+
+def run_gpu_amr(p, n, ref, u0, steps, precision, mode=1, dt_fixed=None):
+    gm = A.Mesh(A.instance(p, n, max_level=2, refine=ref), precision)
+    gm.set_limiter(mode, 1e-4, 1e-3)
+    u = dev(u0)
+    ws = gm.empty_workspace()
+    hist = torch.zeros(steps, dtype=torch.float64, device="cuda")
+    gm.step(u, steps, ws, dt_hist=hist)
+    torch.cuda.synchronize()
+    nl, nr, flags = gm.limiter_stats(flags=True)
+    try:
+        gm.status()
+        ok = True
+    except A.AdgError as e:
+        assert e.code == 5
+        ok = False
+    out = u.cpu().numpy().reshape(u0.shape)
+    gm.close()
+    return out, nl, nr, flags.cpu().numpy(), ok, hist.cpu().numpy()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("p", [2, 3])
+def test_adaptive_blast_limited_run_matches_oracle(p, precision):
+    """3^3 base cells, two levels of refinement in the ball of radius 0.25,
+    the sharp blast's discontinuity at radius 0.2 (inside the finest level):
+    three limited steps against the oracle, flags exactly (FP64) and the
+    state per variable at the stated bar; the unlimited run would fail."""
+    n = (3, 3, 3)
+    ref = inputs.sphere_refine_list(n, 2, radius=0.25)
+    om = oracle.Mesh(p, n, max_level=2, refine=ref)
+    u0 = inputs.blast(om.node_coords(), radius=0.2)
+    want, hw, nt, fw, rc = om.run_limited(u0, 3)
+    assert rc == 0 and nt.min() > 0 and (fw != 3).all()
+    got, nl, nr, fg, ok, hg = run_gpu_amr(p, n, ref, u0, 3, precision)
+    print(f"[limiter amr] p={p} {precision}: limited {nl} (oracle {nt[-1]}), re-run {nr}", flush=True)
+    assert ok
+    if precision == "fp64":
+        assert np.array_equal(fg, fw) and nl == nt[-1]
+        assert np.abs(hg - hw).max() <= 1e-13 * hw.max()
+    else:
+        assert abs(nl - nt[-1]) <= 0.01 * nt[-1]
+    assert close(got, want, TOL[precision])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_adaptive_transition_cells_are_not_limited(precision):
+    """The discontinuity on the refinement boundary (refined ball of radius
+    0.2, blast radius 0.25): one step at the oracle's dt.  Troubled cells with
+    a hanging side get flag 3 (4 if their corrector ran again) and are not
+    limited, as in the oracle; the other flags match."""
+    p, n = 2, (3, 3, 3)
+    ref = inputs.sphere_refine_list(n, 2, radius=0.2)
+    om = oracle.Mesh(p, n, max_level=2, refine=ref)
+    u0 = inputs.blast(om.node_coords())
+    _, _, _, fw, _ = om.run_limited(u0, 1)
+    assert (fw == 3).any() and (fw == 1).any()
+    _, nl, _, fg, _, _ = run_gpu_amr(p, n, ref, u0, 1, precision)
+    fg = np.where(fg == 4, 3, fg)
+    if precision == "fp64":
+        assert np.array_equal(fg, fw)
+    else:
+        assert (fg != fw).mean() <= 0.01
+    assert nl == (fg == 1).sum()
+
+
+def test_every_limitable_cell_on_adaptive_mesh_matches_oracle():
+    """Every-cell mode on an adaptive mesh limits exactly the cells with six
+    conforming sides (level-2 interior of the refined ball and the level-0
+    far field); one step against the oracle."""
+    p, n = 2, (3, 3, 3)
+    ref = inputs.sphere_refine_list(n, 2, radius=0.25)
+    om = oracle.Mesh(p, n, max_level=2, refine=ref)
+    u0 = inputs.density_wave_noisy(om.node_coords(), seed=3, noise=0.02)
+    want, _, nt, fw, rc = om.run_limited(u0, 1, force=True)
+    assert rc == 0
+    got, nl, _, fg, ok, _ = run_gpu_amr(p, n, ref, u0, 1, "fp64", mode=2)
+    assert ok and nl == nt[0]
+    assert np.array_equal(np.where(fg == 4, 3, fg), fw)
+    assert close(got, want, 1e-12)
+

@@ -155,3 +155,48 @@ def test_amr_density_wave_fp64():
     u0 = inputs.density_wave_noisy(om.node_coords(), seed=3, noise=0.01)
     check_phases(om, gm, u0, n, "fp64")
     check_run(om, gm, u0, n, "fp64", 4)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_step_to_end_time(precision):
+    """adg_step with an end time: every step takes min(dt_cfl, t_end - t), the
+    last one lands on t_end, further steps of the call have dt = 0 and change
+    nothing; the state matches the oracle's run to the same end time, and the
+    step-by-step phase loop with the same clamp gives the same bits."""
+    n, p, T = (5, 4, 3), 3, 0.0123
+    om, gm = make_pair(p, n, precision)
+    u0 = inputs.density_wave_noisy(om.node_coords(), seed=8, noise=0.01)
+    ref, dts_ref, rc = om.run(u0, 200, t_end=T)
+    assert rc == 0
+    used = int(np.count_nonzero(dts_ref))
+    u = dev(u0)
+    hist = torch.full((used + 3,), -1.0, dtype=torch.float64, device="cuda")
+    gm.step(u, used + 3, gm.empty_workspace(), dt_hist=hist, t_end=T)
+    torch.cuda.synchronize()
+    gm.status()
+    h = hist.cpu().numpy()
+    print(f"[t_end] {precision}: {used} steps, last dt {h[used - 1]:.3e}, sum {h.sum():.17g}", flush=True)
+    assert np.all(h[used:] == 0.0) and np.all(h[:used] > 0.0)
+    assert abs(h.sum() - T) <= 1e-15
+    assert np.abs(h[:used] - dts_ref[:used]).max() <= (1e-13 if precision == "fp64" else 1e-6) * T
+    e = rel_l2_per_var(u.cpu().numpy(), ref, solution_weights(om, n))
+    assert e.max() <= TOL[precision], e
+    # the phase entry points with the clamp done on the host
+    v = dev(u0)
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    us, tr, fs = gm.empty_u(), gm.empty_traces(), gm.empty_fside()
+    t = 0.0
+    for k in range(used):
+        gm.cfl(v, dt)
+        d = float(dt.item())
+        if d >= T - t:
+            d = T - t
+        dt.fill_(d)
+        gm.predictor(v, dt, us, tr)
+        gm.riemann(tr, fs)
+        gm.corrector(us, fs, dt, v)
+        t += d
+        assert d == h[k], (k, d, h[k])
+    assert torch.equal(u, v)
+    gm.close()
+

@@ -1,6 +1,6 @@
 """Pins of the oracle's linear (elastic-wave) variant with the
-Cauchy-Kowalevski predictor (Sec. 2.1: a linear PDE is integrated in time
-by Cauchy-Kowalevski; Sec. 5: the seismic benchmark).
+Cauchy-Kowalevski predictor (Sec. 2.4: a linear PDE is integrated in time
+by Cauchy-Kowalevski; Sec. 6: the seismic benchmark).
 
 What fixes it independently of the oracle's own code:
   * the flux matrices: eigenvalues +-c_p, +-c_s (twice), 0 (three times);
