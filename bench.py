@@ -161,7 +161,10 @@ def run_amr(A, steps=50, sharp=False):
     """Adaptive mesh: 27^3 base cells, two levels of 3:1 refinement in the
     sphere |x - c| <= 0.25 (1,074,035 cells), p = 4, FP32 form.  The blast
     wave with its interface smoothed over one finest cell (sharp=False), or
-    the sharp blast with the a-posteriori subcell limiter (sharp=True).
+    the sharp blast with the a-posteriori subcell limiter (sharp=True).  The
+    limiter acts on cells of the finest level only (no resolution transition
+    cuts an FV region), so the sharp blast's discontinuity sits one level-1
+    cell inside the refined sphere: radius 0.25 - 1/81.
     Timed both ways: the skeleton/enclave split on the handle's two streams
     (two different caller streams passed), and every phase on one stream."""
     import torch
@@ -170,7 +173,7 @@ def run_amr(A, steps=50, sharp=False):
     ref = inputs.sphere_refine_list(n, 2, radius=0.25)
     mesh = A.Mesh(A.instance(4, n, max_level=2, refine=ref), "fp32")
     xyz = mesh.node_coords().cpu().numpy().reshape(3, -1)
-    state = inputs.blast(xyz) if sharp else inputs.blast_smooth(xyz, width=1.0 / (27 * 9))
+    state = inputs.blast(xyz, radius=0.25 - 1.0 / 81) if sharp else inputs.blast_smooth(xyz, width=1.0 / (27 * 9))
     u0 = torch.from_numpy(state.reshape(-1)).cuda()
     del xyz, state
     if sharp:
@@ -516,6 +519,7 @@ def main():
     }
     if not args.no_extra:
         out["other_workloads"] = {"amr_blast_p4_27cubed_2levels": run_amr(A),
+                                  "amr_sharp_blast_p4_27cubed_2levels_limited": run_amr(A, steps=20, sharp=True),
                                   "batch64_p2to6_seed0": run_batch(A),
                                   "adjoint_p3_27cubed_20steps": run_adjoint(A),
                                   "limiter_blast_p3_81cubed": run_limiter(A),

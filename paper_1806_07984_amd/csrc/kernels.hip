@@ -889,9 +889,13 @@ __device__ __forceinline__ double fibre_sum64(const double c[4], double x, doubl
     return acc;
 }
 
+// STORE: also write iterate it (1 .. npic) of every time node to
+// iters[it-1][j][v][c][node], the layout the adjoint reads
+template <bool STORE>
 __device__ __forceinline__ void pred4_wave_f64(const double *__restrict__ u, double *__restrict__ ustar,
                                                double *__restrict__ traces, int64_t c, int64_t nc, int lev,
-                                               const Geo &geo, double dt, double gamma, int npic)
+                                               const Geo &geo, double dt, double gamma, int npic,
+                                               double *__restrict__ iters)
 {
     constexpr int N = 4, N2 = 16, N3 = 64;
     const DevBasis &B = c_basis[N];
@@ -933,6 +937,15 @@ __device__ __forceinline__ void pred4_wave_f64(const double *__restrict__ u, dou
     };
 
     double q[N][NV];
+    auto store_iterate = [&](int it) {
+        if constexpr (STORE) {
+#pragma unroll
+            for (int j = 0; j < N; ++j)
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+                    *lane_at(iters + (((int64_t(it) * N + j) * NV + v) * nc + c) * N3, lu) = q[j][v];
+        }
+    };
     if (npic > 0) {
         // first iteration from q = u at every time node: one flux and one
         // divergence serve all time nodes; the row sums of KW finish it
@@ -942,6 +955,7 @@ __device__ __forceinline__ void pred4_wave_f64(const double *__restrict__ u, dou
         for (int j = 0; j < N; ++j)
 #pragma unroll
             for (int v = 0; v < NV; ++v) q[j][v] = fma(-B.KWsum[j], g[v], uu[v]);
+        store_iterate(0);
     } else {
 #pragma unroll
         for (int j = 0; j < N; ++j)
@@ -949,24 +963,31 @@ __device__ __forceinline__ void pred4_wave_f64(const double *__restrict__ u, dou
             for (int v = 0; v < NV; ++v) q[j][v] = uu[v];
     }
     for (int it = 1; it < npic; ++it) {
-        double acc[N][NV];
-#pragma unroll
-        for (int i = 0; i < N; ++i)
-#pragma unroll
-            for (int v = 0; v < NV; ++v) acc[i][v] = 0.0;
+        // G_j replaces q_j as soon as it is formed (q_j is not needed
+        // again), so the iterate and the divergences share registers; the
+        // time solve then sums over j in order
 #pragma unroll
         for (int j = 0; j < N; ++j) {
             double g[NV];
             spatial(q[j], g);
 #pragma unroll
-            for (int i = 0; i < N; ++i)
-#pragma unroll
-                for (int v = 0; v < NV; ++v) acc[i][v] = fma(B.KW[i * N + j], g[v], acc[i][v]);
+            for (int v = 0; v < NV; ++v) q[j][v] = g[v];
         }
+        double qn[N][NV];
 #pragma unroll
         for (int i = 0; i < N; ++i)
 #pragma unroll
-            for (int v = 0; v < NV; ++v) q[i][v] = uu[v] - acc[i][v];
+            for (int v = 0; v < NV; ++v) {
+                double acc = 0.0;
+#pragma unroll
+                for (int j = 0; j < N; ++j) acc = fma(B.KW[i * N + j], q[j][v], acc);
+                qn[i][v] = uu[v] - acc;
+            }
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) q[i][v] = qn[i][v];
+        store_iterate(it);
     }
 
     // time averages of the final iterate
@@ -1046,16 +1067,17 @@ __device__ __forceinline__ void pred4_wave_f64(const double *__restrict__ u, dou
     }
 }
 
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
+template <bool STORE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
 k_predictor4_f64(const double *__restrict__ u, double *__restrict__ ustar, double *__restrict__ traces,
                  const int32_t *__restrict__ list, int64_t nlist, int64_t nc, const int8_t *__restrict__ level,
-                 Geo geo, const double *__restrict__ dt_dev, double gamma, int npic)
+                 Geo geo, const double *__restrict__ dt_dev, double gamma, int npic, double *__restrict__ iters)
 {
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
     const int64_t idx = int64_t(blockIdx.x) * (blockDim.x >> 6) + wave;
     if (idx >= nlist) return;  // whole wavefront leaves together
     const int64_t c = list ? int64_t(list[idx]) : idx;
-    pred4_wave_f64(u, ustar, traces, c, nc, level ? level[c] : 0, geo, dt_dev[0], gamma, npic);
+    pred4_wave_f64<STORE>(u, ustar, traces, c, nc, level ? level[c] : 0, geo, dt_dev[0], gamma, npic, iters);
 }
 
 // ---------------------------------------------------------------------------
@@ -3246,10 +3268,14 @@ hipError_t launch_predictor(int N, const double *u, double *ustar, T *traces, co
             return hipGetLastError();
         }
     } else {
-        if (N == 4 && iters == nullptr && g_pred4_f64) {
+        if (N == 4 && g_pred4_f64) {
             const int64_t blocks = (nlist + 3) / 4;
-            hipLaunchKernelGGL(k_predictor4_f64, dim3(unsigned(blocks)), dim3(256), 0, st, u, ustar, traces, list,
-                               nlist, nc, level, geo, dt, gamma, npic);
+            if (iters)
+                hipLaunchKernelGGL(k_predictor4_f64<true>, dim3(unsigned(blocks)), dim3(256), 0, st, u, ustar, traces,
+                                   list, nlist, nc, level, geo, dt, gamma, npic, iters);
+            else
+                hipLaunchKernelGGL(k_predictor4_f64<false>, dim3(unsigned(blocks)), dim3(256), 0, st, u, ustar,
+                                   traces, list, nlist, nc, level, geo, dt, gamma, npic, iters);
             return hipGetLastError();
         }
     }
