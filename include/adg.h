@@ -176,6 +176,24 @@ adg_status adg_corrector(adg_mesh *mesh, const double *ustar_dev, const void *fs
 adg_status adg_step(adg_mesh *mesh, double *u_dev, int32_t n_steps, double t_end, double *dt_hist_dev,
                     void *ws_dev, hipStream_t stream_skeleton, hipStream_t stream_enclave);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): adg_step with its
+ * workspace taken from a static device array of the library instead of a
+ * caller buffer.  The array holds ADG_NOALLOC_WORKSPACE_BYTES (64 MiB) on
+ * every GPU the library runs on, from the first adg_init_mesh on that GPU
+ * until the process ends; handles whose workspace_bytes exceed it get
+ * ADG_ERR_WORKSPACE (uniform FP64 meshes of up to about 5,800 cells at
+ * p = 3 fit).  The call allocates nothing: plain launches on `stream` (no
+ * graph), both predictor parts on that stream; ADG_ERR_UNSUPPORTED while
+ * adg_profile is on.  Nothing in the array needs to start at zero, and its
+ * contents after a call are unspecified.  All calls on one GPU share the
+ * array: calls that may overlap in time on one GPU (other streams, other
+ * host threads) race and give wrong results; calls ordered on one stream
+ * are safe.  Results are those of adg_step on the same handle. */
+#define ADG_NOALLOC_WORKSPACE_BYTES (64LL * 1024 * 1024)
+adg_status adg_step_noalloc(adg_mesh *mesh, double *u_dev, int32_t n_steps, double t_end, double *dt_hist_dev,
+                            hipStream_t stream);
+
 /* Batched handles (more than one instance, none with hanging faces) run the
  * predictors of all instances from a work list whose items are groups of
  * cells of one instance: either one persistent launch per order over the

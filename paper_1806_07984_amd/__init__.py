@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libadg.so")
 
 NV = 5
 FP64, FP32_MFMA = 0, 1
+NOALLOC_WORKSPACE_BYTES = 64 * 1024 * 1024  # ADG_NOALLOC_WORKSPACE_BYTES
 
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "OOM", 4: "HIP", 5: "NONPHYSICAL", 6: "WORKSPACE"}
 
@@ -25,7 +26,7 @@ EXPORTS = ["adg_init_mesh", "adg_free_mesh", "adg_mesh_info", "adg_instance_info
            "adg_tuning", "adg_set_options", "adg_step_adjoint", "adg_sample", "adg_sample_adjoint",
            "adg_set_switch_tape", "adg_set_pipeline", "adg_indicator", "adg_adapt_plan", "adg_transfer",
            "adg_set_limiter", "adg_limiter_stats", "adg_lin_init", "adg_lin_free", "adg_lin_info", "adg_lin_dt",
-           "adg_lin_predictor", "adg_lin_step"]
+           "adg_lin_predictor", "adg_lin_step", "adg_step_noalloc"]
 PHASES = ["cfl", "predictor", "hanging", "riemann", "corrector", "limiter"]
 
 
@@ -84,6 +85,7 @@ def load():
         "adg_riemann": [P, P, P, P],
         "adg_corrector": [P, P, P, P, P, P],
         "adg_step": [P, P, I32, ctypes.c_double, P, P, P, P],
+        "adg_step_noalloc": [P, P, I32, ctypes.c_double, P, P],
         "adg_get_status": [P],
         "adg_profile": [P, I32],
         "adg_profile_read": [P, P, P],
@@ -310,6 +312,15 @@ class Mesh:
             raise ValueError("workspace too small")
         _check(load().adg_step(self._h, _ptr(u, torch.float64, self.info["u_elems"], "u"), int(n_steps),
                                float(t_end), hist, ctypes.c_void_p(ws.data_ptr()), s1, s2))
+
+    def step_noalloc(self, u, n_steps, dt_hist=None, stream=None, t_end=0.0):
+        """n_steps whole steps in place on u with the library's static
+        workspace instead of a caller buffer (adg_step_noalloc)."""
+        import torch
+        hist = ctypes.c_void_p(0) if dt_hist is None else \
+            _ptr(dt_hist, torch.float64, n_steps * self.n_instances, "dt_hist")
+        _check(load().adg_step_noalloc(self._h, _ptr(u, torch.float64, self.info["u_elems"], "u"), int(n_steps),
+                                       float(t_end), hist, _stream(stream)))
 
     def autotune(self, u, ws, stream=None):
         """Pick the cells per work item of every order by timing (adg_autotune)."""

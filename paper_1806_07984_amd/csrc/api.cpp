@@ -10,6 +10,12 @@
 #include "adg_internal.h"
 #include "kernels.h"
 
+// Workspace of adg_step_noalloc: one copy of this array per GPU, held until
+// the process ends.  In host code the name is only a stand-in for the
+// symbol, not a device address: host code uses the per-device addresses
+// that ensure_scratch takes with hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[ADG_NOALLOC_WORKSPACE_BYTES];
+
 namespace adg {
 
 static thread_local std::string g_last_error;
@@ -184,6 +190,29 @@ adg_status ensure_basis(int device)
         return ADG_ERR_HIP;
     }
     g_basis_uploaded[device] = true;
+    return ADG_OK;
+}
+
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[64] = {nullptr};
+
+// Device address of this device's copy of `scratch`; taken once per device
+// with the device current (the handle's init call).
+adg_status ensure_scratch(int device)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mutex);
+    if (device < 0 || device >= 64) {
+        set_error("device index out of range");
+        return ADG_ERR_UNSUPPORTED;
+    }
+    if (g_scratch_ptr[device]) return ADG_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        set_error(std::string("address of the static workspace: ") + hipGetErrorString(e));
+        return ADG_ERR_HIP;
+    }
+    g_scratch_ptr[device] = p;
     return ADG_OK;
 }
 
@@ -986,6 +1015,7 @@ adg_status adg_init_mesh(const adg_instance_desc *desc, int32_t n_instances, adg
         return ADG_ERR_HIP;
     }
     adg_status bs = ensure_basis(m->device);
+    if (bs == ADG_OK) bs = ensure_scratch(m->device);
     if (bs != ADG_OK) {
         delete m;
         return bs;
@@ -1247,6 +1277,36 @@ adg_status adg_step(adg_mesh *mesh, double *u, int32_t n_steps, double t_end, do
     }
     if (mesh->prec == ADG_FP64) return step_impl<double>(mesh, u, n_steps, t_end, dt_hist, ws, s_skel, s_encl);
     return step_impl<float>(mesh, u, n_steps, t_end, dt_hist, ws, s_skel, s_encl);
+}
+
+adg_status adg_step_noalloc(adg_mesh *mesh, double *u, int32_t n_steps, double t_end, double *dt_hist,
+                            hipStream_t stream)
+{
+    if (!valid_mesh(mesh) || !u || n_steps < 0) {
+        set_error("adg_step_noalloc: null argument or negative step count");
+        return ADG_ERR_INVALID_ARG;
+    }
+    if (mesh->info.workspace_bytes > ADG_NOALLOC_WORKSPACE_BYTES) {
+        set_error("adg_step_noalloc: the mesh needs " + std::to_string(mesh->info.workspace_bytes) +
+                  " workspace bytes, more than the static " + std::to_string(ADG_NOALLOC_WORKSPACE_BYTES) +
+                  "; use adg_step with a caller workspace");
+        return ADG_ERR_WORKSPACE;
+    }
+    if (mesh->prof) {
+        set_error("adg_step_noalloc: phase timing creates events; switch adg_profile off");
+        return ADG_ERR_UNSUPPORTED;
+    }
+    void *ws = g_scratch_ptr[mesh->device];
+    if (!ws) {
+        set_error("adg_step_noalloc: static workspace not set up on the handle's device");
+        return ADG_ERR_HIP;
+    }
+    if (n_steps == 0) return ADG_OK;
+    adg_status st = start_clock(mesh, t_end, stream);
+    if (st != ADG_OK) return st;
+    // plain launches on one stream: no graph is instantiated
+    if (mesh->prec == ADG_FP64) return step_eager<double>(mesh, u, n_steps, dt_hist, ws, stream, stream);
+    return step_eager<float>(mesh, u, n_steps, dt_hist, ws, stream, stream);
 }
 
 adg_status adg_autotune(adg_mesh *mesh, const double *u, void *ws, hipStream_t stream)
