@@ -840,11 +840,19 @@ k_predictor4_mfma_order(const PredItem *__restrict__ items, int64_t nitems, cons
 // ---------------------------------------------------------------------------
 // Predictor for N = 4 in FP64 on one wavefront per cell, without LDS memory.
 // The same lane layout as the FP32 kernel above (lane l = node a = l, the
-// whole time history of the node in registers).  A double moves between
-// lanes as two 32-bit halves:
-//   x contraction: DPP quad permutations of both halves, then FMAs;
+// whole time history of the node in registers).
+//   x contraction: DPP quad permutations (a double moves as two 32-bit
+//                  DPP moves into a register pair), then FMAs;
 //   y contraction: DPP row rotations by 4 k lanes;
-//   z contraction: ds_bpermute of both halves (the LDS crossbar);
+//   z contraction: one v_mfma_f64_4x4x4f64 per variable.  Its 4 blocks are
+//                  the lane groups of equal a1; block b takes A[i][k] from
+//                  lane 4b + i + 16k and B[k][j] from lane 4b + j + 16k and
+//                  puts D[i][j] in lane 4b + j + 16i (measured on gfx950).
+//                  With the node layout, B[k][j] is the flux at node
+//                  (a0 = j, a1 = b, a2 = k) and D[i][j] lands on node
+//                  (j, b, i): the matrix core contracts over a2 in place,
+//                  given A[i][k] = (dt/dz) D_ik in lane i + 16k (any block),
+//                  and accumulates onto the x and y sums (C operand);
 //   time solve:    q_l = u - sum_j KW[l][j] G_j with the KW entries
 //                  wave-uniform (scalar operands of the FMAs).
 // ---------------------------------------------------------------------------
@@ -859,34 +867,29 @@ template <int CTRL> __device__ __forceinline__ double dpp64(double x)
 constexpr int DPP_QP1 = 0x39, DPP_QP2 = 0x4E, DPP_QP3 = 0x93;
 constexpr int DPP_ROR4 = 0x124, DPP_ROR8 = 0x128, DPP_ROR12 = 0x12C;
 
-// x of the lane whose byte address (4 x lane index) is addr
-__device__ __forceinline__ double from_lane64(int addr, double x)
-{
-    const long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_ds_bpermute(addr, int(b & 0xffffffff));
-    const int hi = __builtin_amdgcn_ds_bpermute(addr, int(b >> 32));
-    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
-}
-
 // sum_e c[e] x(lane of the e-th neighbour along the axis): x through quad
-// permutations (axis 0), row rotations (axis 1) or the crossbar (axis 2)
+// permutations (axis 0) or row rotations (axis 1)
 template <int AXIS>
-__device__ __forceinline__ double fibre_sum64(const double c[4], double x, double acc, const int pz[4])
+__device__ __forceinline__ double fibre_sum64(const double c[4], double x, double acc)
 {
     acc = fma(c[0], x, acc);
     if constexpr (AXIS == 0) {
         acc = fma(c[1], dpp64<DPP_QP1>(x), acc);
         acc = fma(c[2], dpp64<DPP_QP2>(x), acc);
         acc = fma(c[3], dpp64<DPP_QP3>(x), acc);
-    } else if constexpr (AXIS == 1) {
+    } else {
         acc = fma(c[1], dpp64<DPP_ROR4>(x), acc);
         acc = fma(c[2], dpp64<DPP_ROR8>(x), acc);
         acc = fma(c[3], dpp64<DPP_ROR12>(x), acc);
-    } else {
-#pragma unroll
-        for (int k = 1; k < 4; ++k) acc = fma(c[k], from_lane64(pz[k], x), acc);
     }
     return acc;
+}
+
+// acc + sum_k A[a2][k] x(node a0, a1, k) on the matrix cores; a is this
+// lane's A entry (row lane & 3, column lane >> 4)
+__device__ __forceinline__ double zsum64(double a, double x, double acc)
+{
+    return __builtin_amdgcn_mfma_f64_4x4x4f64(a, x, acc, 0, 0, 0);
 }
 
 // STORE: also write iterate it (1 .. npic) of every time node to
@@ -908,21 +911,19 @@ __device__ __forceinline__ void pred4_wave_f64(const double *__restrict__ u, dou
 #pragma unroll
     for (int v = 0; v < NV; ++v) uu[v] = *lane_at(u + (int64_t(v) * nc + c) * N3, lu);
 
-    // neighbour e of this lane along each axis: a0 + e (quad permutation),
-    // a1 - e (row rotation), a2 + e (crossbar), all mod 4
+    // neighbour e of this lane along x and y: a0 + e (quad permutation),
+    // a1 - e (row rotation), mod 4; the z operator as this lane's MFMA A
+    // entry, row zi = l & 3, column zk = l >> 4
     const int nx[4] = {a0, (a0 + 1) & 3, (a0 + 2) & 3, (a0 + 3) & 3};
     const int ny[4] = {a1, (a1 + 3) & 3, (a1 + 2) & 3, (a1 + 1) & 3};
-    const int nz[4] = {a2, (a2 + 1) & 3, (a2 + 2) & 3, (a2 + 3) & 3};
-    int pz[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) pz[k] = ((l + 16 * k) & 63) * 4;
-    double Cx[4], Cy[4], Cz[4];
+    const int zi = l & 3, zk = l >> 4;
+    double Cx[4], Cy[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         Cx[e] = cd[0] * B.D[a0 * N + nx[e]];
         Cy[e] = cd[1] * B.D[a1 * N + ny[e]];
-        Cz[e] = cd[2] * B.D[a2 * N + nz[e]];
     }
+    const double Az = cd[2] * B.D[zi * N + zk];
 
     // scaled divergence sum_d (dt/dx_d) D_d F_d(qn) at this lane's node
     auto spatial = [&](const double qn[NV], double g[NV]) {
@@ -930,9 +931,9 @@ __device__ __forceinline__ void pred4_wave_f64(const double *__restrict__ u, dou
         euler_flux3(gm1, qn, f);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            double s = fibre_sum64<2>(Cz, f[2][v], 0.0, pz);
-            s = fibre_sum64<0>(Cx, f[0][v], s, pz);
-            g[v] = fibre_sum64<1>(Cy, f[1][v], s, pz);
+            double s = fibre_sum64<0>(Cx, f[0][v], 0.0);
+            s = fibre_sum64<1>(Cy, f[1][v], s);
+            g[v] = zsum64(Az, f[2][v], s);
         }
     };
 
@@ -1012,18 +1013,18 @@ __device__ __forceinline__ void pred4_wave_f64(const double *__restrict__ u, dou
 
     // volume term of the corrector with the weak stiffness Kw
     {
-        double Vx[4], Vy[4], Vz[4];
+        double Vx[4], Vy[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             Vx[e] = cd[0] * B.winv[a0] * B.Kw[a0 * N + nx[e]];
             Vy[e] = cd[1] * B.winv[a1] * B.Kw[a1 * N + ny[e]];
-            Vz[e] = cd[2] * B.winv[a2] * B.Kw[a2 * N + nz[e]];
         }
+        const double Vz = cd[2] * B.winv[zi] * B.Kw[zi * N + zk];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            double V = fibre_sum64<2>(Vz, Fb[2][v], 0.0, pz);
-            V = fibre_sum64<0>(Vx, Fb[0][v], V, pz);
-            V = fibre_sum64<1>(Vy, Fb[1][v], V, pz);
+            double V = fibre_sum64<0>(Vx, Fb[0][v], 0.0);
+            V = fibre_sum64<1>(Vy, Fb[1][v], V);
+            V = zsum64(Vz, Fb[2][v], V);
             *lane_at(ustar + (int64_t(v) * nc + c) * N3, lu) = uu[v] + V;
         }
     }
@@ -1033,13 +1034,14 @@ __device__ __forceinline__ void pred4_wave_f64(const double *__restrict__ u, dou
     // one sum; the others' stores get an offset beyond the 128-byte plane
     // view, which buffer range checking drops
     {
-        double Px[4], Py[4], Pz[4];
+        double Px[4], Py[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             Px[e] = a0 == 0 ? B.L[nx[e]] : B.R[nx[e]];
             Py[e] = a1 == 0 ? B.L[ny[e]] : B.R[ny[e]];
-            Pz[e] = a2 == 0 ? B.L[nz[e]] : B.R[nz[e]];
         }
+        // rows 0 (minus face) and 3 (plus face) of the z projection
+        const double Pz = zi == 0 ? B.L[zk] : B.R[zk];
         constexpr unsigned F = sizeof(double), OUT = 0x80000000u;
         const unsigned bx = (a1 + 4 * a2) * F, by = (a0 + 4 * a2) * F, bz = (a0 + 4 * a1) * F;
         const unsigned o0 = a0 == 0 ? bx : OUT, o1 = a0 == 3 ? bx : OUT;
@@ -1053,13 +1055,13 @@ __device__ __forceinline__ void pred4_wave_f64(const double *__restrict__ u, dou
         for (int v = 0; v < NV; ++v) {
 #pragma unroll
             for (int arr = 0; arr < 2; ++arr) {
-                const double px = fibre_sum64<0>(Px, arr == 0 ? qb[v] : Fb[0][v], 0.0, pz);
+                const double px = fibre_sum64<0>(Px, arr == 0 ? qb[v] : Fb[0][v], 0.0);
                 put(0, arr, v, o0, px);
                 put(1, arr, v, o1, px);
-                const double py = fibre_sum64<1>(Py, arr == 0 ? qb[v] : Fb[1][v], 0.0, pz);
+                const double py = fibre_sum64<1>(Py, arr == 0 ? qb[v] : Fb[1][v], 0.0);
                 put(2, arr, v, o2, py);
                 put(3, arr, v, o3, py);
-                const double pzv = fibre_sum64<2>(Pz, arr == 0 ? qb[v] : Fb[2][v], 0.0, pz);
+                const double pzv = zsum64(Pz, arr == 0 ? qb[v] : Fb[2][v], 0.0);
                 put(4, arr, v, o4, pzv);
                 put(5, arr, v, o5, pzv);
             }
