@@ -1082,6 +1082,213 @@ k_predictor4_f64(const double *__restrict__ u, double *__restrict__ ustar, doubl
     pred4_wave_f64<STORE>(u, ustar, traces, c, nc, level ? level[c] : 0, geo, dt_dev[0], gamma, npic, iters);
 }
 
+// sum_d (d f_d / d q)^T fb[d] added to qb, for the Euler fluxes of the three
+// axes at once (their common terms formed once).  With v = m / rho,
+// H = (E + p) / rho, fb[d] = (a_d, b_d1, b_d2, b_d3, c_d) and
+// S = sum_d (b_dd + v_d c_d), the weight every p-term carries:
+//   qb_rho += -sum_d v_d (sum_k b_dk v_k + H c_d) + S (gamma-1) |v|^2 / 2
+//   qb_m_j += a_j + sum_k b_jk v_k + sum_d b_dj v_d + c_j H - S (gamma-1) v_j
+//   qb_E   += sum_d c_d v_d + S (gamma-1)
+__device__ __forceinline__ void flux3_vjp(double gm1, const double q[NV], const double fb[3][NV], double qb[NV])
+{
+    const double inv = 1.0 / q[0];
+    const double v[3] = {q[1] * inv, q[2] * inv, q[3] * inv};
+    const double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    const double p = gm1 * (q[4] - 0.5 * q[0] * v2);
+    const double H = (q[4] + p) * inv;
+    double S = 0.0, r = 0.0, e = 0.0;
+    double bv[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        bv[d] = fb[d][1] * v[0] + fb[d][2] * v[1] + fb[d][3] * v[2];
+        S += fb[d][1 + d] + v[d] * fb[d][4];
+        r -= v[d] * (bv[d] + H * fb[d][4]);
+        e += fb[d][4] * v[d];
+    }
+    qb[0] += r + S * gm1 * 0.5 * v2;
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+        qb[1 + j] += fb[j][0] + bv[j] + (fb[0][1 + j] * v[0] + fb[1][1 + j] * v[1] + fb[2][1 + j] * v[2]) +
+                     fb[j][4] * H - S * gm1 * v[j];
+    qb[4] += e + S * gm1;
+}
+
+// Adjoint of the FP64 N = 4 predictor (the forward kernel above) on one
+// wavefront per cell, lane = node.  The transposed contractions use the same
+// exchanges as the forward ones with transposed coefficients (x and y by
+// DPP, z on the matrix cores with A[i][k] = transposed operator); the
+// Picard iterates come from the forward run (iters, slots 0..npic-1 =
+// iterates 1..npic).
+__device__ __forceinline__ void pred4_adj_wave(const double *__restrict__ u, const double *__restrict__ iters,
+                                               const double *__restrict__ ubar_next, const double *__restrict__ tbar,
+                                               double *__restrict__ ubar, int64_t c, int64_t nc, int lev,
+                                               const Geo &geo, double dt, double gamma, int npic)
+{
+    constexpr int N = 4, N2 = 16, N3 = 64;
+    const DevBasis &B = c_basis[N];
+    const int l = threadIdx.x & 63;
+    const int a0 = l & 3, a1 = (l >> 2) & 3, a2 = l >> 4;
+    const int bf[3] = {a1 + N * a2, a0 + N * a2, a0 + N * a1};
+    const double cd[3] = {dt * geo.inv_dx[lev][0], dt * geo.inv_dx[lev][1], dt * geo.inv_dx[lev][2]};
+    const double gm1 = gamma - 1.0;
+    const unsigned lu = unsigned(l) * unsigned(sizeof(double));
+    const int nx[4] = {a0, (a0 + 1) & 3, (a0 + 2) & 3, (a0 + 3) & 3};
+    const int ny[4] = {a1, (a1 + 3) & 3, (a1 + 2) & 3, (a1 + 1) & 3};
+    const int zi = l & 3, zk = l >> 4;
+    auto load_q = [&](int r, int j, double q[NV]) {  // iterate r (0 = u) at time node j
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            q[v] = r == 0 ? *lane_at(u + (int64_t(v) * nc + c) * N3, lu)
+                          : *lane_at(iters + (((int64_t(r - 1) * N + j) * NV + v) * nc + c) * N3, lu);
+    };
+
+    // adjoint of u* = u + volume term: identity, and the transposed volume
+    // term into the time-averaged fluxes
+    double ub[NV], acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        ub[v] = *lane_at(ubar_next + (int64_t(v) * nc + c) * N3, lu);
+        acc[v] = ub[v];
+    }
+    double Fbb[3][NV], qbb[NV];
+    {
+        double Vx[4], Vy[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            Vx[e] = cd[0] * B.winv[nx[e]] * B.Kw[nx[e] * N + a0];
+            Vy[e] = cd[1] * B.winv[ny[e]] * B.Kw[ny[e] * N + a1];
+        }
+        const double Vz = cd[2] * B.winv[zk] * B.Kw[zk * N + zi];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            Fbb[0][v] = fibre_sum64<0>(Vx, ub[v], 0.0);
+            Fbb[1][v] = fibre_sum64<1>(Vy, ub[v], 0.0);
+            Fbb[2][v] = zsum64(Vz, ub[v], 0.0);
+        }
+    }
+    // adjoint of the face projections (each node reads its own face entries)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) qbb[v] = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int ad = d == 0 ? a0 : (d == 1 ? a1 : a2);
+        const double Lk = B.L[ad], Rk = B.R[ad];
+        const unsigned fo = unsigned(bf[d]) * unsigned(sizeof(double));
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double *qm = tbar + ((int64_t((2 * d) * 2 + 0) * NV + v) * nc + c) * N2;
+            const double *qp = tbar + ((int64_t((2 * d + 1) * 2 + 0) * NV + v) * nc + c) * N2;
+            const double *fm = tbar + ((int64_t((2 * d) * 2 + 1) * NV + v) * nc + c) * N2;
+            const double *fp = tbar + ((int64_t((2 * d + 1) * 2 + 1) * NV + v) * nc + c) * N2;
+            qbb[v] += Lk * *lane_at(qm, fo) + Rk * *lane_at(qp, fo);
+            Fbb[d][v] += Lk * *lane_at(fm, fo) + Rk * *lane_at(fp, fo);
+        }
+        SCHED_SPLIT();  // one axis of loads in flight at a time
+    }
+    // adjoint of the time averages of the final iterate
+    double qbar[N][NV];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        double q[NV], fbw[3][NV];
+        load_q(npic, j, q);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            qbar[j][v] = B.w[j] * qbb[v];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) fbw[d][v] = B.w[j] * Fbb[d][v];
+        }
+        flux3_vjp(gm1, q, fbw, qbar[j]);
+        SCHED_SPLIT();
+    }
+    // transposed derivative operators (dt/dx_d) D_d^T
+    double Dx[4], Dy[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        Dx[e] = cd[0] * B.D[nx[e] * N + a0];
+        Dy[e] = cd[1] * B.D[ny[e] * N + a1];
+    }
+    const double Dz = cd[2] * B.D[zk * N + zi];
+    // Picard iterations in reverse: q^(r) = u - sum_j KW[l][j] G_j(q^(r-1)),
+    // r = npic .. 2; the divergences' adjoints Gb_j replace the iterate
+    // adjoints, which are then rebuilt time node by time node
+    auto divergence_vjp = [&](const double q[NV], const double gb[NV], double nb[NV]) {
+        double fb[3][NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            fb[0][v] = fibre_sum64<0>(Dx, gb[v], 0.0);
+            fb[1][v] = fibre_sum64<1>(Dy, gb[v], 0.0);
+            fb[2][v] = zsum64(Dz, gb[v], 0.0);
+            nb[v] = 0.0;
+        }
+        flux3_vjp(gm1, q, fb, nb);
+    };
+    for (int r = npic; r >= 2; --r) {
+        double Gb[N][NV];
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                double s = 0.0;
+#pragma unroll
+                for (int i = 0; i < N; ++i) s = fma(B.KW[i * N + j], qbar[i][v], s);
+                Gb[j][v] = -s;
+            }
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[v] += qbar[i][v];
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            double q[NV];
+            load_q(r - 1, j, q);
+            divergence_vjp(q, Gb[j], qbar[j]);
+            SCHED_SPLIT();  // one time node at a time: bounds the live registers
+        }
+    }
+    // r = 1: every q^(0)_j is u, and one divergence served all time nodes
+    // with the row sums of KW; q^(0) = u adds the rest
+    if (npic >= 1) {
+        double gs[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double s = 0.0;
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                s = fma(B.KWsum[i], qbar[i][v], s);
+                acc[v] += qbar[i][v];
+            }
+            gs[v] = -s;
+        }
+        double q[NV], nb[NV];
+        load_q(0, 0, q);
+        divergence_vjp(q, gs, nb);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] += nb[v];
+    } else {
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[v] += qbar[j][v];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) *lane_at(ubar + (int64_t(v) * nc + c) * N3, lu) = acc[v];
+}
+
+// one wave per SIMD: the whole register file (256 VGPRs and the AGPRs) holds
+// the cotangents without spills; at two waves it spills 300 B per lane and the
+// gradient of 20 steps at 27^3 took 3 % longer
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 8)))
+k_predictor4_adj_f64(const double *__restrict__ u, const double *__restrict__ iters,
+                     const double *__restrict__ ubar_next, const double *__restrict__ tbar,
+                     const double *__restrict__ dt_dev, double *__restrict__ ubar, int64_t nc,
+                     const int8_t *__restrict__ level, Geo geo, double gamma, int npic)
+{
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const int64_t c = int64_t(blockIdx.x) * (blockDim.x >> 6) + wave;
+    if (c >= nc) return;  // whole wavefront leaves together
+    pred4_adj_wave(u, iters, ubar_next, tbar, ubar, c, nc, level ? level[c] : 0, geo, dt_dev[0], gamma, npic);
+}
+
 // ---------------------------------------------------------------------------
 // Riemann solves on conforming faces of one axis
 // ---------------------------------------------------------------------------
@@ -3566,9 +3773,13 @@ hipError_t launch_adjoint_step(int N, const double *u, const double *dt, const d
             hipLaunchKernelGGL((k_prolong_adj<NN>), dim3(unsigned((ah.ncs * N2 + 255) / 256)), dim3(256), 0, st,
                                tbar, ah.vbar, ah.hang, ah.ccell, ah.cside, ah.cptr, ah.cchild, ah.ncs, nc, ah.ptab);
         constexpr int CPB = PredCfg<NN>::CPB;
-        hipLaunchKernelGGL((k_predictor_adj<NN, CPB>), dim3(unsigned((nc + CPB - 1) / CPB)),
-                           dim3(round64(CPB * NN * NN * NN)), 0, st, u, iters, ubar_next, tbar, dt, ubar, nc, level,
-                           geo, gamma, npic);
+        if (NN == 4 && g_pred4_f64)
+            hipLaunchKernelGGL(k_predictor4_adj_f64, dim3(unsigned((nc + 3) / 4)), dim3(256), 0, st, u, iters,
+                               ubar_next, tbar, dt, ubar, nc, level, geo, gamma, npic);
+        else
+            hipLaunchKernelGGL((k_predictor_adj<NN, CPB>), dim3(unsigned((nc + CPB - 1) / CPB)),
+                               dim3(round64(CPB * NN * NN * NN)), 0, st, u, iters, ubar_next, tbar, dt, ubar, nc,
+                               level, geo, gamma, npic);
     });
     return hipGetLastError();
 }
