@@ -115,13 +115,48 @@ __device__ __forceinline__ void pred4_wave(const double *__restrict__ u, double 
 // generic path stays compiled for the FP64 form and other orders)
 constexpr bool g_pred4_mfma_dev = true;
 
-// LDS layout of the generic predictor, per cell: the 15 values (3 axes x 5
-// variables) of every node in node order.  A wave's writes are consecutive;
-// a fibre read is a broadcast across the lanes that share the fibre (cheaper
-// in LDS bandwidth than wide loads, which move all their bytes per lane).
-template <typename T, int N> struct Fib {
-    static constexpr int PER_CELL = 15 * N * N * N;
-};
+// a scheduling fence: keeps the compiler from hoisting the loads of later
+// work above it (bounds the live registers of long unrolled sequences)
+#ifndef SCHED_SPLIT
+#define SCHED_SPLIT() __builtin_amdgcn_sched_barrier(0)
+#endif
+
+// LDS of the generic predictor: NBUF buffers of 15 planes (3 axes x 5
+// variables).  A plane holds one value per thread of the block (thread t =
+// cell t / N^3 of the block, node t % N^3) and is padded to whole wavefronts,
+// so every lane writes its slot without a branch.  A fibre read is a
+// broadcast across the lanes that share the fibre (cheaper in LDS bandwidth
+// than wide loads, which move all their bytes per lane).  With two buffers,
+// consecutive flux exchanges alternate and need one barrier each.
+constexpr int pred_plane(int N, int CPB) { return round64(CPB * N * N * N); }
+constexpr int pred_nbuf(int N, int CPB, int real_bytes)
+{
+    return 2 * 15 * pred_plane(N, CPB) * real_bytes <= 65536 ? 2 : 1;
+}
+constexpr int pred_lds_elems(int N, int CPB, int real_bytes)
+{
+    return pred_nbuf(N, CPB, real_bytes) * 15 * pred_plane(N, CPB);
+}
+
+// Write planes (f[d][v] into plane d NV + v, or q[v] into plane v, at this
+// thread's slot) of the next buffer, one barrier, and return that buffer.
+// With a single buffer, a barrier first lets every lane finish reading the
+// previous exchange.
+template <typename T, int P, int NBUF, int ND>
+__device__ __forceinline__ const T *pred_exchange(T *lds, int &buf, int tid, const T (&f)[ND][NV])
+{
+    T *w = lds + buf * (15 * P);
+    if constexpr (NBUF == 1) __syncthreads();
+    if (tid < P) {
+#pragma unroll
+        for (int d = 0; d < ND; ++d)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) w[(d * NV + v) * P + tid] = f[d][v];
+    }
+    __syncthreads();
+    if constexpr (NBUF == 2) buf ^= 1;
+    return w;
+}
 
 // Euler fluxes in FP32: hardware reciprocal for 1/rho, and the symmetric
 // momentum flux formed once
@@ -150,7 +185,8 @@ __device__ __forceinline__ void flux3(T gm1, const T q[NV], T f[3][NV])
 }
 
 // Predictor of CPB cells (list entries first .. first+CPB-1) by one block of
-// at least CPB * N^3 threads; lds holds CPB * Fib<T, N>::PER_CELL reals.
+// at least pred_plane(N, CPB) threads; lds holds pred_lds_elems(N, CPB,
+// sizeof(T)) reals.
 template <typename T, int N, int CPB, bool STORE = false>
 __device__ __forceinline__ void predictor_body(T *__restrict__ lds, const double *__restrict__ u,
                                                double *__restrict__ ustar, T *__restrict__ traces,
@@ -160,17 +196,23 @@ __device__ __forceinline__ void predictor_body(T *__restrict__ lds, const double
                                                T *__restrict__ iters = nullptr)
 {
     constexpr int N2 = N * N, N3 = N2 * N, NT = CPB * N3;
-    constexpr int PC = Fib<T, N>::PER_CELL;
+    constexpr int P = pred_plane(N, CPB);
+    constexpr int NBUF = pred_nbuf(N, CPB, int(sizeof(T)));
     const DevBasis &B = c_basis[N];
 
-    const int tid = threadIdx.x;
-    const int cl = tid / N3, a = tid % N3;
-    const int64_t idx = first + cl;
+    // opaque: in the persistent kernels nothing derived from the lane index is
+    // hoisted out of the loop over work items to hold registers through it
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
     const bool lane_ok = tid < NT;
+    // lanes past the block's cells read cell 0's values and store nothing
+    const int cl = lane_ok ? tid / N3 : 0, a = lane_ok ? tid % N3 : 0;
+    const int64_t idx = first + cl;
     const bool active = lane_ok && idx < nlist;
     const int64_t c = active ? (list ? int64_t(list[idx]) : idx) : 0;
     const int aa[3] = {a % N, (a / N) % N, a / N2};
-    const int bf[3] = {aa[1] + N * aa[2], aa[0] + N * aa[2], aa[0] + N * aa[1]};  // fibre (= face) index per axis
+    // first node of this lane's fibre along each axis (in the block's planes)
+    const int fo[3] = {cl * N3 + a - aa[0], cl * N3 + a - N * aa[1], cl * N3 + a - N2 * aa[2]};
 
     const int lev = level ? level[c] : 0;
     const double cdd[3] = {dt * geo.inv_dx[lev][0], dt * geo.inv_dx[lev][1], dt * geo.inv_dx[lev][2]};
@@ -196,40 +238,35 @@ __device__ __forceinline__ void predictor_body(T *__restrict__ lds, const double
 #pragma unroll
         for (int v = 0; v < NV; ++v) q[l][v] = uu[v];
 
-    T *my = lds + (lane_ok ? cl : 0) * PC;
-    // address of (axis d, variable v) at this lane's node
-    auto put_at = [&](int d, int v) { return (d * NV + v) * N3 + a; };
-    // the N values of the fibre with face index b along d
-    auto fibre = [&](const T *cellbase, int d, int v, int b, T out[N]) {
-        const T *src = cellbase + (d * NV + v) * N3;
+    int buf = 0;
+    // the N values of this lane's fibre along d in plane k of buffer w
+    auto fibre = [&](const T *w, int k, int d, T out[N]) {
+        const T *src = w + k * P + fo[d];
+        const int st = d == 0 ? 1 : (d == 1 ? N : N2);
 #pragma unroll
-        for (int e = 0; e < N; ++e) out[e] = src[node_from_face<N>(d, e, b)];
+        for (int e = 0; e < N; ++e) out[e] = src[e * st];
     };
 
     // scaled divergence sum_d (dt/dx_d) D_d F_d(qn) at this lane's node
     auto divergence = [&](const T qn[NV], T G[NV]) {
         T f[3][NV];
         flux3(gm1, qn, f);
-        __syncthreads();
-        if (lane_ok) {
-#pragma unroll
-            for (int d = 0; d < 3; ++d)
-#pragma unroll
-                for (int v = 0; v < NV; ++v) my[put_at(d, v)] = f[d][v];
-        }
-        __syncthreads();
+        const T *w = pred_exchange<T, P, NBUF>(lds, buf, tid, f);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            G[v] = T(0);
-            if (lane_ok) {
+            T s = T(0);
 #pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    T fib[N];
-                    fibre(my, d, v, bf[d], fib);
+            for (int d = 0; d < 3; ++d) {
+                T fib[N];
+                fibre(w, d * NV + v, d, fib);
 #pragma unroll
-                    for (int e = 0; e < N; ++e) G[v] += Dc[d][e] * fib[e];
-                }
+                for (int e = 0; e < N; ++e) s += Dc[d][e] * fib[e];
             }
+            // pinned here: otherwise the compiler sinks the contraction to
+            // the time solve at the end of the Picard iteration and keeps
+            // every fibre value of every time node live until then
+            asm volatile("" : "+v"(s));
+            G[v] = s;
         }
     };
     // iterate it+1, kept for the adjoint: [slot][l][v][cell][N^3]
@@ -296,14 +333,7 @@ __device__ __forceinline__ void predictor_body(T *__restrict__ lds, const double
             for (int d = 0; d < 3; ++d) Fb[d][v] += wj * f[d][v];
         }
     }
-    __syncthreads();
-    if (lane_ok) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d)
-#pragma unroll
-            for (int v = 0; v < NV; ++v) my[put_at(d, v)] = Fb[d][v];
-    }
-    __syncthreads();
+    const T *wF = pred_exchange<T, P, NBUF>(lds, buf, tid, Fb);
 
     // volume term of the corrector: u* = u + sum_d (dt/dx_d)/w_{a_d} sum_e Kw[a_d][e] Fbar_d
     if (active) {
@@ -318,50 +348,62 @@ __device__ __forceinline__ void predictor_body(T *__restrict__ lds, const double
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 T fib[N];
-                fibre(my, d, v, bf[d], fib);
+                fibre(wF, d * NV + v, d, fib);
 #pragma unroll
                 for (int e = 0; e < N; ++e) V += Kc[d][e] * fib[e];
             }
             ustar[(int64_t(v) * nc + c) * N3 + a] = ud[v] + double(V);
+            SCHED_SPLIT();
         }
     }
 
-    // face projections: normal flux component (arr 1), then the state (arr 0,
-    // stored along all three axes)
-    const int64_t base = first;
-    constexpr int ITEMS = 6 * NV * CPB * N2;
-    for (int arr = 1; arr >= 0; --arr) {
-        if (arr == 0) {
-            __syncthreads();
-            if (lane_ok) {
+    // face projections: lane (cell, node a) takes face node b = a mod N^2 of
+    // the (axis, variable) pairs k = a / N^2, a / N^2 + N, ... (k = d NV + v)
+    // and projects the fibre through it onto both faces of the axis; the
+    // normal flux (array 1) comes from the flux planes, the state (array 0)
+    // from the state planes (plane v for every axis)
+    T Lf[N], Rf[N];
 #pragma unroll
-                for (int d = 0; d < 3; ++d)
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) my[put_at(d, v)] = qb[v];
-            }
-            __syncthreads();
-        }
-        for (int t = tid; t < ITEMS; t += blockDim.x) {
-            const int inner = t % (CPB * N2), sv = t / (CPB * N2);
-            const int s = sv / NV, v = sv % NV, cl2 = inner / N2, b = inner % N2;
-            const int64_t idx2 = base + cl2;
-            if (idx2 >= nlist) continue;
-            const int64_t c2 = list ? int64_t(list[idx2]) : idx2;
-            const int d = s >> 1;
-            const double *E = (s & 1) ? B.R : B.L;
-            T fib[N];
-            fibre(lds + cl2 * PC, d, v, b, fib);
-            T accv = T(0);
-#pragma unroll
-            for (int e = 0; e < N; ++e) accv += T(E[e]) * fib[e];
-            traces[((int64_t(s * 2 + arr) * NV + v) * nc + c2) * N2 + b] = accv;
-        }
+    for (int e = 0; e < N; ++e) {
+        Lf[e] = T(B.L[e]);
+        Rf[e] = T(B.R[e]);
     }
+    const int fb_node = a % N2, g0 = a / N2;
+    const int64_t face_plane = nc * N2;
+    auto project = [&](const T *w, int arr, bool state) {
+        if (!active) return;
+        for (int k = g0; k < 3 * NV; k += N) {
+            const int d = k / NV, v = k - NV * (k / NV);
+            const int st = d == 0 ? 1 : (d == 1 ? N : N2);
+            const int b1 = fb_node % N, b2 = fb_node / N;
+            const int node0 = d == 0 ? N * b1 + N2 * b2 : (d == 1 ? b1 + N2 * b2 : b1 + N * b2);
+            const T *src = w + (state ? v : k) * P + cl * N3 + node0;
+            T sl = T(0), sr = T(0);
+#pragma unroll
+            for (int e = 0; e < N; ++e) {
+                const T x = src[e * st];
+                sl += Lf[e] * x;
+                sr += Rf[e] * x;
+            }
+            const int64_t o = (int64_t((2 * d) * 2 + arr) * NV + v) * face_plane + c * N2 + fb_node;
+            traces[o] = sl;
+            traces[o + int64_t(2 * NV) * face_plane] = sr;  // side 2d+1
+        }
+    };
+    project(wF, 1, false);
+    T qb1[1][NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) qb1[0][v] = qb[v];
+    const T *wq = pred_exchange<T, P, NBUF>(lds, buf, tid, qb1);
+    project(wq, 0, true);
 }
 
 // waves per SIMD asked of the register allocator for the per-launch predictor
+#ifndef ADG_PRED_WAVES5
+#define ADG_PRED_WAVES5 3
+#endif
 template <typename T, int N, bool STORE> struct PredWaves {
-    static constexpr int MIN = (std::is_same<T, float>::value && N == 5 && !STORE) ? 4 : 1;
+    static constexpr int MIN = (std::is_same<T, float>::value && N == 5 && !STORE) ? ADG_PRED_WAVES5 : 1;
 };
 
 template <typename T, int N, int CPB, bool STORE>
@@ -372,7 +414,7 @@ k_predictor(const double *__restrict__ u, double *__restrict__ ustar, T *__restr
             const int8_t *__restrict__ level, Geo geo, const double *__restrict__ dt_dev,
             double gamma, int npic, T *__restrict__ iters)
 {
-    __shared__ __align__(16) T lds[CPB * Fib<T, N>::PER_CELL];
+    __shared__ __align__(16) T lds[pred_lds_elems(N, CPB, int(sizeof(T)))];
     predictor_body<T, N, CPB, STORE>(lds, u, ustar, traces, list, nlist, nc, level, geo, dt_dev[0], gamma, npic,
                                      int64_t(blockIdx.x) * CPB, iters);
 }
@@ -401,8 +443,14 @@ __device__ __forceinline__ void predictor_item(T *lds, const double *u, double *
 // waves per SIMD asked of the register allocator for the per-order
 // persistent predictor (FP32 N = 5 and 6 run faster with a few spills at the
 // higher occupancy; N = 7 does not)
+#ifndef ADG_ORDER_WAVES5
+#define ADG_ORDER_WAVES5 3
+#endif
+#ifndef ADG_ORDER_WAVES6
+#define ADG_ORDER_WAVES6 2
+#endif
 template <typename T, int N> struct PredOrderWaves {
-    static constexpr int MIN = !std::is_same<T, float>::value ? 1 : N == 5 ? 4 : N == 6 ? 3 : 1;
+    static constexpr int MIN = !std::is_same<T, float>::value ? 1 : N == 5 ? ADG_ORDER_WAVES5 : N == 6 ? ADG_ORDER_WAVES6 : 1;
 };
 
 // Persistent predictor over the work items of ONE order (all instances of
@@ -414,7 +462,7 @@ k_predictor_order(const PredItem *__restrict__ items, int64_t nitems, const Pred
                   const double *__restrict__ u, double *__restrict__ ustar, T *__restrict__ traces,
                   const double *__restrict__ dt)
 {
-    __shared__ __align__(16) T lds[CPB * Fib<T, N>::PER_CELL];
+    __shared__ __align__(16) T lds[pred_lds_elems(N, CPB, int(sizeof(T)))];
     for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         const PredItem w = items[it];
         const PredInst &I = insts[w.inst];
@@ -595,10 +643,6 @@ __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned off, d
     using b64 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(b64, x), r, off, 0, 0);
 }
-
-#ifndef SCHED_SPLIT
-#define SCHED_SPLIT() __builtin_amdgcn_sched_barrier(0)
-#endif
 
 // x of the lane whose byte address (4 x lane index) is addr, through the LDS
 // crossbar (no LDS memory is used)
@@ -3598,11 +3642,6 @@ void pred_variant_shape(int code, int *N, int *CPB)
     }
 }
 
-template <typename T>
-size_t fib_per_cell(int N)
-{
-    return size_t(15) * N * N * N;
-}
 
 template <typename T>
 hipError_t launch_predictor_batch(const PredItem *items, int64_t nitems, const PredInst *insts, const double *u,
@@ -3614,7 +3653,7 @@ hipError_t launch_predictor_batch(const PredItem *items, int64_t nitems, const P
     for (int c = 0; c < PRED_VARIANTS; ++c) {
         int N, CPB;
         pred_variant_shape(c, &N, &CPB);
-        if (round64(CPB * N * N * N) <= threads) lds = std::max(lds, size_t(CPB) * fib_per_cell<T>(N) * sizeof(T));
+        if (round64(CPB * N * N * N) <= threads) lds = std::max(lds, size_t(pred_lds_elems(N, CPB, int(sizeof(T)))) * sizeof(T));
     }
     hipLaunchKernelGGL(k_predictor_batch<T>, dim3(grid), dim3(threads), lds, st, items, nitems, insts, u, ustar,
                        traces, dt);
@@ -3669,7 +3708,7 @@ int predictor_batch_occupancy(int threads)
     for (int c = 0; c < PRED_VARIANTS; ++c) {
         int N, CPB;
         pred_variant_shape(c, &N, &CPB);
-        if (round64(CPB * N * N * N) <= threads) lds = std::max(lds, size_t(CPB) * fib_per_cell<T>(N) * sizeof(T));
+        if (round64(CPB * N * N * N) <= threads) lds = std::max(lds, size_t(pred_lds_elems(N, CPB, int(sizeof(T)))) * sizeof(T));
     }
     int blocks = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_predictor_batch<T>, threads, lds) != hipSuccess)
