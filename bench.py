@@ -217,14 +217,15 @@ def run_amr(A, steps=50, sharp=False):
 
 def adapt_once(A, mesh, u, theta_refine, theta_coarsen):
     """One adaptation step of the state after the timed steps: indicator
-    (device), plan (host), the new handle (host mesh build and uploads) and
-    the volumetric transfer (host table, device kernel), timed each."""
+    (device), plan (host, from the leaves the handle keeps), the new handle
+    (host mesh build and uploads) and the volumetric transfer (host table,
+    device kernel), timed each."""
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     eta = mesh.indicator(u).cpu().numpy()
     t1 = time.perf_counter()
-    rows = A.adapt_plan(mesh.descs[0], eta, theta_refine, theta_coarsen)
+    rows = mesh.adapt_plan(eta, theta_refine, theta_coarsen)
     t2 = time.perf_counter()
     new = A.Mesh(dict(mesh.descs[0], refine=rows), mesh.precision)
     t3 = time.perf_counter()

@@ -98,6 +98,7 @@ typedef struct {
     int64_t n_conforming_faces, n_hanging_faces, n_skeleton_cells;
     int32_t real_bytes;       /* 8 (FP64) or 4 (FP32_MFMA)                        */
     int64_t adjoint_workspace_bytes;  /* device bytes adg_step_adjoint needs      */
+    int64_t adjoint_tape_bytes;       /* device bytes of one adg_step_record tape */
 } adg_info;
 
 typedef struct {
@@ -312,6 +313,24 @@ adg_status adg_step_adjoint(adg_mesh *mesh, const double *u_n_dev, const double 
                             const double *ubar_np1_dev, double *ubar_n_dev, void *ws_dev,
                             hipStream_t stream);
 
+/* A recorded step, for reverse sweeps that recompute the forward run from a
+ * checkpoint anyway: adg_step_record advances u_n_dev by one step at the
+ * fixed dt_dev (the predictor, Riemann and corrector of adg_predictor,
+ * adg_riemann and adg_corrector, Eq. 4) into u_np1_dev (which may alias
+ * u_n_dev; NULL: only the tape is written) and keeps in tape_dev what the
+ * step's adjoint reads from its forward run: the predictor's face projections
+ * and Picard iterates (adjoint_tape_bytes, device memory the caller owns).
+ * adg_step_adjoint_tape then gives the result of adg_step_adjoint(u_n_dev,
+ * dt_dev, ...) bit for bit, reading the tape instead of running the
+ * predictor again; u_n_dev and dt_dev must be those of the recording.  Both
+ * take an adjoint workspace (adjoint_workspace_bytes), FP64 handles with the
+ * limiter off (ADG_ERR_UNSUPPORTED otherwise). */
+adg_status adg_step_record(adg_mesh *mesh, const double *u_n_dev, const double *dt_dev, double *u_np1_dev,
+                           void *tape_dev, void *ws_dev, hipStream_t stream);
+adg_status adg_step_adjoint_tape(adg_mesh *mesh, const double *u_n_dev, const double *dt_dev,
+                                 const void *tape_dev, const double *ubar_np1_dev, double *ubar_n_dev,
+                                 void *ws_dev, hipStream_t stream);
+
 /* Switch tape of the Rusanov face speed on conforming faces (for checking
  * derivatives of the piecewise-smooth step).  mode 1 (record): every
  * following adg_riemann stores, per conforming face, the first maximiser of
@@ -340,7 +359,7 @@ adg_status adg_sample_adjoint(adg_mesh *mesh, const double *pts_dev, const doubl
  * epilogue; refinement interpolates volumetric data onto new cells and
  * coarsening merges a cluster of 27 cells; both complete before the next
  * predictor).  A step of adaptation is: adg_indicator on the state,
- * adg_adapt_plan on the host, adg_init_mesh with the new refine rows,
+ * adg_adapt_plan (or adg_adapt_plan_mesh) on the host, adg_init_mesh with the new refine rows,
  * adg_transfer of the state, adg_free_mesh of the old handle.
  *
  * adg_indicator: eta_dev[c] (FP64, one per cell of the handle, cells in the
@@ -360,6 +379,13 @@ adg_status adg_indicator(adg_mesh *mesh, const double *u_dev, double *eta_dev, h
  * is smaller (call again with a larger buffer). */
 adg_status adg_adapt_plan(const adg_instance_desc *desc, const double *eta_host, double theta_refine,
                           double theta_coarsen, int32_t *refine_out, int64_t capacity, int64_t *n_refine_out);
+
+/* adg_adapt_plan_mesh (host only): adg_adapt_plan for the mesh of a
+ * single-instance handle, from the leaves and refine rows the handle keeps
+ * since adg_init_mesh, so the current mesh is not built again.  Same rule,
+ * output and errors; ADG_ERR_UNSUPPORTED for handles of several instances. */
+adg_status adg_adapt_plan_mesh(const adg_mesh *mesh, const double *eta_host, double theta_refine,
+                               double theta_coarsen, int32_t *refine_out, int64_t capacity, int64_t *n_refine_out);
 
 /* adg_transfer: the state u_to_dev of handle `to` from u_from_dev of handle
  * `from` (one instance each, same order and base box; refinement levels may

@@ -26,7 +26,8 @@ EXPORTS = ["adg_init_mesh", "adg_free_mesh", "adg_mesh_info", "adg_instance_info
            "adg_tuning", "adg_set_options", "adg_step_adjoint", "adg_sample", "adg_sample_adjoint",
            "adg_set_switch_tape", "adg_set_pipeline", "adg_indicator", "adg_adapt_plan", "adg_transfer",
            "adg_set_limiter", "adg_limiter_stats", "adg_lin_init", "adg_lin_free", "adg_lin_info", "adg_lin_dt",
-           "adg_lin_predictor", "adg_lin_step", "adg_step_noalloc"]
+           "adg_lin_predictor", "adg_lin_step", "adg_step_noalloc", "adg_adapt_plan_mesh",
+           "adg_step_record", "adg_step_adjoint_tape"]
 PHASES = ["cfl", "predictor", "hanging", "riemann", "corrector", "limiter"]
 
 
@@ -48,7 +49,8 @@ class Info(ctypes.Structure):
                 ("u_elems", ctypes.c_int64), ("trace_elems", ctypes.c_int64), ("fside_elems", ctypes.c_int64),
                 ("workspace_bytes", ctypes.c_int64), ("n_conforming_faces", ctypes.c_int64),
                 ("n_hanging_faces", ctypes.c_int64), ("n_skeleton_cells", ctypes.c_int64),
-                ("real_bytes", ctypes.c_int32), ("adjoint_workspace_bytes", ctypes.c_int64)]
+                ("real_bytes", ctypes.c_int32), ("adjoint_workspace_bytes", ctypes.c_int64),
+                ("adjoint_tape_bytes", ctypes.c_int64)]
 
 
 class InstanceGeom(ctypes.Structure):
@@ -94,11 +96,14 @@ def load():
         "adg_set_options": [P, I32, I32],
         "adg_set_pipeline": [P, I32],
         "adg_step_adjoint": [P, P, P, P, P, P, P],
+        "adg_step_record": [P, P, P, P, P, P, P],
+        "adg_step_adjoint_tape": [P, P, P, P, P, P, P, P],
         "adg_set_switch_tape": [P, P, I32],
         "adg_sample": [P, P, P, I64, P, P],
         "adg_sample_adjoint": [P, P, P, I64, P, P],
         "adg_indicator": [P, P, P, P],
         "adg_adapt_plan": [P, P, ctypes.c_double, ctypes.c_double, P, I64, P],
+        "adg_adapt_plan_mesh": [P, P, ctypes.c_double, ctypes.c_double, P, I64, P],
         "adg_transfer": [P, P, P, P, P],
         "adg_set_limiter": [P, I32, ctypes.c_double, ctypes.c_double],
         "adg_limiter_stats": [P, P, P, P, P],
@@ -193,7 +198,7 @@ def adapt(mesh, u, theta_refine, theta_coarsen, stream=None):
     is left open (close it when done)."""
     import torch
     eta = mesh.indicator(u, stream=stream)
-    rows = adapt_plan(mesh.descs[0], eta.cpu().numpy(), theta_refine, theta_coarsen)
+    rows = mesh.adapt_plan(eta.cpu().numpy(), theta_refine, theta_coarsen)
     desc = dict(mesh.descs[0], refine=rows)
     new = Mesh(desc, mesh.precision)
     u_new = torch.empty(new.info["u_elems"], dtype=torch.float64, device=u.device)
@@ -397,6 +402,37 @@ class Mesh:
                                        _ptr(ubar, torch.float64, n, "ubar"), ctypes.c_void_p(ws.data_ptr()),
                                        _stream(stream)))
 
+    def empty_tape(self, device="cuda"):
+        import torch
+        return torch.empty(self.info["adjoint_tape_bytes"], dtype=torch.uint8, device=device)
+
+    def step_record(self, u, dt, u_next, tape, ws, stream=None):
+        """u_next = step(u; dt) at fixed dt, keeping what its adjoint reads in
+        tape (adg_step_record); u_next may be u, or None for the tape only."""
+        import torch
+        n = self.info["u_elems"]
+        if tape.numel() < self.info["adjoint_tape_bytes"] or ws.numel() < self.info["adjoint_workspace_bytes"]:
+            raise ValueError("tape or adjoint workspace too small")
+        _check(load().adg_step_record(self._h, _ptr(u, torch.float64, n, "u"),
+                                      _ptr(dt, torch.float64, self.n_instances, "dt"),
+                                      None if u_next is None else _ptr(u_next, torch.float64, n, "u_next"),
+                                      ctypes.c_void_p(tape.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                                      _stream(stream)))
+
+    def step_adjoint_tape(self, u, dt, tape, ubar_next, ubar, ws, stream=None):
+        """step_adjoint of the step recorded in tape from the same u and dt
+        (adg_step_adjoint_tape)."""
+        import torch
+        n = self.info["u_elems"]
+        if tape.numel() < self.info["adjoint_tape_bytes"] or ws.numel() < self.info["adjoint_workspace_bytes"]:
+            raise ValueError("tape or adjoint workspace too small")
+        _check(load().adg_step_adjoint_tape(self._h, _ptr(u, torch.float64, n, "u"),
+                                            _ptr(dt, torch.float64, self.n_instances, "dt"),
+                                            ctypes.c_void_p(tape.data_ptr()),
+                                            _ptr(ubar_next, torch.float64, n, "ubar_next"),
+                                            _ptr(ubar, torch.float64, n, "ubar"), ctypes.c_void_p(ws.data_ptr()),
+                                            _stream(stream)))
+
     def sample(self, u, pts, out, stream=None):
         """Density at points pts [n, 3] (adg_sample)."""
         import torch
@@ -420,6 +456,22 @@ class Mesh:
         _check(load().adg_indicator(self._h, _ptr(u, torch.float64, self.info["u_elems"], "u"),
                                     _ptr(eta, torch.float64, self.info["n_cells"], "eta"), _stream(stream)))
         return eta
+
+    def adapt_plan(self, eta, theta_refine, theta_coarsen):
+        """Refine rows [n, 4] (int32) of the next mesh of this single-instance
+        handle (adg_adapt_plan_mesh; host only, eta on the host)."""
+        eta = np.ascontiguousarray(eta, dtype=np.float64)
+        if eta.shape != (self.info["n_cells"],):
+            raise ValueError("eta needs one value per cell")
+        n = ctypes.c_int64(0)
+        ref = self.descs[0].get("refine")
+        n_rows = 0 if ref is None else np.asarray(ref).reshape(-1, 4).shape[0]
+        # at most the current rows plus one per cell above the refinement threshold
+        cap = n_rows + int(np.count_nonzero(eta > theta_refine))
+        out = np.zeros((max(cap, 1), 4), dtype=np.int32)
+        _check(load().adg_adapt_plan_mesh(self._h, eta.ctypes.data, float(theta_refine), float(theta_coarsen),
+                                          out.ctypes.data, out.shape[0], ctypes.byref(n)))
+        return out[: n.value]
 
     def transfer_to(self, u, other, u_other=None, stream=None):
         """State of handle `other` from this handle's u (adg_transfer)."""

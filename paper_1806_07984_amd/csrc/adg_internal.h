@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -87,6 +88,31 @@ struct HostMesh {
 // Returns an empty string on success, otherwise the error text.
 // leaves_only: stop after the sorted cell table (level, ijk)
 std::string build_host_mesh(const adg_instance_desc &d, HostMesh &m, bool leaves_only = false);
+
+// Leaves of a host mesh looked up by (level, i, j, k).  The cell table is
+// sorted by (level, k, j, i), so every level is one block of it and every
+// (level, k, j) row one run inside that block, sorted by i.  The index keeps
+// the start of every row (a dense table over the level's rows when there are
+// at most a few times as many rows as cells, else the sorted list of the
+// non-empty rows) and finds i by binary search along the row.
+class CellIndex {
+  public:
+    void build(const HostMesh &m);
+    // cell index of the leaf, or -1 (also for coordinates outside the grid)
+    int32_t find(int l, int64_t i, int64_t j, int64_t k) const;
+
+  private:
+    const int32_t *ijk_ = nullptr;
+    int max_level_ = -1;
+    int64_t ext_[LMAX + 1][3] = {};
+    bool dense_[LMAX + 1] = {};
+    std::vector<int32_t> start_[LMAX + 1];   // row starts (+ the block end)
+    std::vector<int64_t> rowkey_[LMAX + 1];  // sparse levels: k ext_j + j of each non-empty row
+};
+
+// fn(begin, end) over [0, n) in contiguous chunks on up to 16 host threads
+// (the caller runs the first chunk); chunks hold at least min_chunk items.
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)> &fn, int64_t min_chunk = 32768);
 
 void set_error(const std::string &msg);
 

@@ -1,10 +1,10 @@
 // C ABI of the ADER-DG library: handle management, argument checking and the
 // launch sequences of the phases and of whole steps.
 #include <algorithm>
+#include <iterator>
 #include <cmath>
 #include <cstring>
 #include <mutex>
-#include <unordered_map>
 #include <new>
 
 #include "adg_internal.h"
@@ -28,6 +28,8 @@ constexpr int PIPE_CHUNKS = 8;
 
 struct Instance {
     HostMesh hm;
+    std::vector<int32_t> refine;  // the refine rows the handle was built from (4 per row)
+    CellIndex index;              // leaves by (level, i, j, k), over hm's cell table
     int N = 0, order = 0, npic = 0;
     double gamma = 1.4, cfl = 0.4;
     int64_t nc = 0, cell_off = 0, u_off = 0, tr_off = 0, fs_off = 0;
@@ -984,6 +986,8 @@ adg_status adg_init_mesh(const adg_instance_desc *desc, int32_t n_instances, adg
             delete m;
             return err.rfind("unsupported", 0) == 0 ? ADG_ERR_UNSUPPORTED : ADG_ERR_INVALID_ARG;
         }
+        I.refine.assign(d.refine, d.refine + 4 * d.n_refine);
+        I.index.build(I.hm);
         I.N = I.hm.N;
         I.order = d.order;
         I.npic = d.picard_iters > 0 ? d.picard_iters : d.order + 1;
@@ -1144,6 +1148,8 @@ adg_status adg_init_mesh(const adg_instance_desc *desc, int32_t n_instances, adg
                     align_up(sizeof(double) * fs_off) +
                     align_up(sizeof(double) * std::max<int64_t>(adjoint_iter_elems(m), 1)) +
                     align_up(sizeof(double) * std::max<int64_t>(vb, 1)));
+        inf.adjoint_tape_bytes = int64_t(align_up(sizeof(double) * tr_off) +
+                                         align_up(sizeof(double) * std::max<int64_t>(adjoint_iter_elems(m), 1)));
     }
     *out = m;
     return ADG_OK;
@@ -1482,23 +1488,26 @@ adg_status adg_set_switch_tape(adg_mesh *mesh, int16_t *tape, int32_t mode)
     return ADG_OK;
 }
 
-adg_status adg_step_adjoint(adg_mesh *mesh, const double *u, const double *dt, const double *ubar_next,
-                            double *ubar, void *ws, hipStream_t stream)
+// The adjoint of one step; with a tape (recorded by adg_step_record) the
+// forward predictor's face projections and iterates come from it instead of
+// a new predictor run.
+static adg_status adjoint_impl(adg_mesh *mesh, const double *u, const double *dt, const double *ubar_next,
+                               double *ubar, void *ws, const void *tape, hipStream_t stream, const char *who)
 {
     if (!valid_mesh(mesh) || !u || !dt || !ubar_next || !ubar || !ws) {
-        set_error("adg_step_adjoint: null argument");
+        set_error(std::string(who) + ": null argument");
         return ADG_ERR_INVALID_ARG;
     }
     if (ubar == ubar_next) {
-        set_error("adg_step_adjoint: ubar_n must not alias ubar_np1");
+        set_error(std::string(who) + ": ubar_n must not alias ubar_np1");
         return ADG_ERR_INVALID_ARG;
     }
     if (mesh->prec != ADG_FP64) {
-        set_error("adg_step_adjoint: needs an FP64 handle");
+        set_error(std::string(who) + ": needs an FP64 handle");
         return ADG_ERR_UNSUPPORTED;
     }
     if (mesh->lim_mode) {
-        set_error("adg_step_adjoint: the adjoint is that of the unlimited step; switch the limiter off");
+        set_error(std::string(who) + ": the adjoint is that of the unlimited step; switch the limiter off");
         return ADG_ERR_UNSUPPORTED;
     }
     char *w = static_cast<char *>(ws);
@@ -1513,6 +1522,11 @@ adg_status adg_step_adjoint(adg_mesh *mesh, const double *u, const double *dt, c
     double *iters = reinterpret_cast<double *>(w);
     w += align_up(sizeof(double) * std::max<int64_t>(adjoint_iter_elems(mesh), 1));
     double *vbar = reinterpret_cast<double *>(w);
+    if (tape) {
+        char *t = static_cast<char *>(const_cast<void *>(tape));
+        traces = reinterpret_cast<double *>(t);
+        iters = reinterpret_cast<double *>(t + align_up(sizeof(double) * mesh->info.trace_elems));
+    }
     for (size_t i = 0; i < mesh->inst.size(); ++i) {
         Instance &I = mesh->inst[i];
         const int32_t *fm[3] = {I.face_m[0], I.face_m[1], I.face_m[2]};
@@ -1529,12 +1543,65 @@ adg_status adg_step_adjoint(adg_mesh *mesh, const double *u, const double *dt, c
         ah.vbar = vbar;
         ADG_HIP(launch_adjoint_step(I.N, u + I.u_off, dt + i, ubar_next + I.u_off, ubar + I.u_off, ustar + I.u_off,
                                     traces + I.tr_off, tbar + I.tr_off, fbar + I.fs_off, iters, fm, fp, I.nf, I.nc,
-                                    I.level, I.geo, I.gamma, I.npic, ah, stream),
+                                    I.level, I.geo, I.gamma, I.npic, ah, stream, tape == nullptr),
                 "adjoint step");
         iters += int64_t(I.npic) * I.N * NV * I.nc * I.N * I.N * I.N;
         vbar += I.nh * 2 * NV * I.N * I.N;
     }
     return ADG_OK;
+}
+
+adg_status adg_step_adjoint(adg_mesh *mesh, const double *u, const double *dt, const double *ubar_next,
+                            double *ubar, void *ws, hipStream_t stream)
+{
+    return adjoint_impl(mesh, u, dt, ubar_next, ubar, ws, nullptr, stream, "adg_step_adjoint");
+}
+
+adg_status adg_step_adjoint_tape(adg_mesh *mesh, const double *u, const double *dt, const void *tape,
+                                 const double *ubar_next, double *ubar, void *ws, hipStream_t stream)
+{
+    if (!tape) {
+        set_error("adg_step_adjoint_tape: null tape");
+        return ADG_ERR_INVALID_ARG;
+    }
+    return adjoint_impl(mesh, u, dt, ubar_next, ubar, ws, tape, stream, "adg_step_adjoint_tape");
+}
+
+adg_status adg_step_record(adg_mesh *mesh, const double *u, const double *dt, double *u_next, void *tape, void *ws,
+                           hipStream_t stream)
+{
+    if (!valid_mesh(mesh) || !u || !dt || !tape || !ws) {
+        set_error("adg_step_record: null argument");
+        return ADG_ERR_INVALID_ARG;
+    }
+    if (mesh->prec != ADG_FP64) {
+        set_error("adg_step_record: needs an FP64 handle");
+        return ADG_ERR_UNSUPPORTED;
+    }
+    if (mesh->lim_mode) {
+        set_error("adg_step_record: the recorded step is the unlimited one; switch the limiter off");
+        return ADG_ERR_UNSUPPORTED;
+    }
+    // u* and the face fluxes in the adjoint workspace's u* and fbar slots
+    char *w = static_cast<char *>(ws);
+    double *ustar = reinterpret_cast<double *>(w);
+    w += align_up(sizeof(double) * mesh->info.u_elems) + 2 * align_up(sizeof(double) * mesh->info.trace_elems);
+    double *fside = reinterpret_cast<double *>(w);
+    char *t = static_cast<char *>(tape);
+    double *traces = reinterpret_cast<double *>(t);
+    double *iters = reinterpret_cast<double *>(t + align_up(sizeof(double) * mesh->info.trace_elems));
+    for (size_t i = 0; i < mesh->inst.size(); ++i) {
+        Instance &I = mesh->inst[i];
+        ADG_HIP(launch_predictor<double>(I.N, u + I.u_off, ustar + I.u_off, traces + I.tr_off, nullptr, I.nc, I.nc,
+                                         I.level, I.geo, dt + i, I.gamma, I.npic, stream, iters),
+                "recorded predictor");
+        iters += int64_t(I.npic) * I.N * NV * I.nc * I.N * I.N * I.N;
+    }
+    if (!u_next) return ADG_OK;
+    adg_status st = do_conforming<double>(mesh, traces, fside, stream);
+    if (st == ADG_OK) st = do_hanging<double>(mesh, traces, fside, stream);
+    if (st == ADG_OK) st = do_corrector<double>(mesh, ustar, fside, dt, u_next, stream);
+    return st;
 }
 
 static adg_status sample_geo(adg_mesh *mesh, SampleGeo &sg)
@@ -1605,11 +1672,6 @@ adg_status adg_get_status(adg_mesh *mesh)
 
 namespace {
 
-inline uint64_t cell_key(int l, int64_t i, int64_t j, int64_t k)
-{
-    return (uint64_t(l) << 60) | (uint64_t(k) << 40) | (uint64_t(j) << 20) | uint64_t(i);
-}
-
 int64_t pow3i(int e)
 {
     int64_t r = 1;
@@ -1620,15 +1682,15 @@ int64_t pow3i(int e)
 // Leaves of `from` inside region (l, q) of target cell (lc, kc), in the order
 // z, y, x of the sub-cells at every level; adds 27^(depth - dl) per leaf to
 // *cover (depth = max_level - lc), which sums to 27^depth when covered.
-void collect_kids(const std::unordered_map<uint64_t, int32_t> &index, int max_level, int lc, const int64_t *kc,
+void collect_kids(const adg::CellIndex &index, int max_level, int lc, const int64_t *kc,
                   int l, const int64_t *q, std::vector<adg::VKid> &kids, int64_t &cover)
 {
-    auto it = index.find(cell_key(l, q[0], q[1], q[2]));
-    if (it != index.end()) {
+    const int32_t f = index.find(l, q[0], q[1], q[2]);
+    if (f >= 0) {
         const int dl = l - lc;
         const int64_t r = pow3i(dl);
-        adg::VKid k{it->second, int8_t(dl), {int8_t(q[0] - r * kc[0]), int8_t(q[1] - r * kc[1]),
-                                             int8_t(q[2] - r * kc[2])}};
+        adg::VKid k{f, int8_t(dl), {int8_t(q[0] - r * kc[0]), int8_t(q[1] - r * kc[1]),
+                                    int8_t(q[2] - r * kc[2])}};
         kids.push_back(k);
         cover += pow3i(3 * (max_level - lc - dl));
         return;
@@ -1640,6 +1702,67 @@ void collect_kids(const std::unordered_map<uint64_t, int32_t> &index, int max_le
                 const int64_t q2[3] = {3 * q[0] + c0, 3 * q[1] + c1, 3 * q[2] + c2};
                 collect_kids(index, max_level, lc, kc, l + 1, q2, kids, cover);
             }
+}
+
+// The next refine rows from the current leaves hm (built from the rows
+// refine[0 .. 4 n_refine)) and the indicator eta per leaf: the current rows
+// minus the merged parents, plus the split leaves, sorted by (level, k, j, i).
+adg_status plan_rows(const adg::HostMesh &hm, const adg::CellIndex &index, const int32_t *refine, int64_t n_refine,
+                     const double *eta, double theta_refine, double theta_coarsen, int32_t *refine_out,
+                     int64_t capacity, int64_t *n_refine_out, const char *who)
+{
+    using namespace adg;
+    auto split = [&](int64_t c) { return eta[c] > theta_refine && hm.level[c] < hm.max_level; };
+    // current rows minus the merged parents, plus the split leaves
+    struct Row { int32_t l, i, j, k; };
+    std::vector<Row> rows;
+    for (int64_t r = 0; r < n_refine; ++r) {
+        const int32_t *q = refine + 4 * r;
+        bool merge = true;
+        for (int c2 = 0; c2 < 3 && merge; ++c2)
+            for (int c1 = 0; c1 < 3 && merge; ++c1)
+                for (int c0 = 0; c0 < 3 && merge; ++c0) {
+                    const int64_t f = index.find(q[0] + 1, 3 * int64_t(q[1]) + c0, 3 * int64_t(q[2]) + c1,
+                                                 3 * int64_t(q[3]) + c2);
+                    merge = f >= 0 && !split(f) && eta[f] < theta_coarsen;
+                }
+        if (!merge) rows.push_back(Row{q[0], q[1], q[2], q[3]});
+    }
+    auto less = [](const Row &a, const Row &b) {
+        if (a.l != b.l) return a.l < b.l;
+        if (a.k != b.k) return a.k < b.k;
+        if (a.j != b.j) return a.j < b.j;
+        return a.i < b.i;
+    };
+    if (!std::is_sorted(rows.begin(), rows.end(), less)) std::sort(rows.begin(), rows.end(), less);
+    // the split leaves, gathered per chunk in cell order, which is (level, k,
+    // j, i) order: a merge with the kept rows sorts the plan
+    const int64_t nch = std::max<int64_t>(1, std::min<int64_t>(256, hm.nc / 8192));
+    std::vector<std::vector<Row>> part(static_cast<size_t>(nch));
+    parallel_for(nch, [&](int64_t t0, int64_t t1) {
+        for (int64_t t = t0; t < t1; ++t)
+            for (int64_t c = hm.nc * t / nch; c < hm.nc * (t + 1) / nch; ++c)
+                if (split(c))
+                    part[size_t(t)].push_back(Row{hm.level[c], hm.ijk[3 * c], hm.ijk[3 * c + 1], hm.ijk[3 * c + 2]});
+    }, 1);
+    std::vector<Row> splits;
+    for (auto &p : part) splits.insert(splits.end(), p.begin(), p.end());
+    std::vector<Row> merged;
+    merged.reserve(rows.size() + splits.size());
+    std::merge(rows.begin(), rows.end(), splits.begin(), splits.end(), std::back_inserter(merged), less);
+    rows.swap(merged);
+    *n_refine_out = int64_t(rows.size());
+    if (!refine_out || capacity < int64_t(rows.size())) {
+        set_error(std::string(who) + ": refine_out holds fewer rows than the plan (count returned in n_refine_out)");
+        return ADG_ERR_WORKSPACE;
+    }
+    for (size_t r = 0; r < rows.size(); ++r) {
+        refine_out[4 * r] = rows[r].l;
+        refine_out[4 * r + 1] = rows[r].i;
+        refine_out[4 * r + 2] = rows[r].j;
+        refine_out[4 * r + 3] = rows[r].k;
+    }
+    return ADG_OK;
 }
 
 }  // namespace
@@ -1676,47 +1799,73 @@ adg_status adg_transfer(const adg_mesh *from, const double *u_from, adg_mesh *to
         set_error("adg_transfer: the meshes differ in order or base grid");
         return ADG_ERR_INVALID_ARG;
     }
-    std::unordered_map<uint64_t, int32_t> index;
-    index.reserve(size_t(F.nc) * 2);
-    for (int64_t c = 0; c < F.nc; ++c)
-        index.emplace(cell_key(F.hm.level[c], F.hm.ijk[3 * c], F.hm.ijk[3 * c + 1], F.hm.ijk[3 * c + 2]), int32_t(c));
+    const CellIndex &index = F.index;
+    // copy (the same leaf) or prolongation (a coarser leaf covers the cell),
+    // in parallel; the rest are coarsened cells, gathered in order afterwards
     std::vector<VOp> ops(size_t(T.nc));
-    std::vector<VKid> kids;
-    for (int64_t c = 0; c < T.nc; ++c) {
-        const int l = T.hm.level[c];
-        const int64_t k[3] = {T.hm.ijk[3 * c], T.hm.ijk[3 * c + 1], T.hm.ijk[3 * c + 2]};
-        VOp op{};
-        auto it = index.find(cell_key(l, k[0], k[1], k[2]));
-        if (it != index.end()) {
-            op.kind = 0;
-            op.src = it->second;
-            ops[size_t(c)] = op;
-            continue;
-        }
-        bool found = false;
-        for (int lp = l - 1; lp >= 0 && !found; --lp) {
-            const int64_t r = pow3i(l - lp);
-            auto jt = index.find(cell_key(lp, k[0] / r, k[1] / r, k[2] / r));
-            if (jt == index.end()) continue;
-            op.kind = 1;
-            op.src = jt->second;
-            op.dl = int8_t(l - lp);
-            for (int d = 0; d < 3; ++d) op.s[d] = int8_t(k[d] % r);
-            found = true;
-        }
-        if (!found) {
-            int64_t cover = 0;
+    parallel_for(T.nc, [&](int64_t c0, int64_t c1) {
+        for (int64_t c = c0; c < c1; ++c) {
+            const int l = T.hm.level[size_t(c)];
+            const int64_t k[3] = {T.hm.ijk[size_t(3 * c)], T.hm.ijk[size_t(3 * c + 1)], T.hm.ijk[size_t(3 * c + 2)]};
+            VOp op{};
             op.kind = 2;
-            op.kid0 = int32_t(kids.size());
-            collect_kids(index, F.hm.max_level, l, k, l, k, kids, cover);
-            op.nkid = int32_t(kids.size()) - op.kid0;
-            if (op.nkid == 0 || cover != pow3i(3 * (F.hm.max_level - l))) {
-                set_error("adg_transfer: a cell of the target mesh is only partly covered by the source mesh");
-                return ADG_ERR_INVALID_ARG;
+            int32_t f = index.find(l, k[0], k[1], k[2]);
+            if (f >= 0) {
+                op.kind = 0;
+                op.src = f;
             }
+            for (int lp = l - 1; lp >= 0 && op.kind == 2; --lp) {
+                const int64_t r = pow3i(l - lp);
+                f = index.find(lp, k[0] / r, k[1] / r, k[2] / r);
+                if (f < 0) continue;
+                op.kind = 1;
+                op.src = f;
+                op.dl = int8_t(l - lp);
+                for (int d = 0; d < 3; ++d) op.s[d] = int8_t(k[d] % r);
+            }
+            ops[size_t(c)] = op;
         }
-        ops[size_t(c)] = op;
+    });
+    // the source leaves of every coarsened cell, gathered per chunk of target
+    // cells and concatenated in cell order
+    const int64_t nch = std::max<int64_t>(1, std::min<int64_t>(256, T.nc / 4096));
+    std::vector<std::vector<VKid>> part(static_cast<size_t>(nch));
+    std::vector<char> partial_cover(static_cast<size_t>(nch), 0);
+    parallel_for(nch, [&](int64_t t0, int64_t t1) {
+        for (int64_t t = t0; t < t1; ++t)
+            for (int64_t c = T.nc * t / nch; c < T.nc * (t + 1) / nch; ++c) {
+                VOp &op = ops[size_t(c)];
+                if (op.kind != 2) continue;
+                const int l = T.hm.level[size_t(c)];
+                const int64_t k[3] = {T.hm.ijk[size_t(3 * c)], T.hm.ijk[size_t(3 * c + 1)],
+                                      T.hm.ijk[size_t(3 * c + 2)]};
+                int64_t cover = 0;
+                op.kid0 = int32_t(part[size_t(t)].size());  // within the chunk for now
+                collect_kids(index, F.hm.max_level, l, k, l, k, part[size_t(t)], cover);
+                op.nkid = int32_t(part[size_t(t)].size()) - op.kid0;
+                if (op.nkid == 0 || cover != pow3i(3 * (F.hm.max_level - l))) partial_cover[size_t(t)] = 1;
+            }
+    }, 1);
+    std::vector<int64_t> kid_off(size_t(nch) + 1, 0);
+    for (int64_t t = 0; t < nch; ++t) {
+        if (partial_cover[size_t(t)]) {
+            set_error("adg_transfer: a cell of the target mesh is only partly covered by the source mesh");
+            return ADG_ERR_INVALID_ARG;
+        }
+        kid_off[size_t(t) + 1] = kid_off[size_t(t)] + int64_t(part[size_t(t)].size());
     }
+    if (kid_off[size_t(nch)] > INT32_MAX) {
+        set_error("adg_transfer: too many source cells under coarsened cells");
+        return ADG_ERR_UNSUPPORTED;
+    }
+    std::vector<VKid> kids(static_cast<size_t>(kid_off[static_cast<size_t>(nch)]));
+    parallel_for(nch, [&](int64_t t0, int64_t t1) {
+        for (int64_t t = t0; t < t1; ++t) {
+            std::copy(part[size_t(t)].begin(), part[size_t(t)].end(), kids.begin() + kid_off[size_t(t)]);
+            for (int64_t c = T.nc * t / nch; c < T.nc * (t + 1) / nch; ++c)
+                if (ops[size_t(c)].kind == 2) ops[size_t(c)].kid0 += int32_t(kid_off[size_t(t)]);
+        }
+    }, 1);
     VOp *ops_dev = nullptr;
     VKid *kids_dev = nullptr;
     DeviceGuard dg(to->device);
@@ -1747,50 +1896,26 @@ adg_status adg_adapt_plan(const adg_instance_desc *desc, const double *eta, doub
         set_error("adg_adapt_plan: " + err);
         return err.rfind("unsupported", 0) == 0 ? ADG_ERR_UNSUPPORTED : ADG_ERR_INVALID_ARG;
     }
-    // cells come sorted by (level, k, j, i), which is the order of their keys
-    std::vector<uint64_t> keys(size_t(hm.nc));
-    for (int64_t c = 0; c < hm.nc; ++c)
-        keys[size_t(c)] = cell_key(hm.level[c], hm.ijk[3 * c], hm.ijk[3 * c + 1], hm.ijk[3 * c + 2]);
-    auto find_leaf = [&](uint64_t key) -> int64_t {
-        auto it = std::lower_bound(keys.begin(), keys.end(), key);
-        return (it != keys.end() && *it == key) ? int64_t(it - keys.begin()) : -1;
-    };
-    auto split = [&](int64_t c) { return eta[c] > theta_refine && hm.level[c] < desc->max_level; };
-    // current rows minus the merged parents, plus the split leaves
-    struct Row { int32_t l, i, j, k; };
-    std::vector<Row> rows;
-    for (int64_t r = 0; r < desc->n_refine; ++r) {
-        const int32_t *q = desc->refine + 4 * r;
-        bool merge = true;
-        for (int c2 = 0; c2 < 3 && merge; ++c2)
-            for (int c1 = 0; c1 < 3 && merge; ++c1)
-                for (int c0 = 0; c0 < 3 && merge; ++c0) {
-                    const int64_t f = find_leaf(cell_key(q[0] + 1, 3 * int64_t(q[1]) + c0, 3 * int64_t(q[2]) + c1,
-                                                         3 * int64_t(q[3]) + c2));
-                    merge = f >= 0 && !split(f) && eta[f] < theta_coarsen;
-                }
-        if (!merge) rows.push_back(Row{q[0], q[1], q[2], q[3]});
+    CellIndex index;
+    index.build(hm);
+    return plan_rows(hm, index, desc->refine, desc->n_refine, eta, theta_refine, theta_coarsen, refine_out, capacity,
+                     n_refine_out, "adg_adapt_plan");
+}
+
+adg_status adg_adapt_plan_mesh(const adg_mesh *mesh, const double *eta, double theta_refine, double theta_coarsen,
+                               int32_t *refine_out, int64_t capacity, int64_t *n_refine_out)
+{
+    if (!valid_mesh(mesh) || !eta || !n_refine_out) {
+        set_error("adg_adapt_plan_mesh: null argument");
+        return ADG_ERR_INVALID_ARG;
     }
-    for (int64_t c = 0; c < hm.nc; ++c)
-        if (split(c)) rows.push_back(Row{hm.level[c], hm.ijk[3 * c], hm.ijk[3 * c + 1], hm.ijk[3 * c + 2]});
-    std::sort(rows.begin(), rows.end(), [](const Row &a, const Row &b) {
-        if (a.l != b.l) return a.l < b.l;
-        if (a.k != b.k) return a.k < b.k;
-        if (a.j != b.j) return a.j < b.j;
-        return a.i < b.i;
-    });
-    *n_refine_out = int64_t(rows.size());
-    if (!refine_out || capacity < int64_t(rows.size())) {
-        set_error("adg_adapt_plan: refine_out holds fewer rows than the plan (count returned in n_refine_out)");
-        return ADG_ERR_WORKSPACE;
+    if (mesh->inst.size() != 1) {
+        set_error("adg_adapt_plan_mesh: the handle must hold one instance");
+        return ADG_ERR_UNSUPPORTED;
     }
-    for (size_t r = 0; r < rows.size(); ++r) {
-        refine_out[4 * r] = rows[r].l;
-        refine_out[4 * r + 1] = rows[r].i;
-        refine_out[4 * r + 2] = rows[r].j;
-        refine_out[4 * r + 3] = rows[r].k;
-    }
-    return ADG_OK;
+    const Instance &I = mesh->inst[0];
+    return plan_rows(I.hm, I.index, I.refine.data(), int64_t(I.refine.size() / 4), eta, theta_refine, theta_coarsen,
+                     refine_out, capacity, n_refine_out, "adg_adapt_plan_mesh");
 }
 
 }  // extern "C"

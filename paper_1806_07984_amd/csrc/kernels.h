@@ -193,7 +193,7 @@ hipError_t launch_adjoint_step(int N, const double *u, const double *dt, const d
                                double *ustar, double *traces, double *tbar, double *fbar, double *iters,
                                const int32_t *const fm[3], const int32_t *const fp[3], const int64_t nf[3],
                                int64_t nc, const int8_t *level, const Geo &geo, double gamma, int npic,
-                               const AdjHang &ah, hipStream_t st);
+                               const AdjHang &ah, hipStream_t st, bool forward = true);
 hipError_t launch_sample(int N, const double *u, int64_t nc, const SampleGeo &sg, const double *pts, int64_t npts,
                          double *out, hipStream_t st);
 hipError_t launch_sample_adjoint(int N, const double *pts, const double *wbar, int64_t npts, const SampleGeo &sg,

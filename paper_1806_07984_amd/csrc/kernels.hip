@@ -1686,20 +1686,29 @@ k_corrector4(const double *__restrict__ ustar, const T *__restrict__ fside, cons
          c += int64_t(gridDim.x) * (blockDim.x >> 6)) {
         const int lev = level ? __builtin_amdgcn_readfirstlane(int(level[c])) : 0;
         const double cx = dt * geo.inv_dx[lev][0], cy = dt * geo.inv_dx[lev][1], cz = dt * geo.inv_dx[lev][2];
-        double q[NV];
+        // every load of the cell first (the stores below could alias them for
+        // all the compiler knows, which would serialise the variables)
+        T f[NV][6];
+        double us[NV], q[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            auto face = [&](int side, unsigned off) {
-                return double(buf_ld(buf_view(fside + ((int64_t(side) * NV + v) * nc + c) * N2, N2 * sizeof(T)), off,
-                                     T(0)));
-            };
-            const double fxm = face(0, bx), fxp = face(1, bx);
-            const double fym = face(2, by), fyp = face(3, by);
-            const double fzm = face(4, bz), fzp = face(5, bz);
-            const double sv = cx * (Rx * fxp - Lx * fxm) + cy * (Ry * fyp - Ly * fym) + cz * (Rz * fzp - Lz * fzm);
-            const int64_t o = (int64_t(v) * nc + c) * N3;
-            q[v] = buf_ld(buf_view(ustar + o, N3 * sizeof(double)), lu, 0.0) - sv;
-            buf_st(buf_view(uout + o, N3 * sizeof(double)), lu, q[v]);
+#pragma unroll
+            for (int side = 0; side < 6; ++side)
+                f[v][side] = buf_ld(buf_view(fside + ((int64_t(side) * NV + v) * nc + c) * N2, N2 * sizeof(T)),
+                                    side < 2 ? bx : (side < 4 ? by : bz), T(0));
+            us[v] = buf_ld(buf_view(ustar + (int64_t(v) * nc + c) * N3, N3 * sizeof(double)), lu, 0.0);
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            // explicit fused operations: the same bits in every variant of
+            // the kernel (the compiler may contract a plain expression
+            // differently in the fused-CFL variant)
+            const double tx = fma(Rx, double(f[v][1]), -(Lx * double(f[v][0])));
+            const double ty = fma(Ry, double(f[v][3]), -(Ly * double(f[v][2])));
+            const double tz = fma(Rz, double(f[v][5]), -(Lz * double(f[v][4])));
+            const double sv = fma(cx, tx, fma(cy, ty, cz * tz));
+            q[v] = us[v] - sv;
+            buf_st(buf_view(uout + (int64_t(v) * nc + c) * N3, N3 * sizeof(double)), lu, q[v]);
         }
         if (FUSE) rate = fmax(rate, cfl_rate(gamma, q, geo, lev, status));
     }
@@ -3786,11 +3795,14 @@ hipError_t launch_adjoint_step(int N, const double *u, const double *dt, const d
                                double *ustar, double *traces, double *tbar, double *fbar, double *iters,
                                const int32_t *const fm[3], const int32_t *const fp[3], const int64_t nf[3],
                                int64_t nc, const int8_t *level, const Geo &geo, double gamma, int npic,
-                               const AdjHang &ah, hipStream_t st)
+                               const AdjHang &ah, hipStream_t st, bool forward)
 {
-    hipError_t e = launch_predictor<double>(N, u, ustar, traces, nullptr, nc, nc, level, geo, dt, gamma, npic, st,
-                                            iters);
-    if (e != hipSuccess) return e;
+    // the forward predictor with its iterates, unless the caller recorded them
+    if (forward) {
+        hipError_t e = launch_predictor<double>(N, u, ustar, traces, nullptr, nc, nc, level, geo, dt, gamma, npic,
+                                                st, iters);
+        if (e != hipSuccess) return e;
+    }
     ADG_DISPATCH_N(N, {
         constexpr int N2 = NN * NN;
         constexpr int FPB = FaceCfg<NN>::FPB;

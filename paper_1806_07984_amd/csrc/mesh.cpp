@@ -14,7 +14,7 @@
 #include <algorithm>
 #include <iterator>
 #include <cstdio>
-#include <unordered_map>
+#include <thread>
 
 #include "adg_internal.h"
 
@@ -108,6 +108,11 @@ std::string build_host_mesh(const adg_instance_desc &d, HostMesh &m, bool leaves
     }
     std::vector<uint64_t> all, lev, next;
     lev.reserve(size_t(d.n[0]) * d.n[1] * d.n[2]);
+    {
+        size_t leaves = size_t(d.n[0]) * d.n[1] * d.n[2];
+        for (int l = 0; l < d.max_level; ++l) leaves += 26 * rk[l].size();
+        all.reserve(leaves);
+    }
     for (int k = 0; k < d.n[2]; ++k)
         for (int j = 0; j < d.n[1]; ++j)
             for (int i = 0; i < d.n[0]; ++i) lev.push_back(pack(0, i, j, k));
@@ -136,105 +141,158 @@ std::string build_host_mesh(const adg_instance_desc &d, HostMesh &m, bool leaves
         }
         lev.swap(next);
     }
-    std::vector<Key> cells;
-    cells.reserve(all.size());
-    for (uint64_t p : all) cells.push_back(Key{int(p >> 60), ki(p), kj(p), kk(p)});
-    if (cells.size() > size_t(INT32_MAX) / 8) return "too many cells";
-    m.nc = int64_t(cells.size());
-    m.level.resize(m.nc);
-    m.ijk.resize(3 * m.nc);
-    for (int64_t c = 0; c < m.nc; ++c) {
-        m.level[c] = int8_t(cells[c].l);
-        m.ijk[3 * c] = cells[c].i;
-        m.ijk[3 * c + 1] = cells[c].j;
-        m.ijk[3 * c + 2] = cells[c].k;
-    }
+    if (all.size() > size_t(INT32_MAX) / 8) return "too many cells";
+    m.nc = int64_t(all.size());
+    m.level.resize(size_t(m.nc));
+    m.ijk.resize(size_t(3 * m.nc));
+    parallel_for(m.nc, [&](int64_t c0, int64_t c1) {
+        for (int64_t c = c0; c < c1; ++c) {
+            const uint64_t p = all[size_t(c)];
+            m.level[size_t(c)] = int8_t(p >> 60);
+            m.ijk[size_t(3 * c)] = ki(p);
+            m.ijk[size_t(3 * c + 1)] = kj(p);
+            m.ijk[size_t(3 * c + 2)] = kk(p);
+        }
+    });
+    std::vector<uint64_t>().swap(all);
     if (leaves_only) return "";
-    std::unordered_map<uint64_t, int32_t> index;
-    index.reserve(cells.size() * 2);
-    for (int64_t c = 0; c < m.nc; ++c) index.emplace(all[size_t(c)], int32_t(c));
+    CellIndex index;
+    index.build(m);
 
-    // side classification
-    std::vector<int8_t> kind(6 * m.nc);
-    std::vector<int32_t> nbr(6 * m.nc, -1);
-    for (int64_t c = 0; c < m.nc; ++c) {
-        int l = m.level[c];
-        for (int s = 0; s < 6; ++s) {
-            int ax = s / 2, dir = (s & 1) ? 1 : -1;
-            int q[3] = {m.ijk[3 * c], m.ijk[3 * c + 1], m.ijk[3 * c + 2]};
-            int64_t ext = d.n[ax] * pow3(l);
-            q[ax] = int((q[ax] + dir + ext) % ext);
-            auto it = index.find(pack(l, q[0], q[1], q[2]));
-            if (it != index.end()) {
-                kind[6 * c + s] = SIDE_CONFORMING;
-                nbr[6 * c + s] = it->second;
-                continue;
-            }
-            kind[6 * c + s] = SIDE_COARSE;
-            for (int lc = l - 1; lc >= 0; --lc) {
-                int64_t f = pow3(l - lc);
-                auto jt = index.find(pack(lc, int(q[0] / f), int(q[1] / f), int(q[2] / f)));
-                if (jt != index.end()) {
-                    kind[6 * c + s] = SIDE_FINE;
-                    nbr[6 * c + s] = jt->second;
-                    break;
+    // side classification: the same-level neighbour, else the coarser leaf
+    // that covers the side (fine side), else finer leaves (coarse side).  The
+    // x neighbour of a leaf is usually the next or previous entry of the table.
+    std::vector<int8_t> kind(size_t(6 * m.nc));
+    std::vector<int32_t> nbr(size_t(6 * m.nc), -1);
+    parallel_for(m.nc, [&](int64_t c0, int64_t c1) {
+        for (int64_t c = c0; c < c1; ++c) {
+            const int l = m.level[size_t(c)];
+            const int32_t *p = &m.ijk[size_t(3 * c)];
+            for (int s = 0; s < 6; ++s) {
+                const int ax = s / 2, dir = (s & 1) ? 1 : -1;
+                int64_t q[3] = {p[0], p[1], p[2]};
+                const int64_t ext = d.n[ax] * pow3(l);
+                q[ax] += dir;
+                if (q[ax] < 0) q[ax] += ext;
+                else if (q[ax] >= ext) q[ax] -= ext;
+                int32_t f = -1;
+                const int64_t g = c + dir;
+                if (ax == 0 && g >= 0 && g < m.nc && m.level[size_t(g)] == l && m.ijk[size_t(3 * g)] == q[0] &&
+                    m.ijk[size_t(3 * g + 1)] == q[1] && m.ijk[size_t(3 * g + 2)] == q[2])
+                    f = int32_t(g);
+                if (f < 0) f = index.find(l, q[0], q[1], q[2]);
+                if (f >= 0) {
+                    kind[size_t(6 * c + s)] = SIDE_CONFORMING;
+                    nbr[size_t(6 * c + s)] = f;
+                    continue;
+                }
+                kind[size_t(6 * c + s)] = SIDE_COARSE;
+                for (int lc = l - 1; lc >= 0; --lc) {
+                    const int64_t r = pow3(l - lc);
+                    f = index.find(lc, q[0] / r, q[1] / r, q[2] / r);
+                    if (f >= 0) {
+                        kind[size_t(6 * c + s)] = SIDE_FINE;
+                        nbr[size_t(6 * c + s)] = f;
+                        break;
+                    }
                 }
             }
         }
-    }
+    });
 
-    // conforming faces from the minus cell's plus side
-    for (int a = 0; a < 3; ++a) { m.face_m[a].clear(); m.face_p[a].clear(); }
-    for (int64_t c = 0; c < m.nc; ++c)
-        for (int a = 0; a < 3; ++a)
-            if (kind[6 * c + 2 * a + 1] == SIDE_CONFORMING) {
-                m.face_m[a].push_back(int32_t(c));
-                m.face_p[a].push_back(nbr[6 * c + 2 * a + 1]);
-            }
-
-    // hanging child faces in increasing fine-cell order
-    m.hang.clear();
-    std::vector<char> is_skel(m.nc, 0);
-    for (int64_t c = 0; c < m.nc; ++c)
-        for (int s = 0; s < 6; ++s) {
-            if (kind[6 * c + s] != SIDE_FINE) continue;
-            int ax = s / 2;
-            int t1 = (ax == 0) ? 1 : 0, t2 = (ax == 2) ? 1 : 2;
-            int32_t C = nbr[6 * c + s];
-            int dl = m.level[c] - m.level[C];
-            int64_t r = pow3(dl);
-            HostMesh::Hang h;
-            h.fine = int32_t(c);
-            h.coarse = C;
-            h.d = int8_t(ax);
-            h.fine_minus = int8_t(s & 1);  // fine cell on the minus side if its plus side hangs
-            h.dl = int8_t(dl);
-            h.s1 = int8_t(m.ijk[3 * c + t1] - r * m.ijk[3 * C + t1]);
-            h.s2 = int8_t(m.ijk[3 * c + t2] - r * m.ijk[3 * C + t2]);
-            m.hang.push_back(h);
-            is_skel[c] = 1;
-            is_skel[C] = 1;
-        }
-    // coarse sides and their children (CSR), children sorted by fine cell
-    std::unordered_map<int64_t, int32_t> cs_index;  // 6*cell+side -> coarse slot
-    m.coarse_cell.clear();
-    m.coarse_side.clear();
-    for (int64_t c = 0; c < m.nc; ++c)
+    // Lists, each in increasing cell order, then side order: conforming faces
+    // (from the minus cell's plus side) per axis, hanging child faces (one per
+    // fine side), coarse sides, skeleton cells (a side that is not
+    // conforming: the fine or the coarse cell of a hanging face) and enclave
+    // cells.  Counted per chunk of cells, then written at the chunk offsets.
+    const int64_t nch = std::max<int64_t>(1, std::min<int64_t>(1024, m.nc / 2048));
+    auto cbeg = [&](int64_t t) { return m.nc * t / nch; };
+    struct Count { int64_t face[3], hang, coarse, skel; };
+    std::vector<Count> cnt(size_t(nch) + 1, Count{{0, 0, 0}, 0, 0, 0});
+    auto skeletal = [&](int64_t c) {
         for (int s = 0; s < 6; ++s)
-            if (kind[6 * c + s] == SIDE_COARSE) {
-                cs_index.emplace(6 * c + s, int32_t(m.coarse_cell.size()));
-                m.coarse_cell.push_back(int32_t(c));
-                m.coarse_side.push_back(int8_t(s));
+            if (kind[size_t(6 * c + s)] != SIDE_CONFORMING) return true;
+        return false;
+    };
+    parallel_for(nch, [&](int64_t t0, int64_t t1) {
+        for (int64_t t = t0; t < t1; ++t) {
+            Count &n = cnt[size_t(t) + 1];
+            for (int64_t c = cbeg(t); c < cbeg(t + 1); ++c) {
+                for (int a = 0; a < 3; ++a) n.face[a] += kind[size_t(6 * c + 2 * a + 1)] == SIDE_CONFORMING;
+                for (int s = 0; s < 6; ++s) {
+                    n.hang += kind[size_t(6 * c + s)] == SIDE_FINE;
+                    n.coarse += kind[size_t(6 * c + s)] == SIDE_COARSE;
+                }
+                n.skel += skeletal(c);
             }
+        }
+    }, 1);
+    for (int64_t t = 0; t < nch; ++t) {
+        Count &a = cnt[size_t(t) + 1];
+        const Count &b = cnt[size_t(t)];
+        for (int x = 0; x < 3; ++x) a.face[x] += b.face[x];
+        a.hang += b.hang;
+        a.coarse += b.coarse;
+        a.skel += b.skel;
+    }
+    const Count &tot = cnt[size_t(nch)];
+    for (int a = 0; a < 3; ++a) {
+        m.face_m[a].resize(size_t(tot.face[a]));
+        m.face_p[a].resize(size_t(tot.face[a]));
+    }
+    m.hang.resize(size_t(tot.hang));
+    m.coarse_cell.resize(size_t(tot.coarse));
+    m.coarse_side.resize(size_t(tot.coarse));
+    m.skeleton.resize(size_t(tot.skel));
+    m.enclave.resize(size_t(m.nc - tot.skel));
+    parallel_for(nch, [&](int64_t t0, int64_t t1) {
+        for (int64_t t = t0; t < t1; ++t) {
+            Count o = cnt[size_t(t)];
+            int64_t enc = cbeg(t) - o.skel;
+            for (int64_t c = cbeg(t); c < cbeg(t + 1); ++c) {
+                for (int a = 0; a < 3; ++a)
+                    if (kind[size_t(6 * c + 2 * a + 1)] == SIDE_CONFORMING) {
+                        m.face_m[a][size_t(o.face[a])] = int32_t(c);
+                        m.face_p[a][size_t(o.face[a]++)] = nbr[size_t(6 * c + 2 * a + 1)];
+                    }
+                for (int s = 0; s < 6; ++s) {
+                    const int8_t k = kind[size_t(6 * c + s)];
+                    if (k == SIDE_FINE) {
+                        const int ax = s / 2;
+                        const int t1a = (ax == 0) ? 1 : 0, t2a = (ax == 2) ? 1 : 2;
+                        const int32_t C = nbr[size_t(6 * c + s)];
+                        const int dl = m.level[size_t(c)] - m.level[size_t(C)];
+                        const int64_t r = pow3(dl);
+                        HostMesh::Hang &h = m.hang[size_t(o.hang++)];
+                        h.fine = int32_t(c);
+                        h.coarse = C;
+                        h.d = int8_t(ax);
+                        h.fine_minus = int8_t(s & 1);  // fine cell on the minus side if its plus side hangs
+                        h.dl = int8_t(dl);
+                        h.s1 = int8_t(m.ijk[size_t(3 * c + t1a)] - r * m.ijk[size_t(3 * C + t1a)]);
+                        h.s2 = int8_t(m.ijk[size_t(3 * c + t2a)] - r * m.ijk[size_t(3 * C + t2a)]);
+                    } else if (k == SIDE_COARSE) {
+                        // the slot is kept in the coarse side's (otherwise unused) nbr entry
+                        nbr[size_t(6 * c + s)] = int32_t(o.coarse);
+                        m.coarse_cell[size_t(o.coarse)] = int32_t(c);
+                        m.coarse_side[size_t(o.coarse++)] = int8_t(s);
+                    }
+                }
+                if (skeletal(c)) m.skeleton[size_t(o.skel++)] = int32_t(c);
+                else m.enclave[size_t(enc++)] = int32_t(c);
+            }
+        }
+    }, 1);
+
+    // coarse sides' children (CSR), children sorted by fine cell
     std::vector<int32_t> count(m.coarse_cell.size() + 1, 0);
     std::vector<int32_t> slot_of(m.hang.size());
     for (size_t h = 0; h < m.hang.size(); ++h) {
         const auto &H = m.hang[h];
-        int coarse_side = 2 * H.d + (H.fine_minus ? 0 : 1);
-        auto it = cs_index.find(6 * int64_t(H.coarse) + coarse_side);
-        if (it == cs_index.end()) return "internal: hanging face without a coarse side";
-        slot_of[h] = it->second;
-        count[it->second + 1]++;
+        const int64_t cs = 6 * int64_t(H.coarse) + 2 * H.d + (H.fine_minus ? 0 : 1);
+        if (kind[cs] != SIDE_COARSE) return "internal: hanging face without a coarse side";
+        slot_of[h] = nbr[cs];
+        count[nbr[cs] + 1]++;
     }
     for (size_t i = 1; i < count.size(); ++i) count[i] += count[i - 1];
     m.coarse_ptr = count;
@@ -244,10 +302,88 @@ std::string build_host_mesh(const adg_instance_desc &d, HostMesh &m, bool leaves
     for (size_t i = 0; i + 1 < m.coarse_ptr.size(); ++i)
         if (m.coarse_ptr[i] == m.coarse_ptr[i + 1]) return "internal: coarse side without children";
 
-    m.skeleton.clear();
-    m.enclave.clear();
-    for (int64_t c = 0; c < m.nc; ++c) (is_skel[c] ? m.skeleton : m.enclave).push_back(int32_t(c));
     return "";
+}
+
+void CellIndex::build(const HostMesh &m)
+{
+    ijk_ = m.ijk.data();
+    max_level_ = m.max_level;
+    int64_t c = 0;
+    for (int l = 0; l <= LMAX; ++l) {
+        start_[l].clear();
+        rowkey_[l].clear();
+        if (l > m.max_level) continue;
+        for (int a = 0; a < 3; ++a) ext_[l][a] = m.n[a] * pow3(l);
+        const int64_t lb = c;
+        while (c < m.nc && m.level[c] == l) ++c;
+        const int64_t le = c, rows = ext_[l][1] * ext_[l][2];
+        auto row_of = [&](int64_t x) { return int64_t(m.ijk[3 * x + 2]) * ext_[l][1] + m.ijk[3 * x + 1]; };
+        dense_[l] = rows <= 4 * (le - lb) + 65536;
+        if (dense_[l]) {
+            start_[l].resize(size_t(rows) + 1);
+            int64_t p = lb;
+            for (int64_t r = 0; r < rows; ++r) {
+                start_[l][size_t(r)] = int32_t(p);
+                while (p < le && row_of(p) == r) ++p;
+            }
+            start_[l][size_t(rows)] = int32_t(le);
+        } else {
+            for (int64_t p = lb; p < le; ++p)
+                if (p == lb || row_of(p) != row_of(p - 1)) {
+                    rowkey_[l].push_back(row_of(p));
+                    start_[l].push_back(int32_t(p));
+                }
+            start_[l].push_back(int32_t(le));
+        }
+    }
+}
+
+int32_t CellIndex::find(int l, int64_t i, int64_t j, int64_t k) const
+{
+    if (l < 0 || l > max_level_) return -1;
+    const int64_t *e = ext_[l];
+    if (i < 0 || j < 0 || k < 0 || i >= e[0] || j >= e[1] || k >= e[2]) return -1;
+    const int64_t row = k * e[1] + j;
+    int64_t s, t;
+    if (dense_[l]) {
+        s = start_[l][size_t(row)];
+        t = start_[l][size_t(row) + 1];
+    } else {
+        auto it = std::lower_bound(rowkey_[l].begin(), rowkey_[l].end(), row);
+        if (it == rowkey_[l].end() || *it != row) return -1;
+        const size_t r = size_t(it - rowkey_[l].begin());
+        s = start_[l][r];
+        t = start_[l][r + 1];
+    }
+    const int64_t end = t;
+    while (s < t) {  // first leaf of the row with i' >= i
+        const int64_t mid = (s + t) >> 1;
+        if (ijk_[3 * mid] < i) s = mid + 1;
+        else t = mid;
+    }
+    return (s < end && ijk_[3 * s] == i) ? int32_t(s) : -1;
+}
+
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)> &fn, int64_t min_chunk)
+{
+    if (n <= 0) return;
+    const unsigned hw = std::thread::hardware_concurrency();
+    const int64_t nt = std::max<int64_t>(
+        1, std::min<int64_t>({int64_t(hw ? hw : 1), 16, (n + min_chunk - 1) / std::max<int64_t>(1, min_chunk)}));
+    if (nt == 1) {
+        fn(0, n);
+        return;
+    }
+    const int64_t per = (n + nt - 1) / nt;
+    std::vector<std::thread> th;
+    th.reserve(size_t(nt - 1));
+    for (int64_t t = 1; t < nt; ++t) {
+        const int64_t b = t * per, e = std::min(n, b + per);
+        if (b < e) th.emplace_back(fn, b, e);
+    }
+    fn(0, std::min(n, per));
+    for (auto &x : th) x.join();
 }
 
 }  // namespace adg

@@ -4,7 +4,9 @@ The forward pass advances the state n steps with a FROZEN time-step
 schedule (the dt of every step of the unperturbed run, from adg_step's
 history); the backward pass runs the library's hand-written adjoint
 (adg_step_adjoint) step by step in reverse.  Only every k-th state is kept
-(checkpointing); each segment is recomputed forward before its adjoint steps.
+(checkpointing); each segment is recomputed forward before its adjoint steps,
+by default as recorded steps (adg_step_record) whose tapes the adjoint steps
+read (adg_step_adjoint_tape), so no predictor runs twice.
 The point-sample misfit of the density, J = 1/2 sum_s (rho_h(x_s) - rho*_s)^2,
 is a second Function whose backward scatters through adg_sample_adjoint.
 """
@@ -43,14 +45,14 @@ class Rollout(torch.autograd.Function):
     """u_n = step^n(u_0) at the frozen schedule; checkpoint every k steps."""
 
     @staticmethod
-    def forward(ctx, u0, mesh, dt_sched, n_steps, k):
+    def forward(ctx, u0, mesh, dt_sched, n_steps, k, record=True):
         bufs = _Buffers(mesh)
         u = u0.detach().clone()
         ckpts = []
         for s0 in range(0, n_steps, k):
             ckpts.append(u.clone())
             advance_fixed(mesh, u, dt_sched, s0, min(s0 + k, n_steps), bufs)
-        ctx.mesh, ctx.k, ctx.n_steps = mesh, k, n_steps
+        ctx.mesh, ctx.k, ctx.n_steps, ctx.record = mesh, k, n_steps, record
         ctx.save_for_backward(dt_sched, *ckpts)
         return u
 
@@ -63,9 +65,24 @@ class Rollout(torch.autograd.Function):
         ws = mesh.empty_adjoint_workspace()
         ubar = ubar_out.detach().contiguous().clone()
         nxt = torch.empty_like(ubar)
+        # recorded segments: each forward predictor of the segment runs once
+        # and keeps what its adjoint step reads (k tapes); otherwise the
+        # adjoint step runs the predictor again from the recomputed state
+        tapes = [mesh.empty_tape() for _ in range(min(k, n_steps))] if ctx.record else None
         for si in reversed(range(len(ckpts))):
             s0, s1 = si * k, min(si * k + k, n_steps)
             states = [ckpts[si]]
+            if tapes is not None:
+                for n in range(s0, s1):
+                    nxt_state = torch.empty_like(states[-1]) if n < s1 - 1 else None
+                    mesh.step_record(states[-1], dt_sched[n * ni:(n + 1) * ni], nxt_state, tapes[n - s0], ws)
+                    if nxt_state is not None:
+                        states.append(nxt_state)
+                for n in reversed(range(s0, s1)):
+                    mesh.step_adjoint_tape(states[n - s0], dt_sched[n * ni:(n + 1) * ni], tapes[n - s0], ubar, nxt,
+                                           ws)
+                    ubar, nxt = nxt, ubar
+                continue
             for n in range(s0, s1 - 1):
                 u = states[-1].clone()
                 advance_fixed(mesh, u, dt_sched, n, n + 1, bufs)
@@ -73,7 +90,7 @@ class Rollout(torch.autograd.Function):
             for n in reversed(range(s0, s1)):
                 mesh.step_adjoint(states[n - s0], dt_sched[n * ni:(n + 1) * ni], ubar, nxt, ws)
                 ubar, nxt = nxt, ubar
-        return ubar, None, None, None, None
+        return ubar, None, None, None, None, None
 
 
 class SampledMisfit(torch.autograd.Function):
@@ -98,12 +115,14 @@ class SampledMisfit(torch.autograd.Function):
         return ubar, None, None, None
 
 
-def loss_and_grad(mesh, u0, pts, target, n_steps, k=5, dt_sched=None):
-    """J(u0) after n_steps (frozen schedule) and dJ/du0 through the adjoint."""
+def loss_and_grad(mesh, u0, pts, target, n_steps, k=5, dt_sched=None, record=True):
+    """J(u0) after n_steps (frozen schedule) and dJ/du0 through the adjoint;
+    record: recompute each segment with recorded steps (k tapes of
+    adjoint_tape_bytes) instead of running every predictor twice."""
     if dt_sched is None:
         dt_sched = dt_schedule(mesh, u0, n_steps)
     u0 = u0.detach().clone().requires_grad_(True)
-    uT = Rollout.apply(u0, mesh, dt_sched, n_steps, k)
+    uT = Rollout.apply(u0, mesh, dt_sched, n_steps, k, record)
     J = SampledMisfit.apply(uT, mesh, pts, target)
     J.backward()
     return J.detach(), u0.grad.detach(), dt_sched

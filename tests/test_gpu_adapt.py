@@ -108,3 +108,34 @@ def test_adaptive_run_matches_oracle(precision):
     e = np.abs(u_g.cpu().numpy().reshape(u_o.shape) - u_o).max() / np.abs(u_o).max()
     print(f"   final max relative deviation {e:.2e}", flush=True)
     assert e <= tol
+
+
+def test_handle_plan_and_chunked_transfer_match_oracle():
+    """adg_adapt_plan_mesh (leaves and rows kept by the handle) gives the
+    oracle's plan, and the transfer onto the planned mesh matches the oracle
+    on a mesh large enough (81,953 cells) for the host tables to be built in
+    many chunks on several threads."""
+    p, n, L = 2, (9, 9, 9), 2
+    ref = inputs.sphere_refine_list(n, 2, radius=0.3)
+    om = oracle.Mesh(p, n, max_level=L, refine=ref)
+    gm = A.Mesh(A.instance(p, n, max_level=L, refine=ref), "fp64")
+    u0 = inputs.blast_smooth(om.node_coords(), width=1.0 / 27, radius=0.3)
+    eta = om.indicator(u0)
+    tr, tc = float(np.quantile(eta, 0.9)), float(np.quantile(eta, 0.6))
+    rows = gm.adapt_plan(eta, tr, tc)
+    assert np.array_equal(rows, oracle.adapt_plan(om.cells(), ref, eta, tr, tc, L))
+    assert np.array_equal(rows, A.adapt_plan(gm.descs[0], eta, tr, tc))
+    om2 = oracle.Mesh(p, n, max_level=L, refine=rows)
+    gm2 = A.Mesh(A.instance(p, n, max_level=L, refine=rows), "fp64")
+    print(f"[plan+transfer] cells {om.nc} -> {om2.nc}", flush=True)
+    assert om2.nc != om.nc
+    want = om.transfer_to(u0, om2)
+    got = gm.transfer_to(dev(u0), gm2).cpu().numpy().reshape(want.shape)
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+    # a uniform handle plans too (no rows yet)
+    gu = A.Mesh(A.instance(p, (3, 3, 3), max_level=1), "fp64")
+    e = np.zeros(27)
+    e[13] = 1.0
+    assert np.array_equal(gu.adapt_plan(e, 0.5, 0.1), np.array([[0, 1, 1, 1]], dtype=np.int32))
+    for m in (gm, gm2, gu):
+        m.close()

@@ -20,7 +20,8 @@ gradient against the ORACLE's FP64 gradient (its adjoint chain, element by
 element) and against the oracle's tangent-linear model on all 32 directions
 (an independent FP64 CPU reference, no direction excluded); the adjoint of a
 step on an adaptive mesh against the oracle's adjoint and tangent; the Taylor
-remainder's second order; checkpoint-interval neutrality."""
+remainder's second order; checkpoint-interval neutrality; recorded steps and
+the tape adjoint equal to the plain ones bit for bit."""
 import numpy as np
 import pytest
 
@@ -134,10 +135,11 @@ def test_gradient_27cubed_20_steps_against_finite_differences():
           flush=True)
     assert max(r for r, _ in res) <= 1e-6, res
     assert worst_plain <= 1e-4
-    # checkpoint interval does not change the gradient (bit for bit)
+    # checkpoint interval and recorded segments do not change the gradient (bit for bit)
     _, g1, _ = rollout.loss_and_grad(gm, u0, pts, target, steps, k=1, dt_sched=sched)
     _, g20, _ = rollout.loss_and_grad(gm, u0, pts, target, steps, k=20, dt_sched=sched)
-    assert torch.equal(g1, g) and torch.equal(g20, g)
+    _, g_rerun, _ = rollout.loss_and_grad(gm, u0, pts, target, steps, k=5, dt_sched=sched, record=False)
+    assert torch.equal(g1, g) and torch.equal(g20, g) and torch.equal(g_rerun, g)
     # Taylor remainder |J(u+hv) - J(u) - h<g,v>| is second order in h
     v = dev(dirs[0])
     h0 = 1e-3 * float(u0.norm() / v.norm())
@@ -260,6 +262,46 @@ def test_adaptive_step_adjoint_against_oracle(order):
         assert e <= 1e-12, e
         assert abs(a - b) <= 1e-11 * abs(a), (a, b)
     gm.status()
+
+
+@pytest.mark.parametrize("amr", [False, True])
+def test_recorded_step_and_tape_adjoint(amr):
+    """adg_step_record gives the phase-by-phase step bit for bit (also in
+    place), and adg_step_adjoint_tape on its tape gives adg_step_adjoint bit
+    for bit, on a uniform mesh (p = 3, the wavefront kernels) and on an
+    adaptive one (p = 2, hanging faces)."""
+    if amr:
+        p, n = 2, (3, 3, 3)
+        ref = inputs.sphere_refine_list(n, 2, radius=0.2)
+        om = oracle.Mesh(p, n, max_level=2, refine=ref)
+        gm = A.Mesh(A.instance(p, n, max_level=2, refine=ref), "fp64")
+    else:
+        p, n = 3, (6, 5, 4)
+        om = oracle.Mesh(p, n)
+        gm = A.Mesh(A.instance(p, n), "fp64")
+    u0 = inputs.density_wave_noisy(om.node_coords(), seed=70, noise=0.02)
+    dt_o, st = om.cfl(u0)
+    assert st == 0
+    u, dt = dev(u0), torch.full((1,), dt_o, dtype=torch.float64, device="cuda")
+    ws, tape = gm.empty_adjoint_workspace(), gm.empty_tape()
+    want = u.clone()
+    rollout.advance_fixed(gm, want, dt, 0, 1, rollout._Buffers(gm))
+    got = torch.empty_like(u)
+    gm.step_record(u, dt, got, tape, ws)
+    assert torch.equal(got, want)
+    inplace = u.clone()
+    gm.step_record(inplace, dt, inplace, gm.empty_tape(), ws)
+    assert torch.equal(inplace, want)
+    w = dev(inputs.directions(u0.shape, 1, seed=71)[0])
+    a, b = torch.empty_like(u), torch.empty_like(u)
+    gm.step_adjoint(u, dt, w, a, ws)
+    tape2 = gm.empty_tape()
+    gm.step_record(u, dt, None, tape2, ws)  # tape only
+    gm.step_adjoint_tape(u, dt, tape2, w, b, ws)
+    print(f"[tape] amr={amr} tape {gm.info['adjoint_tape_bytes'] / 2**20:.1f} MiB", flush=True)
+    assert torch.equal(a, b)
+    gm.status()
+    gm.close()
 
 
 def test_adjoint_rejects_unsupported_handles():
