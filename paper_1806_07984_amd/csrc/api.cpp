@@ -2,6 +2,7 @@
 // launch sequences of the phases and of whole steps.
 #include <algorithm>
 #include <iterator>
+#include <memory>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -1715,19 +1716,36 @@ adg_status plan_rows(const adg::HostMesh &hm, const adg::CellIndex &index, const
     auto split = [&](int64_t c) { return eta[c] > theta_refine && hm.level[c] < hm.max_level; };
     // current rows minus the merged parents, plus the split leaves
     struct Row { int32_t l, i, j, k; };
-    std::vector<Row> rows;
-    for (int64_t r = 0; r < n_refine; ++r) {
-        const int32_t *q = refine + 4 * r;
-        bool merge = true;
-        for (int c2 = 0; c2 < 3 && merge; ++c2)
-            for (int c1 = 0; c1 < 3 && merge; ++c1)
-                for (int c0 = 0; c0 < 3 && merge; ++c0) {
-                    const int64_t f = index.find(q[0] + 1, 3 * int64_t(q[1]) + c0, 3 * int64_t(q[2]) + c1,
-                                                 3 * int64_t(q[3]) + c2);
-                    merge = f >= 0 && !split(f) && eta[f] < theta_coarsen;
+    // a row merges when its 27 children are leaves, none split, all quiet;
+    // the three children along x of one (k, j) row of children are
+    // consecutive in the cell table, so one lookup finds them
+    std::vector<char> keep(static_cast<size_t>(std::max<int64_t>(n_refine, 1)));
+    parallel_for(n_refine, [&](int64_t r0, int64_t r1) {
+        for (int64_t r = r0; r < r1; ++r) {
+            const int32_t *q = refine + 4 * r;
+            const int lc = q[0] + 1;
+            const int64_t i0 = 3 * int64_t(q[1]);
+            bool merge = true;
+            for (int c2 = 0; c2 < 3 && merge; ++c2)
+                for (int c1 = 0; c1 < 3 && merge; ++c1) {
+                    const int64_t j = 3 * int64_t(q[2]) + c1, k = 3 * int64_t(q[3]) + c2;
+                    const int64_t f = index.find(lc, i0, j, k);
+                    for (int c0 = 0; c0 < 3 && merge; ++c0) {
+                        const int64_t g = f + c0;
+                        merge = f >= 0 && g < hm.nc && hm.level[g] == lc && hm.ijk[3 * g] == i0 + c0 &&
+                                hm.ijk[3 * g + 1] == j && hm.ijk[3 * g + 2] == k && !split(g) &&
+                                eta[g] < theta_coarsen;
+                    }
                 }
-        if (!merge) rows.push_back(Row{q[0], q[1], q[2], q[3]});
-    }
+            keep[size_t(r)] = !merge;
+        }
+    }, 4096);
+    std::vector<Row> rows;
+    for (int64_t r = 0; r < n_refine; ++r)
+        if (keep[size_t(r)]) {
+            const int32_t *q = refine + 4 * r;
+            rows.push_back(Row{q[0], q[1], q[2], q[3]});
+        }
     auto less = [](const Row &a, const Row &b) {
         if (a.l != b.l) return a.l < b.l;
         if (a.k != b.k) return a.k < b.k;
@@ -1802,7 +1820,8 @@ adg_status adg_transfer(const adg_mesh *from, const double *u_from, adg_mesh *to
     const CellIndex &index = F.index;
     // copy (the same leaf) or prolongation (a coarser leaf covers the cell),
     // in parallel; the rest are coarsened cells, gathered in order afterwards
-    std::vector<VOp> ops(size_t(T.nc));
+    // every entry is written by the loop below (first touch on its threads)
+    std::unique_ptr<VOp[]> ops(new VOp[size_t(std::max<int64_t>(T.nc, 1))]);
     parallel_for(T.nc, [&](int64_t c0, int64_t c1) {
         for (int64_t c = c0; c < c1; ++c) {
             const int l = T.hm.level[size_t(c)];
@@ -1826,16 +1845,22 @@ adg_status adg_transfer(const adg_mesh *from, const double *u_from, adg_mesh *to
             ops[size_t(c)] = op;
         }
     });
-    // the source leaves of every coarsened cell, gathered per chunk of target
-    // cells and concatenated in cell order
-    const int64_t nch = std::max<int64_t>(1, std::min<int64_t>(256, T.nc / 4096));
+    // the source leaves of every coarsened cell, gathered per chunk of the
+    // coarsened cells (they cluster in the cell table) and concatenated in
+    // cell order
+    std::vector<int32_t> coarsened;
+    for (int64_t c = 0; c < T.nc; ++c)
+        if (ops[size_t(c)].kind == 2) coarsened.push_back(int32_t(c));
+    const int64_t ncs = int64_t(coarsened.size());
+    const int64_t nch = std::max<int64_t>(1, std::min<int64_t>(256, ncs / 64));
+    auto cbeg = [&](int64_t t) { return ncs * t / nch; };
     std::vector<std::vector<VKid>> part(static_cast<size_t>(nch));
     std::vector<char> partial_cover(static_cast<size_t>(nch), 0);
     parallel_for(nch, [&](int64_t t0, int64_t t1) {
         for (int64_t t = t0; t < t1; ++t)
-            for (int64_t c = T.nc * t / nch; c < T.nc * (t + 1) / nch; ++c) {
+            for (int64_t x = cbeg(t); x < cbeg(t + 1); ++x) {
+                const int64_t c = coarsened[size_t(x)];
                 VOp &op = ops[size_t(c)];
-                if (op.kind != 2) continue;
                 const int l = T.hm.level[size_t(c)];
                 const int64_t k[3] = {T.hm.ijk[size_t(3 * c)], T.hm.ijk[size_t(3 * c + 1)],
                                       T.hm.ijk[size_t(3 * c + 2)]};
@@ -1862,16 +1887,16 @@ adg_status adg_transfer(const adg_mesh *from, const double *u_from, adg_mesh *to
     parallel_for(nch, [&](int64_t t0, int64_t t1) {
         for (int64_t t = t0; t < t1; ++t) {
             std::copy(part[size_t(t)].begin(), part[size_t(t)].end(), kids.begin() + kid_off[size_t(t)]);
-            for (int64_t c = T.nc * t / nch; c < T.nc * (t + 1) / nch; ++c)
-                if (ops[size_t(c)].kind == 2) ops[size_t(c)].kid0 += int32_t(kid_off[size_t(t)]);
+            for (int64_t x = cbeg(t); x < cbeg(t + 1); ++x)
+                ops[size_t(coarsened[size_t(x)])].kid0 += int32_t(kid_off[size_t(t)]);
         }
     }, 1);
     VOp *ops_dev = nullptr;
     VKid *kids_dev = nullptr;
     DeviceGuard dg(to->device);
-    ADG_HIP(hipMalloc(&ops_dev, sizeof(VOp) * ops.size()), "transfer table");
+    ADG_HIP(hipMalloc(&ops_dev, sizeof(VOp) * size_t(T.nc)), "transfer table");
     hipError_t e = hipMalloc(&kids_dev, sizeof(VKid) * std::max<size_t>(1, kids.size()));
-    if (e == hipSuccess) e = hipMemcpyAsync(ops_dev, ops.data(), sizeof(VOp) * ops.size(), hipMemcpyHostToDevice,
+    if (e == hipSuccess) e = hipMemcpyAsync(ops_dev, ops.get(), sizeof(VOp) * size_t(T.nc), hipMemcpyHostToDevice,
                                             stream);
     if (e == hipSuccess && !kids.empty())
         e = hipMemcpyAsync(kids_dev, kids.data(), sizeof(VKid) * kids.size(), hipMemcpyHostToDevice, stream);

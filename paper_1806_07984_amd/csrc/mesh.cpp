@@ -13,6 +13,7 @@
 //     enclave: the rest.
 #include <algorithm>
 #include <iterator>
+#include <memory>
 #include <cstdio>
 #include <thread>
 
@@ -162,8 +163,9 @@ std::string build_host_mesh(const adg_instance_desc &d, HostMesh &m, bool leaves
     // side classification: the same-level neighbour, else the coarser leaf
     // that covers the side (fine side), else finer leaves (coarse side).  The
     // x neighbour of a leaf is usually the next or previous entry of the table.
-    std::vector<int8_t> kind(size_t(6 * m.nc));
-    std::vector<int32_t> nbr(size_t(6 * m.nc), -1);
+    // every entry is written by the loop below (first touch on its threads)
+    std::unique_ptr<int8_t[]> kind(new int8_t[size_t(std::max<int64_t>(6 * m.nc, 1))]);
+    std::unique_ptr<int32_t[]> nbr(new int32_t[size_t(std::max<int64_t>(6 * m.nc, 1))]);
     parallel_for(m.nc, [&](int64_t c0, int64_t c1) {
         for (int64_t c = c0; c < c1; ++c) {
             const int l = m.level[size_t(c)];
@@ -187,6 +189,7 @@ std::string build_host_mesh(const adg_instance_desc &d, HostMesh &m, bool leaves
                     continue;
                 }
                 kind[size_t(6 * c + s)] = SIDE_COARSE;
+                nbr[size_t(6 * c + s)] = -1;
                 for (int lc = l - 1; lc >= 0; --lc) {
                     const int64_t r = pow3(l - lc);
                     f = index.find(lc, q[0] / r, q[1] / r, q[2] / r);
