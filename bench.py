@@ -61,14 +61,19 @@ def predictor_bytes_per_cell(N, real_bytes):
     return 2 * 5 * N ** 3 * 8 + 12 * 5 * N ** 2 * real_bytes
 
 
-def step_bytes_per_cell(N, real_bytes):
+def step_bytes_per_cell(N, real_bytes, fused=True):
     """Algorithmic HBM bytes of one whole step per cell of a uniform periodic
     mesh (3 faces per cell): the predictor (read u, write u* and the 12 face
-    projection arrays), the Riemann solves (read both sides' state and normal
-    flux projections, write the flux both sides see), the corrector (read u*
-    and the 6 face fluxes, write u; the next step's CFL maximum is fused into
-    it).  The CFL final reduction reads one value per corrector block."""
+    projection arrays), then either (fused, the step at p = 3) one kernel that
+    solves every cell's face problems and runs its corrector (read u* and the
+    12 face projection arrays once, write u), or the separate Riemann solves
+    (read both sides' state and normal flux projections, write the flux both
+    sides see) and corrector (read u* and the 6 face fluxes, write u).  The
+    next step's CFL maximum is fused into the corrector; the CFL final
+    reduction reads one value per corrector block."""
     pred = predictor_bytes_per_cell(N, real_bytes)
+    if fused:
+        return pred + 2 * 5 * N ** 3 * 8 + 12 * 5 * N ** 2 * real_bytes
     riem = 3 * 6 * 5 * N ** 2 * real_bytes
     corr = 2 * 5 * N ** 3 * 8 + 6 * 5 * N ** 2 * real_bytes
     return pred + riem + corr

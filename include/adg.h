@@ -235,6 +235,18 @@ adg_status adg_set_options(adg_mesh *mesh, int32_t use_graph, int32_t batched);
  * (locality only); it is slower (3.26 ms). */
 adg_status adg_set_pipeline(adg_mesh *mesh, int32_t enable);
 
+/* Face fusion (on by default): for a handle of one uniform instance at p = 3,
+ * adg_step solves the Riemann problems of each cell's six faces (Eq. 3, the
+ * Rusanov flux with one speed per face, Sec. 2.4) inside that cell's corrector
+ * (Eq. 4) instead of in separate per-axis face kernels: each face is solved
+ * by both of its cells, with the same operands in the same order, and the
+ * fluxes stay on chip, so no face-flux array goes through device memory.
+ * Results are the same bits either way.  Not used while a switch tape is on,
+ * with the limiter or the pipelined step, or for other handles; the phase
+ * entry points adg_riemann and adg_corrector are unaffected.  enable = 0
+ * switches it off. */
+adg_status adg_set_face_fusion(adg_mesh *mesh, int32_t enable);
+
 /* A-posteriori finite-volume subcell limiter (Sec. 5.3, block-structured
  * methods; Sec. 6, Euler with shocks: a cell whose ADER-DG update is
  * physically wrong or oscillates is rolled back and advanced over the same dt

@@ -27,7 +27,7 @@ EXPORTS = ["adg_init_mesh", "adg_free_mesh", "adg_mesh_info", "adg_instance_info
            "adg_set_switch_tape", "adg_set_pipeline", "adg_indicator", "adg_adapt_plan", "adg_transfer",
            "adg_set_limiter", "adg_limiter_stats", "adg_lin_init", "adg_lin_free", "adg_lin_info", "adg_lin_dt",
            "adg_lin_predictor", "adg_lin_step", "adg_step_noalloc", "adg_adapt_plan_mesh",
-           "adg_step_record", "adg_step_adjoint_tape"]
+           "adg_step_record", "adg_step_adjoint_tape", "adg_set_face_fusion"]
 PHASES = ["cfl", "predictor", "hanging", "riemann", "corrector", "limiter"]
 
 
@@ -97,6 +97,7 @@ def load():
         "adg_set_pipeline": [P, I32],
         "adg_step_adjoint": [P, P, P, P, P, P, P],
         "adg_step_record": [P, P, P, P, P, P, P],
+        "adg_set_face_fusion": [P, I32],
         "adg_step_adjoint_tape": [P, P, P, P, P, P, P, P],
         "adg_set_switch_tape": [P, P, I32],
         "adg_sample": [P, P, P, I64, P, P],
@@ -349,6 +350,11 @@ class Mesh:
         """Pipelined step over cell chunks (single instance, no hanging faces):
         0/False off, 1/True predictor and face/corrector streams, 2 one stream."""
         _check(load().adg_set_pipeline(self._h, int(mode)))
+
+    def set_face_fusion(self, enable):
+        """Riemann problems solved inside the corrector (adg_set_face_fusion;
+        one uniform instance at p = 3; on by default, same bits either way)."""
+        _check(load().adg_set_face_fusion(self._h, int(bool(enable))))
 
     def set_limiter(self, mode, delta0=1e-4, eps=1e-3):
         """A-posteriori subcell limiter: 0/False off, 1/True on, 2 every cell

@@ -95,6 +95,8 @@ struct adg_mesh {
     // Rusanov switch tape (conforming faces, axis-major per instance)
     int16_t *tape = nullptr;
     int tape_mode = 0;
+    // uniform N = 4 instances: Riemann problems fused into the corrector
+    bool fuse_faces = true;
     // captured step (hipGraph) replayed by adg_step
     bool use_graph = false;  // set at init: on for handles with more than one instance
     hipStream_t gs_a = nullptr, gs_b = nullptr;
@@ -472,6 +474,26 @@ adg_status do_corrector(adg_mesh *m, const double *ustar, const T *fside, const 
     return ADG_OK;
 }
 
+// The Riemann problems of every cell's faces inside its corrector (one
+// uniform periodic instance at N = 4, no switch tape): the same bits as
+// do_conforming then do_corrector with fuse_cfl, without the face fluxes.
+bool can_fuse_faces(const adg_mesh *m)
+{
+    return m->fuse_faces && m->inst.size() == 1 && m->inst[0].N == 4 && m->inst[0].hm.max_level == 0 &&
+           m->inst[0].nh == 0 && m->tape_mode == 0;
+}
+
+template <typename T>
+adg_status do_face_corrector(adg_mesh *m, const double *ustar, const T *traces, double *u, hipStream_t st)
+{
+    PhaseTimer tm(m, ADG_PHASE_CORRECTOR, st);
+    Instance &I = m->inst[0];
+    ADG_HIP(launch_face_corrector4<T>(ustar, traces, m->dt_dev, u, I.nc, I.hm.n, I.geo, I.gamma, I.partial,
+                                      m->status_dev, st),
+            "riemann + corrector");
+    return ADG_OK;
+}
+
 // number of CFL block maxima the corrector leaves for the next step
 int nparts(const adg_mesh *m, const Instance &I)
 {
@@ -661,10 +683,15 @@ adg_status enqueue_step(adg_mesh *m, double *u, double *hist, void *ws, hipStrea
             ADG_HIP(hipEventRecord(m->ev_encl, s_encl), "event record");
             ADG_HIP(hipStreamWaitEvent(s_skel, m->ev_encl, 0), "stream wait");
         }
-        st = do_conforming<T>(m, traces, fside, s_skel);
-        if (st != ADG_OK) return st;
-        st = do_corrector<T>(m, ustar, fside, m->dt_dev, u, s_skel, true);
-        if (st != ADG_OK) return st;
+        if (can_fuse_faces(m)) {
+            st = do_face_corrector<T>(m, ustar, traces, u, s_skel);
+            if (st != ADG_OK) return st;
+        } else {
+            st = do_conforming<T>(m, traces, fside, s_skel);
+            if (st != ADG_OK) return st;
+            st = do_corrector<T>(m, ustar, fside, m->dt_dev, u, s_skel, true);
+            if (st != ADG_OK) return st;
+        }
     }
     return ADG_OK;
 }
@@ -1357,6 +1384,14 @@ adg_status adg_set_options(adg_mesh *mesh, int32_t use_graph, int32_t batched)
     }
     mesh->use_graph = use_graph != 0;
     mesh->batched = batched;
+    drop_graph(mesh);
+    return ADG_OK;
+}
+
+adg_status adg_set_face_fusion(adg_mesh *mesh, int32_t enable)
+{
+    if (!valid_mesh(mesh)) return ADG_ERR_INVALID_ARG;
+    mesh->fuse_faces = enable != 0;
     drop_graph(mesh);
     return ADG_OK;
 }

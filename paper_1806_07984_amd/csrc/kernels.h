@@ -84,6 +84,14 @@ hipError_t launch_corrector(int N, const double *ustar, const T *fside, const do
                             int64_t nc, const int8_t *level, const Geo &geo, hipStream_t st, double gamma = 0.0,
                             double *partial = nullptr, int *status = nullptr, int64_t c0 = 0, int64_t c1 = -1);
 int corrector_blocks(int N, int64_t nc);
+// The conforming Riemann problems and the corrector in one kernel, for one
+// uniform periodic instance at N = 4 with n[0] x n[1] x n[2] cells: the same
+// bits as launch_riemann on every axis followed by launch_corrector (partial
+// as there), without the face-flux array.
+template <typename T>
+hipError_t launch_face_corrector4(const double *ustar, const T *traces, const double *dt, double *uout, int64_t nc,
+                                  const int n[3], const Geo &geo, double gamma, double *partial, int *status,
+                                  hipStream_t st);
 // block maxima of the CFL rate of u, nb blocks (the number of maxima the next
 // launch_cfl_final reads)
 hipError_t launch_cfl_prime(int N, const double *u, int64_t nc, const int8_t *level, const Geo &geo, double gamma,

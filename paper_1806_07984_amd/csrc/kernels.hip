@@ -1377,6 +1377,15 @@ template <int N> struct FaceCfg {
 // B32: every trace and face plane (one side, array and variable over all
 // cells) is below 2 GiB, so accesses are buffer loads and stores from a
 // scalar plane base with a 32-bit per-lane offset
+// Rusanov flux of one face node from both sides' projections and the face
+// speed s: one fixed chain of operations, shared by every kernel that solves
+// conforming faces, so they all give the same bits.
+template <typename T>
+__device__ __forceinline__ T rusanov(T FL, T FR, T QL, T QR, T s)
+{
+    return fma(T(-0.5) * s, QR - QL, T(0.5) * (FL + FR));
+}
+
 template <typename T, int N, bool B32>
 __global__ void __launch_bounds__(FaceCfg<N>::THREADS)
 k_riemann(const T *__restrict__ traces, T *__restrict__ fside, const int32_t *__restrict__ fm,
@@ -1458,7 +1467,7 @@ k_riemann(const T *__restrict__ traces, T *__restrict__ fside, const int32_t *__
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-        const T F = T(0.5) * (FL[v] + FR[v]) - T(0.5) * s * (QR[v] - QL[v]);
+        const T F = rusanov(FL[v], FR[v], QL[v], QR[v], s);
         if constexpr (B32) {
             const int pb = int(nc * N2 * int64_t(sizeof(T)));
             buf_st(buf_view(fside + (int64_t(sL) * NV + v) * nc * N2, pb), unsigned(cL * N2 + b) * unsigned(sizeof(T)), F);
@@ -1538,7 +1547,7 @@ k_hang(const T *__restrict__ traces, T *__restrict__ fside, const HangDev *__res
     const T *QR = fine_minus ? Qv : Qf, *FR = fine_minus ? Fv : Ff;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-        const T F = T(0.5) * (FL[v] + FR[v]) - T(0.5) * s * (QR[v] - QL[v]);
+        const T F = rusanov(FL[v], FR[v], QL[v], QR[v], s);
         fside[(int64_t(sf * NV + v) * nc + fine) * N2 + b] = F;
     }
 }
@@ -1725,6 +1734,102 @@ k_corrector4(const double *__restrict__ ustar, const T *__restrict__ fside, cons
             buf_st(buf_view(uout + (int64_t(v) * nc + c) * N3, N3 * sizeof(double)), lu, q[v]);
         }
         if (FUSE) rate = fmax(rate, cfl_rate(gamma, q, geo, lev, status));
+    }
+    if (FUSE) {
+        __shared__ double sh[4];
+        rate = block_max(rate, sh);
+        if (threadIdx.x == 0) partial[blockIdx.x] = rate;
+    }
+}
+
+// The Riemann problems of a cell's six faces and the cell's corrector in one
+// pass, for one uniform periodic instance at N = 4 (cells in (k, j, i) order,
+// one wavefront per cell, four cells per block).  Rows of 16 lanes take one
+// face each: faces 0-3 in a first round, 4-5 in a second (lanes 32-63 idle);
+// lane b of a row is face node b, reads its own side's and the neighbour's
+// projections, and the row's maximum is the face speed.  Both cells of a face
+// solve it, with the same operands in the same order as k_riemann, so the
+// flux is bit for bit the one k_riemann stores; the six faces' fluxes go
+// through the block's LDS to the nodes, and the update is that of
+// k_corrector4.  No face-flux array is written or read.
+template <typename T, bool FUSE>
+__global__ void __launch_bounds__(256)
+k_face_corrector4(const double *__restrict__ ustar, const T *__restrict__ traces, const double *__restrict__ dt_dev,
+                  double *__restrict__ uout, int64_t nc, int nx, int ny, int nz, Geo geo, double gamma,
+                  double *__restrict__ partial, int *__restrict__ status)
+{
+    constexpr int N2 = 16, N3 = 64;
+    __shared__ T fs[4 * 6 * NV * N2];
+    const int l = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    T *fw = fs + wave * (6 * NV * N2);
+    const unsigned lu = unsigned(l) * unsigned(sizeof(double));
+    const int bxi = (l >> 2) & 15, byi = (l & 3) + 4 * (l >> 4), bzi = l & 15;
+    const double *Wl = lane_at(static_cast<const double *>(c_corr4), unsigned(l) * unsigned(6 * sizeof(double)));
+    const double Rx = Wl[0], Ry = Wl[1], Rz = Wl[2], Lx = Wl[3], Ly = Wl[4], Lz = Wl[5];
+    const T g = T(gamma), gm1 = T(gamma - 1.0);
+    const int64_t nxy = int64_t(nx) * ny, plane = nc * N2;
+    const int b = l & 15;
+    const double dt = dt_dev[0];
+    const double cx = dt * geo.inv_dx[0][0], cy = dt * geo.inv_dx[0][1], cz = dt * geo.inv_dx[0][2];
+    double rate = 0.0;
+    for (int64_t base = int64_t(blockIdx.x) * 4; base < nc; base += int64_t(gridDim.x) * 4) {
+        const int64_t c = base + wave;
+        const bool cell_ok = c < nc;  // uniform per wavefront
+        if (cell_ok) {
+            const int64_t ijk[3] = {c % nx, (c / nx) % ny, c / nxy};
+            const int64_t ext[3] = {nx, ny, nz}, str[3] = {1, nx, nxy};
+#pragma unroll 1
+            for (int r = 0; r < 2; ++r) {  // one round's loads in flight: bounds the registers
+                const int side = 4 * r + (l >> 4);
+                const bool face_ok = side < 6;
+                const int sd = face_ok ? side : 0, d = sd >> 1, plus = sd & 1;
+                // the neighbour across this side (periodic)
+                const int64_t q = ijk[d] + (plus ? 1 : -1);
+                const int64_t qn = q < 0 ? q + ext[d] : (q >= ext[d] ? q - ext[d] : q);
+                const int64_t n = c + (qn - ijk[d]) * str[d];
+                // minus cell's plus side on the left, plus cell's minus side on the right
+                const int64_t cL = plus ? c : n, cR = plus ? n : c;
+                const int sL = 2 * d + 1, sR = 2 * d;
+                T QL[NV], FL[NV], QR[NV], FR[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    QL[v] = traces[(int64_t(sL * 2 + 0) * NV + v) * plane + cL * N2 + b];
+                    FL[v] = traces[(int64_t(sL * 2 + 1) * NV + v) * plane + cL * N2 + b];
+                    QR[v] = traces[(int64_t(sR * 2 + 0) * NV + v) * plane + cR * N2 + b];
+                    FR[v] = traces[(int64_t(sR * 2 + 1) * NV + v) * plane + cR * N2 + b];
+                }
+                bool badL, badR;
+                const T lL = wave_speed(g, gm1, QL, d, badL);
+                const T lR = wave_speed(g, gm1, QR, d, badR);
+                if (face_ok && (badL || badR)) *status = 1;
+                const T sf = row_max16(lL > lR ? lL : lR);
+                if (face_ok) {
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) fw[(sd * NV + v) * N2 + b] = rusanov(FL[v], FR[v], QL[v], QR[v], sf);
+                }
+            }
+        }
+        __syncthreads();
+        if (cell_ok) {
+            double q[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const double f0 = double(fw[(0 * NV + v) * N2 + bxi]), f1 = double(fw[(1 * NV + v) * N2 + bxi]);
+                const double f2 = double(fw[(2 * NV + v) * N2 + byi]), f3 = double(fw[(3 * NV + v) * N2 + byi]);
+                const double f4 = double(fw[(4 * NV + v) * N2 + bzi]), f5 = double(fw[(5 * NV + v) * N2 + bzi]);
+                const double us = buf_ld(buf_view(ustar + (int64_t(v) * nc + c) * N3, N3 * sizeof(double)), lu, 0.0);
+                // the update of k_corrector4, operation for operation
+                const double tx = fma(Rx, f1, -(Lx * f0));
+                const double ty = fma(Ry, f3, -(Ly * f2));
+                const double tz = fma(Rz, f5, -(Lz * f4));
+                const double sv = fma(cx, tx, fma(cy, ty, cz * tz));
+                q[v] = us - sv;
+                buf_st(buf_view(uout + (int64_t(v) * nc + c) * N3, N3 * sizeof(double)), lu, q[v]);
+            }
+            if (FUSE) rate = fmax(rate, cfl_rate(gamma, q, geo, 0, status));
+        }
+        __syncthreads();  // the next cells overwrite the fluxes
     }
     if (FUSE) {
         __shared__ double sh[4];
@@ -3652,6 +3757,21 @@ hipError_t launch_corrector(int N, const double *ustar, const T *fside, const do
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_face_corrector4(const double *ustar, const T *traces, const double *dt, double *uout, int64_t nc,
+                                  const int n[3], const Geo &geo, double gamma, double *partial, int *status,
+                                  hipStream_t st)
+{
+    const int64_t blocks = corrector_blocks(4, nc);
+    if (partial)
+        hipLaunchKernelGGL((k_face_corrector4<T, true>), dim3(unsigned(blocks)), dim3(256), 0, st, ustar, traces, dt,
+                           uout, nc, n[0], n[1], n[2], geo, gamma, partial, status);
+    else
+        hipLaunchKernelGGL((k_face_corrector4<T, false>), dim3(unsigned(blocks)), dim3(256), 0, st, ustar, traces, dt,
+                           uout, nc, n[0], n[1], n[2], geo, gamma, partial, status);
+    return hipGetLastError();
+}
+
 int pred_variant_count() { return PRED_VARIANTS; }
 
 void pred_variant_shape(int code, int *N, int *CPB)
@@ -4016,7 +4136,10 @@ hipError_t launch_lin_corrector(int N, const double *ustar, const double *fside,
                                            const double *, hipStream_t);                                 \
     template hipError_t launch_corrector<T>(int, const double *, const T *, const double *, double *,    \
                                             int64_t, const int8_t *, const Geo &, hipStream_t, double,    \
-                                            double *, int *, int64_t, int64_t);
+                                            double *, int *, int64_t, int64_t);                           \
+    template hipError_t launch_face_corrector4<T>(const double *, const T *, const double *, double *,   \
+                                                  int64_t, const int[3], const Geo &, double, double *,    \
+                                                  int *, hipStream_t);
 
 ADG_INSTANTIATE(double)
 ADG_INSTANTIATE(float)

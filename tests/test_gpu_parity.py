@@ -200,3 +200,32 @@ def test_step_to_end_time(precision):
     assert torch.equal(u, v)
     gm.close()
 
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", [(6, 5, 7), (1, 4, 2), (3, 1, 1)])
+def test_face_fusion_same_bits(precision, n):
+    """adg_step with the Riemann problems inside the corrector (the default for
+    one uniform p = 3 instance) against the separate face and corrector
+    kernels: the same bits after several steps, including the step sizes, on
+    meshes with unequal and single-cell axes (a cell that is its own
+    periodic neighbour); and the oracle's run to the stated bar."""
+    om, gm = make_pair(3, n, precision)
+    u0 = inputs.density_wave_noisy(om.node_coords(), seed=31, noise=0.02)
+    steps = 4
+    runs = []
+    for fuse in (True, False):
+        gm.set_face_fusion(fuse)
+        u = dev(u0)
+        hist = torch.zeros(steps, dtype=torch.float64, device="cuda")
+        gm.step(u, steps, gm.empty_workspace(), dt_hist=hist)
+        gm.status()
+        runs.append((u, hist))
+    print(f"[face fusion] {precision} n={n}", flush=True)
+    assert torch.equal(runs[0][1], runs[1][1])
+    assert torch.equal(runs[0][0], runs[1][0])
+    ref, _, rc = om.run(u0, steps)
+    assert rc == 0
+    e = rel_l2_per_var(runs[0][0].cpu().numpy(), ref, solution_weights(om, n))
+    assert e.max() <= TOL[precision], e
+    gm.close()
