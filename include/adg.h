@@ -332,6 +332,7 @@ adg_status adg_step_adjoint(adg_mesh *mesh, const double *u_n_dev, const double 
  * u_n_dev; NULL: only the tape is written) and keeps in tape_dev what the
  * step's adjoint reads from its forward run: the predictor's face projections
  * and Picard iterates (adjoint_tape_bytes, device memory the caller owns).
+ * tape_dev NULL: a plain step at the fixed dt (then u_np1_dev is required).
  * adg_step_adjoint_tape then gives the result of adg_step_adjoint(u_n_dev,
  * dt_dev, ...) bit for bit, reading the tape instead of running the
  * predictor again; u_n_dev and dt_dev must be those of the recording.  Both

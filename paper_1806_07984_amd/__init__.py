@@ -414,16 +414,20 @@ class Mesh:
 
     def step_record(self, u, dt, u_next, tape, ws, stream=None):
         """u_next = step(u; dt) at fixed dt, keeping what its adjoint reads in
-        tape (adg_step_record); u_next may be u, or None for the tape only."""
+        tape (adg_step_record); u_next may be u, or None for the tape only;
+        tape None: a plain step at the fixed dt."""
         import torch
         n = self.info["u_elems"]
-        if tape.numel() < self.info["adjoint_tape_bytes"] or ws.numel() < self.info["adjoint_workspace_bytes"]:
+        if ws.numel() < self.info["adjoint_workspace_bytes"] or (
+                tape is not None and tape.numel() < self.info["adjoint_tape_bytes"]):
             raise ValueError("tape or adjoint workspace too small")
+        if tape is None and u_next is None:
+            raise ValueError("a step without a tape needs u_next")
         _check(load().adg_step_record(self._h, _ptr(u, torch.float64, n, "u"),
                                       _ptr(dt, torch.float64, self.n_instances, "dt"),
                                       None if u_next is None else _ptr(u_next, torch.float64, n, "u_next"),
-                                      ctypes.c_void_p(tape.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
-                                      _stream(stream)))
+                                      None if tape is None else ctypes.c_void_p(tape.data_ptr()),
+                                      ctypes.c_void_p(ws.data_ptr()), _stream(stream)))
 
     def step_adjoint_tape(self, u, dt, tape, ubar_next, ubar, ws, stream=None):
         """step_adjoint of the step recorded in tape from the same u and dt

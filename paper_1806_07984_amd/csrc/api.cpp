@@ -484,12 +484,13 @@ bool can_fuse_faces(const adg_mesh *m)
 }
 
 template <typename T>
-adg_status do_face_corrector(adg_mesh *m, const double *ustar, const T *traces, double *u, hipStream_t st)
+adg_status do_face_corrector(adg_mesh *m, const double *ustar, const T *traces, const double *dt, double *u,
+                             hipStream_t st, bool fuse_cfl)
 {
     PhaseTimer tm(m, ADG_PHASE_CORRECTOR, st);
     Instance &I = m->inst[0];
-    ADG_HIP(launch_face_corrector4<T>(ustar, traces, m->dt_dev, u, I.nc, I.hm.n, I.geo, I.gamma, I.partial,
-                                      m->status_dev, st),
+    ADG_HIP(launch_face_corrector4<T>(ustar, traces, dt, u, I.nc, I.hm.n, I.geo, I.gamma,
+                                      fuse_cfl ? I.partial : nullptr, m->status_dev, st),
             "riemann + corrector");
     return ADG_OK;
 }
@@ -684,7 +685,7 @@ adg_status enqueue_step(adg_mesh *m, double *u, double *hist, void *ws, hipStrea
             ADG_HIP(hipStreamWaitEvent(s_skel, m->ev_encl, 0), "stream wait");
         }
         if (can_fuse_faces(m)) {
-            st = do_face_corrector<T>(m, ustar, traces, u, s_skel);
+            st = do_face_corrector<T>(m, ustar, traces, m->dt_dev, u, s_skel, true);
             if (st != ADG_OK) return st;
         } else {
             st = do_conforming<T>(m, traces, fside, s_skel);
@@ -1606,7 +1607,7 @@ adg_status adg_step_adjoint_tape(adg_mesh *mesh, const double *u, const double *
 adg_status adg_step_record(adg_mesh *mesh, const double *u, const double *dt, double *u_next, void *tape, void *ws,
                            hipStream_t stream)
 {
-    if (!valid_mesh(mesh) || !u || !dt || !tape || !ws) {
+    if (!valid_mesh(mesh) || !u || !dt || !ws || (!tape && !u_next)) {
         set_error("adg_step_record: null argument");
         return ADG_ERR_INVALID_ARG;
     }
@@ -1623,17 +1624,24 @@ adg_status adg_step_record(adg_mesh *mesh, const double *u, const double *dt, do
     double *ustar = reinterpret_cast<double *>(w);
     w += align_up(sizeof(double) * mesh->info.u_elems) + 2 * align_up(sizeof(double) * mesh->info.trace_elems);
     double *fside = reinterpret_cast<double *>(w);
-    char *t = static_cast<char *>(tape);
-    double *traces = reinterpret_cast<double *>(t);
-    double *iters = reinterpret_cast<double *>(t + align_up(sizeof(double) * mesh->info.trace_elems));
+    // no tape: a plain step at the fixed dt, its face projections in the
+    // workspace's trace slot
+    double *traces = reinterpret_cast<double *>(static_cast<char *>(ws) + align_up(sizeof(double) * mesh->info.u_elems));
+    double *iters = nullptr;
+    if (tape) {
+        char *t = static_cast<char *>(tape);
+        traces = reinterpret_cast<double *>(t);
+        iters = reinterpret_cast<double *>(t + align_up(sizeof(double) * mesh->info.trace_elems));
+    }
     for (size_t i = 0; i < mesh->inst.size(); ++i) {
         Instance &I = mesh->inst[i];
         ADG_HIP(launch_predictor<double>(I.N, u + I.u_off, ustar + I.u_off, traces + I.tr_off, nullptr, I.nc, I.nc,
                                          I.level, I.geo, dt + i, I.gamma, I.npic, stream, iters),
                 "recorded predictor");
-        iters += int64_t(I.npic) * I.N * NV * I.nc * I.N * I.N * I.N;
+        if (iters) iters += int64_t(I.npic) * I.N * NV * I.nc * I.N * I.N * I.N;
     }
     if (!u_next) return ADG_OK;
+    if (can_fuse_faces(mesh)) return do_face_corrector<double>(mesh, ustar, traces, dt, u_next, stream, false);
     adg_status st = do_conforming<double>(mesh, traces, fside, stream);
     if (st == ADG_OK) st = do_hanging<double>(mesh, traces, fside, stream);
     if (st == ADG_OK) st = do_corrector<double>(mesh, ustar, fside, dt, u_next, stream);

@@ -46,12 +46,15 @@ class Rollout(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, u0, mesh, dt_sched, n_steps, k, record=True):
-        bufs = _Buffers(mesh)
         u = u0.detach().clone()
         ckpts = []
+        ws = mesh.empty_adjoint_workspace()
+        ni = mesh.n_instances
         for s0 in range(0, n_steps, k):
             ckpts.append(u.clone())
-            advance_fixed(mesh, u, dt_sched, s0, min(s0 + k, n_steps), bufs)
+            for n in range(s0, min(s0 + k, n_steps)):
+                # one step at the frozen dt (adg_step_record without a tape)
+                mesh.step_record(u, dt_sched[n * ni:(n + 1) * ni], u, None, ws)
         ctx.mesh, ctx.k, ctx.n_steps, ctx.record = mesh, k, n_steps, record
         ctx.save_for_backward(dt_sched, *ckpts)
         return u

@@ -292,6 +292,9 @@ def test_recorded_step_and_tape_adjoint(amr):
     inplace = u.clone()
     gm.step_record(inplace, dt, inplace, gm.empty_tape(), ws)
     assert torch.equal(inplace, want)
+    plain = u.clone()
+    gm.step_record(plain, dt, plain, None, ws)  # no tape: a plain step at the fixed dt
+    assert torch.equal(plain, want)
     w = dev(inputs.directions(u0.shape, 1, seed=71)[0])
     a, b = torch.empty_like(u), torch.empty_like(u)
     gm.step_adjoint(u, dt, w, a, ws)
