@@ -1773,8 +1773,17 @@ k_face_corrector4(const double *__restrict__ ustar, const T *__restrict__ traces
     const double dt = dt_dev[0];
     const double cx = dt * geo.inv_dx[0][0], cy = dt * geo.inv_dx[0][1], cz = dt * geo.inv_dx[0][2];
     double rate = 0.0;
-    for (int64_t base = int64_t(blockIdx.x) * 4; base < nc; base += int64_t(gridDim.x) * 4) {
-        const int64_t c = base + wave;
+    // Workgroups go to the 8 XCDs in turn (workgroup i to XCD i mod 8): each
+    // XCD walks one contiguous eighth of the cells, so the face neighbours
+    // along y (nx cells away) are read on the XCD, and around the time, that
+    // read them as their own, while they are still in that XCD's L2.
+    const int64_t units = (nc + 3) / 4;
+    const bool by_xcd = gridDim.x % 8 == 0;
+    const int xcd = by_xcd ? int(blockIdx.x % 8) : 0;
+    const int64_t stride = by_xcd ? gridDim.x / 8 : gridDim.x;
+    const int64_t ub = by_xcd ? units * xcd / 8 : 0, ue = by_xcd ? units * (xcd + 1) / 8 : units;
+    for (int64_t unit = ub + (by_xcd ? blockIdx.x / 8 : blockIdx.x); unit < ue; unit += stride) {
+        const int64_t c = unit * 4 + wave;
         const bool cell_ok = c < nc;  // uniform per wavefront
         if (cell_ok) {
             const int64_t ijk[3] = {c % nx, (c / nx) % ny, c / nxy};
