@@ -1193,11 +1193,14 @@ __device__ __forceinline__ void pred4_adj_wave(const double *__restrict__ u, con
     const int nx[4] = {a0, (a0 + 1) & 3, (a0 + 2) & 3, (a0 + 3) & 3};
     const int ny[4] = {a1, (a1 + 3) & 3, (a1 + 2) & 3, (a1 + 1) & 3};
     const int zi = l & 3, zk = l >> 4;
-    auto load_q = [&](int r, int j, double q[NV]) {  // iterate r (0 = u) at time node j
+    // iterate r >= 1 at time node j (the launch requires npic >= 1, so a
+    // stored iterate is never the state u itself; a select between the two
+    // had the compiler split the kernel into branches, across which the
+    // exchanged values stayed live: 330 registers instead of 168)
+    auto load_q = [&](int r, int j, double q[NV]) {
+        const double *base = iters + ((int64_t(r - 1) * N + j) * NV * nc + c) * N3;
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
-            q[v] = r == 0 ? *lane_at(u + (int64_t(v) * nc + c) * N3, lu)
-                          : *lane_at(iters + (((int64_t(r - 1) * N + j) * NV + v) * nc + c) * N3, lu);
+        for (int v = 0; v < NV; ++v) q[v] = *lane_at(base + int64_t(v) * nc * N3, lu);
     };
 
     // adjoint of u* = u + volume term: identity, and the transposed volume
@@ -1222,6 +1225,7 @@ __device__ __forceinline__ void pred4_adj_wave(const double *__restrict__ u, con
             Fbb[0][v] = fibre_sum64<0>(Vx, ub[v], 0.0);
             Fbb[1][v] = fibre_sum64<1>(Vy, ub[v], 0.0);
             Fbb[2][v] = zsum64(Vz, ub[v], 0.0);
+            SCHED_SPLIT();
         }
     }
     // adjoint of the face projections (each node reads its own face entries)
@@ -1305,7 +1309,7 @@ __device__ __forceinline__ void pred4_adj_wave(const double *__restrict__ u, con
     }
     // r = 1: every q^(0)_j is u, and one divergence served all time nodes
     // with the row sums of KW; q^(0) = u adds the rest
-    if (npic >= 1) {
+    {
         double gs[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -1318,24 +1322,19 @@ __device__ __forceinline__ void pred4_adj_wave(const double *__restrict__ u, con
             gs[v] = -s;
         }
         double q[NV], nb[NV];
-        load_q(0, 0, q);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) q[v] = *lane_at(u + (int64_t(v) * nc + c) * N3, lu);
         divergence_vjp(q, gs, nb);
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[v] += nb[v];
-    } else {
-#pragma unroll
-        for (int j = 0; j < N; ++j)
-#pragma unroll
-            for (int v = 0; v < NV; ++v) acc[v] += qbar[j][v];
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) *lane_at(ubar + (int64_t(v) * nc + c) * N3, lu) = acc[v];
 }
 
-// one wave per SIMD: the whole register file (256 VGPRs and the AGPRs) holds
-// the cotangents without spills; at two waves it spills 300 B per lane and the
-// gradient of 20 steps at 27^3 took 3 % longer
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 8)))
+// 168 VGPRs, no spills: three waves per SIMD (asking for three makes the
+// scheduler spill four registers; asking for two gives three without spills)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
 k_predictor4_adj_f64(const double *__restrict__ u, const double *__restrict__ iters,
                      const double *__restrict__ ubar_next, const double *__restrict__ tbar,
                      const double *__restrict__ dt_dev, double *__restrict__ ubar, int64_t nc,
@@ -3967,7 +3966,7 @@ hipError_t launch_adjoint_step(int N, const double *u, const double *dt, const d
             hipLaunchKernelGGL((k_prolong_adj<NN>), dim3(unsigned((ah.ncs * N2 + 255) / 256)), dim3(256), 0, st,
                                tbar, ah.vbar, ah.hang, ah.ccell, ah.cside, ah.cptr, ah.cchild, ah.ncs, nc, ah.ptab);
         constexpr int CPB = PredCfg<NN>::CPB;
-        if (NN == 4 && g_pred4_f64)
+        if (NN == 4 && g_pred4_f64 && npic >= 1)
             hipLaunchKernelGGL(k_predictor4_adj_f64, dim3(unsigned((nc + 3) / 4)), dim3(256), 0, st, u, iters,
                                ubar_next, tbar, dt, ubar, nc, level, geo, gamma, npic);
         else
