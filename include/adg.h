@@ -331,7 +331,9 @@ adg_status adg_step_adjoint(adg_mesh *mesh, const double *u_n_dev, const double 
  * adg_riemann and adg_corrector, Eq. 4) into u_np1_dev (which may alias
  * u_n_dev; NULL: only the tape is written) and keeps in tape_dev what the
  * step's adjoint reads from its forward run: the predictor's face projections
- * and Picard iterates (adjoint_tape_bytes, device memory the caller owns).
+ * and Picard iterates (at p = 3 the first iterate as the divergence it is
+ * formed from, rebuilt from u_n_dev by the adjoint; adjoint_tape_bytes,
+ * device memory the caller owns).
  * tape_dev NULL: a plain step at the fixed dt (then u_np1_dev is required).
  * adg_step_adjoint_tape then gives the result of adg_step_adjoint(u_n_dev,
  * dt_dev, ...) bit for bit, reading the tape instead of running the

@@ -950,8 +950,12 @@ __device__ __forceinline__ double zsum64(double a, double x, double acc)
     return __builtin_amdgcn_mfma_f64_4x4x4f64(a, x, acc, 0, 0, 0);
 }
 
-// STORE: also write iterate it (1 .. npic) of every time node to
-// iters[it-1][j][v][c][node], the layout the adjoint reads
+// STORE: also write what the adjoint reads, in planes [v][c][node] of one
+// time node each: the final iterate (time node j in plane j), the first
+// iteration's divergence G(u) in plane N (npic >= 2; the first iterate is
+// u - KWsum_j G(u), which the adjoint rebuilds with the same fma), and
+// iterate r = 2 .. npic-1 at time node j in plane N + 1 + (r-2) N + j.
+// At most npic N planes.
 template <bool STORE>
 __device__ __forceinline__ void pred4_wave_f64(const double *__restrict__ u, double *__restrict__ ustar,
                                                double *__restrict__ traces, int64_t c, int64_t nc, int lev,
@@ -996,13 +1000,14 @@ __device__ __forceinline__ void pred4_wave_f64(const double *__restrict__ u, dou
     };
 
     double q[N][NV];
-    auto store_iterate = [&](int it) {
+    // time node j of the current iterate into plane p0 + j
+    auto store_iterate = [&](int64_t p0) {
         if constexpr (STORE) {
 #pragma unroll
             for (int j = 0; j < N; ++j)
 #pragma unroll
                 for (int v = 0; v < NV; ++v)
-                    *lane_at(iters + (((int64_t(it) * N + j) * NV + v) * nc + c) * N3, lu) = q[j][v];
+                    *lane_at(iters + (((p0 + j) * NV + v) * nc + c) * N3, lu) = q[j][v];
         }
     };
     if (npic > 0) {
@@ -1010,11 +1015,15 @@ __device__ __forceinline__ void pred4_wave_f64(const double *__restrict__ u, dou
         // divergence serve all time nodes; the row sums of KW finish it
         double g[NV];
         spatial(uu, g);
+        if constexpr (STORE) {
+            if (npic >= 2)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) *lane_at(iters + ((int64_t(N) * NV + v) * nc + c) * N3, lu) = g[v];
+        }
 #pragma unroll
         for (int j = 0; j < N; ++j)
 #pragma unroll
             for (int v = 0; v < NV; ++v) q[j][v] = fma(-B.KWsum[j], g[v], uu[v]);
-        store_iterate(0);
     } else {
 #pragma unroll
         for (int j = 0; j < N; ++j)
@@ -1046,8 +1055,9 @@ __device__ __forceinline__ void pred4_wave_f64(const double *__restrict__ u, dou
         for (int i = 0; i < N; ++i)
 #pragma unroll
             for (int v = 0; v < NV; ++v) q[i][v] = qn[i][v];
-        store_iterate(it);
+        if (it + 1 < npic) store_iterate(N + 1 + int64_t(it - 1) * N);  // iterate it + 1
     }
+    if (npic > 0) store_iterate(0);  // the final iterate
 
     // time averages of the final iterate
     double qb[NV], Fb[3][NV];
@@ -1193,12 +1203,12 @@ __device__ __forceinline__ void pred4_adj_wave(const double *__restrict__ u, con
     const int nx[4] = {a0, (a0 + 1) & 3, (a0 + 2) & 3, (a0 + 3) & 3};
     const int ny[4] = {a1, (a1 + 3) & 3, (a1 + 2) & 3, (a1 + 1) & 3};
     const int zi = l & 3, zk = l >> 4;
-    // iterate r >= 1 at time node j (the launch requires npic >= 1, so a
-    // stored iterate is never the state u itself; a select between the two
-    // had the compiler split the kernel into branches, across which the
-    // exchanged values stayed live: 330 registers instead of 168)
-    auto load_q = [&](int r, int j, double q[NV]) {
-        const double *base = iters + ((int64_t(r - 1) * N + j) * NV * nc + c) * N3;
+    // the iterates from the forward kernel's planes (the launch requires
+    // npic >= 1, so none of them is the state u itself; a select between the
+    // state and the tape had the compiler split the kernel into branches,
+    // across which the exchanged values stayed live: 330 registers, not 168)
+    auto load_plane = [&](int64_t pl, double q[NV]) {
+        const double *base = iters + (pl * NV * nc + c) * N3;
 #pragma unroll
         for (int v = 0; v < NV; ++v) q[v] = *lane_at(base + int64_t(v) * nc * N3, lu);
     };
@@ -1252,7 +1262,7 @@ __device__ __forceinline__ void pred4_adj_wave(const double *__restrict__ u, con
 #pragma unroll
     for (int j = 0; j < N; ++j) {
         double q[NV], fbw[3][NV];
-        load_q(npic, j, q);
+        load_plane(j, q);  // the final iterate
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             qbar[j][v] = B.w[j] * qbb[v];
@@ -1284,7 +1294,8 @@ __device__ __forceinline__ void pred4_adj_wave(const double *__restrict__ u, con
         }
         flux3_vjp(gm1, q, fb, nb);
     };
-    for (int r = npic; r >= 2; --r) {
+    // one reverse iteration, given the iterate it was formed from
+    auto reverse_iteration = [&](auto &&load_prev) {
         double Gb[N][NV];
 #pragma unroll
         for (int j = 0; j < N; ++j)
@@ -1302,11 +1313,20 @@ __device__ __forceinline__ void pred4_adj_wave(const double *__restrict__ u, con
 #pragma unroll
         for (int j = 0; j < N; ++j) {
             double q[NV];
-            load_q(r - 1, j, q);
+            load_prev(j, q);
             divergence_vjp(q, Gb[j], qbar[j]);
             SCHED_SPLIT();  // one time node at a time: bounds the live registers
         }
-    }
+    };
+    for (int r = npic; r >= 3; --r)  // iterate r - 1 >= 2 is stored
+        reverse_iteration([&](int j, double q[NV]) { load_plane(N + 1 + int64_t(r - 3) * N + j, q); });
+    if (npic >= 2)  // iterate 1 = u - KWsum_j G(u), as the forward kernel formed it
+        reverse_iteration([&](int j, double q[NV]) {
+            double g[NV];
+            load_plane(N, g);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) q[v] = fma(-B.KWsum[j], g[v], *lane_at(u + (int64_t(v) * nc + c) * N3, lu));
+        });
     // r = 1: every q^(0)_j is u, and one divergence served all time nodes
     // with the row sums of KW; q^(0) = u adds the rest
     {
@@ -1332,9 +1352,10 @@ __device__ __forceinline__ void pred4_adj_wave(const double *__restrict__ u, con
     for (int v = 0; v < NV; ++v) *lane_at(ubar + (int64_t(v) * nc + c) * N3, lu) = acc[v];
 }
 
-// 168 VGPRs, no spills: three waves per SIMD (asking for three makes the
-// scheduler spill four registers; asking for two gives three without spills)
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
+// three waves per SIMD (168 VGPRs, 12 of them spilled around the rebuilt
+// first iterate); at two waves (176 VGPRs, no spills) the gradient of 20
+// steps at 27^3 took 1 % longer
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
 k_predictor4_adj_f64(const double *__restrict__ u, const double *__restrict__ iters,
                      const double *__restrict__ ubar_next, const double *__restrict__ tbar,
                      const double *__restrict__ dt_dev, double *__restrict__ ubar, int64_t nc,
@@ -2070,6 +2091,38 @@ k_corrector_adj(const double *__restrict__ ubar, double *__restrict__ fbar, cons
     for (int e = 0; e < N; ++e)
         acc += B.winv[e] * E[e] * ubar[(int64_t(v) * nc + c) * N3 + node_from_face<N>(d, e, b)];
     fbar[t] = sign * sc * acc;
+}
+
+// The same at N = 4 with one wavefront per cell: the cell's cotangent is read
+// once, coalesced (lane = node), into LDS, and the lanes form the 6 x 5 x 16
+// side sums from there with the operations of k_corrector_adj (same bits).
+// The thread-per-output form reads every cell once per side.
+__global__ void __launch_bounds__(256)
+k_corrector_adj4(const double *__restrict__ ubar, double *__restrict__ fbar, const double *__restrict__ dt_dev,
+                 int64_t nc, const int8_t *__restrict__ level, Geo geo)
+{
+    constexpr int N = 4, N2 = 16, N3 = 64, OUT = 6 * NV * N2;
+    __shared__ double ls[4][NV * N3];
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int64_t c = int64_t(blockIdx.x) * 4 + wave;
+    const bool ok = c < nc;  // uniform per wavefront; every wavefront reaches the barrier
+    if (ok)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) ls[wave][v * N3 + l] = ubar[(int64_t(v) * nc + c) * N3 + l];
+    __syncthreads();
+    if (!ok) return;
+    const DevBasis &B = c_basis[N];
+    const int lev = level ? level[c] : 0;
+    for (int o = l; o < OUT; o += 64) {
+        const int s = o / (NV * N2), v = (o / N2) % NV, b = o % N2, d = s >> 1;
+        const double sc = dt_dev[0] * geo.inv_dx[lev][d];
+        const double *E = (s & 1) ? B.R : B.L;
+        const double sign = (s & 1) ? -1.0 : 1.0;
+        double acc = 0.0;
+#pragma unroll
+        for (int e = 0; e < N; ++e) acc += B.winv[e] * E[e] * ls[wave][v * N3 + node_from_face<N>(d, e, b)];
+        fbar[(int64_t(s * NV + v) * nc + c) * N2 + b] = sign * sc * acc;
+    }
 }
 
 // Transpose of the Rusanov solve on the conforming faces of one axis: writes
@@ -3949,8 +4002,12 @@ hipError_t launch_adjoint_step(int N, const double *u, const double *dt, const d
         constexpr int N2 = NN * NN;
         constexpr int FPB = FaceCfg<NN>::FPB;
         const int64_t items = 6 * int64_t(NV) * nc * N2;
-        hipLaunchKernelGGL((k_corrector_adj<NN>), dim3(unsigned((items + 255) / 256)), dim3(256), 0, st, ubar_next,
-                           fbar, dt, nc, level, geo);
+        if (NN == 4)
+            hipLaunchKernelGGL(k_corrector_adj4, dim3(unsigned((nc + 3) / 4)), dim3(256), 0, st, ubar_next, fbar, dt,
+                               nc, level, geo);
+        else
+            hipLaunchKernelGGL((k_corrector_adj<NN>), dim3(unsigned((items + 255) / 256)), dim3(256), 0, st,
+                               ubar_next, fbar, dt, nc, level, geo);
         if (ah.nh > 0)
             hipLaunchKernelGGL((k_restrict_adj<NN>), dim3(unsigned((ah.nh * N2 + 255) / 256)), dim3(256), 0, st,
                                fbar, ah.hang, ah.nh, nc, ah.ptab);

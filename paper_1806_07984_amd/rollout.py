@@ -6,7 +6,9 @@ history); the backward pass runs the library's hand-written adjoint
 (adg_step_adjoint) step by step in reverse.  Only every k-th state is kept
 (checkpointing); each segment is recomputed forward before its adjoint steps,
 by default as recorded steps (adg_step_record) whose tapes the adjoint steps
-read (adg_step_adjoint_tape), so no predictor runs twice.
+read (adg_step_adjoint_tape), so no predictor runs twice.  The last segment is
+recorded by the forward pass itself, since its tapes are the first the
+backward pass needs.
 The point-sample misfit of the density, J = 1/2 sum_s (rho_h(x_s) - rho*_s)^2,
 is a second Function whose backward scatters through adg_sample_adjoint.
 """
@@ -50,12 +52,23 @@ class Rollout(torch.autograd.Function):
         ckpts = []
         ws = mesh.empty_adjoint_workspace()
         ni = mesh.n_instances
+        # with recording, the last segment keeps its tapes and states for the
+        # backward pass, which starts there
+        tapes = [mesh.empty_tape() for _ in range(min(k, n_steps))] if record and n_steps > 0 else None
+        last = ((n_steps - 1) // k) * k if n_steps > 0 else 0
+        states = []
         for s0 in range(0, n_steps, k):
             ckpts.append(u.clone())
             for n in range(s0, min(s0 + k, n_steps)):
-                # one step at the frozen dt (adg_step_record without a tape)
-                mesh.step_record(u, dt_sched[n * ni:(n + 1) * ni], u, None, ws)
+                dt = dt_sched[n * ni:(n + 1) * ni]
+                if tapes is not None and s0 == last:
+                    states.append(u.clone())
+                    mesh.step_record(states[-1], dt, u, tapes[n - s0], ws)
+                else:
+                    # one step at the frozen dt (adg_step_record without a tape)
+                    mesh.step_record(u, dt, u, None, ws)
         ctx.mesh, ctx.k, ctx.n_steps, ctx.record = mesh, k, n_steps, record
+        ctx.tapes, ctx.last_states = tapes, states
         ctx.save_for_backward(dt_sched, *ckpts)
         return u
 
@@ -71,16 +84,20 @@ class Rollout(torch.autograd.Function):
         # recorded segments: each forward predictor of the segment runs once
         # and keeps what its adjoint step reads (k tapes); otherwise the
         # adjoint step runs the predictor again from the recomputed state
-        tapes = [mesh.empty_tape() for _ in range(min(k, n_steps))] if ctx.record else None
+        tapes = ctx.tapes
         for si in reversed(range(len(ckpts))):
             s0, s1 = si * k, min(si * k + k, n_steps)
             states = [ckpts[si]]
             if tapes is not None:
-                for n in range(s0, s1):
-                    nxt_state = torch.empty_like(states[-1]) if n < s1 - 1 else None
-                    mesh.step_record(states[-1], dt_sched[n * ni:(n + 1) * ni], nxt_state, tapes[n - s0], ws)
-                    if nxt_state is not None:
-                        states.append(nxt_state)
+                if si == len(ckpts) - 1:
+                    # recorded by the forward pass
+                    states, ctx.last_states = ctx.last_states, None
+                else:
+                    for n in range(s0, s1):
+                        nxt_state = torch.empty_like(states[-1]) if n < s1 - 1 else None
+                        mesh.step_record(states[-1], dt_sched[n * ni:(n + 1) * ni], nxt_state, tapes[n - s0], ws)
+                        if nxt_state is not None:
+                            states.append(nxt_state)
                 for n in reversed(range(s0, s1)):
                     mesh.step_adjoint_tape(states[n - s0], dt_sched[n * ni:(n + 1) * ni], tapes[n - s0], ubar, nxt,
                                            ws)
@@ -93,6 +110,7 @@ class Rollout(torch.autograd.Function):
             for n in reversed(range(s0, s1)):
                 mesh.step_adjoint(states[n - s0], dt_sched[n * ni:(n + 1) * ni], ubar, nxt, ws)
                 ubar, nxt = nxt, ubar
+        ctx.tapes = None
         return ubar, None, None, None, None, None
 
 

@@ -135,11 +135,13 @@ def test_gradient_27cubed_20_steps_against_finite_differences():
           flush=True)
     assert max(r for r, _ in res) <= 1e-6, res
     assert worst_plain <= 1e-4
-    # checkpoint interval and recorded segments do not change the gradient (bit for bit)
+    # checkpoint interval and recorded segments do not change the gradient (bit for bit); the
+    # forward pass records the last segment (all 20 steps at k = 20, the last 2 at k = 3)
     _, g1, _ = rollout.loss_and_grad(gm, u0, pts, target, steps, k=1, dt_sched=sched)
+    _, g3, _ = rollout.loss_and_grad(gm, u0, pts, target, steps, k=3, dt_sched=sched)
     _, g20, _ = rollout.loss_and_grad(gm, u0, pts, target, steps, k=20, dt_sched=sched)
     _, g_rerun, _ = rollout.loss_and_grad(gm, u0, pts, target, steps, k=5, dt_sched=sched, record=False)
-    assert torch.equal(g1, g) and torch.equal(g20, g) and torch.equal(g_rerun, g)
+    assert torch.equal(g1, g) and torch.equal(g3, g) and torch.equal(g20, g) and torch.equal(g_rerun, g)
     # Taylor remainder |J(u+hv) - J(u) - h<g,v>| is second order in h
     v = dev(dirs[0])
     h0 = 1e-3 * float(u0.norm() / v.norm())
