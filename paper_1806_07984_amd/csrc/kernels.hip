@@ -955,7 +955,10 @@ __device__ __forceinline__ double zsum64(double a, double x, double acc)
 // iteration's divergence G(u) in plane N (npic >= 2; the first iterate is
 // u - KWsum_j G(u), which the adjoint rebuilds with the same fma), and
 // iterate r = 2 .. npic-1 at time node j in plane N + 1 + (r-2) N + j.
-// At most npic N planes.
+// At most npic N planes.  The tape is read once, by the adjoint step, and
+// goes out with non-temporal stores: at 27^3 its 650 MB per step otherwise
+// pushed the step's own projections out of the 256 MB Infinity Cache before
+// the face kernel read them (that kernel took 89 instead of 56 us).
 template <bool STORE>
 __device__ __forceinline__ void pred4_wave_f64(const double *__restrict__ u, double *__restrict__ ustar,
                                                double *__restrict__ traces, int64_t c, int64_t nc, int lev,
@@ -1007,7 +1010,7 @@ __device__ __forceinline__ void pred4_wave_f64(const double *__restrict__ u, dou
             for (int j = 0; j < N; ++j)
 #pragma unroll
                 for (int v = 0; v < NV; ++v)
-                    *lane_at(iters + (((p0 + j) * NV + v) * nc + c) * N3, lu) = q[j][v];
+                    __builtin_nontemporal_store(q[j][v], lane_at(iters + (((p0 + j) * NV + v) * nc + c) * N3, lu));
         }
     };
     if (npic > 0) {
@@ -1018,7 +1021,8 @@ __device__ __forceinline__ void pred4_wave_f64(const double *__restrict__ u, dou
         if constexpr (STORE) {
             if (npic >= 2)
 #pragma unroll
-                for (int v = 0; v < NV; ++v) *lane_at(iters + ((int64_t(N) * NV + v) * nc + c) * N3, lu) = g[v];
+                for (int v = 0; v < NV; ++v)
+                    __builtin_nontemporal_store(g[v], lane_at(iters + ((int64_t(N) * NV + v) * nc + c) * N3, lu));
         }
 #pragma unroll
         for (int j = 0; j < N; ++j)
@@ -1207,10 +1211,10 @@ __device__ __forceinline__ void pred4_adj_wave(const double *__restrict__ u, con
     // npic >= 1, so none of them is the state u itself; a select between the
     // state and the tape had the compiler split the kernel into branches,
     // across which the exchanged values stayed live: 330 registers, not 168)
-    auto load_plane = [&](int64_t pl, double q[NV]) {
+    auto load_plane = [&](int64_t pl, double q[NV]) {  // read once: non-temporal
         const double *base = iters + (pl * NV * nc + c) * N3;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) q[v] = *lane_at(base + int64_t(v) * nc * N3, lu);
+        for (int v = 0; v < NV; ++v) q[v] = __builtin_nontemporal_load(lane_at(base + int64_t(v) * nc * N3, lu));
     };
 
     // adjoint of u* = u + volume term: identity, and the transposed volume
@@ -1322,10 +1326,10 @@ __device__ __forceinline__ void pred4_adj_wave(const double *__restrict__ u, con
         reverse_iteration([&](int j, double q[NV]) { load_plane(N + 1 + int64_t(r - 3) * N + j, q); });
     if (npic >= 2)  // iterate 1 = u - KWsum_j G(u), as the forward kernel formed it
         reverse_iteration([&](int j, double q[NV]) {
-            double g[NV];
-            load_plane(N, g);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) q[v] = fma(-B.KWsum[j], g[v], *lane_at(u + (int64_t(v) * nc + c) * N3, lu));
+            for (int v = 0; v < NV; ++v)
+                q[v] = fma(-B.KWsum[j], *lane_at(iters + ((int64_t(N) * NV + v) * nc + c) * N3, lu),
+                           *lane_at(u + (int64_t(v) * nc + c) * N3, lu));
         });
     // r = 1: every q^(0)_j is u, and one divergence served all time nodes
     // with the row sums of KW; q^(0) = u adds the rest
@@ -1352,7 +1356,7 @@ __device__ __forceinline__ void pred4_adj_wave(const double *__restrict__ u, con
     for (int v = 0; v < NV; ++v) *lane_at(ubar + (int64_t(v) * nc + c) * N3, lu) = acc[v];
 }
 
-// three waves per SIMD (168 VGPRs, 12 of them spilled around the rebuilt
+// three waves per SIMD (168 VGPRs, 14 of them spilled around the rebuilt
 // first iterate); at two waves (176 VGPRs, no spills) the gradient of 20
 // steps at 27^3 took 1 % longer
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
