@@ -1768,7 +1768,7 @@ k_corrector4(const double *__restrict__ ustar, const T *__restrict__ fside, cons
 
 // The Riemann problems of a cell's six faces and the cell's corrector in one
 // pass, for one uniform periodic instance at N = 4 (cells in (k, j, i) order,
-// one wavefront per cell, four cells per block).  Rows of 16 lanes take one
+// one wavefront per cell, four cells per block, cells visited tile by tile).  Rows of 16 lanes take one
 // face each: faces 0-3 in a first round, 4-5 in a second (lanes 32-63 idle);
 // lane b of a row is face node b, reads its own side's and the neighbour's
 // projections, and the row's maximum is the face speed.  Both cells of a face
@@ -1779,8 +1779,8 @@ k_corrector4(const double *__restrict__ ustar, const T *__restrict__ fside, cons
 template <typename T, bool FUSE>
 __global__ void __launch_bounds__(256)
 k_face_corrector4(const double *__restrict__ ustar, const T *__restrict__ traces, const double *__restrict__ dt_dev,
-                  double *__restrict__ uout, int64_t nc, int nx, int ny, int nz, Geo geo, double gamma,
-                  double *__restrict__ partial, int *__restrict__ status)
+                  double *__restrict__ uout, int64_t nc, int nx, int ny, int nz, int tx, int ty, int tz, Geo geo,
+                  double gamma, double *__restrict__ partial, int *__restrict__ status)
 {
     constexpr int N2 = 16, N3 = 64;
     __shared__ T fs[4 * 6 * NV * N2];
@@ -1797,20 +1797,29 @@ k_face_corrector4(const double *__restrict__ ustar, const T *__restrict__ traces
     const double dt = dt_dev[0];
     const double cx = dt * geo.inv_dx[0][0], cy = dt * geo.inv_dx[0][1], cz = dt * geo.inv_dx[0][2];
     double rate = 0.0;
-    // Workgroups go to the 8 XCDs in turn (workgroup i to XCD i mod 8): each
-    // XCD walks one contiguous eighth of the cells, so the face neighbours
-    // along y (nx cells away) are read on the XCD, and around the time, that
-    // read them as their own, while they are still in that XCD's L2.
-    const int64_t units = (nc + 3) / 4;
+    // Cells are visited in tiles of tx x ty x tz (tx a multiple of 4, so the
+    // four cells of a block are neighbours along x), x fastest inside a tile
+    // and over the tiles: the cells in flight at one time form about a tile,
+    // and most face neighbours along all three axes are read while the cell
+    // that owns them is also being read.  Slots past the mesh's edge are idle
+    // wavefronts.  Workgroups go to the 8 XCDs in turn (workgroup i to XCD
+    // i mod 8), each with its own L2, and each XCD walks one contiguous eighth
+    // of the slots.
+    const int64_t ntx = (nx + tx - 1) / tx, nty = (ny + ty - 1) / ty, ntz = (nz + tz - 1) / tz;
+    const int64_t tsz = int64_t(tx) * ty * tz;
+    const int64_t units = ntx * nty * ntz * tsz / 4;
     const bool by_xcd = gridDim.x % 8 == 0;
     const int xcd = by_xcd ? int(blockIdx.x % 8) : 0;
     const int64_t stride = by_xcd ? gridDim.x / 8 : gridDim.x;
     const int64_t ub = by_xcd ? units * xcd / 8 : 0, ue = by_xcd ? units * (xcd + 1) / 8 : units;
     for (int64_t unit = ub + (by_xcd ? blockIdx.x / 8 : blockIdx.x); unit < ue; unit += stride) {
-        const int64_t c = unit * 4 + wave;
-        const bool cell_ok = c < nc;  // uniform per wavefront
+        const int64_t slot = unit * 4 + wave, t = slot / tsz, o = slot % tsz;
+        const int64_t x = (t % ntx) * tx + o % tx, y = ((t / ntx) % nty) * ty + (o / tx) % ty,
+                      z = (t / (ntx * nty)) * tz + o / (int64_t(tx) * ty);
+        const bool cell_ok = x < nx && y < ny && z < nz;  // uniform per wavefront
+        const int64_t c = cell_ok ? x + nx * (y + int64_t(ny) * z) : 0;
         if (cell_ok) {
-            const int64_t ijk[3] = {c % nx, (c / nx) % ny, c / nxy};
+            const int64_t ijk[3] = {x, y, z};
             const int64_t ext[3] = {nx, ny, nz}, str[3] = {1, nx, nxy};
 #pragma unroll 1
             for (int r = 0; r < 2; ++r) {  // one round's loads in flight: bounds the registers
@@ -3828,12 +3837,21 @@ hipError_t launch_face_corrector4(const double *ustar, const T *traces, const do
                                   hipStream_t st)
 {
     const int64_t blocks = corrector_blocks(4, nc);
+    // tiles of about 12 x 9 x 9 cells (about what the chip holds in flight);
+    // tx, a multiple of 4, leaves the fewest idle slots along x (closest to 12
+    // among equals: 12 at 81 cells, 4 at 27)
+    int tx = 4;
+    for (int t = 4, best = 1 << 30; t <= 28; t += 4) {
+        const int padded = (n[0] + t - 1) / t * t;
+        if (padded < best || (padded == best && std::abs(t - 12) < std::abs(tx - 12))) best = padded, tx = t;
+    }
+    const int ty = std::min(9, n[1]), tz = std::min(9, n[2]);
     if (partial)
         hipLaunchKernelGGL((k_face_corrector4<T, true>), dim3(unsigned(blocks)), dim3(256), 0, st, ustar, traces, dt,
-                           uout, nc, n[0], n[1], n[2], geo, gamma, partial, status);
+                           uout, nc, n[0], n[1], n[2], tx, ty, tz, geo, gamma, partial, status);
     else
         hipLaunchKernelGGL((k_face_corrector4<T, false>), dim3(unsigned(blocks)), dim3(256), 0, st, ustar, traces, dt,
-                           uout, nc, n[0], n[1], n[2], geo, gamma, partial, status);
+                           uout, nc, n[0], n[1], n[2], tx, ty, tz, geo, gamma, partial, status);
     return hipGetLastError();
 }
 
