@@ -203,13 +203,14 @@ def test_step_to_end_time(precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("n", [(6, 5, 7), (1, 4, 2), (3, 1, 1)])
+@pytest.mark.parametrize("n", [(6, 5, 7), (1, 4, 2), (3, 1, 1), (13, 17, 11)])
 def test_face_fusion_same_bits(precision, n):
     """adg_step with the Riemann problems inside the corrector (the default for
     one uniform p = 3 instance) against the separate face and corrector
     kernels: the same bits after several steps, including the step sizes, on
     meshes with unequal and single-cell axes (a cell that is its own
-    periodic neighbour); and the oracle's run to the stated bar."""
+    periodic neighbour) and with partial cell tiles along every axis (13 x 17
+    x 11: tiles of 8 x 9 x 9); and the oracle's run to the stated bar."""
     om, gm = make_pair(3, n, precision)
     u0 = inputs.density_wave_noisy(om.node_coords(), seed=31, noise=0.02)
     steps = 4
