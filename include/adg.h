@@ -465,6 +465,13 @@ adg_status adg_lin_predictor(adg_lin *lin, const double *material, const double 
  * dt.  ws holds workspace_bytes.  Enqueued on stream, no synchronisation. */
 adg_status adg_lin_step(adg_lin *lin, const double *material, double *u, int32_t n_steps, double *dt_out,
                         void *ws, hipStream_t stream);
+/* Face fusion of the elastic step (on by default, p = 3 only): adg_lin_step
+ * solves each cell's six face problems (the flux of Sec. 2.4 with the larger
+ * P-wave speed of the two cells) inside that cell's corrector (Eq. 4), each
+ * face by both of its cells with the same operands in the same order, so no
+ * face-flux array goes through device memory; the same bits either way.
+ * enable = 0 switches it off.  ADG_ERR_INVALID_ARG for a bad handle. */
+adg_status adg_lin_set_face_fusion(adg_lin *lin, int32_t enable);
 
 const char *adg_last_error(void);
 

@@ -27,7 +27,7 @@ EXPORTS = ["adg_init_mesh", "adg_free_mesh", "adg_mesh_info", "adg_instance_info
            "adg_set_switch_tape", "adg_set_pipeline", "adg_indicator", "adg_adapt_plan", "adg_transfer",
            "adg_set_limiter", "adg_limiter_stats", "adg_lin_init", "adg_lin_free", "adg_lin_info", "adg_lin_dt",
            "adg_lin_predictor", "adg_lin_step", "adg_step_noalloc", "adg_adapt_plan_mesh",
-           "adg_step_record", "adg_step_adjoint_tape", "adg_set_face_fusion"]
+           "adg_step_record", "adg_step_adjoint_tape", "adg_set_face_fusion", "adg_lin_set_face_fusion"]
 PHASES = ["cfl", "predictor", "hanging", "riemann", "corrector", "limiter"]
 
 
@@ -114,6 +114,7 @@ def load():
         "adg_lin_dt": [P, P, P, P],
         "adg_lin_predictor": [P, P, P, P, P, P, P],
         "adg_lin_step": [P, P, P, I32, P, P, P],
+        "adg_lin_set_face_fusion": [P, I32],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -552,6 +553,11 @@ class LinMesh:
                                         _ptr(dt, torch.float64, 1, "dt"), ctypes.c_void_p(ustar.data_ptr()),
                                         ctypes.c_void_p(traces.data_ptr()), _stream(stream)))
         return ustar, traces
+
+    def set_face_fusion(self, enable):
+        """Faces inside the corrector at p = 3 (adg_lin_set_face_fusion; on by
+        default, the same bits either way)."""
+        _check(load().adg_lin_set_face_fusion(self._h, int(bool(enable))))
 
     def step(self, material, u, n_steps, ws, dt_out=None, stream=None):
         import torch

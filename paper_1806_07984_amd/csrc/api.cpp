@@ -2000,6 +2000,7 @@ struct adg_lin {
     double cfl = 0.0;
     int64_t nc = 0;
     double *dt_dev = nullptr;
+    bool fuse_faces = true;  // N = 4: faces inside the corrector
 };
 
 namespace {
@@ -2116,6 +2117,16 @@ adg_status adg_lin_predictor(adg_lin *lin, const double *material, const double 
     return ADG_OK;
 }
 
+adg_status adg_lin_set_face_fusion(adg_lin *lin, int32_t enable)
+{
+    if (!valid_lin(lin)) {
+        set_error("adg_lin_set_face_fusion: invalid handle");
+        return ADG_ERR_INVALID_ARG;
+    }
+    lin->fuse_faces = enable != 0;
+    return ADG_OK;
+}
+
 adg_status adg_lin_step(adg_lin *lin, const double *material, double *u, int32_t n_steps, double *dt_out, void *ws,
                         hipStream_t stream)
 {
@@ -2134,6 +2145,12 @@ adg_status adg_lin_step(adg_lin *lin, const double *material, double *u, int32_t
     for (int32_t k = 0; k < n_steps; ++k) {
         ADG_HIP(launch_lin_predictor(lin->N, u, material, lin->dt_dev, ustar, traces, lin->nc, lin->inv_dx, stream),
                 "linear predictor");
+        if (lin->N == 4 && lin->fuse_faces) {
+            ADG_HIP(launch_lin_face_corrector4(ustar, traces, material, lin->dt_dev, u, lin->nc, lin->n, lin->inv_dx,
+                                               stream),
+                    "linear faces and corrector");
+            continue;
+        }
         ADG_HIP(launch_lin_riemann(lin->N, traces, material, fside, lin->nc, lin->n, stream), "linear riemann");
         ADG_HIP(launch_lin_corrector(lin->N, ustar, fside, lin->dt_dev, u, lin->nc, lin->inv_dx, stream),
                 "linear corrector");

@@ -84,6 +84,9 @@ hipError_t launch_corrector(int N, const double *ustar, const T *fside, const do
                             int64_t nc, const int8_t *level, const Geo &geo, hipStream_t st, double gamma = 0.0,
                             double *partial = nullptr, int *status = nullptr, int64_t c0 = 0, int64_t c1 = -1);
 int corrector_blocks(int N, int64_t nc);
+// tiles (tx x ty x tz cells) in which the fused face kernels visit an
+// n[0] x n[1] x n[2] mesh
+void face_tiles(const int n[3], int &tx, int &ty, int &tz);
 // The conforming Riemann problems and the corrector in one kernel, for one
 // uniform periodic instance at N = 4 with n[0] x n[1] x n[2] cells: the same
 // bits as launch_riemann on every axis followed by launch_corrector (partial
@@ -169,6 +172,10 @@ hipError_t launch_lin_riemann(int N, const double *traces, const double *mat, do
                               const int n[3], hipStream_t st);
 hipError_t launch_lin_corrector(int N, const double *ustar, const double *fside, const double *dt, double *u,
                                 int64_t nc, const double inv_dx[3], hipStream_t st);
+// N = 4: launch_lin_riemann followed by launch_lin_corrector in one kernel,
+// the same bits, without the face-flux array.
+hipError_t launch_lin_face_corrector4(const double *ustar, const double *traces, const double *mat, const double *dt,
+                                      double *u, int64_t nc, const int n[3], const double inv_dx[3], hipStream_t st);
 
 int cfl_blocks(int N, int64_t nc);
 // factor = cfl / (2p + 1); writes dt_out[0] (and hist[0] if not null)

@@ -1766,6 +1766,43 @@ k_corrector4(const double *__restrict__ ustar, const T *__restrict__ fside, cons
     }
 }
 
+// Cells of an nx x ny x nz mesh visited in tiles of tx x ty x tz (tx a
+// multiple of 4, so the four cells of a block are neighbours along x), x
+// fastest inside a tile and over the tiles: the cells in flight at one time
+// form about a tile, and most face neighbours along all three axes are read
+// while the cell that owns them is also being read.  Workgroups go to the 8
+// XCDs in turn (workgroup i to XCD i mod 8), each with its own L2, and each
+// XCD walks one contiguous eighth of the blocks of four slots.
+struct TileWalk {
+    int64_t nx, ny, nz, tx, ty, tz, ntx, nty, tsz, ub, ue, stride, first;
+    __device__ TileWalk(int nx_, int ny_, int nz_, int tx_, int ty_, int tz_)
+        : nx(nx_), ny(ny_), nz(nz_), tx(tx_), ty(ty_), tz(tz_)
+    {
+        ntx = (nx + tx - 1) / tx;
+        nty = (ny + ty - 1) / ty;
+        const int64_t ntz = (nz + tz - 1) / tz;
+        tsz = tx * ty * tz;
+        const int64_t units = ntx * nty * ntz * tsz / 4;
+        const bool by_xcd = gridDim.x % 8 == 0;
+        const int xcd = by_xcd ? int(blockIdx.x % 8) : 0;
+        stride = by_xcd ? gridDim.x / 8 : gridDim.x;
+        ub = by_xcd ? units * xcd / 8 : 0;
+        ue = by_xcd ? units * (xcd + 1) / 8 : units;
+        first = ub + (by_xcd ? blockIdx.x / 8 : blockIdx.x);
+    }
+    // slot `wave` of block-unit `unit`: its cell and coordinates, false past the mesh's edge
+    __device__ bool cell(int64_t unit, int wave, int64_t &c, int64_t ijk[3]) const
+    {
+        const int64_t slot = unit * 4 + wave, t = slot / tsz, o = slot % tsz;
+        ijk[0] = (t % ntx) * tx + o % tx;
+        ijk[1] = ((t / ntx) % nty) * ty + (o / tx) % ty;
+        ijk[2] = (t / (ntx * nty)) * tz + o / (tx * ty);
+        const bool ok = ijk[0] < nx && ijk[1] < ny && ijk[2] < nz;
+        c = ok ? ijk[0] + nx * (ijk[1] + ny * ijk[2]) : 0;
+        return ok;
+    }
+};
+
 // The Riemann problems of a cell's six faces and the cell's corrector in one
 // pass, for one uniform periodic instance at N = 4 (cells in (k, j, i) order,
 // one wavefront per cell, four cells per block, cells visited tile by tile).  Rows of 16 lanes take one
@@ -1797,29 +1834,11 @@ k_face_corrector4(const double *__restrict__ ustar, const T *__restrict__ traces
     const double dt = dt_dev[0];
     const double cx = dt * geo.inv_dx[0][0], cy = dt * geo.inv_dx[0][1], cz = dt * geo.inv_dx[0][2];
     double rate = 0.0;
-    // Cells are visited in tiles of tx x ty x tz (tx a multiple of 4, so the
-    // four cells of a block are neighbours along x), x fastest inside a tile
-    // and over the tiles: the cells in flight at one time form about a tile,
-    // and most face neighbours along all three axes are read while the cell
-    // that owns them is also being read.  Slots past the mesh's edge are idle
-    // wavefronts.  Workgroups go to the 8 XCDs in turn (workgroup i to XCD
-    // i mod 8), each with its own L2, and each XCD walks one contiguous eighth
-    // of the slots.
-    const int64_t ntx = (nx + tx - 1) / tx, nty = (ny + ty - 1) / ty, ntz = (nz + tz - 1) / tz;
-    const int64_t tsz = int64_t(tx) * ty * tz;
-    const int64_t units = ntx * nty * ntz * tsz / 4;
-    const bool by_xcd = gridDim.x % 8 == 0;
-    const int xcd = by_xcd ? int(blockIdx.x % 8) : 0;
-    const int64_t stride = by_xcd ? gridDim.x / 8 : gridDim.x;
-    const int64_t ub = by_xcd ? units * xcd / 8 : 0, ue = by_xcd ? units * (xcd + 1) / 8 : units;
-    for (int64_t unit = ub + (by_xcd ? blockIdx.x / 8 : blockIdx.x); unit < ue; unit += stride) {
-        const int64_t slot = unit * 4 + wave, t = slot / tsz, o = slot % tsz;
-        const int64_t x = (t % ntx) * tx + o % tx, y = ((t / ntx) % nty) * ty + (o / tx) % ty,
-                      z = (t / (ntx * nty)) * tz + o / (int64_t(tx) * ty);
-        const bool cell_ok = x < nx && y < ny && z < nz;  // uniform per wavefront
-        const int64_t c = cell_ok ? x + nx * (y + int64_t(ny) * z) : 0;
+    const TileWalk walk(nx, ny, nz, tx, ty, tz);  // slots past the mesh's edge are idle wavefronts
+    for (int64_t unit = walk.first; unit < walk.ue; unit += walk.stride) {
+        int64_t c, ijk[3];
+        const bool cell_ok = walk.cell(unit, wave, c, ijk);  // uniform per wavefront
         if (cell_ok) {
-            const int64_t ijk[3] = {x, y, z};
             const int64_t ext[3] = {nx, ny, nz}, str[3] = {1, nx, nxy};
 #pragma unroll 1
             for (int r = 0; r < 2; ++r) {  // one round's loads in flight: bounds the registers
@@ -3635,6 +3654,78 @@ k_lin_corrector(const double *__restrict__ ustar, const double *__restrict__ fsi
     }
 }
 
+// The elastic step's faces inside its corrector at N = 4: one wavefront per
+// cell, four cells per block, cells visited by TileWalk.  Rows of 16 lanes
+// take one face each (faces 0-3, then 4-5), lane b of a row face node b; the
+// face's flux is that of k_lin_riemann (same operands, same operations), so
+// both cells of a face get its bits, and the update through the block's LDS
+// is that of k_lin_corrector.  No face-flux array is written or read.
+__global__ void __launch_bounds__(256)
+k_lin_face_corrector4(const double *__restrict__ ustar, const double *__restrict__ traces,
+                      const double *__restrict__ mat, const double *__restrict__ dt_dev, double *__restrict__ u,
+                      int64_t nc, int nx, int ny, int nz, int tx, int ty, int tz, double idx0, double idx1,
+                      double idx2)
+{
+    constexpr int N = 4, N2 = 16, N3 = 64;
+    __shared__ double fs[4 * 6 * NLV * N2];
+    const int l = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    double *fw = fs + wave * (6 * NLV * N2);
+    const DevBasis &B = c_basis[N];
+    const int b = l & 15;
+    const int a0 = l % N, a1 = (l / N) % N, a2 = l / N2;
+    const int bx = a1 + N * a2, by = a0 + N * a2, bz = a0 + N * a1;
+    const double dt = dt_dev[0];
+    const double sx = dt * idx0 * B.winv[a0], sy = dt * idx1 * B.winv[a1], sz = dt * idx2 * B.winv[a2];
+    const int64_t nxy = int64_t(nx) * ny;
+    const TileWalk walk(nx, ny, nz, tx, ty, tz);  // slots past the mesh's edge are idle wavefronts
+    for (int64_t unit = walk.first; unit < walk.ue; unit += walk.stride) {
+        int64_t c, ijk[3];
+        const bool cell_ok = walk.cell(unit, wave, c, ijk);  // uniform per wavefront
+        if (cell_ok) {
+            const int64_t ext[3] = {nx, ny, nz}, str[3] = {1, nx, nxy};
+#pragma unroll 1
+            for (int r = 0; r < 2; ++r) {
+                const int side = 4 * r + (l >> 4);
+                if (side < 6) {
+                    const int d = side >> 1, plus = side & 1;
+                    // the neighbour across this side (periodic)
+                    const int64_t q = ijk[d] + (plus ? 1 : -1);
+                    const int64_t qn = q < 0 ? q + ext[d] : (q >= ext[d] ? q - ext[d] : q);
+                    const int64_t n = c + (qn - ijk[d]) * str[d];
+                    // the minus cell's plus side on the left, the plus cell's minus side on the right
+                    const int64_t cl = plus ? c : n, cr = plus ? n : c;
+                    const double sl = sqrt((mat[nc + cl] + 2.0 * mat[2 * nc + cl]) / mat[cl]);
+                    const double sr = sqrt((mat[nc + cr] + 2.0 * mat[2 * nc + cr]) / mat[cr]);
+                    const double sp = fmax(sl, sr);
+                    const int side_l = 2 * d + 1, side_r = 2 * d;
+#pragma unroll
+                    for (int v = 0; v < NLV; ++v) {
+                        const double QL = traces[((int64_t(side_l * 2 + 0) * NLV + v) * nc + cl) * N2 + b];
+                        const double FL = traces[((int64_t(side_l * 2 + 1) * NLV + v) * nc + cl) * N2 + b];
+                        const double QR = traces[((int64_t(side_r * 2 + 0) * NLV + v) * nc + cr) * N2 + b];
+                        const double FR = traces[((int64_t(side_r * 2 + 1) * NLV + v) * nc + cr) * N2 + b];
+                        fw[(side * NLV + v) * N2 + b] = 0.5 * (FL + FR) - 0.5 * sp * (QR - QL);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (cell_ok) {
+#pragma unroll
+            for (int v = 0; v < NLV; ++v) {
+                auto F = [&](int side, int bb) { return fw[(side * NLV + v) * N2 + bb]; };
+                const double s = sx * (B.R[a0] * F(1, bx) - B.L[a0] * F(0, bx)) +
+                                 sy * (B.R[a1] * F(3, by) - B.L[a1] * F(2, by)) +
+                                 sz * (B.R[a2] * F(5, bz) - B.L[a2] * F(4, bz));
+                const int64_t o = (int64_t(v) * nc + c) * N3 + l;
+                u[o] = ustar[o] - s;
+            }
+        }
+        __syncthreads();  // the next cells overwrite the fluxes
+    }
+}
+
 // dt = factor / max_c c_p(c) (one block); factor = cfl / ((2p+1) sum_d 1/dx_d)
 __global__ void __launch_bounds__(1024)
 k_lin_cfl(const double *__restrict__ mat, int64_t nc, double factor, double *__restrict__ dt_out)
@@ -3837,15 +3928,8 @@ hipError_t launch_face_corrector4(const double *ustar, const T *traces, const do
                                   hipStream_t st)
 {
     const int64_t blocks = corrector_blocks(4, nc);
-    // tiles of about 12 x 9 x 9 cells (about what the chip holds in flight);
-    // tx, a multiple of 4, leaves the fewest idle slots along x (closest to 12
-    // among equals: 12 at 81 cells, 4 at 27)
-    int tx = 4;
-    for (int t = 4, best = 1 << 30; t <= 28; t += 4) {
-        const int padded = (n[0] + t - 1) / t * t;
-        if (padded < best || (padded == best && std::abs(t - 12) < std::abs(tx - 12))) best = padded, tx = t;
-    }
-    const int ty = std::min(9, n[1]), tz = std::min(9, n[2]);
+    int tx, ty, tz;
+    face_tiles(n, tx, ty, tz);
     if (partial)
         hipLaunchKernelGGL((k_face_corrector4<T, true>), dim3(unsigned(blocks)), dim3(256), 0, st, ustar, traces, dt,
                            uout, nc, n[0], n[1], n[2], tx, ty, tz, geo, gamma, partial, status);
@@ -3963,6 +4047,20 @@ hipError_t launch_cfl(int N, const double *u, int64_t nc, const int8_t *level, c
     hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(1024), 0, st, partial, nb, factor, dt_out, hist, 0.0,
                        static_cast<double *>(nullptr));
     return hipGetLastError();
+}
+
+// Tiles of the fused face kernels' cell walk: about 12 x 9 x 9 cells (about
+// what the chip holds in flight); tx, a multiple of 4, leaves the fewest idle
+// slots along x (closest to 12 among equals: 12 at 81 cells, 4 at 27).
+void face_tiles(const int n[3], int &tx, int &ty, int &tz)
+{
+    tx = 4;
+    for (int t = 4, best = 1 << 30; t <= 28; t += 4) {
+        const int padded = (n[0] + t - 1) / t * t;
+        if (padded < best || (padded == best && std::abs(t - 12) < std::abs(tx - 12))) best = padded, tx = t;
+    }
+    ty = std::min(9, n[1]);
+    tz = std::min(9, n[2]);
 }
 
 int corrector_blocks(int N, int64_t nc)
@@ -4164,6 +4262,17 @@ hipError_t launch_lim_recorrect(int N, const double *ustar, const T *fside, doub
         hipLaunchKernelGGL((k_lim_recorrect<T, NN>), dim3(LIM_GRID), dim3(round64(NN * NN * NN)), 0, st, ustar, fside,
                            dt, u, nc, geo, L.rlist, L.cnt, L.level);
     });
+    return hipGetLastError();
+}
+
+hipError_t launch_lin_face_corrector4(const double *ustar, const double *traces, const double *mat, const double *dt,
+                                      double *u, int64_t nc, const int n[3], const double inv_dx[3], hipStream_t st)
+{
+    if (nc <= 0) return hipSuccess;
+    int tx, ty, tz;
+    face_tiles(n, tx, ty, tz);
+    hipLaunchKernelGGL(k_lin_face_corrector4, dim3(unsigned(corrector_blocks(4, nc))), dim3(256), 0, st, ustar, traces,
+                       mat, dt, u, nc, n[0], n[1], n[2], tx, ty, tz, inv_dx[0], inv_dx[1], inv_dx[2]);
     return hipGetLastError();
 }
 
