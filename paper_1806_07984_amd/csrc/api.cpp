@@ -1110,9 +1110,10 @@ adg_status adg_init_mesh(const adg_instance_desc *desc, int32_t n_instances, adg
     ok = ok && dev_alloc(m, m->status_dev, 1) && dev_alloc(m, m->dt_dev, size_t(n_instances)) &&
          dev_alloc(m, m->clock_dev, size_t(n_instances));
     if (ok) {
-        hipDeviceProp_t prop;
-        ok = hipGetDeviceProperties(&prop, m->device) == hipSuccess;
-        m->n_cu = ok ? prop.multiProcessorCount : 1;
+        // one attribute, not the whole property record (a handle is made per adaptation)
+        int ncu = 1;
+        ok = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, m->device) == hipSuccess;
+        m->n_cu = ok ? ncu : 1;
         ok = ok && hipStreamCreateWithFlags(&m->gs_a, hipStreamNonBlocking) == hipSuccess &&
              hipStreamCreateWithFlags(&m->gs_b, hipStreamNonBlocking) == hipSuccess &&
              hipEventCreateWithFlags(&m->ev_in, hipEventDisableTiming) == hipSuccess &&
