@@ -2143,10 +2143,13 @@ adg_status adg_lin_step(adg_lin *lin, const double *material, double *u, int32_t
     double *fside = reinterpret_cast<double *>(w);
     adg_status s = lin_dt(lin, material, stream);
     if (s != ADG_OK) return s;
+    const bool fused = lin->N == 4 && lin->fuse_faces;
     for (int32_t k = 0; k < n_steps; ++k) {
-        ADG_HIP(launch_lin_predictor(lin->N, u, material, lin->dt_dev, ustar, traces, lin->nc, lin->inv_dx, stream),
+        // the fused faces form the flux traces from the state traces
+        ADG_HIP(launch_lin_predictor(lin->N, u, material, lin->dt_dev, ustar, traces, lin->nc, lin->inv_dx, stream,
+                                     !fused),
                 "linear predictor");
-        if (lin->N == 4 && lin->fuse_faces) {
+        if (fused) {
             ADG_HIP(launch_lin_face_corrector4(ustar, traces, material, lin->dt_dev, u, lin->nc, lin->n, lin->inv_dx,
                                                stream),
                     "linear faces and corrector");

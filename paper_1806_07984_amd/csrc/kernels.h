@@ -166,14 +166,16 @@ hipError_t launch_lim_recorrect(int N, const double *ustar, const T *fside, doub
 // Linear variant (elastic waves, 9 unknowns, uniform periodic mesh, FP64).
 // mat: [3][nc] (rho, lambda, mu); factor = cfl / ((2p+1) sum_d 1/dx_d).
 hipError_t launch_lin_cfl(const double *mat, int64_t nc, double factor, double *dt, hipStream_t st);
+// flux_traces = false: only the state traces (array 0 of each side) are written
 hipError_t launch_lin_predictor(int N, const double *u, const double *mat, const double *dt, double *ustar,
-                                double *traces, int64_t nc, const double inv_dx[3], hipStream_t st);
+                                double *traces, int64_t nc, const double inv_dx[3], hipStream_t st,
+                                bool flux_traces = true);
 hipError_t launch_lin_riemann(int N, const double *traces, const double *mat, double *fside, int64_t nc,
                               const int n[3], hipStream_t st);
 hipError_t launch_lin_corrector(int N, const double *ustar, const double *fside, const double *dt, double *u,
                                 int64_t nc, const double inv_dx[3], hipStream_t st);
 // N = 4: launch_lin_riemann followed by launch_lin_corrector in one kernel,
-// the same bits, without the face-flux array.
+// the same bits, without the face-flux array; reads only the state traces.
 hipError_t launch_lin_face_corrector4(const double *ustar, const double *traces, const double *mat, const double *dt,
                                       double *u, int64_t nc, const int n[3], const double inv_dx[3], hipStream_t st);
 

@@ -3483,8 +3483,10 @@ template <int N> struct LinCfg {
     static constexpr int MIN_WAVES = N <= 4 ? 4 : 1;
 };
 
-// CPB cells per block, one thread per node.
-template <int N>
+// CPB cells per block, one thread per node.  FTR: also write the normal-flux
+// traces (the flux of the state trace, lin_flux); the fused elastic step
+// forms them again from the state traces and needs only those.
+template <int N, bool FTR = true>
 __global__ void __launch_bounds__(LinCfg<N>::THREADS) __attribute__((amdgpu_waves_per_eu(LinCfg<N>::MIN_WAVES, 8)))
 k_lin_predictor(const double *__restrict__ u, const double *__restrict__ mat, const double *__restrict__ dt_dev,
                 double *__restrict__ ustar, double *__restrict__ traces, int64_t nc, double idx0, double idx1,
@@ -3593,7 +3595,7 @@ k_lin_predictor(const double *__restrict__ u, const double *__restrict__ mat, co
 #pragma unroll
             for (int v = 0; v < NLV; ++v) {
                 traces[((int64_t(side * 2 + 0) * NLV + v) * nc + c) * N2 + b] = qf[v];
-                traces[((int64_t(side * 2 + 1) * NLV + v) * nc + c) * N2 + b] = f[v];
+                if constexpr (FTR) traces[((int64_t(side * 2 + 1) * NLV + v) * nc + c) * N2 + b] = f[v];
             }
         }
     }
@@ -3659,7 +3661,10 @@ k_lin_corrector(const double *__restrict__ ustar, const double *__restrict__ fsi
 // take one face each (faces 0-3, then 4-5), lane b of a row face node b; the
 // face's flux is that of k_lin_riemann (same operands, same operations), so
 // both cells of a face get its bits, and the update through the block's LDS
-// is that of k_lin_corrector.  No face-flux array is written or read.
+// is that of k_lin_corrector.  No face-flux array is written or read, and
+// the normal-flux traces are formed from the state traces with the
+// predictor's lin_flux and material terms (the values it would have stored),
+// so only the state traces are read.
 __global__ void __launch_bounds__(256)
 k_lin_face_corrector4(const double *__restrict__ ustar, const double *__restrict__ traces,
                       const double *__restrict__ mat, const double *__restrict__ dt_dev, double *__restrict__ u,
@@ -3699,14 +3704,29 @@ k_lin_face_corrector4(const double *__restrict__ ustar, const double *__restrict
                     const double sr = sqrt((mat[nc + cr] + 2.0 * mat[2 * nc + cr]) / mat[cr]);
                     const double sp = fmax(sl, sr);
                     const int side_l = 2 * d + 1, side_r = 2 * d;
+                    double QL[NLV], QR[NLV], FL[NLV], FR[NLV];
 #pragma unroll
                     for (int v = 0; v < NLV; ++v) {
-                        const double QL = traces[((int64_t(side_l * 2 + 0) * NLV + v) * nc + cl) * N2 + b];
-                        const double FL = traces[((int64_t(side_l * 2 + 1) * NLV + v) * nc + cl) * N2 + b];
-                        const double QR = traces[((int64_t(side_r * 2 + 0) * NLV + v) * nc + cr) * N2 + b];
-                        const double FR = traces[((int64_t(side_r * 2 + 1) * NLV + v) * nc + cr) * N2 + b];
-                        fw[(side * NLV + v) * N2 + b] = 0.5 * (FL + FR) - 0.5 * sp * (QR - QL);
+                        QL[v] = traces[((int64_t(side_l * 2 + 0) * NLV + v) * nc + cl) * N2 + b];
+                        QR[v] = traces[((int64_t(side_r * 2 + 0) * NLV + v) * nc + cr) * N2 + b];
                     }
+                    {
+                        const double rho = mat[cl], lam = mat[nc + cl], mu = mat[2 * nc + cl];
+                        const double lam2 = lam + 2.0 * mu, irho = 1.0 / rho;
+                        lin_flux(d, lam, mu, lam2, irho, QL, FL);
+                    }
+                    {
+                        const double rho = mat[cr], lam = mat[nc + cr], mu = mat[2 * nc + cr];
+                        const double lam2 = lam + 2.0 * mu, irho = 1.0 / rho;
+                        lin_flux(d, lam, mu, lam2, irho, QR, FR);
+                    }
+                    // rounded as the predictor stores them: without the pin the compiler
+                    // fuses the flux products into the sum below (other bits)
+#pragma unroll
+                    for (int v = 0; v < NLV; ++v) asm volatile("" : "+v"(FL[v]), "+v"(FR[v]));
+#pragma unroll
+                    for (int v = 0; v < NLV; ++v)
+                        fw[(side * NLV + v) * N2 + b] = 0.5 * (FL[v] + FR[v]) - 0.5 * sp * (QR[v] - QL[v]);
                 }
             }
         }
@@ -4283,13 +4303,19 @@ hipError_t launch_lin_cfl(const double *mat, int64_t nc, double factor, double *
 }
 
 hipError_t launch_lin_predictor(int N, const double *u, const double *mat, const double *dt, double *ustar,
-                                double *traces, int64_t nc, const double inv_dx[3], hipStream_t st)
+                                double *traces, int64_t nc, const double inv_dx[3], hipStream_t st, bool flux_traces)
 {
     if (nc <= 0) return hipSuccess;
     ADG_DISPATCH_N(N, {
         constexpr int CPB = LinCfg<NN>::CPB;
-        hipLaunchKernelGGL((k_lin_predictor<NN>), dim3(unsigned((nc + CPB - 1) / CPB)), dim3(LinCfg<NN>::THREADS), 0,
-                           st, u, mat, dt, ustar, traces, nc, inv_dx[0], inv_dx[1], inv_dx[2]);
+        if (flux_traces)
+            hipLaunchKernelGGL((k_lin_predictor<NN, true>), dim3(unsigned((nc + CPB - 1) / CPB)),
+                               dim3(LinCfg<NN>::THREADS), 0, st, u, mat, dt, ustar, traces, nc, inv_dx[0], inv_dx[1],
+                               inv_dx[2]);
+        else
+            hipLaunchKernelGGL((k_lin_predictor<NN, false>), dim3(unsigned((nc + CPB - 1) / CPB)),
+                               dim3(LinCfg<NN>::THREADS), 0, st, u, mat, dt, ustar, traces, nc, inv_dx[0], inv_dx[1],
+                               inv_dx[2]);
     });
     return hipGetLastError();
 }
