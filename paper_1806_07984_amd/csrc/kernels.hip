@@ -3601,6 +3601,126 @@ k_lin_predictor(const double *__restrict__ u, const double *__restrict__ mat, co
     }
 }
 
+// The elastic predictor at N = 4 on one wavefront per cell (lane = node
+// a = a0 + 4 a1 + 16 a2, as the FP64 Euler predictor), with nothing staged in
+// LDS: x and y contractions by DPP, z on v_mfma_f64_4x4x4f64.  The material
+// is constant in a cell, so the flux matrix A_d commutes with the derivative
+// along d: each application of L forms A_d of the node's state first and then
+// contracts, -sum_d (1/dx_d) D_d (A_d dk); the volume term likewise contracts
+// A_d qbar with the weak stiffness.  The same quantities as k_lin_predictor,
+// in another order of rounding.  FTR as there.  Three waves per SIMD (144
+// VGPRs; at two, 172 VGPRs, the 81^3 step took 4.73 instead of 4.48 ms; at
+// four it spills).
+template <bool FTR>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
+k_lin_predictor4(const double *__restrict__ u, const double *__restrict__ mat, const double *__restrict__ dt_dev,
+                 double *__restrict__ ustar, double *__restrict__ traces, int64_t nc, double idx0, double idx1,
+                 double idx2)
+{
+    constexpr int N = 4, N2 = 16, N3 = 64;
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const int64_t c = int64_t(blockIdx.x) * 4 + wave;
+    if (c >= nc) return;  // whole wavefront leaves together
+    const DevBasis &B = c_basis[N];
+    const int l = threadIdx.x & 63;
+    const int a0 = l & 3, a1 = (l >> 2) & 3, a2 = l >> 4;
+    // neighbour e of this lane along x (quad permutation) and y (row
+    // rotation), as in the FP64 Euler predictor; the z operator as this
+    // lane's MFMA A entry (row zi, column zk)
+    const int nx[4] = {a0, (a0 + 1) & 3, (a0 + 2) & 3, (a0 + 3) & 3};
+    const int ny[4] = {a1, (a1 + 3) & 3, (a1 + 2) & 3, (a1 + 1) & 3};
+    const int zi = l & 3, zk = l >> 4;
+    const double rho = mat[c], lam = mat[nc + c], mu = mat[2 * nc + c];
+    const double lam2 = lam + 2.0 * mu, irho = 1.0 / rho;
+    const double dt = dt_dev[0];
+    const double idx[3] = {idx0, idx1, idx2};
+    double uc[NLV], dk[NLV], qbar[NLV];
+#pragma unroll
+    for (int v = 0; v < NLV; ++v) {
+        uc[v] = u[(int64_t(v) * nc + c) * N3 + l];
+        dk[v] = uc[v];
+        qbar[v] = uc[v];
+    }
+    // -(1/dx_d) D_d rows of this lane
+    double Cx[4], Cy[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        Cx[e] = -idx[0] * B.D[a0 * N + nx[e]];
+        Cy[e] = -idx[1] * B.D[a1 * N + ny[e]];
+    }
+    const double Az = -idx[2] * B.D[zi * N + zk];
+    double fac = 1.0;
+    for (int k = 1; k < N; ++k) {
+        double nd[NLV], f[NLV];
+        lin_flux(0, lam, mu, lam2, irho, dk, f);
+#pragma unroll
+        for (int v = 0; v < NLV; ++v) nd[v] = fibre_sum64<0>(Cx, f[v], 0.0);
+        lin_flux(1, lam, mu, lam2, irho, dk, f);
+#pragma unroll
+        for (int v = 0; v < NLV; ++v) nd[v] = fibre_sum64<1>(Cy, f[v], nd[v]);
+        lin_flux(2, lam, mu, lam2, irho, dk, f);
+#pragma unroll
+        for (int v = 0; v < NLV; ++v) nd[v] = zsum64(Az, f[v], nd[v]);
+        fac *= dt / (k + 1);
+#pragma unroll
+        for (int v = 0; v < NLV; ++v) {
+            dk[v] = nd[v];
+            qbar[v] = fma(fac, nd[v], qbar[v]);
+        }
+    }
+    // volume term: u + sum_d (dt/dx_d) (1/w_{a_d}) Kw_d (A_d qbar)
+    {
+        double Vx[4], Vy[4], us[NLV], f[NLV];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            Vx[e] = dt * idx[0] * B.winv[a0] * B.Kw[a0 * N + nx[e]];
+            Vy[e] = dt * idx[1] * B.winv[a1] * B.Kw[a1 * N + ny[e]];
+        }
+        const double Vz = dt * idx[2] * B.winv[zi] * B.Kw[zi * N + zk];
+        lin_flux(0, lam, mu, lam2, irho, qbar, f);
+#pragma unroll
+        for (int v = 0; v < NLV; ++v) us[v] = fibre_sum64<0>(Vx, f[v], 0.0);
+        lin_flux(1, lam, mu, lam2, irho, qbar, f);
+#pragma unroll
+        for (int v = 0; v < NLV; ++v) us[v] = fibre_sum64<1>(Vy, f[v], us[v]);
+        lin_flux(2, lam, mu, lam2, irho, qbar, f);
+#pragma unroll
+        for (int v = 0; v < NLV; ++v) {
+            us[v] = zsum64(Vz, f[v], us[v]);
+            ustar[(int64_t(v) * nc + c) * N3 + l] = uc[v] + us[v];
+        }
+    }
+    // face projections: along each axis the lanes at index 0 hold the minus
+    // face (L weights) and those at index 3 the plus face (R weights) of one
+    // sum, then the normal flux of that state
+    double Px[4], Py[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        Px[e] = a0 == 0 ? B.L[nx[e]] : B.R[nx[e]];
+        Py[e] = a1 == 0 ? B.L[ny[e]] : B.R[ny[e]];
+    }
+    const double Pz = zi == 0 ? B.L[zk] : B.R[zk];
+    const int bf[3] = {a1 + N * a2, a0 + N * a2, a0 + N * a1};
+    const int ad[3] = {a0, a1, a2};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        double qf[NLV], f[NLV];
+#pragma unroll
+        for (int v = 0; v < NLV; ++v)
+            qf[v] = d == 0 ? fibre_sum64<0>(Px, qbar[v], 0.0)
+                           : (d == 1 ? fibre_sum64<1>(Py, qbar[v], 0.0) : zsum64(Pz, qbar[v], 0.0));
+        if (ad[d] == 0 || ad[d] == N - 1) {
+            const int side = 2 * d + (ad[d] == 0 ? 0 : 1);
+            if constexpr (FTR) lin_flux(d, lam, mu, lam2, irho, qf, f);
+#pragma unroll
+            for (int v = 0; v < NLV; ++v) {
+                traces[((int64_t(side * 2 + 0) * NLV + v) * nc + c) * N2 + bf[d]] = qf[v];
+                if constexpr (FTR) traces[((int64_t(side * 2 + 1) * NLV + v) * nc + c) * N2 + bf[d]] = f[v];
+            }
+        }
+    }
+}
+
 // Rusanov on the +d faces: thread per (cell, face node); both sides written.
 template <int N>
 __global__ void __launch_bounds__(256)
@@ -3776,6 +3896,7 @@ k_lin_cfl(const double *__restrict__ mat, int64_t nc, double factor, double *__r
 
 bool g_pred4_mfma = true;
 bool g_pred4_f64 = true;
+bool g_lin_pred4 = true;
 
 hipError_t upload_basis(const DevBasis *tab)
 {
@@ -4306,6 +4427,15 @@ hipError_t launch_lin_predictor(int N, const double *u, const double *mat, const
                                 double *traces, int64_t nc, const double inv_dx[3], hipStream_t st, bool flux_traces)
 {
     if (nc <= 0) return hipSuccess;
+    if (N == 4 && g_lin_pred4) {
+        if (flux_traces)
+            hipLaunchKernelGGL(k_lin_predictor4<true>, dim3(unsigned((nc + 3) / 4)), dim3(256), 0, st, u, mat, dt,
+                               ustar, traces, nc, inv_dx[0], inv_dx[1], inv_dx[2]);
+        else
+            hipLaunchKernelGGL(k_lin_predictor4<false>, dim3(unsigned((nc + 3) / 4)), dim3(256), 0, st, u, mat, dt,
+                               ustar, traces, nc, inv_dx[0], inv_dx[1], inv_dx[2]);
+        return hipGetLastError();
+    }
     ADG_DISPATCH_N(N, {
         constexpr int CPB = LinCfg<NN>::CPB;
         if (flux_traces)
