@@ -294,7 +294,7 @@ def run_batch(A, steps=10, seed=0):
     return out
 
 
-def run_limiter(A, steps=20, warmup=2):
+def run_limiter(A, steps=20, warmup=10):
     """A-posteriori subcell limiter: uniform periodic 81^3 mesh, p = 3, the
     discontinuous spherical blast wave (rho, p = 1, 1 inside radius 0.25,
     0.125, 0.1 outside, at rest), delta0 = 1e-4, eps = 1e-3; both precisions.
@@ -339,7 +339,7 @@ def run_limiter(A, steps=20, warmup=2):
     return out
 
 
-def run_linear(A, steps=20, warmup=2):
+def run_linear(A, steps=20, warmup=10):
     """Linear variant: elastic waves, uniform periodic 81^3 mesh, p = 3,
     Cauchy-Kowalevski predictor, FP64.  Synthetic layered medium (a softer
     layer, rho, lambda, mu = 2.0, 2.0, 1.0, for z > 0.75 over rho, lambda,
@@ -440,7 +440,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["fp64", "fp32"], default=None,
                     help="run one path only (for profiling runs)")
