@@ -294,6 +294,38 @@ def run_batch(A, steps=10, seed=0):
     return out
 
 
+def run_uniform(A, order, n, steps=10, warmup=10):
+    """The headline's workload at another order: a periodic n^3 mesh with about
+    the same number of degrees of freedom, the density wave with seeded node
+    noise, both precisions (the generic predictor and the separate face and
+    corrector kernels at p != 3).  DoF-updates/s and ms per step of plain
+    launches."""
+    import torch
+    from paper_1806_07984_amd import inputs
+    out = {"order": order, "cells": n ** 3, "dofs": 5 * n ** 3 * (order + 1) ** 3}
+    for prec in ("fp64", "fp32"):
+        mesh = A.Mesh(A.instance(order, (n,) * 3), prec)
+        xyz = mesh.node_coords().cpu().numpy().reshape(3, -1)
+        u = torch.from_numpy(inputs.density_wave_noisy(xyz, seed=SEED, noise=0.01).reshape(-1)).cuda()
+        del xyz
+        ws = mesh.empty_workspace()
+        s = torch.cuda.current_stream()
+        mesh.step(u, warmup, ws, stream_skeleton=s, stream_enclave=s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mesh.step(u, steps, ws, stream_skeleton=s, stream_enclave=s)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        mesh.status()
+        out[prec] = {"value": out["dofs"] * steps / dt, "ms_per_step": dt * 1e3 / steps}
+        mesh.close()
+        del u, ws
+    torch.cuda.empty_cache()
+    out["value"] = out["fp64"]["value"]
+    out["unit"] = "DoF-updates/s"
+    return out
+
+
 def run_limiter(A, steps=20, warmup=10):
     """A-posteriori subcell limiter: uniform periodic 81^3 mesh, p = 3, the
     discontinuous spherical blast wave (rho, p = 1, 1 inside radius 0.25,
@@ -445,7 +477,8 @@ def main():
     ap.add_argument("--only", choices=["fp64", "fp32"], default=None,
                     help="run one path only (for profiling runs)")
     ap.add_argument("--no-extra", action="store_true", help="skip the AMR and batch workloads")
-    ap.add_argument("--extra-only", choices=["amr", "amr_sharp", "batch", "adjoint", "limiter", "linear"],
+    ap.add_argument("--extra-only", choices=["amr", "amr_sharp", "batch", "adjoint", "limiter", "linear", "uniform_p4",
+                                             "uniform_p5"],
                     default=None,
                     help="run only one of the other workloads and print its JSON (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -471,6 +504,7 @@ def main():
     A.load()
     if args.extra_only:
         res = {"amr": run_amr, "amr_sharp": lambda A: run_amr(A, sharp=True), "batch": run_batch,
+               "uniform_p4": lambda A: run_uniform(A, 4, 65), "uniform_p5": lambda A: run_uniform(A, 5, 54),
                "adjoint": run_adjoint, "limiter": run_limiter, "linear": run_linear}[args.extra_only](A)
         print(json.dumps({"workload": args.extra_only, **res}))
         return
@@ -528,7 +562,9 @@ def main():
                       "roofline": roofline(k), "whole_step_roofline": whole_step(k)} for k, v in res.items()},
     }
     if not args.no_extra:
-        out["other_workloads"] = {"amr_blast_p4_27cubed_2levels": run_amr(A),
+        out["other_workloads"] = {"uniform_p4_65cubed": run_uniform(A, 4, 65),
+                                  "uniform_p5_54cubed": run_uniform(A, 5, 54),
+                                  "amr_blast_p4_27cubed_2levels": run_amr(A),
                                   "amr_sharp_blast_p4_27cubed_2levels_limited": run_amr(A, steps=20, sharp=True),
                                   "batch64_p2to6_seed0": run_batch(A),
                                   "adjoint_p3_27cubed_20steps": run_adjoint(A),
