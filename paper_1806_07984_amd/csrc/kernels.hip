@@ -199,9 +199,9 @@ __device__ __forceinline__ void flux3(T gm1, const T q[NV], T f[3][NV])
 }
 
 // Predictor of CPB cells (list entries first .. first+CPB-1) by one block of
-// at least pred_plane(N, CPB) threads; lds holds pred_lds_elems(N, CPB,
-// sizeof(T)) reals.
-template <typename T, int N, int CPB, bool STORE = false>
+// at least pred_plane(N, CPB) threads; lds holds NBUF x 15 planes
+// (pred_lds_elems(N, CPB, sizeof(T)) reals with the default NBUF).
+template <typename T, int N, int CPB, bool STORE = false, int NBUF = pred_nbuf(N, CPB, int(sizeof(T)))>
 __device__ __forceinline__ void predictor_body(T *__restrict__ lds, const double *__restrict__ u,
                                                double *__restrict__ ustar, T *__restrict__ traces,
                                                const int32_t *__restrict__ list, int64_t nlist, int64_t nc,
@@ -211,7 +211,6 @@ __device__ __forceinline__ void predictor_body(T *__restrict__ lds, const double
 {
     constexpr int N2 = N * N, N3 = N2 * N, NT = CPB * N3;
     constexpr int P = pred_plane(N, CPB);
-    constexpr int NBUF = pred_nbuf(N, CPB, int(sizeof(T)));
     const DevBasis &B = c_basis[N];
 
     // opaque: in the persistent kernels nothing derived from the lane index is
@@ -416,8 +415,14 @@ __device__ __forceinline__ void predictor_body(T *__restrict__ lds, const double
 #ifndef ADG_PRED_WAVES5
 #define ADG_PRED_WAVES5 3
 #endif
+// At N = 5 (not recording) three waves per SIMD.  In FP64 that also takes one
+// plane buffer (30 KB instead of 61 KB per block, so that three blocks fit a
+// CU) and spills 9 registers: the uniform p = 4 step at 65^3 went from 11.78
+// to 11.25 ms (one buffer at two waves: 12.0 ms).
 template <typename T, int N, bool STORE> struct PredWaves {
-    static constexpr int MIN = (std::is_same<T, float>::value && N == 5 && !STORE) ? ADG_PRED_WAVES5 : 1;
+    static constexpr int MIN = (N == 5 && !STORE) ? ADG_PRED_WAVES5 : 1;
+    static constexpr int NBUF = (!std::is_same<T, float>::value && N == 5 && !STORE)
+                                    ? 1 : pred_nbuf(N, PredCfg<N>::CPB, int(sizeof(T)));
 };
 
 template <typename T, int N, int CPB, bool STORE>
@@ -428,9 +433,10 @@ k_predictor(const double *__restrict__ u, double *__restrict__ ustar, T *__restr
             const int8_t *__restrict__ level, Geo geo, const double *__restrict__ dt_dev,
             double gamma, int npic, T *__restrict__ iters)
 {
-    __shared__ __align__(16) T lds[pred_lds_elems(N, CPB, int(sizeof(T)))];
-    predictor_body<T, N, CPB, STORE>(lds, u, ustar, traces, list, nlist, nc, level, geo, dt_dev[0], gamma, npic,
-                                     int64_t(blockIdx.x) * CPB, iters);
+    constexpr int NBUF = CPB == PredCfg<N>::CPB ? PredWaves<T, N, STORE>::NBUF : pred_nbuf(N, CPB, int(sizeof(T)));
+    __shared__ __align__(16) T lds[NBUF * 15 * pred_plane(N, CPB)];
+    predictor_body<T, N, CPB, STORE, NBUF>(lds, u, ustar, traces, list, nlist, nc, level, geo, dt_dev[0], gamma,
+                                           npic, int64_t(blockIdx.x) * CPB, iters);
 }
 
 // One variant of the batched predictor on one work item.
